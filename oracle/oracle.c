@@ -1,0 +1,348 @@
+/*
+ * oracle.c -- TEST INFRASTRUCTURE ONLY.  A plain, slow, obviously correct CPU
+ * implementation of what the swept rule computes.  Only tests, the smoke
+ * check and the benchmark's CPU-baseline leg may load this code; the product
+ * path never calls it.  It shares no source with the HIP library.
+ *
+ * What is computed.  The swept rule (paper, Sections 2-3) does not change the
+ * numbers a time-stepper produces: it only reorders the per-point sub-timestep
+ * updates in space-time so that nodes communicate once per many sub-timesteps,
+ * with no redundant work.  So the oracle is the plain definition: apply the
+ * sub-timestep update to every point of the periodic 1D grid (Section 3: the
+ * domain is periodic, every point has a left and a right neighbour), one
+ * sub-timestep after the other, from two full-grid buffers.
+ *
+ * Schemes (the paper fixes their structure, not every rounding; the readings
+ * below are the oracle's definition and every GPU path must reproduce them
+ * bit for bit):
+ *
+ *  Heat, 3-point finite difference with forward Euler (Section 4 names this
+ *  scheme as the cheapest sub-timestep, "3 FLOPs"); one sub-timestep per step:
+ *      u'[i] = u[i] + r * ((u[i-1] + u[i+1]) - 2*u[i])
+ *  evaluated in exactly that association, in the storage precision
+ *  (binary64 or binary32), with no fused multiply-add.
+ *
+ *  Kuramoto-Sivashinsky u_t = -u u_x - u_xx - u_xxxx (Section 6: finite
+ *  differences in space, explicit second-order Runge-Kutta in time).  The RK2
+ *  midpoint rule is split into four radius-1 sub-timesteps that forward the
+ *  variables the next one needs (Section 2: a sub-timestep reads the inputs
+ *  of a point and of its two neighbours and forwards unused variables):
+ *      D2(a)[i]  = ((a[i-1] + a[i+1]) - 2*a[i]) * c2          c2 = 1/(dx*dx)
+ *      D1(a)[i]  = (a[i+1] - a[i-1]) * c1                     c1 = 1/(2*dx)
+ *      F(a,b)[i] = -(((a[i]*D1(a)[i]) + b[i]) + D2(b)[i])
+ *      sub0: (u)      -> (u, w),    w  = D2(u)
+ *      sub1: (u,w)    -> (u, v),    v  = u + h*F(u,w)          h  = dt/2
+ *      sub2: (u,v)    -> (u, v, z), z  = D2(v)
+ *      sub3: (u,v,z)  -> (u'),      u' = u + dt*F(v,z)
+ *  F(u,w) is the right-hand side with u_xxxx = D2(D2 u); the midpoint stage
+ *  follows the two-stage Runge-Kutta example of Section 2.  The constants
+ *  c1, c2, h are rounded once, here, exactly as written above.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC.
+ * -ffp-contract=off is required so that no multiply-add is fused.  OpenMP
+ * only splits the independent per-point loop of a sub-timestep, so results do
+ * not depend on the thread count.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_OK 0
+#define ORACLE_EINVAL (-1)
+#define ORACLE_ENOMEM (-3)
+
+static int64_t wrap(int64_t i, int64_t n)
+{
+    int64_t m = i % n;
+    return m < 0 ? m + n : m;
+}
+
+static void set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------ heat */
+
+/* One forward-Euler heat sub-timestep on the whole periodic grid. */
+static void heat_step_f64(const double *a, double *b, int64_t n, double r)
+{
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < n; ++i) {
+        double left = a[wrap(i - 1, n)];
+        double mid = a[i];
+        double right = a[wrap(i + 1, n)];
+        double lap = (left + right) - 2.0 * mid;
+        b[i] = mid + r * lap;
+    }
+}
+
+static void heat_step_f32(const float *a, float *b, int64_t n, float r)
+{
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < n; ++i) {
+        float left = a[wrap(i - 1, n)];
+        float mid = a[i];
+        float right = a[wrap(i + 1, n)];
+        float lap = (left + right) - 2.0f * mid;
+        b[i] = mid + r * lap;
+    }
+}
+
+/* Advance u (n points, in place) by nsteps heat steps with coefficient r. */
+int oracle_heat_f64(double *u, int64_t n, int64_t nsteps, double r, int nthreads)
+{
+    double *a, *b, *t;
+    int64_t s;
+    if (!u || n < 3 || nsteps < 0)
+        return ORACLE_EINVAL;
+    set_threads(nthreads);
+    b = (double *)malloc((size_t)n * sizeof(double));
+    if (!b)
+        return ORACLE_ENOMEM;
+    a = u;
+    for (s = 0; s < nsteps; ++s) {
+        heat_step_f64(a, b, n, r);
+        t = a; a = b; b = t;
+    }
+    if (a != u) {
+        memcpy(u, a, (size_t)n * sizeof(double));
+        free(a);
+    } else {
+        free(b);
+    }
+    return ORACLE_OK;
+}
+
+int oracle_heat_f32(float *u, int64_t n, int64_t nsteps, float r, int nthreads)
+{
+    float *a, *b, *t;
+    int64_t s;
+    if (!u || n < 3 || nsteps < 0)
+        return ORACLE_EINVAL;
+    set_threads(nthreads);
+    b = (float *)malloc((size_t)n * sizeof(float));
+    if (!b)
+        return ORACLE_ENOMEM;
+    a = u;
+    for (s = 0; s < nsteps; ++s) {
+        heat_step_f32(a, b, n, r);
+        t = a; a = b; b = t;
+    }
+    if (a != u) {
+        memcpy(u, a, (size_t)n * sizeof(float));
+        free(a);
+    } else {
+        free(b);
+    }
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------ Kuramoto-Sivashinsky */
+
+typedef struct {
+    double dt, h, c1, c2;
+} ks_consts;
+
+static ks_consts ks_make(double dt, double dx)
+{
+    ks_consts k;
+    k.dt = dt;
+    k.h = 0.5 * dt;
+    k.c1 = 1.0 / (2.0 * dx);
+    k.c2 = 1.0 / (dx * dx);
+    return k;
+}
+
+/* -( (a_i * D1(a)_i + b_i) + D2(b)_i ), from the three neighbours of a and b */
+static double ks_rhs(double al, double am, double ar,
+                     double bl, double bm, double br, const ks_consts *k)
+{
+    double d1a = (ar - al) * k->c1;
+    double d2b = ((bl + br) - 2.0 * bm) * k->c2;
+    return -(((am * d1a) + bm) + d2b);
+}
+
+static double ks_d2(double l, double m, double r, const ks_consts *k)
+{
+    return ((l + r) - 2.0 * m) * k->c2;
+}
+
+/* Advance u (n points, in place) by nsteps RK2 steps = 4*nsteps sub-timesteps. */
+int oracle_ks_f64(double *u, int64_t n, int64_t nsteps, double dt, double dx,
+                  int nthreads)
+{
+    ks_consts k;
+    double *un, *w, *v, *z;
+    int64_t s, i;
+    if (!u || n < 3 || nsteps < 0 || !(dx > 0.0))
+        return ORACLE_EINVAL;
+    set_threads(nthreads);
+    k = ks_make(dt, dx);
+    un = (double *)malloc((size_t)n * sizeof(double));
+    w = (double *)malloc((size_t)n * sizeof(double));
+    v = (double *)malloc((size_t)n * sizeof(double));
+    z = (double *)malloc((size_t)n * sizeof(double));
+    if (!un || !w || !v || !z) {
+        free(un); free(w); free(v); free(z);
+        return ORACLE_ENOMEM;
+    }
+    for (s = 0; s < nsteps; ++s) {
+        /* sub0: w = D2(u) */
+#pragma omp parallel for schedule(static)
+        for (i = 0; i < n; ++i)
+            w[i] = ks_d2(u[wrap(i - 1, n)], u[i], u[wrap(i + 1, n)], &k);
+        /* sub1: v = u + h * F(u, w) */
+#pragma omp parallel for schedule(static)
+        for (i = 0; i < n; ++i) {
+            int64_t l = wrap(i - 1, n), r = wrap(i + 1, n);
+            v[i] = u[i] + k.h * ks_rhs(u[l], u[i], u[r], w[l], w[i], w[r], &k);
+        }
+        /* sub2: z = D2(v) */
+#pragma omp parallel for schedule(static)
+        for (i = 0; i < n; ++i)
+            z[i] = ks_d2(v[wrap(i - 1, n)], v[i], v[wrap(i + 1, n)], &k);
+        /* sub3: u' = u + dt * F(v, z) */
+#pragma omp parallel for schedule(static)
+        for (i = 0; i < n; ++i) {
+            int64_t l = wrap(i - 1, n), r = wrap(i + 1, n);
+            un[i] = u[i] + k.dt * ks_rhs(v[l], v[i], v[r], z[l], z[i], z[r], &k);
+        }
+        memcpy(u, un, (size_t)n * sizeof(double));
+    }
+    free(un); free(w); free(v); free(z);
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------ single outputs by cone */
+/*
+ * The value of point i after L sub-timesteps depends only on the inputs
+ * within L points of i (paper, Section 2: over n sub-timesteps the domain of
+ * dependence grows to the points within n edges).  These functions evaluate
+ * a few outputs of a large run one at a time: they apply the same update as
+ * above, level by level, on the shrinking window [i-L+l, i+L-l] of the
+ * periodic grid.  Used when the full grid is too large for the full run.
+ */
+
+int oracle_heat_f64_points(const double *u0, int64_t n, int64_t nsteps, double r,
+                           const int64_t *idx, int64_t count, double *out)
+{
+    int64_t q;
+    if (!u0 || !idx || !out || n < 3 || nsteps < 0 || count < 0)
+        return ORACLE_EINVAL;
+    for (q = 0; q < count; ++q) {
+        int64_t width = 2 * nsteps + 1, l, j;
+        double *a = (double *)malloc((size_t)width * sizeof(double));
+        double *b = (double *)malloc((size_t)width * sizeof(double));
+        if (!a || !b) {
+            free(a); free(b);
+            return ORACLE_ENOMEM;
+        }
+        for (j = 0; j < width; ++j)
+            a[j] = u0[wrap(idx[q] - nsteps + j, n)];
+        for (l = 1; l <= nsteps; ++l) {
+            int64_t wnew = width - 2 * l;
+            for (j = 0; j < wnew; ++j) {
+                double lap = (a[j] + a[j + 2]) - 2.0 * a[j + 1];
+                b[j] = a[j + 1] + r * lap;
+            }
+            { double *t = a; a = b; b = t; }
+        }
+        out[q] = a[0];
+        free(a); free(b);
+    }
+    return ORACLE_OK;
+}
+
+int oracle_heat_f32_points(const float *u0, int64_t n, int64_t nsteps, float r,
+                           const int64_t *idx, int64_t count, float *out)
+{
+    int64_t q;
+    if (!u0 || !idx || !out || n < 3 || nsteps < 0 || count < 0)
+        return ORACLE_EINVAL;
+    for (q = 0; q < count; ++q) {
+        int64_t width = 2 * nsteps + 1, l, j;
+        float *a = (float *)malloc((size_t)width * sizeof(float));
+        float *b = (float *)malloc((size_t)width * sizeof(float));
+        if (!a || !b) {
+            free(a); free(b);
+            return ORACLE_ENOMEM;
+        }
+        for (j = 0; j < width; ++j)
+            a[j] = u0[wrap(idx[q] - nsteps + j, n)];
+        for (l = 1; l <= nsteps; ++l) {
+            int64_t wnew = width - 2 * l;
+            for (j = 0; j < wnew; ++j) {
+                float lap = (a[j] + a[j + 2]) - 2.0f * a[j + 1];
+                b[j] = a[j + 1] + r * lap;
+            }
+            { float *t = a; a = b; b = t; }
+        }
+        out[q] = a[0];
+        free(a); free(b);
+    }
+    return ORACLE_OK;
+}
+
+int oracle_ks_f64_points(const double *u0, int64_t n, int64_t nsteps, double dt,
+                         double dx, const int64_t *idx, int64_t count, double *out)
+{
+    ks_consts k;
+    int64_t q;
+    if (!u0 || !idx || !out || n < 3 || nsteps < 0 || count < 0 || !(dx > 0.0))
+        return ORACLE_EINVAL;
+    k = ks_make(dt, dx);
+    for (q = 0; q < count; ++q) {
+        /* 4 sub-timesteps per step, each of radius 1 */
+        int64_t rad = 4 * nsteps, width = 2 * rad + 1, s, j;
+        double *u = (double *)malloc((size_t)width * sizeof(double));
+        double *w = (double *)malloc((size_t)width * sizeof(double));
+        double *v = (double *)malloc((size_t)width * sizeof(double));
+        double *z = (double *)malloc((size_t)width * sizeof(double));
+        double *un = (double *)malloc((size_t)width * sizeof(double));
+        int64_t lo = 0; /* live window is [lo, width-lo) of the index frame */
+        if (!u || !w || !v || !z || !un) {
+            free(u); free(w); free(v); free(z); free(un);
+            return ORACLE_ENOMEM;
+        }
+        for (j = 0; j < width; ++j)
+            u[j] = u0[wrap(idx[q] - rad + j, n)];
+        for (s = 0; s < nsteps; ++s) {
+            for (j = lo + 1; j < width - lo - 1; ++j)
+                w[j] = ks_d2(u[j - 1], u[j], u[j + 1], &k);
+            for (j = lo + 2; j < width - lo - 2; ++j)
+                v[j] = u[j] + k.h * ks_rhs(u[j - 1], u[j], u[j + 1],
+                                            w[j - 1], w[j], w[j + 1], &k);
+            for (j = lo + 3; j < width - lo - 3; ++j)
+                z[j] = ks_d2(v[j - 1], v[j], v[j + 1], &k);
+            for (j = lo + 4; j < width - lo - 4; ++j)
+                un[j] = u[j] + k.dt * ks_rhs(v[j - 1], v[j], v[j + 1],
+                                              z[j - 1], z[j], z[j + 1], &k);
+            lo += 4;
+            for (j = lo; j < width - lo; ++j)
+                u[j] = un[j];
+        }
+        out[q] = u[rad];
+        free(u); free(w); free(v); free(z); free(un);
+    }
+    return ORACLE_OK;
+}

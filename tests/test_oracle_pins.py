@@ -1,0 +1,285 @@
+"""Pins for the CPU oracle: each check compares the oracle with something other
+than itself -- a closed form, an exact rational computation, an invariant or a
+symmetry of the discrete scheme -- chosen so that a dropped term, a wrong sign
+or index, or a misplaced constant fails at least one of them.
+
+Schemes (paper Section 4 for the 3-point heat sub-timestep; Section 6 for KS
+by finite differences and explicit RK2, split into radius-1 sub-timesteps as
+in Section 2).
+"""
+from fractions import Fraction
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+
+EPS64 = np.finfo(np.float64).eps
+EPS32 = float(np.finfo(np.float32).eps)
+
+
+# ------------------------------------------------------------------ helpers
+
+def heat_closed_form(u0: np.ndarray, nsteps: int, r: float) -> np.ndarray:
+    """Each discrete Fourier mode m of the periodic 3-point scheme is an
+    eigenvector with eigenvalue g_m = 1 - 4 r sin^2(pi m / N)."""
+    n = u0.size
+    m = np.arange(n)
+    g = 1.0 - 4.0 * r * np.sin(np.pi * m / n) ** 2
+    return np.real(np.fft.ifft(np.fft.fft(u0.astype(np.float64)) * g ** nsteps))
+
+
+def heat_rational(u0, nsteps, r):
+    """Exact rational time stepping of u' = u + r (u[i-1] - 2u[i] + u[i+1])."""
+    u = [Fraction(float(x)) for x in u0]
+    r = Fraction(r)
+    n = len(u)
+    for _ in range(nsteps):
+        u = [u[i] + r * (u[i - 1] - 2 * u[i] + u[(i + 1) % n]) for i in range(n)]
+    return u
+
+
+def ks_rational_step(u0, dt, dx):
+    """One exact RK2-midpoint step of u_t = -u u_x - u_xx - u_xxxx with central
+    differences: D1 a = (a[i+1]-a[i-1])/(2dx), D2 a = (a[i-1]-2a[i]+a[i+1])/dx^2,
+    u_xxxx = D2(D2 u); v = u + dt/2 f(u), u' = u + dt f(v)."""
+    n = len(u0)
+    dt, dx = Fraction(dt), Fraction(dx)
+
+    def d1(a):
+        return [(a[(i + 1) % n] - a[i - 1]) / (2 * dx) for i in range(n)]
+
+    def d2(a):
+        return [(a[i - 1] - 2 * a[i] + a[(i + 1) % n]) / (dx * dx) for i in range(n)]
+
+    def f(a):
+        a1, a2 = d1(a), d2(a)
+        a4 = d2(a2)
+        return [-a[i] * a1[i] - a2[i] - a4[i] for i in range(n)]
+
+    u = [Fraction(float(x)) for x in u0]
+    fu = f(u)
+    v = [u[i] + dt / 2 * fu[i] for i in range(n)]
+    fv = f(v)
+    return [u[i] + dt * fv[i] for i in range(n)]
+
+
+# ----------------------------------------------------------------- heat f64
+
+@pytest.mark.parametrize("r", [0.25, 0.3, 0.1])
+def test_heat_fourier_decay_f64(oracle_mod, r):
+    n, steps = 256, 500
+    u0 = workloads.white_noise(n, seed=7)
+    got = oracle_mod.heat(u0, steps, r)
+    want = heat_closed_form(u0, steps, r)
+    # coefficients r, 1-2r, r are >= 0 here, so the step is non-expansive and
+    # rounding errors add at most ~2 eps |u|_inf per step.
+    tol = 4.0 * steps * EPS64 * np.abs(u0).max() + 1e-13
+    assert np.abs(got - want).max() <= tol
+
+
+def test_heat_small_workload_mode_decay(oracle_mod):
+    """The 4096-point, 10,000-step sine-mode workload: every mode decays by
+    exactly g_m^n (closed form applied to the rounded input array)."""
+    w = workloads.WORKLOADS["heat_small"]
+    u0 = workloads.initial("heat_small")
+    got = oracle_mod.heat(u0, w["nsteps"], w["r"])
+    want = heat_closed_form(u0, w["nsteps"], w["r"])
+    tol = 4.0 * w["nsteps"] * EPS64 * np.abs(u0).max()
+    assert np.abs(got - want).max() <= tol
+    # the decay factors of the extreme modes, from the closed form
+    g1 = (1 - math.sin(math.pi / 4096) ** 2) ** 10_000
+    g64 = (1 - math.sin(64 * math.pi / 4096) ** 2) ** 10_000
+    assert abs(g1 - 0.99413) < 1e-5 and abs(g64 / 3.40e-11 - 1) < 1e-2
+
+
+@pytest.mark.parametrize("n,steps", [(16, 12), (37, 9), (64, 12)])
+def test_heat_exact_rational_f64(oracle_mod, n, steps):
+    """Integers |u| <= 2^20 with r = 1/4: every intermediate fits in 53 bits,
+    so IEEE binary64 must agree with exact rational arithmetic bit for bit."""
+    u0 = workloads.integer_field(n, seed=n, amp=1 << 20)
+    got = oracle_mod.heat(u0, steps, 0.25)
+    want = np.array([float(x) for x in heat_rational(u0, steps, Fraction(1, 4))])
+    assert np.array_equal(got, want)
+    # and the periodic sum is conserved exactly
+    assert math.fsum(got) == math.fsum(u0)
+
+
+def test_heat_conservation_f64(oracle_mod):
+    n, steps = 1000, 300
+    u0 = workloads.white_noise(n, seed=3)
+    got = oracle_mod.heat(u0, steps, 0.25)
+    assert abs(math.fsum(got) - math.fsum(u0)) <= 4 * steps * n * EPS64
+
+
+def test_heat_special_cases(oracle_mod):
+    u0 = workloads.white_noise(101, seed=5)
+    assert np.array_equal(oracle_mod.heat(u0, 17, 0.0), u0)           # r = 0: identity
+    c = np.full(64, 0.7)
+    assert np.array_equal(oracle_mod.heat(c, 50, 0.25), c)              # constants are fixed
+    nyq = np.array([(-1.0) ** j for j in range(64)])
+    assert np.array_equal(oracle_mod.heat(nyq, 1, 0.25), np.zeros(64))  # g_{N/2} = 0 at r = 1/4
+    assert np.array_equal(oracle_mod.heat(u0, 0, 0.25), u0)             # zero steps
+
+
+def test_heat_reflection_and_translation(oracle_mod):
+    n, steps = 96, 40
+    u0 = workloads.white_noise(n, seed=11)
+    base = oracle_mod.heat(u0, steps, 0.3)
+    # reflection i -> -i commutes with the symmetric stencil, bit for bit
+    refl = oracle_mod.heat(np.roll(u0[::-1], 1), steps, 0.3)
+    assert np.array_equal(refl, np.roll(base[::-1], 1))
+    # translation equivariance
+    assert np.array_equal(oracle_mod.heat(np.roll(u0, 13), steps, 0.3), np.roll(base, 13))
+
+
+def test_heat_thread_count_independent(oracle_mod):
+    u0 = workloads.white_noise(5000, seed=2)
+    a = oracle_mod.heat(u0, 50, 0.25, threads=1)
+    b = oracle_mod.heat(u0, 50, 0.25, threads=4)
+    assert np.array_equal(a, b)
+
+
+def test_heat_cone_points_match_full(oracle_mod):
+    n, steps = 300, 70
+    u0 = workloads.white_noise(n, seed=9)
+    full = oracle_mod.heat(u0, steps, 0.25)
+    idx = np.array([0, 1, 149, 298, 299])
+    assert np.array_equal(oracle_mod.heat_points(u0, steps, 0.25, idx), full[idx])
+    # cone wider than the grid (wrap-around)
+    full2 = oracle_mod.heat(u0[:50], 40, 0.25)
+    assert np.array_equal(oracle_mod.heat_points(u0[:50], 40, 0.25, [0, 7, 49]),
+                          full2[[0, 7, 49]])
+
+
+# ----------------------------------------------------------------- heat f32
+
+def test_heat_fourier_decay_f32(oracle_mod):
+    n, steps = 256, 400
+    u0 = workloads.white_noise(n, seed=8, dtype=np.float32)
+    got = oracle_mod.heat(u0, steps, 0.25)
+    assert got.dtype == np.float32
+    want = heat_closed_form(u0.astype(np.float64), steps, 0.25)
+    assert np.abs(got - want).max() <= 4.0 * steps * EPS32 * np.abs(u0).max()
+
+
+@pytest.mark.parametrize("n", [16, 29])
+def test_heat_exact_rational_f32(oracle_mod, n):
+    """Integers |u| <= 2^8, r = 1/4, 6 steps: all values fit in 24 bits."""
+    u0 = workloads.integer_field(n, seed=n, amp=1 << 8, dtype=np.float32)
+    got = oracle_mod.heat(u0, 6, 0.25)
+    want = np.array([float(x) for x in heat_rational(u0, 6, Fraction(1, 4))], dtype=np.float32)
+    assert np.array_equal(got, want)
+
+
+def test_heat_f32_rounds_every_operation(oracle_mod):
+    """With a non-dyadic r the binary32 result depends on per-operation
+    rounding; numpy float32 elementwise arithmetic is correctly rounded per
+    operation, so it fixes the expected bits (a float64 evaluation rounded at
+    the end, or a fused multiply-add, would differ)."""
+    u0 = workloads.white_noise(200, seed=4, dtype=np.float32)
+    r = np.float32(0.3)
+    u = u0.copy()
+    for _ in range(25):
+        left, right = np.roll(u, 1), np.roll(u, -1)
+        u = (u + r * ((left + right) - np.float32(2.0) * u)).astype(np.float32)
+    got = oracle_mod.heat(u0, 25, 0.3)
+    assert np.array_equal(got, u)
+    wide = oracle_mod.heat(u0.astype(np.float64), 25, float(r)).astype(np.float32)
+    assert not np.array_equal(got, wide)
+
+
+# ----------------------------------------------------------------------- KS
+
+def ks_symbol(m, n, dx):
+    """Eigenvalue of the linear part -D2 - D2 D2 on mode m."""
+    s = math.sin(math.pi * m / n) ** 2
+    return 4.0 * s / dx ** 2 - 16.0 * s * s / dx ** 4
+
+
+@pytest.mark.parametrize("m", [1, 3, 7])
+def test_ks_linear_growth(oracle_mod, m):
+    """Small-amplitude cosine: u^n = R(dt lam)^n u0 with R(z) = 1 + z + z^2/2
+    (RK2 midpoint) and lam the discrete symbol of -u_xx - u_xxxx.  The
+    nonlinear term only feeds other harmonics at O(A^2)."""
+    n, dt, dx, steps, amp = 64, 0.005, 0.5, 200, 1e-6
+    j = np.arange(n)
+    u0 = amp * np.cos(2 * np.pi * m * j / n)
+    got = oracle_mod.ks(u0, steps, dt, dx)
+    z = dt * ks_symbol(m, n, dx)
+    want_amp = amp * (1 + z + z * z / 2) ** steps
+    proj = 2.0 / n * np.dot(got, np.cos(2 * np.pi * m * j / n))
+    assert abs(proj / want_amp - 1) < 1e-8
+    # forward Euler (1+z)^n, or dt in place of dt/2 in the midpoint, would be
+    # off by far more than the tolerance above
+    assert abs((1 + z) ** steps / (1 + z + z * z / 2) ** steps - 1) > 1e-6
+
+
+def test_ks_nonlinear_second_harmonic(oracle_mod):
+    """-u u_x on A cos(t j) with the central difference gives exactly
+    (A^2 sin t / (2 dx)) sin(2 t j); after one short step the sin(2 t j)
+    coefficient is dt times that, to O(dt)."""
+    n, dt, dx, amp, m = 64, 1e-4, 0.5, 0.5, 3
+    th = 2 * np.pi * m / n
+    j = np.arange(n)
+    u0 = amp * np.cos(th * j)
+    got = oracle_mod.ks(u0, 1, dt, dx)
+    coef = 2.0 / n * np.dot(got, np.sin(2 * th * j))
+    want = dt * amp * amp * math.sin(th) / (2 * dx)
+    assert abs(coef / want - 1) < 1e-2
+
+
+@pytest.mark.parametrize("amp", [1 << 8, 1 << 10])
+def test_ks_exact_rational_one_step(oracle_mod, amp):
+    """Integers |u| <= 2^10, dx = 1/2, dt = 2^-8: one RK2 step needs at most
+    ~49 significant bits, so binary64 equals exact rational arithmetic."""
+    n = 32
+    u0 = workloads.integer_field(n, seed=amp, amp=amp)
+    got = oracle_mod.ks(u0, 1, 2.0 ** -8, 0.5)
+    want = np.array([float(x) for x in ks_rational_step(u0, Fraction(1, 256), Fraction(1, 2))])
+    assert np.array_equal(got, want)
+    assert math.fsum(got) == math.fsum(u0)
+
+
+def test_ks_conservation(oracle_mod):
+    n, steps = 512, 400
+    u0 = workloads.smoothed_noise(n, seed=12)
+    got = oracle_mod.ks(u0, steps, 0.005, 0.5)
+    assert np.all(np.isfinite(got))
+    assert abs(math.fsum(got) - math.fsum(u0)) <= 1e-12 * steps
+
+
+def test_ks_symmetries(oracle_mod):
+    """KS is invariant under (x, u) -> (-x, -u), and the central scheme keeps
+    that bit for bit; a one-sided difference would not.  Also translation
+    equivariance and fixed constants."""
+    n, steps = 128, 60
+    u0 = workloads.smoothed_noise(n, seed=21)
+    base = oracle_mod.ks(u0, steps, 0.005, 0.5)
+    flip = oracle_mod.ks(-np.roll(u0[::-1], 1), steps, 0.005, 0.5)
+    assert np.array_equal(flip, -np.roll(base[::-1], 1))
+    assert np.array_equal(oracle_mod.ks(np.roll(u0, 17), steps, 0.005, 0.5), np.roll(base, 17))
+    c = np.full(40, -1.25)
+    assert np.array_equal(oracle_mod.ks(c, 30, 0.005, 0.5), c)
+
+
+def test_ks_cone_points_match_full(oracle_mod):
+    n, steps = 200, 20
+    u0 = workloads.smoothed_noise(n, seed=13)
+    full = oracle_mod.ks(u0, steps, 0.005, 0.5)
+    idx = np.array([0, 5, 100, 199])
+    assert np.array_equal(oracle_mod.ks_points(u0, steps, 0.005, 0.5, idx), full[idx])
+
+
+def test_ks_literal_domain_blows_up(oracle_mod):
+    """The literal 128*pi domain at N = 2^20 gives dx = 3.8e-4: explicit RK2
+    is violently unstable there (|R(dt lam)| ~ 1e24 for the top mode); a short
+    run on the same dx at a small N already overflows.  This is why the
+    workloads use dx = 0.5."""
+    dx = 128 * math.pi / (1 << 20)
+    z = 0.005 * ks_symbol(32, 64, dx)
+    assert abs(1 + z + z * z / 2) > 1e20
+    u0 = workloads.smoothed_noise(64, seed=1)
+    out = oracle_mod.ks(u0, 5, 0.005, dx)
+    assert not np.all(np.isfinite(out))
