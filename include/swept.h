@@ -1,0 +1,152 @@
+/*
+ * swept.h -- C ABI of the MI355X swept-rule stencil library (libswept.so).
+ *
+ * The library advances 1D periodic explicit stencil PDEs in time on one AMD
+ * Instinct MI355X (gfx950).  Two schedules produce the same bits:
+ *
+ *  - swept_advance: the swept rule (paper, Section 3).  Each workgroup owns a
+ *    tile of W = 2k points (the paper's node, which owns an even number of
+ *    points).  It first computes the shrinking space-time triangle that its
+ *    own points determine, then, in every later stage, the diamond whose
+ *    domain of dependence is covered by the V formed by two swept leading
+ *    edges.  Only those edges (two points per sub-timestep and side) travel
+ *    between workgroups, through HBM, once per stage of k sub-timesteps.
+ *  - swept_naive_advance: the straight decomposition (paper, Sections 1 and
+ *    4), one kernel launch per time step (or per sub-timestep).
+ *
+ * The local code -- what one sub-timestep does to one point -- is selected by
+ * a stencil id (the paper's Section 5 separates it from the global, swept
+ * ordering code; here it is compiled in rather than called back).
+ *
+ * Conventions for every entry point:
+ *  - Return 0 (SWEPT_OK) on success or a negative swept_status.  Nothing
+ *    aborts or throws across the ABI; swept_last_error() returns a message
+ *    for the last failure of the calling thread.
+ *  - Pointers named u are DEVICE pointers to nx contiguous elements of the
+ *    stencil's type (double for *_F64, float for *_F32), owned by the caller.
+ *    They are updated in place to the state after nsteps full time steps.
+ *  - Work is enqueued on the library's current stream (swept_set_stream) and
+ *    is asynchronous: the caller keeps u alive until that stream is
+ *    synchronised.  Errors raised by kernels that are still running surface
+ *    at swept_sync().
+ *  - params points to HOST memory and is read during the call only.
+ *  - The library owns its scratch (edge buffers of the swept path, a second
+ *    field for the naive path).  It grows on demand, synchronising the
+ *    current stream first, and is released by swept_finalize().
+ */
+#ifndef SWEPT_H
+#define SWEPT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SWEPT_OK = 0,
+    SWEPT_EINVAL = -1,        /* bad argument: null pointer, nx < 3, nsteps < 0, bad id, bad params */
+    SWEPT_ENOTINIT = -2,      /* swept_init was not called (or failed) */
+    SWEPT_ENOMEM = -3,        /* device allocation of scratch failed */
+    SWEPT_EHIP = -4,          /* a HIP runtime call or kernel launch failed */
+    SWEPT_EUNSUPPORTED = -5,  /* valid request this build cannot run (e.g. tiling impossible) */
+    SWEPT_ETIMEOUT = -6       /* reserved: a bounded device-side wait gave up */
+} swept_status;
+
+/*
+ * Stencil ids.  Each defines one time step as a sequence of radius-1
+ * sub-timesteps (paper, Section 2) and the parameters it reads:
+ *
+ * SWEPT_HEAT_F64 / SWEPT_HEAT_F32: heat equation u_t = u_xx by the 3-point
+ *   forward-Euler finite difference, one sub-timestep per step (the paper's
+ *   Section 4 "3 FLOPs" scheme):  u' = u + r*((u[i-1] + u[i+1]) - 2*u[i]),
+ *   evaluated in that association in binary64 / binary32 without fused
+ *   multiply-add.  params = { r } (nparams >= 1); for F32, r is rounded to
+ *   float once.
+ *
+ * SWEPT_KS_F64: Kuramoto-Sivashinsky u_t = -u u_x - u_xx - u_xxxx by central
+ *   differences and the RK2 midpoint rule (paper, Section 6; RK2 as
+ *   sub-timesteps, Section 2), four sub-timesteps per step:
+ *     w = D2(u);  v = u + h*F(u,w);  z = D2(v);  u' = u + dt*F(v,z)
+ *   with D2(a) = ((a[i-1]+a[i+1]) - 2a[i])*c2, D1(a) = (a[i+1]-a[i-1])*c1,
+ *   F(a,b) = -(((a*D1(a)) + b) + D2(b)), c1 = 1/(2dx), c2 = 1/(dx*dx),
+ *   h = dt/2, all in binary64.  params = { dt, dx } (nparams >= 2, dx > 0).
+ */
+enum {
+    SWEPT_HEAT_F64 = 0,
+    SWEPT_HEAT_F32 = 1,
+    SWEPT_KS_F64 = 2
+};
+
+/* Schedules for swept_set_tuning. */
+enum {
+    SWEPT_MODE_AUTO = 0,      /* swept stages when the grid can be tiled, else naive */
+    SWEPT_MODE_STAGE = 1,     /* swept: one kernel launch per stage (triangle, diamonds) */
+    SWEPT_MODE_NAIVE = 2      /* one launch per time step */
+};
+
+/*
+ * Select the device and reset the stream to the null stream.  Must precede
+ * every other call except swept_last_error.  Calling it again with another
+ * device releases the scratch of the previous one.
+ */
+int swept_init(int device);
+
+/* Enqueue all later work on this hipStream_t (NULL = the null stream). */
+int swept_set_stream(void *hip_stream);
+
+/*
+ * Tuning of the swept path.  tile_w: points per tile W (even, W divides nx);
+ * 0 = automatic.  pairs_per_lane: 1, 2, 4 or 8 (0 = automatic); each lane of
+ * a tile's wavefront carries that many adjacent point pairs.  mode: one of
+ * SWEPT_MODE_*.  The values persist until changed.  Results do not depend on
+ * the tuning, bit for bit.
+ */
+int swept_set_tuning(int32_t tile_w, int32_t pairs_per_lane, int32_t mode);
+
+/*
+ * Plan the swept run swept_advance would use for these arguments, without
+ * running it.  out[0..5] = { tile_w, depth_k, tiles, stages, pairs_per_lane,
+ * mode_used }.  Returns SWEPT_EINVAL for invalid arguments.
+ */
+int swept_plan(int64_t nx, int64_t nsteps, int32_t stencil_id, int64_t *out);
+
+/*
+ * Advance u (device, nx points of the stencil's type, periodic) by nsteps
+ * time steps with the swept rule.  nsteps == 0 is a no-op.  If the grid
+ * cannot be tiled (no even tile width divides nx) the automatic mode uses the
+ * naive schedule, which gives the same bits.
+ */
+int swept_advance(void *u, int64_t nx, int64_t nsteps, int32_t stencil_id,
+                  const double *params, int32_t nparams);
+
+/*
+ * Advance u by nsteps time steps with one kernel launch per time step
+ * (KS: the four sub-timesteps of a step fused in one launch, the halo of
+ * each block recomputed).  Same arguments and results as swept_advance.
+ */
+int swept_naive_advance(void *u, int64_t nx, int64_t nsteps, int32_t stencil_id,
+                        const double *params, int32_t nparams);
+
+/*
+ * KS only: one kernel launch per sub-timestep (four per step), the paper's
+ * straight decomposition that communicates every sub-timestep.  Same
+ * results as swept_naive_advance.
+ */
+int swept_naive_substep_advance(void *u, int64_t nx, int64_t nsteps, int32_t stencil_id,
+                                const double *params, int32_t nparams);
+
+/* Wait for the current stream; report asynchronous kernel errors. */
+int swept_sync(void);
+
+/* Message for the last failure on this thread ("" if none).  Never NULL. */
+const char *swept_last_error(void);
+
+/* Release scratch and forget the device.  Safe to call more than once. */
+void swept_finalize(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWEPT_H */

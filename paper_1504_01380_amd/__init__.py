@@ -1,0 +1,174 @@
+"""Python binding of libswept.so, the MI355X swept-rule stencil library.
+
+Argument marshalling only: every sub-timestep of every point runs in the HIP
+kernels behind the C ABI declared in include/swept.h.  PyTorch supplies device
+memory and the stream.  If the library has not been built this module raises
+at import time -- there is no other implementation to fall back to.
+
+    import torch, paper_1504_01380_amd as swept
+    u = torch.randn(1 << 20, dtype=torch.float64, device="cuda")
+    swept.advance(u, 1000, "heat", [0.25])          # in place, on torch's stream
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libswept.so")
+
+HEAT_F64, HEAT_F32, KS_F64 = 0, 1, 2
+MODE_AUTO, MODE_STAGE, MODE_NAIVE = 0, 1, 2
+
+_STATUS = {0: "SWEPT_OK", -1: "SWEPT_EINVAL", -2: "SWEPT_ENOTINIT", -3: "SWEPT_ENOMEM",
+           -4: "SWEPT_EHIP", -5: "SWEPT_EUNSUPPORTED", -6: "SWEPT_ETIMEOUT"}
+
+EXPORTS = ("swept_init", "swept_set_stream", "swept_set_tuning", "swept_plan",
+           "swept_advance", "swept_naive_advance", "swept_naive_substep_advance",
+           "swept_sync", "swept_last_error", "swept_finalize")
+
+
+class SweptError(RuntimeError):
+    def __init__(self, code: int, what: str, msg: str):
+        super().__init__("%s failed: %s (%s)" % (what, msg, _STATUS.get(code, code)))
+        self.code = code
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libswept.so is not built (expected at %s); run "
+                          "__graft_entry__.build() or python paper_1504_01380_amd/build.py"
+                          % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.swept_init.argtypes = [ctypes.c_int]
+    L.swept_set_stream.argtypes = [vp]
+    L.swept_set_tuning.argtypes = [i32, i32, i32]
+    L.swept_plan.argtypes = [i64, i64, i32, ctypes.POINTER(i64)]
+    for f in (L.swept_advance, L.swept_naive_advance, L.swept_naive_substep_advance):
+        f.argtypes = [vp, i64, i64, i32, dp, i32]
+    L.swept_sync.argtypes = []
+    L.swept_last_error.argtypes = []
+    L.swept_last_error.restype = ctypes.c_char_p
+    L.swept_finalize.argtypes = []
+    L.swept_finalize.restype = None
+    for name in EXPORTS:
+        if name not in ("swept_last_error", "swept_finalize"):
+            getattr(L, name).restype = ctypes.c_int
+    return L
+
+
+_lib = _load()
+_device = None
+
+
+def lib() -> ctypes.CDLL:
+    return _lib
+
+
+def last_error() -> str:
+    return _lib.swept_last_error().decode()
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != 0:
+        raise SweptError(rc, what, last_error())
+
+
+def stencil_id(stencil, dtype: torch.dtype | None = None) -> int:
+    """'heat' (float64 or float32 by dtype), 'ks', or an integer id."""
+    if isinstance(stencil, int):
+        return stencil
+    s = stencil.lower()
+    if s == "heat":
+        return HEAT_F32 if dtype == torch.float32 else HEAT_F64
+    if s == "ks":
+        return KS_F64
+    raise ValueError("unknown stencil %r" % (stencil,))
+
+
+def dtype_of(sid: int) -> torch.dtype:
+    return torch.float32 if sid == HEAT_F32 else torch.float64
+
+
+def substeps(sid: int) -> int:
+    return 4 if sid == KS_F64 else 1
+
+
+def init(device: int = 0) -> None:
+    global _device
+    _check(_lib.swept_init(int(device)), "swept_init")
+    _device = int(device)
+
+
+def _prepare(u: torch.Tensor, sid: int) -> None:
+    if not u.is_cuda:
+        raise ValueError("u must be a device tensor")
+    if u.dtype != dtype_of(sid):
+        raise TypeError("stencil %d needs %s, got %s" % (sid, dtype_of(sid), u.dtype))
+    if not u.is_contiguous() or u.dim() != 1:
+        raise ValueError("u must be a contiguous 1-D tensor")
+    if _device != u.device.index:
+        init(u.device.index)
+    _check(_lib.swept_set_stream(ctypes.c_void_p(torch.cuda.current_stream(u.device).cuda_stream)),
+           "swept_set_stream")
+
+
+def _params(params: Sequence[float]):
+    arr = (ctypes.c_double * max(1, len(params)))(*[float(p) for p in params])
+    return arr, len(params)
+
+
+def set_tuning(tile_w: int = 0, pairs_per_lane: int = 0, mode: int = MODE_AUTO) -> None:
+    _check(_lib.swept_set_tuning(int(tile_w), int(pairs_per_lane), int(mode)), "swept_set_tuning")
+
+
+def plan(nx: int, nsteps: int, stencil, dtype: torch.dtype | None = None) -> dict:
+    out = (ctypes.c_int64 * 6)()
+    _check(_lib.swept_plan(int(nx), int(nsteps), stencil_id(stencil, dtype), out), "swept_plan")
+    keys = ("tile_w", "depth_k", "tiles", "stages", "pairs_per_lane", "mode")
+    return dict(zip(keys, [int(v) for v in out]))
+
+
+def advance(u: torch.Tensor, nsteps: int, stencil, params: Sequence[float]) -> torch.Tensor:
+    """Advance u in place by nsteps time steps with the swept rule."""
+    sid = stencil_id(stencil, u.dtype)
+    _prepare(u, sid)
+    p, npar = _params(params)
+    _check(_lib.swept_advance(ctypes.c_void_p(u.data_ptr()), u.numel(), int(nsteps), sid, p, npar),
+           "swept_advance")
+    return u
+
+
+def naive_advance(u: torch.Tensor, nsteps: int, stencil, params: Sequence[float]) -> torch.Tensor:
+    """Advance u in place with one kernel launch per time step."""
+    sid = stencil_id(stencil, u.dtype)
+    _prepare(u, sid)
+    p, npar = _params(params)
+    _check(_lib.swept_naive_advance(ctypes.c_void_p(u.data_ptr()), u.numel(), int(nsteps), sid,
+                                    p, npar), "swept_naive_advance")
+    return u
+
+
+def naive_substep_advance(u: torch.Tensor, nsteps: int, stencil, params: Sequence[float]):
+    """KS only: one kernel launch per sub-timestep."""
+    sid = stencil_id(stencil, u.dtype)
+    _prepare(u, sid)
+    p, npar = _params(params)
+    _check(_lib.swept_naive_substep_advance(ctypes.c_void_p(u.data_ptr()), u.numel(), int(nsteps),
+                                            sid, p, npar), "swept_naive_substep_advance")
+    return u
+
+
+def sync() -> None:
+    _check(_lib.swept_sync(), "swept_sync")
+
+
+def finalize() -> None:
+    global _device
+    _lib.swept_finalize()
+    _device = None

@@ -1,0 +1,45 @@
+"""Build libswept.so (HIP, gfx950) in-tree with hipcc."""
+from __future__ import annotations
+
+import os
+import subprocess
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+SRC = os.path.join(PKG, "csrc", "swept.hip")
+DEPS = [os.path.join(PKG, "csrc", f) for f in ("stencils.hpp", "kernels.hpp")] + \
+    [os.path.join(ROOT, "include", "swept.h")]
+LIB = os.path.join(PKG, "libswept.so")
+ARCH = os.environ.get("SWEPT_OFFLOAD_ARCH", "gfx950")
+
+# -ffp-contract=off: no fused multiply-add, so every schedule gives the
+# oracle's bits.  Packed FP32 instructions are disabled for all device code.
+HIPCC_FLAGS = [
+    "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-ffp-contract=off", "-fno-fast-math",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-command-line-argument",
+]
+
+
+def build(verbose: bool = False) -> str:
+    """Compile csrc/swept.hip into libswept.so next to this file."""
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = ["hipcc", *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"),
+           "-I", os.path.join(PKG, "csrc"), SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def stale() -> bool:
+    if not os.path.exists(LIB):
+        return True
+    t = os.path.getmtime(LIB)
+    return any(os.path.getmtime(p) > t for p in [SRC, *DEPS])
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

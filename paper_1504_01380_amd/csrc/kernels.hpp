@@ -1,0 +1,322 @@
+// kernels.hpp -- the "global code" of the swept rule on gfx950 (paper,
+// Sections 3 and 5): which point advances which sub-timestep, where and when.
+//
+// Geometry of one stage.  A stage s is computed region by region; region t is
+// owned by one workgroup (the paper's node).  With tile width W = 2k:
+//   stage 0   (Section 3, 1st local computation): the triangle over tile
+//             [tW, tW+W): levels 1..k-1 on [tW+l, tW+W-1-l].
+//   stage s>0 (Section 3, 2nd and later local computations): the diamond
+//             centred at J = tW + k + s*k with base level b = (s-1)k; at
+//             relative level j (level b+j) it covers [J-j, J+j-1] for j <= k
+//             and [J-2k+j, J+2k-1-j] for k < j < 2k.
+// Every stage is capped at the target level L; points that reach level L are
+// written to u.  The region of stage s+1 for workgroup t sits k points to the
+// right of its stage-s region, so the V it needs is its own right leading
+// edge (the "kept" edge, buffer RE) and the left leading edge of workgroup
+// t+1 (the "sent" edge, buffer LE) -- the paper's rule of keeping one swept
+// edge and receiving the other (Section 3, Fig. 3c/3e), with the tiles
+// drifting right instead of alternating, which is the same schedule relabelled.
+//
+// Inside a region.  Rotated by 45 degrees a diamond is a k x k square of
+// point pairs: pair d at step m (0 <= d, m < k) holds A at x = J+m-d and B at
+// x-1, both at relative level m+d+1.  Its inputs are its own state at step
+// m-1 and pair d-1 at step m; pair -1 is the right V edge, the state of pair
+// d at step -1 is the left V edge at level d, pair k-1 traces the new left
+// edge and the final states (m = k-1) are the new right edge.
+//
+// A wavefront sweeps this square in bands of 64*P pairs: lane r owns pairs
+// e = rP..rP+P-1 of the band and pair e works on step m = tau - e at wave
+// step tau.  At a given tau the whole band therefore sits on one level, a
+// contiguous run of 128P points that slides up-right one point per level.
+// Per wave step every lane updates its 2P points in registers and passes its
+// last pair to the next lane with one DPP row shift per 32-bit word; lane 0
+// receives pair -1 from LDS (the right V edge for the first band, the last
+// pair of the previous band otherwise).  All points of a band are at the
+// same sub-timestep, so multi-substep schemes need no divergence.
+#pragma once
+
+#include "stencils.hpp"
+
+namespace swept {
+
+template <class S>
+struct StageArgs {
+    using Pt = typename S::Pt;
+    typename S::T* u;        // the field, n points
+    Pt* re;                  // [tiles][k][2]: kept right edge, own region only
+    const Pt* le_in;         // [tiles][k][2]: left edges written by stage s-1
+    Pt* le_out;              // [tiles][k][2]: left edges of this stage
+    int64_t n;               // grid points
+    int64_t L;               // target level (sub-timesteps)
+    int64_t b;               // base level of this stage: (s-1)k
+    int64_t J0;              // centre of region 0: (k + s*k) mod n
+    int k;                   // sweep depth; tile width W = 2k
+    int tiles;               // n / W
+    int tri;                 // 1 for stage 0
+    typename S::Consts c;
+};
+
+__device__ __forceinline__ int64_t wrapn(int64_t x, int64_t n)
+{
+    // callers keep x in (-n, 2n)
+    return x < 0 ? x + n : (x >= n ? x - n : x);
+}
+
+template <int NPH>
+__device__ __forceinline__ int phase_of(int64_t level)
+{
+    if constexpr (NPH == 1) {
+        return 0;
+    } else {
+        const int64_t m = level % NPH;
+        return int(m < 0 ? m + NPH : m);
+    }
+}
+
+// One wave step of a band: every active pair advances one level.  Pairs are
+// visited from the last to the first so that pair q still reads pair q-1's
+// state from the previous step.
+template <class S, int P, int PH>
+__device__ __forceinline__ void band_update(typename S::Pt (&A)[P], typename S::Pt (&B)[P],
+                                            const typename S::Pt& inA,
+                                            const typename S::Pt& inB, int mlane, int elane,
+                                            int nvalid, int k, const typename S::Consts& c)
+{
+    using Pt = typename S::Pt;
+#pragma unroll
+    for (int q = P - 1; q >= 0; --q) {
+        const int m = mlane - q;
+        const bool act = (unsigned)m < (unsigned)k && elane + q < nvalid;
+        if (act) {
+            const Pt rA = (q == 0) ? inA : A[q - 1];
+            const Pt cB = (q == 0) ? inB : B[q - 1];
+            const Pt nA = S::template step<PH>(A[q], cB, rA, c);
+            const Pt nB = S::template step<PH>(B[q], A[q], cB, c);
+            A[q] = nA;
+            B[q] = nB;
+        }
+    }
+}
+
+template <class S, int P>
+__global__ __launch_bounds__(64) void swept_stage_kernel(StageArgs<S> g)
+{
+    using Pt = typename S::Pt;
+    using T = typename S::T;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Pt* chain = reinterpret_cast<Pt*>(smem_raw);  // [k][2] = (B, A) per step
+
+    const int lane = threadIdx.x;
+    const int t = blockIdx.x;
+    const int k = g.k;
+    const int64_t n = g.n;
+    const int64_t J = wrapn((int64_t)t * (2 * (int64_t)k) + g.J0, n);
+    T* u = g.u;
+
+    // right V edge of this diamond = left edge of region t+1 from stage s-1
+    if (!g.tri) {
+        const int tn = (t + 1 == g.tiles) ? 0 : t + 1;
+        const Pt* src = g.le_in + (size_t)tn * k * 2;
+        for (int i = lane; i < 2 * k; i += 64)
+            chain[i] = src[i];
+    }
+    __syncthreads();
+
+    Pt* re = g.re + (size_t)t * k * 2;
+    const int64_t top = g.L - g.b;  // highest relative level of this stage that is <= L
+
+    for (int base = 0; base < k; base += 64 * P) {
+        const int nvalid = min(64 * P, k - base);
+        const int elane = lane * P;
+        const int tau_first = g.tri ? (k - base) : 0;
+        const int64_t tau_cap = top - base - 1;  // wave step at which the band reaches level L
+        const int64_t tau_end = min((int64_t)(nvalid + k - 2), tau_cap);
+        if (tau_end < tau_first && !g.tri)
+            continue;  // the whole band lies above level L (a triangle band
+                       // with no step still hands on its level-0 edges)
+
+        Pt A[P], B[P];
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const int d = base + elane + q;
+            if (elane + q < nvalid) {
+                if (g.tri) {  // level 0 of the tile: pair d starts at step k-1-d
+                    const int64_t xa = J + k - 1 - 2 * (int64_t)d;
+                    A[q] = S::from_field(u[xa]);
+                    B[q] = S::from_field(u[xa - 1]);
+                } else {      // left V edge at relative level d (own right edge of stage s-1)
+                    B[q] = re[2 * d];
+                    A[q] = re[2 * d + 1];
+                }
+            } else {
+                A[q] = S::from_field(T(0));
+                B[q] = S::from_field(T(0));
+            }
+        }
+
+        const int eL = nvalid - 1;       // last valid pair of the band
+        const int rL = eL / P, qL = eL - rL * P;
+        if (g.tri && lane == rL) {       // its level-0 state is part of the new left edge
+#pragma unroll
+            for (int q = 0; q < P; ++q)
+                if (q == qL) {
+                    const int m = k - 1 - (base + eL);
+                    chain[2 * m] = B[q];
+                    chain[2 * m + 1] = A[q];
+                }
+        }
+
+        int slot = min(tau_first, k - 1);
+        Pt cA = chain[2 * slot + 1], cB = chain[2 * slot];
+        for (int tau = tau_first; tau <= (int)tau_end; ++tau) {
+            const Pt inA = S::shr1(A[P - 1], cA);
+            const Pt inB = S::shr1(B[P - 1], cB);
+            slot = min(tau + 1, k - 1);  // prefetch pair -1 for the next step
+            const Pt nA = chain[2 * slot + 1], nB = chain[2 * slot];
+
+            const int mlane = tau - elane;
+            const int ph = phase_of<S::NPHASE>(g.b + base + tau);
+            if constexpr (S::NPHASE == 1) {
+                band_update<S, P, 0>(A, B, inA, inB, mlane, elane, nvalid, k, g.c);
+            } else {
+                switch (ph) {
+                case 0: band_update<S, P, 0>(A, B, inA, inB, mlane, elane, nvalid, k, g.c); break;
+                case 1: band_update<S, P, 1>(A, B, inA, inB, mlane, elane, nvalid, k, g.c); break;
+                case 2: band_update<S, P, 2>(A, B, inA, inB, mlane, elane, nvalid, k, g.c); break;
+                default: band_update<S, P, 3>(A, B, inA, inB, mlane, elane, nvalid, k, g.c); break;
+                }
+            }
+
+            if (tau == tau_cap) {  // the band is at level L: write it out
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    const int m = mlane - q;
+                    if ((unsigned)m < (unsigned)k && elane + q < nvalid) {
+                        const int d = base + elane + q;
+                        const int64_t xa = wrapn(J + m - d, n);
+                        u[xa] = S::to_field(A[q]);
+                        u[xa == 0 ? n - 1 : xa - 1] = S::to_field(B[q]);
+                    }
+                }
+            }
+            if (lane == rL) {      // the last pair traces the band's left edge
+#pragma unroll
+                for (int q = 0; q < P; ++q)
+                    if (q == qL) {
+                        const int m = tau - eL;
+                        if ((unsigned)m < (unsigned)k) {
+                            chain[2 * m] = B[q];
+                            chain[2 * m + 1] = A[q];
+                        }
+                    }
+            }
+            cA = nA;
+            cB = nB;
+        }
+
+        // final states = new right edge (levels above L are never read)
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const int d = base + elane + q;
+            if (elane + q < nvalid) {
+                re[2 * d] = B[q];
+                re[2 * d + 1] = A[q];
+            }
+        }
+    }
+
+    __syncthreads();
+    Pt* dst = g.le_out + (size_t)t * k * 2;
+    for (int i = lane; i < 2 * k; i += 64)
+        dst[i] = chain[i];
+}
+
+// ------------------------------------------------------------- naive paths
+// The straight decomposition: every sub-timestep of every point, one launch
+// per time step, from two full fields.
+
+template <class S>
+__global__ __launch_bounds__(256) void naive_step_kernel(const typename S::T* __restrict__ in,
+                                                        typename S::T* __restrict__ out,
+                                                        int64_t n, typename S::Consts c)
+{
+    static_assert(S::NPHASE == 1, "single-substep schemes only");
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int64_t il = i == 0 ? n - 1 : i - 1;
+        const int64_t ir = i == n - 1 ? 0 : i + 1;
+        out[i] = S::to_field(S::template step<0>(S::from_field(in[il]), S::from_field(in[i]),
+                                                 S::from_field(in[ir]), c));
+    }
+}
+
+// KS: the four sub-timesteps of one RK2 step in one launch.  Each block of
+// NB points stages u on [i0-4, i0+NB+4) in LDS and recomputes the
+// intermediate levels on its halo (the same per-point operations, so the
+// same bits).
+template <class S, int NB>
+__global__ __launch_bounds__(NB) void naive_fused_kernel(const typename S::T* __restrict__ in,
+                                                        typename S::T* __restrict__ out,
+                                                        int64_t n, typename S::Consts c)
+{
+    using Pt = typename S::Pt;
+    static_assert(S::NPHASE == 4, "four-substep schemes only");
+    __shared__ Pt s0[NB + 8], s1[NB + 6], s2[NB + 4], s3[NB + 2];
+    const int64_t i0 = (int64_t)blockIdx.x * NB;
+    const int tid = threadIdx.x;
+    for (int j = tid; j < NB + 8; j += NB) {
+        int64_t x = (i0 - 4 + j) % n;
+        if (x < 0) x += n;
+        s0[j] = S::from_field(in[x]);
+    }
+    __syncthreads();
+    for (int j = tid; j < NB + 6; j += NB)
+        s1[j] = S::template step<0>(s0[j], s0[j + 1], s0[j + 2], c);
+    __syncthreads();
+    for (int j = tid; j < NB + 4; j += NB)
+        s2[j] = S::template step<1>(s1[j], s1[j + 1], s1[j + 2], c);
+    __syncthreads();
+    for (int j = tid; j < NB + 2; j += NB)
+        s3[j] = S::template step<2>(s2[j], s2[j + 1], s2[j + 2], c);
+    __syncthreads();
+    const int64_t i = i0 + tid;
+    if (i < n)
+        out[i] = S::to_field(S::template step<3>(s3[tid], s3[tid + 1], s3[tid + 2], c));
+}
+
+// KS: one launch per sub-timestep (the paper's straight decomposition that
+// communicates every sub-timestep).  Fields of per-point inputs Pt.
+template <class S, int PH>
+__global__ __launch_bounds__(256) void naive_substep_kernel(const typename S::Pt* __restrict__ in,
+                                                           typename S::Pt* __restrict__ out,
+                                                           int64_t n, typename S::Consts c)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int64_t il = i == 0 ? n - 1 : i - 1;
+        const int64_t ir = i == n - 1 ? 0 : i + 1;
+        out[i] = S::template step<PH>(in[il], in[i], in[ir], c);
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void field_to_pt_kernel(const typename S::T* __restrict__ in,
+                                                         typename S::Pt* __restrict__ out,
+                                                         int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = S::from_field(in[i]);
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void pt_to_field_kernel(const typename S::Pt* __restrict__ in,
+                                                         typename S::T* __restrict__ out,
+                                                         int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = S::to_field(in[i]);
+}
+
+}  // namespace swept

@@ -1,0 +1,461 @@
+// swept.hip -- host runtime and C ABI of libswept.so (declared in swept.h).
+//
+// Planning, scratch management, stream handling and the launch sequences of
+// the swept and naive schedules.  All arithmetic runs in the kernels of
+// kernels.hpp; this file only validates, plans and enqueues.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "swept.h"
+#include "kernels.hpp"
+
+namespace {
+
+using namespace swept;
+
+struct Context {
+    bool ready = false;
+    int device = -1;
+    hipStream_t stream = nullptr;
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    int tile_w = 0;   // 0 = automatic
+    int ppl = 0;      // pairs per lane, 0 = automatic
+    int mode = SWEPT_MODE_AUTO;
+};
+
+Context g_ctx;
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(SWEPT_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                        \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr);    \
+    } while (0)
+
+int ensure_scratch(size_t bytes)
+{
+    if (bytes <= g_ctx.scratch_bytes)
+        return SWEPT_OK;
+    if (g_ctx.scratch) {
+        HIP_TRY(hipStreamSynchronize(g_ctx.stream));
+        HIP_TRY(hipFree(g_ctx.scratch));
+        g_ctx.scratch = nullptr;
+        g_ctx.scratch_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&g_ctx.scratch, bytes);
+    if (e != hipSuccess) {
+        g_ctx.scratch = nullptr;
+        (void)hipGetLastError();
+        return fail(SWEPT_ENOMEM, "hipMalloc of %zu bytes of scratch failed: %s", bytes,
+                    hipGetErrorString(e));
+    }
+    g_ctx.scratch_bytes = bytes;
+    return SWEPT_OK;
+}
+
+// ------------------------------------------------------------------ stencils
+
+int substeps_of(int id) { return id == SWEPT_KS_F64 ? 4 : 1; }
+
+size_t pt_bytes(int id)
+{
+    switch (id) {
+    case SWEPT_HEAT_F64: return sizeof(HeatF64::Pt);
+    case SWEPT_HEAT_F32: return sizeof(HeatF32::Pt);
+    default: return sizeof(KSF64::Pt);
+    }
+}
+
+int check_common(const void* u, int64_t nx, int64_t nsteps, int32_t id, const double* params,
+                 int32_t nparams)
+{
+    if (!g_ctx.ready)
+        return fail(SWEPT_ENOTINIT, "swept_init has not been called");
+    if (!u)
+        return fail(SWEPT_EINVAL, "u is NULL");
+    if (nx < 3)
+        return fail(SWEPT_EINVAL, "nx = %lld: need at least 3 points", (long long)nx);
+    if (nsteps < 0)
+        return fail(SWEPT_EINVAL, "nsteps = %lld is negative", (long long)nsteps);
+    if (id != SWEPT_HEAT_F64 && id != SWEPT_HEAT_F32 && id != SWEPT_KS_F64)
+        return fail(SWEPT_EINVAL, "unknown stencil id %d", id);
+    const int need = id == SWEPT_KS_F64 ? 2 : 1;
+    if (!params || nparams < need)
+        return fail(SWEPT_EINVAL, "stencil %d needs %d parameter(s)", id, need);
+    for (int i = 0; i < need; ++i)
+        if (!std::isfinite(params[i]))
+            return fail(SWEPT_EINVAL, "parameter %d is not finite", i);
+    if (id == SWEPT_KS_F64 && !(params[1] > 0.0))
+        return fail(SWEPT_EINVAL, "KS needs dx > 0");
+    return SWEPT_OK;
+}
+
+HeatF64::Consts heat64_consts(const double* p) { return HeatF64::Consts{p[0]}; }
+HeatF32::Consts heat32_consts(const double* p) { return HeatF32::Consts{(float)p[0]}; }
+KSF64::Consts ks_consts(const double* p)
+{
+    const double dt = p[0], dx = p[1];
+    return KSF64::Consts{dt, 0.5 * dt, 1.0 / (2.0 * dx), 1.0 / (dx * dx)};
+}
+
+// --------------------------------------------------------------------- plan
+
+struct Plan {
+    int64_t W = 0, k = 0, tiles = 0, stages = 0;
+    int P = 1;
+    int mode = SWEPT_MODE_NAIVE;
+};
+
+constexpr size_t kMaxLds = 64 * 1024;
+
+int64_t target_tile(int id)
+{
+    switch (id) {
+    case SWEPT_HEAT_F64: return 2048;
+    case SWEPT_HEAT_F32: return 4096;
+    default: return 1024;
+    }
+}
+
+int auto_ppl(int id, int64_t k)
+{
+    if (id == SWEPT_KS_F64)
+        return k >= 512 ? 2 : 1;
+    return k >= 1024 ? 4 : (k >= 256 ? 2 : 1);
+}
+
+bool tile_fits(int id, int64_t nx, int64_t W)
+{
+    return W >= 2 && W % 2 == 0 && nx % W == 0 && (size_t)W * pt_bytes(id) <= kMaxLds;
+}
+
+// Tiles of W = 2k points (paper, Section 3: each node owns an even number of
+// points); stages 0..ceil(L/k).
+int make_plan(int64_t nx, int64_t nsteps, int32_t id, Plan* p)
+{
+    *p = Plan{};
+    const int64_t L = nsteps * substeps_of(id);
+    if (g_ctx.mode == SWEPT_MODE_NAIVE) {
+        p->mode = SWEPT_MODE_NAIVE;
+        return SWEPT_OK;
+    }
+    int64_t W = 0;
+    if (g_ctx.tile_w > 0) {
+        if (!tile_fits(id, nx, g_ctx.tile_w))
+            return fail(SWEPT_EINVAL,
+                        "tile width %d must be even, divide nx = %lld and fit 64 KB of LDS",
+                        g_ctx.tile_w, (long long)nx);
+        W = g_ctx.tile_w;
+    } else {
+        const int64_t cap = std::min(target_tile(id), std::max<int64_t>(2, nx / 8));
+        for (int64_t w = cap - (cap & 1); w >= 2; w -= 2)
+            if (tile_fits(id, nx, w)) {
+                W = w;
+                break;
+            }
+    }
+    if (W == 0) {
+        if (g_ctx.mode == SWEPT_MODE_STAGE)
+            return fail(SWEPT_EUNSUPPORTED, "nx = %lld has no even tile width", (long long)nx);
+        p->mode = SWEPT_MODE_NAIVE;
+        return SWEPT_OK;
+    }
+    p->W = W;
+    p->k = W / 2;
+    p->tiles = nx / W;
+    p->stages = L == 0 ? 0 : 1 + (L + p->k - 1) / p->k;
+    p->P = g_ctx.ppl > 0 ? g_ctx.ppl : auto_ppl(id, p->k);
+    p->mode = SWEPT_MODE_STAGE;
+    return SWEPT_OK;
+}
+
+// ------------------------------------------------------------- swept launch
+
+template <class S, int P>
+void launch_stage(const StageArgs<S>& a, size_t lds, hipStream_t st, int tiles)
+{
+    hipLaunchKernelGGL((swept_stage_kernel<S, P>), dim3(tiles), dim3(64), lds, st, a);
+}
+
+template <class S>
+int run_swept(void* u, int64_t nx, int64_t L, const typename S::Consts& c, const Plan& p)
+{
+    using Pt = typename S::Pt;
+    const size_t edge = (size_t)nx * sizeof(Pt);  // tiles * k * 2 points
+    int rc = ensure_scratch(3 * edge);
+    if (rc)
+        return rc;
+    Pt* re = static_cast<Pt*>(g_ctx.scratch);
+    Pt* le[2] = {re + nx, re + 2 * nx};
+    const size_t lds = (size_t)p.W * sizeof(Pt);
+
+    StageArgs<S> a{};
+    a.u = static_cast<typename S::T*>(u);
+    a.re = re;
+    a.n = nx;
+    a.L = L;
+    a.k = (int)p.k;
+    a.tiles = (int)p.tiles;
+    a.c = c;
+    for (int64_t s = 0; s < p.stages; ++s) {
+        a.tri = s == 0;
+        a.b = (s - 1) * p.k;
+        a.J0 = (p.k + s * p.k) % nx;
+        a.le_in = le[(s + 1) & 1];
+        a.le_out = le[s & 1];
+        switch (p.P) {
+        case 1: launch_stage<S, 1>(a, lds, g_ctx.stream, (int)p.tiles); break;
+        case 2: launch_stage<S, 2>(a, lds, g_ctx.stream, (int)p.tiles); break;
+        case 4: launch_stage<S, 4>(a, lds, g_ctx.stream, (int)p.tiles); break;
+        case 8: launch_stage<S, 8>(a, lds, g_ctx.stream, (int)p.tiles); break;
+        default: return fail(SWEPT_EINVAL, "pairs per lane %d not in {1,2,4,8}", p.P);
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    return SWEPT_OK;
+}
+
+// ------------------------------------------------------------- naive launch
+
+unsigned grid_for(int64_t n, int block)
+{
+    const int64_t b = (n + block - 1) / block;
+    return (unsigned)std::min<int64_t>(b, 1 << 20);
+}
+
+template <class S>
+int run_naive_single(void* u, int64_t nx, int64_t nsteps, const typename S::Consts& c)
+{
+    using T = typename S::T;
+    int rc = ensure_scratch((size_t)nx * sizeof(T));
+    if (rc)
+        return rc;
+    T* a = static_cast<T*>(u);
+    T* b = static_cast<T*>(g_ctx.scratch);
+    const unsigned grid = grid_for(nx, 256);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        hipLaunchKernelGGL((naive_step_kernel<S>), dim3(grid), dim3(256), 0, g_ctx.stream, a, b,
+                           nx, c);
+        std::swap(a, b);
+    }
+    if (a != u)
+        HIP_TRY(hipMemcpyAsync(u, a, (size_t)nx * sizeof(T), hipMemcpyDeviceToDevice,
+                               g_ctx.stream));
+    HIP_TRY(hipGetLastError());
+    return SWEPT_OK;
+}
+
+int run_naive_ks_fused(void* u, int64_t nx, int64_t nsteps, const KSF64::Consts& c)
+{
+    int rc = ensure_scratch((size_t)nx * sizeof(double));
+    if (rc)
+        return rc;
+    double* a = static_cast<double*>(u);
+    double* b = static_cast<double*>(g_ctx.scratch);
+    constexpr int NB = 256;
+    const unsigned grid = (unsigned)((nx + NB - 1) / NB);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        hipLaunchKernelGGL((naive_fused_kernel<KSF64, NB>), dim3(grid), dim3(NB), 0,
+                           g_ctx.stream, a, b, nx, c);
+        std::swap(a, b);
+    }
+    if (a != u)
+        HIP_TRY(hipMemcpyAsync(u, a, (size_t)nx * sizeof(double), hipMemcpyDeviceToDevice,
+                               g_ctx.stream));
+    HIP_TRY(hipGetLastError());
+    return SWEPT_OK;
+}
+
+int run_naive_ks_substep(void* u, int64_t nx, int64_t nsteps, const KSF64::Consts& c)
+{
+    using Pt = KSF64::Pt;
+    int rc = ensure_scratch(2 * (size_t)nx * sizeof(Pt));
+    if (rc)
+        return rc;
+    Pt* a = static_cast<Pt*>(g_ctx.scratch);
+    Pt* b = a + nx;
+    const unsigned grid = grid_for(nx, 256);
+    double* uf = static_cast<double*>(u);
+    hipLaunchKernelGGL((field_to_pt_kernel<KSF64>), dim3(grid), dim3(256), 0, g_ctx.stream, uf,
+                       a, nx);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        hipLaunchKernelGGL((naive_substep_kernel<KSF64, 0>), dim3(grid), dim3(256), 0,
+                           g_ctx.stream, a, b, nx, c);
+        hipLaunchKernelGGL((naive_substep_kernel<KSF64, 1>), dim3(grid), dim3(256), 0,
+                           g_ctx.stream, b, a, nx, c);
+        hipLaunchKernelGGL((naive_substep_kernel<KSF64, 2>), dim3(grid), dim3(256), 0,
+                           g_ctx.stream, a, b, nx, c);
+        hipLaunchKernelGGL((naive_substep_kernel<KSF64, 3>), dim3(grid), dim3(256), 0,
+                           g_ctx.stream, b, a, nx, c);
+    }
+    hipLaunchKernelGGL((pt_to_field_kernel<KSF64>), dim3(grid), dim3(256), 0, g_ctx.stream, a,
+                       uf, nx);
+    HIP_TRY(hipGetLastError());
+    return SWEPT_OK;
+}
+
+int naive_dispatch(void* u, int64_t nx, int64_t nsteps, int32_t id, const double* params)
+{
+    switch (id) {
+    case SWEPT_HEAT_F64: return run_naive_single<HeatF64>(u, nx, nsteps, heat64_consts(params));
+    case SWEPT_HEAT_F32: return run_naive_single<HeatF32>(u, nx, nsteps, heat32_consts(params));
+    default: return run_naive_ks_fused(u, nx, nsteps, ks_consts(params));
+    }
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+
+extern "C" {
+
+int swept_init(int device)
+{
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= count)
+        return fail(SWEPT_EINVAL, "device %d out of range [0, %d)", device, count);
+    if (g_ctx.ready && g_ctx.device != device)
+        swept_finalize();
+    HIP_TRY(hipSetDevice(device));
+    g_ctx.ready = true;
+    g_ctx.device = device;
+    g_ctx.stream = nullptr;
+    g_err.clear();
+    return SWEPT_OK;
+}
+
+int swept_set_stream(void* hip_stream)
+{
+    if (!g_ctx.ready)
+        return fail(SWEPT_ENOTINIT, "swept_init has not been called");
+    g_ctx.stream = static_cast<hipStream_t>(hip_stream);
+    return SWEPT_OK;
+}
+
+int swept_set_tuning(int32_t tile_w, int32_t pairs_per_lane, int32_t mode)
+{
+    if (tile_w < 0 || (tile_w != 0 && (tile_w % 2 != 0 || tile_w < 2)))
+        return fail(SWEPT_EINVAL, "tile width %d must be 0 or even and >= 2", tile_w);
+    if (pairs_per_lane != 0 && pairs_per_lane != 1 && pairs_per_lane != 2 && pairs_per_lane != 4 &&
+        pairs_per_lane != 8)
+        return fail(SWEPT_EINVAL, "pairs per lane %d not in {0,1,2,4,8}", pairs_per_lane);
+    if (mode != SWEPT_MODE_AUTO && mode != SWEPT_MODE_STAGE && mode != SWEPT_MODE_NAIVE)
+        return fail(SWEPT_EINVAL, "unknown mode %d", mode);
+    g_ctx.tile_w = tile_w;
+    g_ctx.ppl = pairs_per_lane;
+    g_ctx.mode = mode;
+    return SWEPT_OK;
+}
+
+int swept_plan(int64_t nx, int64_t nsteps, int32_t stencil_id, int64_t* out)
+{
+    if (!out || nx < 3 || nsteps < 0 ||
+        (stencil_id != SWEPT_HEAT_F64 && stencil_id != SWEPT_HEAT_F32 &&
+         stencil_id != SWEPT_KS_F64))
+        return fail(SWEPT_EINVAL, "invalid plan request");
+    Plan p;
+    int rc = make_plan(nx, nsteps, stencil_id, &p);
+    if (rc)
+        return rc;
+    out[0] = p.W;
+    out[1] = p.k;
+    out[2] = p.tiles;
+    out[3] = p.stages;
+    out[4] = p.P;
+    out[5] = p.mode;
+    return SWEPT_OK;
+}
+
+int swept_advance(void* u, int64_t nx, int64_t nsteps, int32_t stencil_id, const double* params,
+                  int32_t nparams)
+{
+    int rc = check_common(u, nx, nsteps, stencil_id, params, nparams);
+    if (rc)
+        return rc;
+    if (nsteps == 0)
+        return SWEPT_OK;
+    Plan p;
+    rc = make_plan(nx, nsteps, stencil_id, &p);
+    if (rc)
+        return rc;
+    if (p.mode == SWEPT_MODE_NAIVE)
+        return naive_dispatch(u, nx, nsteps, stencil_id, params);
+    const int64_t L = nsteps * substeps_of(stencil_id);
+    switch (stencil_id) {
+    case SWEPT_HEAT_F64: return run_swept<HeatF64>(u, nx, L, heat64_consts(params), p);
+    case SWEPT_HEAT_F32: return run_swept<HeatF32>(u, nx, L, heat32_consts(params), p);
+    default: return run_swept<KSF64>(u, nx, L, ks_consts(params), p);
+    }
+}
+
+int swept_naive_advance(void* u, int64_t nx, int64_t nsteps, int32_t stencil_id,
+                        const double* params, int32_t nparams)
+{
+    int rc = check_common(u, nx, nsteps, stencil_id, params, nparams);
+    if (rc)
+        return rc;
+    if (nsteps == 0)
+        return SWEPT_OK;
+    return naive_dispatch(u, nx, nsteps, stencil_id, params);
+}
+
+int swept_naive_substep_advance(void* u, int64_t nx, int64_t nsteps, int32_t stencil_id,
+                                const double* params, int32_t nparams)
+{
+    int rc = check_common(u, nx, nsteps, stencil_id, params, nparams);
+    if (rc)
+        return rc;
+    if (stencil_id != SWEPT_KS_F64)
+        return fail(SWEPT_EINVAL, "per-sub-timestep launches exist for the KS stencil only");
+    if (nsteps == 0)
+        return SWEPT_OK;
+    return run_naive_ks_substep(u, nx, nsteps, ks_consts(params));
+}
+
+int swept_sync(void)
+{
+    if (!g_ctx.ready)
+        return fail(SWEPT_ENOTINIT, "swept_init has not been called");
+    HIP_TRY(hipStreamSynchronize(g_ctx.stream));
+    HIP_TRY(hipGetLastError());
+    return SWEPT_OK;
+}
+
+const char* swept_last_error(void) { return g_err.c_str(); }
+
+void swept_finalize(void)
+{
+    if (g_ctx.scratch) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(g_ctx.scratch);
+    }
+    g_ctx = Context{};
+}
+
+}  // extern "C"

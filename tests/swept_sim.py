@@ -1,0 +1,141 @@
+"""CPU emulation of the swept stage kernel's schedule (tests only).
+
+Re-expresses, index for index, what swept_stage_kernel in
+paper_1504_01380_amd/csrc/kernels.hpp does -- tiles, stages, bands of 64*P
+pairs, wave steps, the lane-to-lane shift, the LDS chain and the RE/LE edge
+buffers -- on plain Python values, so the schedule can be checked on a CPU:
+every (point, level) must be computed exactly once, after its inputs, and the
+values must equal the oracle's bit for bit.  The per-point update is passed
+in (the scheme's local code), so the same emulation serves every stencil.
+"""
+from __future__ import annotations
+
+import math
+
+
+def heat_step(r):
+    def f(ph, l, c, rr):
+        return c + r * ((l + rr) - 2.0 * c)
+    return f, 1, (lambda v: v), (lambda p: p)
+
+
+def ks_step(dt, dx):
+    h, c1, c2 = 0.5 * dt, 1.0 / (2.0 * dx), 1.0 / (dx * dx)
+
+    def rhs(l, c, r):
+        d1a = (r[1] - l[1]) * c1
+        d2b = ((l[2] + r[2]) - 2.0 * c[2]) * c2
+        return -(((c[1] * d1a) + c[2]) + d2b)
+
+    def f(ph, l, c, r):
+        if ph in (0, 2):
+            return (c[0], c[1], ((l[1] + r[1]) - 2.0 * c[1]) * c2)
+        if ph == 1:
+            return (c[0], c[0] + h * rhs(l, c, r), c[2])
+        un = c[0] + dt * rhs(l, c, r)
+        return (un, un, c[2])
+    return f, 4, (lambda v: (v, v, 0.0)), (lambda p: p[0])
+
+
+def simulate(u0, nsteps, k, P, stencil, lanes=64, track=False):
+    """Run the swept schedule on a Python list; returns (u, visits) where
+    visits maps (x, level) -> number of times it was computed (if track)."""
+    step, nph, from_field, to_field = stencil
+    n = len(u0)
+    W = 2 * k
+    assert n % W == 0
+    T = n // W
+    L = nsteps * nph
+    u = list(u0)
+    visits = {} if track else None
+    if L == 0:
+        return u, visits
+    stages = 1 + (L + k - 1) // k
+    RE = [[None] * (2 * k) for _ in range(T)]
+    LE = [[[None] * (2 * k) for _ in range(T)] for _ in range(2)]
+    band = lanes * P
+    for s in range(stages):
+        tri = s == 0
+        b = (s - 1) * k
+        J0 = (k + s * k) % n
+        le_in, le_out = LE[(s + 1) % 2], LE[s % 2]
+        for t in range(T):
+            J = (t * W + J0) % n
+            chain = list(le_in[(t + 1) % T]) if not tri else [None] * (2 * k)
+            top = L - b
+            for base in range(0, k, band):
+                nvalid = min(band, k - base)
+                tau_first = (k - base) if tri else 0
+                tau_cap = top - base - 1
+                tau_end = min(nvalid + k - 2, tau_cap)
+                if tau_end < tau_first and not tri:
+                    continue
+                A = [None] * band
+                B = [None] * band
+                for e in range(nvalid):
+                    d = base + e
+                    if tri:
+                        xa = J + k - 1 - 2 * d
+                        A[e], B[e] = from_field(u[xa]), from_field(u[xa - 1])
+                    else:
+                        B[e], A[e] = RE[t][2 * d], RE[t][2 * d + 1]
+                eL = nvalid - 1
+                if tri:
+                    m = k - 1 - (base + eL)
+                    chain[2 * m], chain[2 * m + 1] = B[eL], A[eL]
+                slot = min(tau_first, k - 1)
+                cA, cB = chain[2 * slot + 1], chain[2 * slot]
+                for tau in range(tau_first, tau_end + 1):
+                    # lane r receives lane r-1's last pair; lane 0 the chain
+                    inA = [cA] + [A[(r - 1) * P + P - 1] for r in range(1, lanes)]
+                    inB = [cB] + [B[(r - 1) * P + P - 1] for r in range(1, lanes)]
+                    slot = min(tau + 1, k - 1)
+                    nA, nB = chain[2 * slot + 1], chain[2 * slot]
+                    ph = (b + base + tau) % nph
+                    for r in range(lanes):
+                        for q in range(P - 1, -1, -1):
+                            e = r * P + q
+                            m = tau - e
+                            if not (0 <= m < k and e < nvalid):
+                                continue
+                            rA = inA[r] if q == 0 else A[e - 1]
+                            cBv = inB[r] if q == 0 else B[e - 1]
+                            nAv = step(ph, A[e], cBv, rA)
+                            nBv = step(ph, B[e], A[e], cBv)
+                            A[e], B[e] = nAv, nBv
+                            if track:
+                                d = base + e
+                                lvl = b + m + d + 1
+                                xa = (J + m - d) % n
+                                for x in (xa, (xa - 1) % n):
+                                    visits[(x, lvl)] = visits.get((x, lvl), 0) + 1
+                    if tau == tau_cap:
+                        for e in range(nvalid):
+                            m = tau - e
+                            if 0 <= m < k:
+                                d = base + e
+                                xa = (J + m - d) % n
+                                u[xa] = to_field(A[e])
+                                u[(xa - 1) % n] = to_field(B[e])
+                    m = tau - eL
+                    if 0 <= m < k:
+                        chain[2 * m], chain[2 * m + 1] = B[eL], A[eL]
+                    cA, cB = nA, nB
+                for e in range(nvalid):
+                    d = base + e
+                    RE[t][2 * d], RE[t][2 * d + 1] = B[e], A[e]
+            le_out[t] = chain
+    return u, visits
+
+
+def levels_complete(visits, n, L, k):
+    """Every (x, 1..L) computed exactly once (levels above L may appear: a
+    band stops at L, so nothing above it is computed either)."""
+    for x in range(n):
+        for lvl in range(1, L + 1):
+            if visits.get((x, lvl), 0) != 1:
+                return False, (x, lvl, visits.get((x, lvl), 0))
+    extra = [key for key in visits if key[1] > L]
+    if extra:
+        return False, ("above L", extra[:3])
+    return True, None

@@ -1,0 +1,84 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point include/swept.h declares, and rejects bad calls with the
+documented status codes instead of aborting."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "swept.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(swept_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def swept():
+    import paper_1504_01380_amd as swept
+    return swept
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_functions()
+    for must in ("swept_init", "swept_advance", "swept_naive_advance", "swept_plan",
+                 "swept_set_stream", "swept_set_tuning", "swept_sync", "swept_last_error",
+                 "swept_finalize", "swept_naive_substep_advance"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(swept):
+    lib = ctypes.CDLL(swept.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(swept.EXPORTS) == declared_functions()
+
+
+def test_calls_before_init_fail_cleanly(swept):
+    lib = swept.lib()
+    lib.swept_finalize()
+    par = (ctypes.c_double * 1)(0.25)
+    rc = lib.swept_advance(ctypes.c_void_p(1), 64, 1, 0, par, 1)
+    assert rc == -2  # SWEPT_ENOTINIT
+    assert "swept_init" in swept.last_error()
+    assert lib.swept_sync() == -2
+    assert lib.swept_set_stream(None) == -2
+
+
+def test_tuning_validation(swept):
+    lib = swept.lib()
+    assert lib.swept_set_tuning(3, 0, 0) == -1      # odd tile
+    assert lib.swept_set_tuning(0, 3, 0) == -1      # bad pairs per lane
+    assert lib.swept_set_tuning(0, 0, 9) == -1      # bad mode
+    assert lib.swept_set_tuning(0, 0, 0) == 0
+    assert lib.swept_set_tuning(128, 2, 1) == 0
+    assert lib.swept_set_tuning(0, 0, 0) == 0
+
+
+def test_plan_geometry(swept):
+    """The planner (host logic, no device needed): tiles of W = 2k points that
+    divide the grid, ceil(L/k)+1 stages, naive fallback for odd grids."""
+    lib = swept.lib()
+    lib.swept_set_tuning(0, 0, 0)
+    p = swept.plan(1 << 24, 20000, "heat")
+    assert p["tile_w"] == 2048 and p["depth_k"] == 1024 and p["tiles"] == 8192
+    assert p["stages"] == 1 + (20000 + 1023) // 1024 and p["mode"] == swept.MODE_STAGE
+    p = swept.plan(4096, 10000, "heat")
+    assert (1 << 24) % p["tile_w"] == 0 and p["tiles"] * p["tile_w"] == 4096
+    p = swept.plan(1 << 20, 50000, "ks")
+    assert p["stages"] == 1 + (4 * 50000 + p["depth_k"] - 1) // p["depth_k"]
+    assert swept.plan(1001, 5, "heat")["mode"] == swept.MODE_NAIVE   # odd: no even tile
+    lib.swept_set_tuning(0, 0, swept.MODE_STAGE)
+    out = (ctypes.c_int64 * 6)()
+    assert lib.swept_plan(1001, 5, 0, out) == -5                    # SWEPT_EUNSUPPORTED
+    lib.swept_set_tuning(48, 0, swept.MODE_STAGE)
+    assert swept.plan(96, 5, "heat")["depth_k"] == 24
+    assert lib.swept_plan(100, 5, 0, out) == -1                     # 48 does not divide 100
+    lib.swept_set_tuning(0, 0, 0)
+    assert lib.swept_plan(2, 5, 0, out) == -1                       # nx < 3
+    assert lib.swept_plan(64, -1, 0, out) == -1
+    assert lib.swept_plan(64, 1, 7, out) == -1

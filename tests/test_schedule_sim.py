@@ -1,0 +1,69 @@
+"""The swept stage kernel's schedule, emulated on the CPU (tests/swept_sim.py),
+must compute every (point, level) up to the target exactly once and give the
+oracle's bits (paper, Section 3: the swept decomposition computes everything
+exactly once, without redundancy; Section 2: the result is that of plain
+stepping).  Covers the triangle, diamonds, the cap at an arbitrary level,
+bands of 64*P pairs including a partial last band, one tile (T = 1), and the
+four-sub-timestep KS scheme."""
+import numpy as np
+import pytest
+
+import workloads
+from tests import swept_sim
+
+
+@pytest.mark.parametrize("n,k,P,nsteps", [
+    (16, 4, 1, 1), (16, 4, 1, 3), (16, 4, 1, 4), (16, 4, 1, 7), (16, 4, 1, 8),
+    (16, 4, 1, 9), (16, 4, 1, 29), (48, 8, 1, 50), (32, 16, 1, 33), (12, 6, 1, 40),
+    (20, 1, 1, 5), (40, 2, 2, 13), (24, 3, 1, 17),
+])
+def test_heat_exactly_once_and_bitwise(oracle_mod, n, k, P, nsteps):
+    u0 = workloads.white_noise(n, seed=n + k)
+    got, visits = swept_sim.simulate(list(u0), nsteps, k, P, swept_sim.heat_step(0.25),
+                                     lanes=64, track=True)
+    ok, why = swept_sim.levels_complete(visits, n, nsteps, k)
+    assert ok, why
+    want = oracle_mod.heat(u0, nsteps, 0.25)
+    assert np.array_equal(np.array(got), want)
+
+
+@pytest.mark.parametrize("lanes,P,k,nsteps", [
+    (4, 1, 10, 37),   # bands of 4 pairs, partial last band (10 = 4+4+2)
+    (4, 2, 12, 40),   # bands of 8 pairs, partial last band
+    (2, 2, 8, 21),    # full bands
+    (3, 1, 7, 30),    # odd band size
+])
+def test_heat_multiband(oracle_mod, lanes, P, k, nsteps):
+    n = 4 * k
+    u0 = workloads.white_noise(n, seed=lanes * 100 + k)
+    got, visits = swept_sim.simulate(list(u0), nsteps, k, P, swept_sim.heat_step(0.3),
+                                     lanes=lanes, track=True)
+    ok, why = swept_sim.levels_complete(visits, n, nsteps, k)
+    assert ok, why
+    assert np.array_equal(np.array(got), oracle_mod.heat(u0, nsteps, 0.3))
+
+
+@pytest.mark.parametrize("lanes,P,k,nsteps", [(64, 1, 8, 9), (4, 2, 12, 11), (64, 2, 6, 5)])
+def test_ks_bitwise(oracle_mod, lanes, P, k, nsteps):
+    n = 4 * k
+    u0 = workloads.smoothed_noise(n, seed=k)
+    got, visits = swept_sim.simulate(list(u0), nsteps, k, P, swept_sim.ks_step(0.005, 0.5),
+                                     lanes=lanes, track=True)
+    ok, why = swept_sim.levels_complete(visits, n, 4 * nsteps, k)
+    assert ok, why
+    assert np.array_equal(np.array(got), oracle_mod.ks(u0, nsteps, 0.005, 0.5))
+
+
+def test_dropped_update_is_caught(oracle_mod):
+    """A schedule that skips one wave step must fail the exactly-once check."""
+    n, k, nsteps = 16, 4, 9
+    u0 = workloads.white_noise(n, seed=1)
+    step, nph, ff, tf = swept_sim.heat_step(0.25)
+    calls = {"n": 0}
+
+    def skipping(ph, l, c, r):
+        calls["n"] += 1
+        return c if calls["n"] == 37 else step(ph, l, c, r)
+
+    got, _ = swept_sim.simulate(list(u0), nsteps, k, 1, (skipping, nph, ff, tf), track=True)
+    assert not np.array_equal(np.array(got), oracle_mod.heat(u0, nsteps, 0.25))
