@@ -1,0 +1,156 @@
+"""Benchmark: point-updates/s of the swept rule vs naive per-step stepping on
+one MI355X, with the roofline fraction of the dominant kernel and the CPU
+oracle timed beside it.
+
+Workload (one bench "step" = one whole run of it, inputs resident in HBM):
+heat equation u_t = u_xx, periodic, N = 2^24 points, 3-point forward Euler,
+r = 0.25, 20,000 time steps, u0 ~ U[-1, 1] (seed 1001), binary64.  The same
+run in binary32 and the naive one-launch-per-step schedule are reported
+beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published figures; VALU issue rate derived from the unit counts.
+CUS, SIMDS_PER_CU, LANES_PER_SIMD, CLOCK_HZ = 256, 4, 16, 2.4e9
+VALU_LANE_OPS = CUS * SIMDS_PER_CU * LANES_PER_SIMD * CLOCK_HZ   # 39.3e12 per second
+HBM_PEAK = 8.0e12
+HEAT_OPS_PER_UPDATE = 5           # add, mul, sub, mul, add (no fused multiply-add)
+HEAT_NAIVE_BYTES = {8: 16, 4: 8}  # read u, write u' per point-update
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1 << 24)
+    ap.add_argument("--nsteps", type=int, default=20_000)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-naive", action="store_true", help="skip the naive and f32 legs")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def timed_runs(sw, torch, fn, u0, nsteps, params, reps, warmup):
+    """Run fn `reps` times on copies of u0; HIP events on the stream the
+    library launches on (torch's current stream) bracket each run."""
+    stream = torch.cuda.current_stream()
+    u = u0.clone()
+    for _ in range(warmup):
+        u.copy_(u0)
+        fn(u, nsteps, "heat", params)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        u.copy_(u0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn(u, nsteps, "heat", params)
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+    sw.sync()
+    return times, u
+
+
+def cpu_baseline(u0_np, nsteps_full, seconds):
+    """The oracle as it stands, on the host cores, on the first few steps of
+    the same workload (all N points), sized to about `seconds` of work."""
+    import oracle
+    oracle.build(force=False)
+    n = u0_np.size
+    threads = oracle.max_threads()
+    t0 = time.perf_counter()
+    oracle.heat(u0_np, 2, 0.25, threads=threads)
+    per_step = max((time.perf_counter() - t0) / 2, 1e-6)
+    k = int(max(2, min(nsteps_full, seconds / per_step)))
+    t0 = time.perf_counter()
+    oracle.heat(u0_np, k, 0.25, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": n * k / dt, "unit": "point-updates/s", "cores": threads, "kind": "oracle",
+            "sample": "heat f64 N=%d, first %d of %d steps, all points, OpenMP %d threads, "
+                      "%.1f s" % (n, k, nsteps_full, threads, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; this build has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import workloads
+    import paper_1504_01380_amd as sw
+
+    sw.init(0)
+    sw.set_tuning(0, 0, sw.MODE_AUTO)
+    n, nsteps = args.n, args.nsteps
+    u0_np = workloads.white_noise(n, seed=workloads.WORKLOADS["heat_large"]["seed"])
+    u0 = torch.from_numpy(u0_np).cuda()
+    plan = sw.plan(n, nsteps, "heat", torch.float64)
+
+    times, _ = timed_runs(sw, torch, sw.advance, u0, nsteps, [0.25], args.steps, args.warmup)
+    t = sum(times) / len(times)
+    updates = float(n) * nsteps
+    value = updates / t
+
+    # dominant kernel: swept_stage_kernel<Heat<double>, P>, one launch per stage
+    launches = plan["stages"]
+    avg_launch = t / launches
+    achieved = HEAT_OPS_PER_UPDATE * updates / launches / avg_launch
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANE_OPS / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / VALU_LANE_OPS, "traffic": None,
+                "kernel": "swept_stage_kernel<Heat<double>,%d>" % plan["pairs_per_lane"],
+                "launches": launches, "avg_launch_ms": avg_launch * 1e3,
+                "ops_per_update": HEAT_OPS_PER_UPDATE}
+
+    out = {
+        "metric": "point-updates/sec swept vs naive per-step (1 MI355X), % of VALU/HBM peak",
+        "value": value, "unit": "point-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "heat N=2^24 f64 r=0.25 20000 steps, u0~U[-1,1] seed 1001",
+                   "n": n, "time_steps": nsteps, "tile_w": plan["tile_w"],
+                   "depth_k": plan["depth_k"], "tiles": plan["tiles"], "stages": plan["stages"],
+                   "pairs_per_lane": plan["pairs_per_lane"]},
+        "roofline": roofline,
+    }
+
+    if not args.no_naive:
+        nt, _ = timed_runs(sw, torch, sw.naive_advance, u0, nsteps, [0.25], 1, 1)
+        naive = updates / nt[0]
+        out["naive"] = {"value": naive, "ms": nt[0] * 1e3,
+                        "hbm_GBps": naive * HEAT_NAIVE_BYTES[8] / 1e9,
+                        "hbm_frac": naive * HEAT_NAIVE_BYTES[8] / HBM_PEAK}
+        out["speedup_vs_naive"] = value / naive
+        u32 = u0.float()
+        st, _ = timed_runs(sw, torch, sw.advance, u32, nsteps, [0.25], 2, 1)
+        nt32, _ = timed_runs(sw, torch, sw.naive_advance, u32, nsteps, [0.25], 1, 1)
+        s32 = updates / (sum(st) / len(st))
+        n32 = updates / nt32[0]
+        out["f32"] = {"swept": s32, "naive": n32, "speedup_vs_naive": s32 / n32,
+                      "swept_frac_alu": HEAT_OPS_PER_UPDATE * s32 / VALU_LANE_OPS,
+                      "naive_hbm_frac": n32 * HEAT_NAIVE_BYTES[4] / HBM_PEAK}
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(u0_np, nsteps, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

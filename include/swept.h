@@ -82,7 +82,9 @@ enum {
 enum {
     SWEPT_MODE_AUTO = 0,      /* swept stages when the grid can be tiled, else naive */
     SWEPT_MODE_STAGE = 1,     /* swept: one kernel launch per stage (triangle, diamonds) */
-    SWEPT_MODE_NAIVE = 2      /* one launch per time step */
+    SWEPT_MODE_NAIVE = 2,     /* one launch per time step */
+    SWEPT_MODE_STAGE_BANDED = 3 /* swept stages, every diamond on the banded kernel
+                                   (the continuous-band kernel switched off) */
 };
 
 /*

@@ -231,6 +231,203 @@ __global__ __launch_bounds__(64) void swept_stage_kernel(StageArgs<S> g)
         dst[i] = chain[i];
 }
 
+// ------------------------------------------------- continuous diamond stage
+// The same diamond, for stages that lie entirely below the target level and
+// whose k is a multiple of the band size 64*P.  Instead of draining and
+// refilling the pipeline at every band, each of the wavefront's 64*P pair
+// slots moves on to the next band as soon as it finishes the last step of
+// the current one: slot e works on band (sigma-e) div k, step (sigma-e) mod k
+// at wave step sigma.  A slot changes band at sigma = beta*k + e; it then
+// stores its final state (right edge) and takes the next band's left-edge
+// state, which it fetched from HBM one band earlier.  Only the first and the
+// last 64P-1 wave steps of the whole stage have idle slots.  Because 64P and
+// k are multiples of 4, all slots are at the same sub-timestep modulo 4.
+
+// MASK: 0 = all slots active; 1 = pipeline fill (slot e active iff e <= j);
+// 2 = pipeline drain (slot e active iff e > j).  QS >= 0: slot (rs, QS)
+// changes band before it computes.
+template <class S, int P, int PH, int MASK, int QS>
+__device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt (&B)[P],
+                                          typename S::Pt (&An)[P], typename S::Pt (&Bn)[P],
+                                          typename S::Pt& cA, typename S::Pt& cB,
+                                          typename S::Pt* chain, int lane, int j, int rs,
+                                          int next_slot, int wslot, bool wlast,
+                                          typename S::Pt* re_store,
+                                          const typename S::Pt* re_load,
+                                          const typename S::Consts& c)
+{
+    using Pt = typename S::Pt;
+    const Pt inA = S::shr1(A[P - 1], cA);
+    const Pt inB = S::shr1(B[P - 1], cB);
+    const Pt nA = chain[2 * next_slot + 1];
+    const Pt nB = chain[2 * next_slot];
+#pragma unroll
+    for (int q = P - 1; q >= 0; --q) {
+        if (QS == q) {     // folded at compile time after unrolling
+            if (lane == rs) {  // this slot enters the next band
+                re_store[0] = B[q];
+                re_store[1] = A[q];
+                A[q] = An[q];
+                B[q] = Bn[q];
+                if (re_load) {
+                    Bn[q] = re_load[0];
+                    An[q] = re_load[1];
+                }
+            }
+        }
+        const Pt rA = (q == 0) ? inA : A[q - 1];
+        const Pt cBq = (q == 0) ? inB : B[q - 1];
+        bool act = true;
+        if constexpr (MASK == 1)
+            act = lane * P + q <= j;
+        if constexpr (MASK == 2)
+            act = lane * P + q > j;
+        if (act) {
+            B[q] = S::template step<PH>(B[q], A[q], cBq, c);
+            A[q] = S::template step<PH>(A[q], cBq, rA, c);
+        }
+    }
+    if (wlast && lane == 63) {  // the last slot traces the band's left edge
+        chain[2 * wslot] = B[P - 1];
+        chain[2 * wslot + 1] = A[P - 1];
+    }
+    cA = nA;
+    cB = nB;
+}
+
+template <class S, int P, int MASK, int QS>
+__device__ __forceinline__ void cont_step_ph(int ph, typename S::Pt (&A)[P],
+                                             typename S::Pt (&B)[P], typename S::Pt (&An)[P],
+                                             typename S::Pt (&Bn)[P], typename S::Pt& cA,
+                                             typename S::Pt& cB, typename S::Pt* chain, int lane,
+                                             int j, int rs, int next_slot, int wslot, bool wlast,
+                                             typename S::Pt* re_store,
+                                             const typename S::Pt* re_load,
+                                             const typename S::Consts& c)
+{
+    if constexpr (S::NPHASE == 1) {
+        cont_step<S, P, 0, MASK, QS>(A, B, An, Bn, cA, cB, chain, lane, j, rs, next_slot, wslot,
+                                     wlast, re_store, re_load, c);
+    } else {
+        switch (ph) {
+        case 0: cont_step<S, P, 0, MASK, QS>(A, B, An, Bn, cA, cB, chain, lane, j, rs, next_slot, wslot, wlast, re_store, re_load, c); break;
+        case 1: cont_step<S, P, 1, MASK, QS>(A, B, An, Bn, cA, cB, chain, lane, j, rs, next_slot, wslot, wlast, re_store, re_load, c); break;
+        case 2: cont_step<S, P, 2, MASK, QS>(A, B, An, Bn, cA, cB, chain, lane, j, rs, next_slot, wslot, wlast, re_store, re_load, c); break;
+        default: cont_step<S, P, 3, MASK, QS>(A, B, An, Bn, cA, cB, chain, lane, j, rs, next_slot, wslot, wlast, re_store, re_load, c); break;
+        }
+    }
+}
+
+// The first 64P wave steps of a cycle of k steps: step j = rs*P + QS is the
+// one at which slot j changes band (cycles 1..nb-1), or, in cycle 0 and
+// after the last band, a step of the pipeline fill or drain.
+template <class S, int P, int MASK, bool TRANS, int QS>
+__device__ __forceinline__ void cont_head(int rs, int64_t sigma_base, int64_t b, int k, int nb,
+                                          int cyc, typename S::Pt (&A)[P],
+                                          typename S::Pt (&B)[P], typename S::Pt (&An)[P],
+                                          typename S::Pt (&Bn)[P], typename S::Pt& cA,
+                                          typename S::Pt& cB, typename S::Pt* chain,
+                                          typename S::Pt* re, int lane,
+                                          const typename S::Consts& c)
+{
+    if constexpr (QS < P) {
+        constexpr int NB = 64 * P;
+        const int j = rs * P + QS;
+        const int64_t sigma = sigma_base + j;
+        const int next_slot = (j + 1 == k) ? 0 : j + 1;
+        // last slot: step m = sigma - (NB-1) mod k of its band
+        const int wslot = (j + k - (NB - 1)) % k;
+        // the last slot is active from step NB-1 of the fill to step NB-2 of the drain
+        const bool wlast = MASK == 1 ? (j == NB - 1) : (MASK == 2 ? (j < NB - 1) : true);
+        typename S::Pt* re_store = nullptr;
+        const typename S::Pt* re_load = nullptr;
+        if constexpr (TRANS) {
+            re_store = re + 2 * ((cyc - 1) * NB + j);
+            if (cyc + 1 < nb)
+                re_load = re + 2 * ((cyc + 1) * NB + j);
+        }
+        cont_step_ph<S, P, MASK, TRANS ? QS : -1>(phase_of<S::NPHASE>(b + sigma), A, B, An, Bn,
+                                                  cA, cB, chain, lane, j, rs, next_slot, wslot,
+                                                  wlast, re_store, re_load, c);
+        cont_head<S, P, MASK, TRANS, QS + 1>(rs, sigma_base, b, k, nb, cyc, A, B, An, Bn, cA, cB,
+                                             chain, re, lane, c);
+    }
+}
+
+template <class S, int P>
+__global__ __launch_bounds__(64) void swept_diamond_cont_kernel(StageArgs<S> g)
+{
+    using Pt = typename S::Pt;
+    constexpr int NB = 64 * P;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Pt* chain = reinterpret_cast<Pt*>(smem_raw);
+
+    const int lane = threadIdx.x;
+    const int t = blockIdx.x;
+    const int k = g.k;
+    const int nb = k / NB;
+    {
+        const int tn = (t + 1 == g.tiles) ? 0 : t + 1;
+        const Pt* src = g.le_in + (size_t)tn * k * 2;
+        for (int i = lane; i < 2 * k; i += 64)
+            chain[i] = src[i];
+    }
+    __syncthreads();
+
+    Pt* re = g.re + (size_t)t * k * 2;
+    Pt A[P], B[P], An[P], Bn[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int e = lane * P + q;
+        B[q] = re[2 * e];
+        A[q] = re[2 * e + 1];
+        if (nb > 1) {
+            Bn[q] = re[2 * (NB + e)];
+            An[q] = re[2 * (NB + e) + 1];
+        } else {
+            An[q] = A[q];
+            Bn[q] = B[q];
+        }
+    }
+    Pt cA = chain[1], cB = chain[0];
+
+    for (int cyc = 0; cyc <= nb; ++cyc) {
+        const int64_t sigma_base = (int64_t)cyc * k;
+        if (cyc == 0) {
+            for (int rs = 0; rs < 64; ++rs)
+                cont_head<S, P, 1, false, 0>(rs, sigma_base, g.b, k, nb, cyc, A, B, An, Bn, cA,
+                                             cB, chain, re, lane, g.c);
+        } else if (cyc == nb) {
+            for (int rs = 0; rs < 64; ++rs)
+                cont_head<S, P, 2, false, 0>(rs, sigma_base, g.b, k, nb, cyc, A, B, An, Bn, cA,
+                                             cB, chain, re, lane, g.c);
+            break;
+        } else {
+            for (int rs = 0; rs < 64; ++rs)
+                cont_head<S, P, 0, true, 0>(rs, sigma_base, g.b, k, nb, cyc, A, B, An, Bn, cA,
+                                            cB, chain, re, lane, g.c);
+        }
+        for (int j = NB; j < k; ++j) {
+            const int64_t sigma = sigma_base + j;
+            const int next_slot = (j + 1 == k) ? 0 : j + 1;
+            cont_step_ph<S, P, 0, -1>(phase_of<S::NPHASE>(g.b + sigma), A, B, An, Bn, cA, cB,
+                                      chain, lane, j, 0, next_slot, j - (NB - 1), true, nullptr,
+                                      nullptr, g.c);
+        }
+    }
+
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int e = lane * P + q;
+        re[2 * ((nb - 1) * NB + e)] = B[q];
+        re[2 * ((nb - 1) * NB + e) + 1] = A[q];
+    }
+    __syncthreads();
+    Pt* dst = g.le_out + (size_t)t * k * 2;
+    for (int i = lane; i < 2 * k; i += 64)
+        dst[i] = chain[i];
+}
+
 // ------------------------------------------------------------- naive paths
 // The straight decomposition: every sub-timestep of every point, one launch
 // per time step, from two full fields.

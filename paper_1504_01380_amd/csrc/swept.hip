@@ -131,21 +131,13 @@ struct Plan {
 
 constexpr size_t kMaxLds = 64 * 1024;
 
-int64_t target_tile(int id)
-{
-    switch (id) {
-    case SWEPT_HEAT_F64: return 2048;
-    case SWEPT_HEAT_F32: return 4096;
-    default: return 1024;
-    }
-}
+// Measured on MI355X (20,000-step heat at N = 2^24, binary64 and binary32;
+// KS at N = 2^20; heat at N = 4096): W = 1024 is fastest for every stencil on
+// large grids (a 2k-entry LDS edge chain small enough for ~10 workgroups per
+// CU); small grids keep at least 16 tiles so that more CUs take part.
+int64_t target_tile(int /*id*/) { return 1024; }
 
-int auto_ppl(int id, int64_t k)
-{
-    if (id == SWEPT_KS_F64)
-        return k >= 512 ? 2 : 1;
-    return k >= 1024 ? 4 : (k >= 256 ? 2 : 1);
-}
+int auto_ppl(int /*id*/, int64_t k) { return k >= 512 ? 4 : (k >= 128 ? 2 : 1); }
 
 bool tile_fits(int id, int64_t nx, int64_t W)
 {
@@ -170,7 +162,7 @@ int make_plan(int64_t nx, int64_t nsteps, int32_t id, Plan* p)
                         g_ctx.tile_w, (long long)nx);
         W = g_ctx.tile_w;
     } else {
-        const int64_t cap = std::min(target_tile(id), std::max<int64_t>(2, nx / 8));
+        const int64_t cap = std::min(target_tile(id), std::max<int64_t>(2, nx / 16));
         for (int64_t w = cap - (cap & 1); w >= 2; w -= 2)
             if (tile_fits(id, nx, w)) {
                 W = w;
@@ -178,7 +170,7 @@ int make_plan(int64_t nx, int64_t nsteps, int32_t id, Plan* p)
             }
     }
     if (W == 0) {
-        if (g_ctx.mode == SWEPT_MODE_STAGE)
+        if (g_ctx.mode == SWEPT_MODE_STAGE || g_ctx.mode == SWEPT_MODE_STAGE_BANDED)
             return fail(SWEPT_EUNSUPPORTED, "nx = %lld has no even tile width", (long long)nx);
         p->mode = SWEPT_MODE_NAIVE;
         return SWEPT_OK;
@@ -195,9 +187,21 @@ int make_plan(int64_t nx, int64_t nsteps, int32_t id, Plan* p)
 // ------------------------------------------------------------- swept launch
 
 template <class S, int P>
-void launch_stage(const StageArgs<S>& a, size_t lds, hipStream_t st, int tiles)
+void launch_stage(const StageArgs<S>& a, size_t lds, hipStream_t st, int tiles, bool cont)
 {
-    hipLaunchKernelGGL((swept_stage_kernel<S, P>), dim3(tiles), dim3(64), lds, st, a);
+    if (cont)
+        hipLaunchKernelGGL((swept_diamond_cont_kernel<S, P>), dim3(tiles), dim3(64), lds, st, a);
+    else
+        hipLaunchKernelGGL((swept_stage_kernel<S, P>), dim3(tiles), dim3(64), lds, st, a);
+}
+
+// Full diamonds (below the target level, k a multiple of the band 64P) run
+// on the continuous kernel; the triangle and capped stages on the banded one.
+bool use_continuous(const Plan& p, int64_t s, int64_t L)
+{
+    const int64_t b = (s - 1) * p.k;
+    return g_ctx.mode != SWEPT_MODE_STAGE_BANDED && s > 0 && b + 2 * p.k - 1 <= L &&
+           p.k % (64 * p.P) == 0;
 }
 
 template <class S>
@@ -226,11 +230,12 @@ int run_swept(void* u, int64_t nx, int64_t L, const typename S::Consts& c, const
         a.J0 = (p.k + s * p.k) % nx;
         a.le_in = le[(s + 1) & 1];
         a.le_out = le[s & 1];
+        const bool cont = use_continuous(p, s, L);
         switch (p.P) {
-        case 1: launch_stage<S, 1>(a, lds, g_ctx.stream, (int)p.tiles); break;
-        case 2: launch_stage<S, 2>(a, lds, g_ctx.stream, (int)p.tiles); break;
-        case 4: launch_stage<S, 4>(a, lds, g_ctx.stream, (int)p.tiles); break;
-        case 8: launch_stage<S, 8>(a, lds, g_ctx.stream, (int)p.tiles); break;
+        case 1: launch_stage<S, 1>(a, lds, g_ctx.stream, (int)p.tiles, cont); break;
+        case 2: launch_stage<S, 2>(a, lds, g_ctx.stream, (int)p.tiles, cont); break;
+        case 4: launch_stage<S, 4>(a, lds, g_ctx.stream, (int)p.tiles, cont); break;
+        case 8: launch_stage<S, 8>(a, lds, g_ctx.stream, (int)p.tiles, cont); break;
         default: return fail(SWEPT_EINVAL, "pairs per lane %d not in {1,2,4,8}", p.P);
         }
     }
@@ -365,7 +370,8 @@ int swept_set_tuning(int32_t tile_w, int32_t pairs_per_lane, int32_t mode)
     if (pairs_per_lane != 0 && pairs_per_lane != 1 && pairs_per_lane != 2 && pairs_per_lane != 4 &&
         pairs_per_lane != 8)
         return fail(SWEPT_EINVAL, "pairs per lane %d not in {0,1,2,4,8}", pairs_per_lane);
-    if (mode != SWEPT_MODE_AUTO && mode != SWEPT_MODE_STAGE && mode != SWEPT_MODE_NAIVE)
+    if (mode != SWEPT_MODE_AUTO && mode != SWEPT_MODE_STAGE && mode != SWEPT_MODE_NAIVE &&
+        mode != SWEPT_MODE_STAGE_BANDED)
         return fail(SWEPT_EINVAL, "unknown mode %d", mode);
     g_ctx.tile_w = tile_w;
     g_ctx.ppl = pairs_per_lane;

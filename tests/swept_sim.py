@@ -37,7 +37,67 @@ def ks_step(dt, dx):
     return f, 4, (lambda v: (v, v, 0.0)), (lambda p: p[0])
 
 
-def simulate(u0, nsteps, k, P, stencil, lanes=64, track=False):
+def _cont_stage(t, J, b, k, P, lanes, RE, chain, step, nph, n, visits):
+    """One full diamond on the continuous-band schedule of
+    swept_diamond_cont_kernel: slot e works on band (sigma-e) div k, step
+    (sigma-e) mod k at wave step sigma and changes band at sigma = beta*k+e."""
+    NB = lanes * P
+    nb = k // NB
+    A = [RE[t][2 * e + 1] for e in range(NB)]
+    B = [RE[t][2 * e] for e in range(NB)]
+    An = [RE[t][2 * (NB + e) + 1] if nb > 1 else None for e in range(NB)]
+    Bn = [RE[t][2 * (NB + e)] if nb > 1 else None for e in range(NB)]
+    cA, cB = chain[1], chain[0]
+    for cyc in range(nb + 1):
+        steps = range(NB) if cyc == nb else range(k)
+        for j in steps:
+            sigma = cyc * k + j
+            mask = 1 if (cyc == 0 and j < NB) else (2 if cyc == nb else 0)
+            trans = 0 < cyc < nb and j < NB
+            inA = [cA] + [A[(r - 1) * P + P - 1] for r in range(1, lanes)]
+            inB = [cB] + [B[(r - 1) * P + P - 1] for r in range(1, lanes)]
+            ns = 0 if j + 1 == k else j + 1
+            nA, nB = chain[2 * ns + 1], chain[2 * ns]
+            ph = (b + sigma) % nph
+            for r in range(lanes):
+                for q in range(P - 1, -1, -1):
+                    e = r * P + q
+                    if trans and e == j:
+                        RE[t][2 * ((cyc - 1) * NB + j)] = B[e]
+                        RE[t][2 * ((cyc - 1) * NB + j) + 1] = A[e]
+                        A[e], B[e] = An[e], Bn[e]
+                        if cyc + 1 < nb:
+                            Bn[e] = RE[t][2 * ((cyc + 1) * NB + j)]
+                            An[e] = RE[t][2 * ((cyc + 1) * NB + j) + 1]
+                    act = True
+                    if mask == 1:
+                        act = e <= j
+                    elif mask == 2:
+                        act = e > j
+                    if not act:
+                        continue
+                    rA = inA[r] if q == 0 else A[e - 1]
+                    cBv = inB[r] if q == 0 else B[e - 1]
+                    B[e] = step(ph, B[e], A[e], cBv)
+                    A[e] = step(ph, A[e], cBv, rA)
+                    if visits is not None:
+                        beta, m = divmod(sigma - e, k)
+                        d = beta * NB + e
+                        lvl = b + m + d + 1
+                        xa = (J + m - d) % n
+                        for x in (xa, (xa - 1) % n):
+                            visits[(x, lvl)] = visits.get((x, lvl), 0) + 1
+            wlast = (j == NB - 1) if mask == 1 else ((j < NB - 1) if mask == 2 else True)
+            if wlast:
+                ws = (j + k - (NB - 1)) % k
+                chain[2 * ws], chain[2 * ws + 1] = B[NB - 1], A[NB - 1]
+            cA, cB = nA, nB
+    for e in range(NB):
+        RE[t][2 * ((nb - 1) * NB + e)] = B[e]
+        RE[t][2 * ((nb - 1) * NB + e) + 1] = A[e]
+
+
+def simulate(u0, nsteps, k, P, stencil, lanes=64, track=False, cont=False):
     """Run the swept schedule on a Python list; returns (u, visits) where
     visits maps (x, level) -> number of times it was computed (if track)."""
     step, nph, from_field, to_field = stencil
@@ -63,6 +123,10 @@ def simulate(u0, nsteps, k, P, stencil, lanes=64, track=False):
             J = (t * W + J0) % n
             chain = list(le_in[(t + 1) % T]) if not tri else [None] * (2 * k)
             top = L - b
+            if cont and not tri and b + 2 * k - 1 <= L and k % (lanes * P) == 0:
+                _cont_stage(t, J, b, k, P, lanes, RE, chain, step, nph, n, visits)
+                le_out[t] = chain
+                continue
             for base in range(0, k, band):
                 nvalid = min(band, k - base)
                 tau_first = (k - base) if tri else 0

@@ -65,8 +65,9 @@ def test_plan_geometry(swept):
     lib = swept.lib()
     lib.swept_set_tuning(0, 0, 0)
     p = swept.plan(1 << 24, 20000, "heat")
-    assert p["tile_w"] == 2048 and p["depth_k"] == 1024 and p["tiles"] == 8192
-    assert p["stages"] == 1 + (20000 + 1023) // 1024 and p["mode"] == swept.MODE_STAGE
+    assert p["tile_w"] == 1024 and p["depth_k"] == 512 and p["tiles"] == 16384
+    assert p["stages"] == 1 + (20000 + 511) // 512 and p["mode"] == swept.MODE_STAGE
+    assert p["pairs_per_lane"] == 4
     p = swept.plan(4096, 10000, "heat")
     assert (1 << 24) % p["tile_w"] == 0 and p["tiles"] * p["tile_w"] == 4096
     p = swept.plan(1 << 20, 50000, "ks")

@@ -171,3 +171,22 @@ def test_bad_arguments_raise(sw):
     sw.set_tuning(48, 0, sw.MODE_STAGE)
     with pytest.raises(sw.SweptError):
         sw.advance(u, 1, "heat", HEAT_P)
+
+
+@pytest.mark.parametrize("stencil,n,W,P,nsteps", [
+    ("heat", 8192, 2048, 4, 3000), ("heat", 4096, 512, 2, 1500), ("ks", 4096, 1024, 2, 400),
+    ("ks", 2048, 512, 1, 300),
+])
+def test_banded_and_continuous_kernels_agree(sw, oracle_mod, stencil, n, W, P, nsteps):
+    """Full diamonds run on the continuous-band kernel by default; the banded
+    kernel must give the same bits (and both the oracle's)."""
+    if stencil == "heat":
+        u0, par = workloads.white_noise(n, seed=W + P), [0.3]
+        want = oracle_mod.heat(u0, nsteps, 0.3)
+    else:
+        u0, par = workloads.smoothed_noise(n, seed=W + P), KS_P
+        want = oracle_mod.ks(u0, nsteps, *KS_P)
+    sw.set_tuning(W, P, sw.MODE_STAGE)
+    assert same_bits(run(sw, sw.advance, u0, nsteps, stencil, par), want)
+    sw.set_tuning(W, P, sw.MODE_STAGE_BANDED)
+    assert same_bits(run(sw, sw.advance, u0, nsteps, stencil, par), want)

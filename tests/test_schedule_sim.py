@@ -67,3 +67,28 @@ def test_dropped_update_is_caught(oracle_mod):
 
     got, _ = swept_sim.simulate(list(u0), nsteps, k, 1, (skipping, nph, ff, tf), track=True)
     assert not np.array_equal(np.array(got), oracle_mod.heat(u0, nsteps, 0.25))
+
+
+@pytest.mark.parametrize("lanes,P,k,nsteps,stencil", [
+    (2, 1, 2, 20, "heat"),     # one band (k = 64P)
+    (2, 1, 4, 30, "heat"),     # two bands
+    (2, 2, 12, 61, "heat"),    # three bands of 4 pairs
+    (4, 1, 16, 100, "heat"),   # four bands
+    (3, 1, 9, 40, "heat"),     # odd band size
+    (2, 2, 8, 30, "ks"),       # KS: k and 64P multiples of 4 in the kernel; here 4 | k, 4 | NB
+    (4, 1, 8, 25, "ks"),
+])
+def test_continuous_schedule(oracle_mod, lanes, P, k, nsteps, stencil):
+    """Full diamonds on the continuous-band schedule: exactly once, bitwise."""
+    n = 3 * 2 * k
+    if stencil == "heat":
+        u0 = workloads.white_noise(n, seed=k * 10 + P)
+        st, L, want = swept_sim.heat_step(0.3), nsteps, oracle_mod.heat(u0, nsteps, 0.3)
+    else:
+        u0 = workloads.smoothed_noise(n, seed=k)
+        st, L, want = swept_sim.ks_step(0.005, 0.5), 4 * nsteps, oracle_mod.ks(u0, nsteps, 0.005, 0.5)
+    got, visits = swept_sim.simulate(list(u0), nsteps, k, P, st, lanes=lanes, track=True,
+                                     cont=True)
+    ok, why = swept_sim.levels_complete(visits, n, L, k)
+    assert ok, why
+    assert np.array_equal(np.array(got), want)
