@@ -25,7 +25,10 @@ sys.path.insert(0, ROOT)
 
 # MI355X published figures; VALU issue rate derived from the unit counts.
 CUS, SIMDS_PER_CU, LANES_PER_SIMD, CLOCK_HZ = 256, 4, 16, 2.4e9
-VALU_LANE_OPS = CUS * SIMDS_PER_CU * LANES_PER_SIMD * CLOCK_HZ   # 39.3e12 per second
+VALU_LANE_OPS = CUS * SIMDS_PER_CU * LANES_PER_SIMD * CLOCK_HZ   # 39.3e12 FP64 ops per second
+# 32-bit VALU operations issue at twice that rate on CDNA4 (the published
+# 157.3 TFLOP/s FP32 vector peak = 78.6e12 non-fused FP32 ops/s x 2 for FMA).
+VALU_LANE_OPS_F32 = 2 * VALU_LANE_OPS
 HBM_PEAK = 8.0e12
 HEAT_OPS_PER_UPDATE = 5           # add, mul, sub, mul, add (no fused multiply-add)
 HEAT_NAIVE_BYTES = {8: 16, 4: 8}  # read u, write u' per point-update
@@ -40,13 +43,17 @@ def parse():
     ap.add_argument("--nsteps", type=int, default=20_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-naive", action="store_true", help="skip the naive and f32 legs")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for rocprofv3: a plain copy of u (calibration), then the "
+                         "timed swept runs only")
     return ap.parse_args()
 
 
-def timed_runs(sw, torch, fn, u0, nsteps, params, reps, warmup):
+def timed_runs(sw, torch, fn, u0, nsteps, params, reps, warmup, after=None):
     """Run fn `reps` times on copies of u0; HIP events on the stream the
-    library launches on (torch's current stream) bracket each run."""
+    library launches on (torch's current stream) bracket each run.  `after`
+    runs once the closing event of a timed run has completed."""
     stream = torch.cuda.current_stream()
     u = u0.clone()
     for _ in range(warmup):
@@ -63,8 +70,38 @@ def timed_runs(sw, torch, fn, u0, nsteps, params, reps, warmup):
         e1.record(stream)
         e1.synchronize()
         times.append(e0.elapsed_time(e1) / 1e3)
+        if after is not None:
+            after()
     sw.sync()
     return times, u
+
+
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1504_01380_amd", "csrc", f)
+                  for f in ("kernels.hpp", "stencils.hpp")]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_heat_f64.json")
+
+
+def kernel_source_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None if
+    there is none or the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha") != kernel_source_sha() or rec.get("kernel") != kernel:
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def cpu_baseline(u0_np, nsteps_full, seconds):
@@ -74,9 +111,10 @@ def cpu_baseline(u0_np, nsteps_full, seconds):
     oracle.build(force=False)
     n = u0_np.size
     threads = oracle.max_threads()
+    oracle.heat(u0_np, 2, 0.25, threads=threads)      # first touch, thread start-up
     t0 = time.perf_counter()
-    oracle.heat(u0_np, 2, 0.25, threads=threads)
-    per_step = max((time.perf_counter() - t0) / 2, 1e-6)
+    oracle.heat(u0_np, 20, 0.25, threads=threads)
+    per_step = max((time.perf_counter() - t0) / 20, 1e-6)
     k = int(max(2, min(nsteps_full, seconds / per_step)))
     t0 = time.perf_counter()
     oracle.heat(u0_np, k, 0.25, threads=threads)
@@ -104,20 +142,47 @@ def main():
     u0 = torch.from_numpy(u0_np).cuda()
     plan = sw.plan(n, nsteps, "heat", torch.float64)
 
-    times, _ = timed_runs(sw, torch, sw.advance, u0, nsteps, [0.25], args.steps, args.warmup)
+    if args.profile:
+        # a plain device copy of known size, for scaling the HBM counters
+        dst = torch.empty_like(u0)
+        dst.copy_(u0)
+        torch.cuda.synchronize()
+
+    # The stage launches of every timed run are bracketed by HIP events on
+    # the library's stream (torch's current stream).
+    sw.set_profiling(True)
+    cont_ms, stage_ms = [], []
+
+    def record():
+        ms, kind = sw.stage_times()
+        stage_ms.append(sum(ms))
+        cont_ms.extend(m for m, kd in zip(ms, kind) if kd == 1)
+
+    times, _ = timed_runs(sw, torch, sw.advance, u0, nsteps, [0.25], args.steps, args.warmup,
+                          after=record)
+    sw.set_profiling(False)
     t = sum(times) / len(times)
     updates = float(n) * nsteps
     value = updates / t
 
-    # dominant kernel: swept_stage_kernel<Heat<double>, P>, one launch per stage
-    launches = plan["stages"]
-    avg_launch = t / launches
-    achieved = HEAT_OPS_PER_UPDATE * updates / launches / avg_launch
+    # Dominant kernel: the continuous-band diamond kernel, one launch per full
+    # diamond stage; each launch computes 2k^2 point-updates per tile.
+    k, tiles = plan["depth_k"], plan["tiles"]
+    kname = "swept_diamond_cont_kernel<Heat<double>,%d>" % plan["pairs_per_lane"]
+    updates_per_launch = float(tiles) * 2 * k * k
+    flops_per_launch = HEAT_OPS_PER_UPDATE * updates_per_launch
+    avg_launch = (sum(cont_ms) / len(cont_ms) / 1e3) if cont_ms else float("nan")
+    achieved = flops_per_launch / avg_launch
+    edge_bytes = float(tiles) * 4 * 2 * k * 8   # RE in/out + LE in/out, 2k values each
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANE_OPS / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / VALU_LANE_OPS, "traffic": None,
-                "kernel": "swept_stage_kernel<Heat<double>,%d>" % plan["pairs_per_lane"],
-                "launches": launches, "avg_launch_ms": avg_launch * 1e3,
-                "ops_per_update": HEAT_OPS_PER_UPDATE}
+                "unit": "TFLOP/s", "frac": achieved / VALU_LANE_OPS,
+                "traffic": measured_traffic(kname),
+                "kernel": kname, "launches_per_step": len(cont_ms) // max(1, args.steps),
+                "stages_per_step": plan["stages"], "avg_launch_ms": avg_launch * 1e3,
+                "flops_per_launch": flops_per_launch, "ops_per_update": HEAT_OPS_PER_UPDATE,
+                "stage_sum_ms": sum(stage_ms) / max(1, len(stage_ms)),
+                "algorithmic_bytes_per_launch": edge_bytes,
+                "whole_run_frac": HEAT_OPS_PER_UPDATE * value / VALU_LANE_OPS}
 
     out = {
         "metric": "point-updates/sec swept vs naive per-step (1 MI355X), % of VALU/HBM peak",
@@ -131,6 +196,8 @@ def main():
         "roofline": roofline,
     }
 
+    if args.profile:
+        args.no_naive = args.no_cpu = True
     if not args.no_naive:
         nt, _ = timed_runs(sw, torch, sw.naive_advance, u0, nsteps, [0.25], 1, 1)
         naive = updates / nt[0]
@@ -144,7 +211,7 @@ def main():
         s32 = updates / (sum(st) / len(st))
         n32 = updates / nt32[0]
         out["f32"] = {"swept": s32, "naive": n32, "speedup_vs_naive": s32 / n32,
-                      "swept_frac_alu": HEAT_OPS_PER_UPDATE * s32 / VALU_LANE_OPS,
+                      "swept_frac_alu": HEAT_OPS_PER_UPDATE * s32 / VALU_LANE_OPS_F32,
                       "naive_hbm_frac": n32 * HEAT_NAIVE_BYTES[4] / HBM_PEAK}
 
     if not args.no_cpu:

@@ -138,6 +138,20 @@ int swept_naive_advance(void *u, int64_t nx, int64_t nsteps, int32_t stencil_id,
 int swept_naive_substep_advance(void *u, int64_t nx, int64_t nsteps, int32_t stencil_id,
                                 const double *params, int32_t nparams);
 
+/*
+ * Per-stage timing.  With profiling enabled, swept_advance records a HIP
+ * event on the current stream before its first and after every stage
+ * launch.  swept_stage_times waits for those events and returns, for the
+ * most recent swept_advance, the duration of each stage launch in
+ * milliseconds (ms_out[i]) and which kernel ran it (kind_out[i]: 0 = banded
+ * kernel -- the triangle or a stage capped at the target level, 1 =
+ * continuous-band diamond kernel).  At most cap entries are written; *count
+ * receives the number of stages.  Either output array may be NULL.
+ * Returns SWEPT_EINVAL if profiling is off or no swept run was recorded.
+ */
+int swept_set_profiling(int enable);
+int swept_stage_times(double *ms_out, int32_t *kind_out, int64_t cap, int64_t *count);
+
 /* Wait for the current stream; report asynchronous kernel errors. */
 int swept_sync(void);
 

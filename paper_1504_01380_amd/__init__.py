@@ -28,6 +28,7 @@ _STATUS = {0: "SWEPT_OK", -1: "SWEPT_EINVAL", -2: "SWEPT_ENOTINIT", -3: "SWEPT_E
 
 EXPORTS = ("swept_init", "swept_set_stream", "swept_set_tuning", "swept_plan",
            "swept_advance", "swept_naive_advance", "swept_naive_substep_advance",
+           "swept_set_profiling", "swept_stage_times",
            "swept_sync", "swept_last_error", "swept_finalize")
 
 
@@ -51,6 +52,9 @@ def _load() -> ctypes.CDLL:
     L.swept_plan.argtypes = [i64, i64, i32, ctypes.POINTER(i64)]
     for f in (L.swept_advance, L.swept_naive_advance, L.swept_naive_substep_advance):
         f.argtypes = [vp, i64, i64, i32, dp, i32]
+    L.swept_set_profiling.argtypes = [ctypes.c_int]
+    L.swept_stage_times.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), i64,
+                                    ctypes.POINTER(i64)]
     L.swept_sync.argtypes = []
     L.swept_last_error.argtypes = []
     L.swept_last_error.restype = ctypes.c_char_p
@@ -162,6 +166,22 @@ def naive_substep_advance(u: torch.Tensor, nsteps: int, stencil, params: Sequenc
     _check(_lib.swept_naive_substep_advance(ctypes.c_void_p(u.data_ptr()), u.numel(), int(nsteps),
                                             sid, p, npar), "swept_naive_substep_advance")
     return u
+
+
+def set_profiling(enable: bool) -> None:
+    _check(_lib.swept_set_profiling(1 if enable else 0), "swept_set_profiling")
+
+
+def stage_times():
+    """(ms, kind) per stage launch of the most recent profiled swept_advance;
+    kind 0 = banded kernel (triangle or capped stage), 1 = continuous kernel."""
+    count = ctypes.c_int64(0)
+    _check(_lib.swept_stage_times(None, None, 0, ctypes.byref(count)), "swept_stage_times")
+    n = count.value
+    ms = (ctypes.c_double * max(1, n))()
+    kind = (ctypes.c_int32 * max(1, n))()
+    _check(_lib.swept_stage_times(ms, kind, n, ctypes.byref(count)), "swept_stage_times")
+    return [float(ms[i]) for i in range(n)], [int(kind[i]) for i in range(n)]
 
 
 def sync() -> None:

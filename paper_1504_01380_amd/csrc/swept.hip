@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "swept.h"
 #include "kernels.hpp"
@@ -28,6 +29,10 @@ struct Context {
     int tile_w = 0;   // 0 = automatic
     int ppl = 0;      // pairs per lane, 0 = automatic
     int mode = SWEPT_MODE_AUTO;
+    bool profiling = false;
+    std::vector<hipEvent_t> events;   // events[i] before stage i, events[i+1] after it
+    std::vector<int32_t> kinds;       // kernel used by each recorded stage
+    int64_t recorded = 0;             // stages recorded by the last swept run
 };
 
 Context g_ctx;
@@ -204,6 +209,27 @@ bool use_continuous(const Plan& p, int64_t s, int64_t L)
            p.k % (64 * p.P) == 0;
 }
 
+int reserve_events(int64_t stages)
+{
+    g_ctx.recorded = 0;
+    while ((int64_t)g_ctx.events.size() < stages + 1) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        g_ctx.events.push_back(e);
+    }
+    g_ctx.kinds.assign((size_t)stages, 0);
+    return SWEPT_OK;
+}
+
+void release_events()
+{
+    for (hipEvent_t e : g_ctx.events)
+        (void)hipEventDestroy(e);
+    g_ctx.events.clear();
+    g_ctx.kinds.clear();
+    g_ctx.recorded = 0;
+}
+
 template <class S>
 int run_swept(void* u, int64_t nx, int64_t L, const typename S::Consts& c, const Plan& p)
 {
@@ -224,6 +250,12 @@ int run_swept(void* u, int64_t nx, int64_t L, const typename S::Consts& c, const
     a.k = (int)p.k;
     a.tiles = (int)p.tiles;
     a.c = c;
+    if (g_ctx.profiling) {
+        rc = reserve_events(p.stages);
+        if (rc)
+            return rc;
+        HIP_TRY(hipEventRecord(g_ctx.events[0], g_ctx.stream));
+    }
     for (int64_t s = 0; s < p.stages; ++s) {
         a.tri = s == 0;
         a.b = (s - 1) * p.k;
@@ -238,8 +270,14 @@ int run_swept(void* u, int64_t nx, int64_t L, const typename S::Consts& c, const
         case 8: launch_stage<S, 8>(a, lds, g_ctx.stream, (int)p.tiles, cont); break;
         default: return fail(SWEPT_EINVAL, "pairs per lane %d not in {1,2,4,8}", p.P);
         }
+        if (g_ctx.profiling) {
+            g_ctx.kinds[(size_t)s] = cont ? 1 : 0;
+            HIP_TRY(hipEventRecord(g_ctx.events[(size_t)s + 1], g_ctx.stream));
+        }
     }
     HIP_TRY(hipGetLastError());
+    if (g_ctx.profiling)
+        g_ctx.recorded = p.stages;
     return SWEPT_OK;
 }
 
@@ -444,6 +482,39 @@ int swept_naive_substep_advance(void* u, int64_t nx, int64_t nsteps, int32_t ste
     return run_naive_ks_substep(u, nx, nsteps, ks_consts(params));
 }
 
+int swept_set_profiling(int enable)
+{
+    if (!g_ctx.ready)
+        return fail(SWEPT_ENOTINIT, "swept_init has not been called");
+    g_ctx.profiling = enable != 0;
+    g_ctx.recorded = 0;
+    return SWEPT_OK;
+}
+
+int swept_stage_times(double* ms_out, int32_t* kind_out, int64_t cap, int64_t* count)
+{
+    if (!g_ctx.ready)
+        return fail(SWEPT_ENOTINIT, "swept_init has not been called");
+    if (!g_ctx.profiling || g_ctx.recorded == 0)
+        return fail(SWEPT_EINVAL, "no profiled swept run recorded");
+    if (cap < 0)
+        return fail(SWEPT_EINVAL, "negative capacity");
+    const int64_t n = g_ctx.recorded;
+    HIP_TRY(hipEventSynchronize(g_ctx.events[(size_t)n]));
+    for (int64_t i = 0; i < n && i < cap; ++i) {
+        if (ms_out) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, g_ctx.events[(size_t)i], g_ctx.events[(size_t)i + 1]));
+            ms_out[i] = ms;
+        }
+        if (kind_out)
+            kind_out[i] = g_ctx.kinds[(size_t)i];
+    }
+    if (count)
+        *count = n;
+    return SWEPT_OK;
+}
+
 int swept_sync(void)
 {
     if (!g_ctx.ready)
@@ -457,10 +528,11 @@ const char* swept_last_error(void) { return g_err.c_str(); }
 
 void swept_finalize(void)
 {
-    if (g_ctx.scratch) {
+    if (g_ctx.ready)
         (void)hipDeviceSynchronize();
+    if (g_ctx.scratch)
         (void)hipFree(g_ctx.scratch);
-    }
+    release_events();
     g_ctx = Context{};
 }
 
