@@ -295,49 +295,34 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
     cB = nB;
 }
 
-template <class S, int P, int MASK, int QS>
-__device__ __forceinline__ void cont_step_ph(int ph, typename S::Pt (&A)[P],
-                                             typename S::Pt (&B)[P], typename S::Pt (&An)[P],
-                                             typename S::Pt (&Bn)[P], typename S::Pt& cA,
-                                             typename S::Pt& cB, typename S::Pt* chain, int lane,
-                                             int j, int rs, int next_slot, int wslot, bool wlast,
-                                             typename S::Pt* re_store,
-                                             const typename S::Pt* re_load,
-                                             const typename S::Consts& c)
-{
-    if constexpr (S::NPHASE == 1) {
-        cont_step<S, P, 0, MASK, QS>(A, B, An, Bn, cA, cB, chain, lane, j, rs, next_slot, wslot,
-                                     wlast, re_store, re_load, c);
-    } else {
-        switch (ph) {
-        case 0: cont_step<S, P, 0, MASK, QS>(A, B, An, Bn, cA, cB, chain, lane, j, rs, next_slot, wslot, wlast, re_store, re_load, c); break;
-        case 1: cont_step<S, P, 1, MASK, QS>(A, B, An, Bn, cA, cB, chain, lane, j, rs, next_slot, wslot, wlast, re_store, re_load, c); break;
-        case 2: cont_step<S, P, 2, MASK, QS>(A, B, An, Bn, cA, cB, chain, lane, j, rs, next_slot, wslot, wlast, re_store, re_load, c); break;
-        default: cont_step<S, P, 3, MASK, QS>(A, B, An, Bn, cA, cB, chain, lane, j, rs, next_slot, wslot, wlast, re_store, re_load, c); break;
-        }
-    }
-}
+// Wave steps are issued in statically unrolled groups.  Every cycle starts at
+// a step sigma = cyc*k with b + sigma = 0 mod 4 (k and 64P are multiples of
+// 4), so inside a group the sub-timestep of step i is i mod NPHASE, known at
+// compile time.
 
-// The first 64P wave steps of a cycle of k steps: step j = rs*P + QS is the
-// one at which slot j changes band (cycles 1..nb-1), or, in cycle 0 and
-// after the last band, a step of the pipeline fill or drain.
-template <class S, int P, int MASK, bool TRANS, int QS>
-__device__ __forceinline__ void cont_head(int rs, int64_t sigma_base, int64_t b, int k, int nb,
-                                          int cyc, typename S::Pt (&A)[P],
-                                          typename S::Pt (&B)[P], typename S::Pt (&An)[P],
-                                          typename S::Pt (&Bn)[P], typename S::Pt& cA,
-                                          typename S::Pt& cB, typename S::Pt* chain,
-                                          typename S::Pt* re, int lane,
-                                          const typename S::Consts& c)
+// Head of a cycle, steps j = j0 .. j0+G-1 (G = max(P, NPHASE) divides 64P):
+// step j = rs*P + QS is the one at which slot j changes band (cycles
+// 1..nb-1), or a step of the pipeline fill (cycle 0) or drain (after the
+// last band).
+template <class S, int P, int MASK, bool TRANS, int I, int G>
+__device__ __forceinline__ void cont_head_group(int j0, int k, int nb, int cyc,
+                                                typename S::Pt (&A)[P], typename S::Pt (&B)[P],
+                                                typename S::Pt (&An)[P],
+                                                typename S::Pt (&Bn)[P], typename S::Pt& cA,
+                                                typename S::Pt& cB, typename S::Pt* chain,
+                                                typename S::Pt* re, int lane,
+                                                const typename S::Consts& c)
 {
-    if constexpr (QS < P) {
+    if constexpr (I < G) {
         constexpr int NB = 64 * P;
-        const int j = rs * P + QS;
-        const int64_t sigma = sigma_base + j;
+        constexpr int QS = I % P;
+        constexpr int PH = I % S::NPHASE;
+        const int j = j0 + I;
+        const int rs = j / P;
         const int next_slot = (j + 1 == k) ? 0 : j + 1;
         // last slot: step m = sigma - (NB-1) mod k of its band
         const int wslot = (j + k - (NB - 1)) % k;
-        // the last slot is active from step NB-1 of the fill to step NB-2 of the drain
+        // it is active from step NB-1 of the fill to step NB-2 of the drain
         const bool wlast = MASK == 1 ? (j == NB - 1) : (MASK == 2 ? (j < NB - 1) : true);
         typename S::Pt* re_store = nullptr;
         const typename S::Pt* re_load = nullptr;
@@ -346,11 +331,29 @@ __device__ __forceinline__ void cont_head(int rs, int64_t sigma_base, int64_t b,
             if (cyc + 1 < nb)
                 re_load = re + 2 * ((cyc + 1) * NB + j);
         }
-        cont_step_ph<S, P, MASK, TRANS ? QS : -1>(phase_of<S::NPHASE>(b + sigma), A, B, An, Bn,
-                                                  cA, cB, chain, lane, j, rs, next_slot, wslot,
-                                                  wlast, re_store, re_load, c);
-        cont_head<S, P, MASK, TRANS, QS + 1>(rs, sigma_base, b, k, nb, cyc, A, B, An, Bn, cA, cB,
-                                             chain, re, lane, c);
+        cont_step<S, P, PH, MASK, TRANS ? QS : -1>(A, B, An, Bn, cA, cB, chain, lane, j, rs,
+                                                   next_slot, wslot, wlast, re_store, re_load, c);
+        cont_head_group<S, P, MASK, TRANS, I + 1, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB, chain,
+                                                     re, lane, c);
+    }
+}
+
+// Body of a cycle, steps j = j0 .. j0+U-1 with 64P <= j < k: no slot changes
+// band and every slot is active.
+template <class S, int P, int I, int U>
+__device__ __forceinline__ void cont_body_group(int j0, int k, typename S::Pt (&A)[P],
+                                                typename S::Pt (&B)[P], typename S::Pt (&An)[P],
+                                                typename S::Pt (&Bn)[P], typename S::Pt& cA,
+                                                typename S::Pt& cB, typename S::Pt* chain,
+                                                int lane, const typename S::Consts& c)
+{
+    if constexpr (I < U) {
+        constexpr int NB = 64 * P;
+        const int j = j0 + I;
+        const int next_slot = (j + 1 == k) ? 0 : j + 1;
+        cont_step<S, P, I % S::NPHASE, 0, -1>(A, B, An, Bn, cA, cB, chain, lane, j, 0, next_slot,
+                                              j - (NB - 1), true, nullptr, nullptr, c);
+        cont_body_group<S, P, I + 1, U>(j0, k, A, B, An, Bn, cA, cB, chain, lane, c);
     }
 }
 
@@ -359,6 +362,8 @@ __global__ __launch_bounds__(64) void swept_diamond_cont_kernel(StageArgs<S> g)
 {
     using Pt = typename S::Pt;
     constexpr int NB = 64 * P;
+    constexpr int G = P > S::NPHASE ? P : S::NPHASE;  // head group: QS and phase static
+    constexpr int U = 4;                               // body group; k - NB is a multiple of 4
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Pt* chain = reinterpret_cast<Pt*>(smem_raw);
 
@@ -391,29 +396,23 @@ __global__ __launch_bounds__(64) void swept_diamond_cont_kernel(StageArgs<S> g)
     }
     Pt cA = chain[1], cB = chain[0];
 
-    for (int cyc = 0; cyc <= nb; ++cyc) {
-        const int64_t sigma_base = (int64_t)cyc * k;
+    for (int cyc = 0;; ++cyc) {
         if (cyc == 0) {
-            for (int rs = 0; rs < 64; ++rs)
-                cont_head<S, P, 1, false, 0>(rs, sigma_base, g.b, k, nb, cyc, A, B, An, Bn, cA,
-                                             cB, chain, re, lane, g.c);
+            for (int j0 = 0; j0 < NB; j0 += G)
+                cont_head_group<S, P, 1, false, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
+                                                      chain, re, lane, g.c);
         } else if (cyc == nb) {
-            for (int rs = 0; rs < 64; ++rs)
-                cont_head<S, P, 2, false, 0>(rs, sigma_base, g.b, k, nb, cyc, A, B, An, Bn, cA,
-                                             cB, chain, re, lane, g.c);
+            for (int j0 = 0; j0 < NB; j0 += G)
+                cont_head_group<S, P, 2, false, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
+                                                      chain, re, lane, g.c);
             break;
         } else {
-            for (int rs = 0; rs < 64; ++rs)
-                cont_head<S, P, 0, true, 0>(rs, sigma_base, g.b, k, nb, cyc, A, B, An, Bn, cA,
-                                            cB, chain, re, lane, g.c);
+            for (int j0 = 0; j0 < NB; j0 += G)
+                cont_head_group<S, P, 0, true, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
+                                                     chain, re, lane, g.c);
         }
-        for (int j = NB; j < k; ++j) {
-            const int64_t sigma = sigma_base + j;
-            const int next_slot = (j + 1 == k) ? 0 : j + 1;
-            cont_step_ph<S, P, 0, -1>(phase_of<S::NPHASE>(g.b + sigma), A, B, An, Bn, cA, cB,
-                                      chain, lane, j, 0, next_slot, j - (NB - 1), true, nullptr,
-                                      nullptr, g.c);
-        }
+        for (int j0 = NB; j0 < k; j0 += U)
+            cont_body_group<S, P, 0, U>(j0, k, A, B, An, Bn, cA, cB, chain, lane, g.c);
     }
 
 #pragma unroll
