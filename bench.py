@@ -124,6 +124,58 @@ def cpu_baseline(u0_np, nsteps_full, seconds):
                       "%.1f s" % (n, k, nsteps_full, threads, dt)}
 
 
+KS_OPS_PER_STEP = 30  # per point-step: 4 sub-timesteps (4 + 11 + 4 + 11 flops, no FMA)
+
+
+def other_workloads(sw, torch, workloads):
+    """The other two single-GPU workloads: heat N=4096 (launch-latency bound
+    when stepped naively) and KS N=2^20 (four sub-timesteps per step)."""
+    out = {}
+    cases = [("heat_small", "heat", workloads.WORKLOADS["heat_small"], [0.25],
+              HEAT_OPS_PER_UPDATE, 16),
+             ("ks", "ks", workloads.WORKLOADS["ks"],
+              [workloads.KS_DT, workloads.KS_DX], KS_OPS_PER_STEP, 16)]
+    for name, st, w, par, ops, naive_bytes in cases:
+        u0 = torch.from_numpy(workloads.initial(name)).cuda()
+        n, nsteps = u0.numel(), w["nsteps"]
+        plan = sw.plan(n, nsteps, st)
+        rec = {"n": n, "time_steps": nsteps, "tile_w": plan["tile_w"],
+               "pairs_per_lane": plan["pairs_per_lane"], "stages": plan["stages"]}
+        for label, fn, reps in (("swept", sw.advance, 3), ("naive", sw.naive_advance, 1)):
+            u = u0.clone()
+            fn(u, nsteps, st, par)           # warm-up
+            ts = []
+            for _ in range(reps):
+                u.copy_(u0)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn(u, nsteps, st, par)
+                e1.record()
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1) / 1e3)
+            t = sum(ts) / len(ts)
+            rec[label] = n * nsteps / t
+            rec[label + "_ms"] = t * 1e3
+        rec["speedup_vs_naive"] = rec["swept"] / rec["naive"]
+        rec["swept_frac_alu"] = ops * rec["swept"] / VALU_LANE_OPS
+        rec["naive_GBps"] = naive_bytes * rec["naive"] / 1e9
+        if st == "ks":
+            u = u0.clone()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sw.naive_substep_advance(u, nsteps, st, par)
+            e1.record()
+            e1.synchronize()
+            t = e0.elapsed_time(e1) / 1e3
+            rec["naive_substep"] = n * nsteps / t
+            rec["speedup_vs_naive_substep"] = rec["swept"] / rec["naive_substep"]
+        sw.sync()
+        out[name] = rec
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -213,6 +265,9 @@ def main():
         out["f32"] = {"swept": s32, "naive": n32, "speedup_vs_naive": s32 / n32,
                       "swept_frac_alu": HEAT_OPS_PER_UPDATE * s32 / VALU_LANE_OPS_F32,
                       "naive_hbm_frac": n32 * HEAT_NAIVE_BYTES[4] / HBM_PEAK}
+
+    if not args.no_naive:
+        out["workloads"] = other_workloads(sw, torch, workloads)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(u0_np, nsteps, args.cpu_seconds)

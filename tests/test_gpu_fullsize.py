@@ -1,0 +1,74 @@
+"""Parity at the benchmark sizes, in the launch configuration bench.py times
+(automatic tuning): outputs the oracle can evaluate one at a time from their
+cone of dependence (paper, Section 2: after n sub-timesteps a point depends
+only on the points within n edges), plus whole-field bitwise agreement of the
+swept and the naive GPU schedules, whose own parity with the oracle the
+smaller tests establish."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from tests.conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def sw():
+    import paper_1504_01380_amd as swept
+    swept.init(0)
+    swept.set_tuning(0, 0, swept.MODE_AUTO)
+    return swept
+
+
+def gpu_run(sw, fn, u0, nsteps, stencil, params):
+    import torch
+    u = torch.from_numpy(np.ascontiguousarray(u0)).to("cuda")
+    fn(u, nsteps, stencil, params)
+    torch.cuda.synchronize()
+    sw.sync()
+    return u.cpu().numpy()
+
+
+def sample_indices(n, tile, seed):
+    g = workloads.rng(seed)
+    picks = [0, 1, tile - 1, tile, n // 2 + tile // 2, n - 1]
+    return np.array(sorted(set(picks + list(g.integers(0, n, size=2)))), dtype=np.int64)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_heat_large_full_size(sw, oracle_mod, dtype):
+    w = workloads.WORKLOADS["heat_large"]
+    n, nsteps = w["n"], w["nsteps"]
+    u0 = workloads.initial("heat_large", dtype=dtype)
+    plan = sw.plan(n, nsteps, "heat", None if dtype == np.float64 else __import__("torch").float32)
+    print("heat N=%d steps=%d %s plan=%s" % (n, nsteps, np.dtype(dtype).name, plan), flush=True)
+    swept = gpu_run(sw, sw.advance, u0, nsteps, "heat", [w["r"]])
+    idx = sample_indices(n, plan["tile_w"], 77)
+    want = oracle_mod.heat_points(u0, nsteps, w["r"], idx)
+    assert np.array_equal(swept[idx].view(np.uint8), want.view(np.uint8))
+    naive = gpu_run(sw, sw.naive_advance, u0, nsteps, "heat", [w["r"]])
+    assert np.array_equal(swept.view(np.uint8), naive.view(np.uint8))
+
+
+def test_ks_full_size(sw, oracle_mod):
+    w = workloads.WORKLOADS["ks"]
+    n, nsteps, par = w["n"], w["nsteps"], [w["dt"], w["dx"]]
+    u0 = workloads.initial("ks")
+    plan = sw.plan(n, nsteps, "ks")
+    print("ks N=%d steps=%d plan=%s" % (n, nsteps, plan), flush=True)
+    swept = gpu_run(sw, sw.advance, u0, nsteps, "ks", par)
+    naive = gpu_run(sw, sw.naive_advance, u0, nsteps, "ks", par)
+    assert np.array_equal(swept.view(np.uint8), naive.view(np.uint8))
+    assert np.all(np.isfinite(swept))
+    # the grid sum is conserved up to rounding (both D1 and D2 telescope)
+    assert abs(math.fsum(swept) - math.fsum(u0)) < 1e-6
+    # oracle, one output at a time, on a shorter horizon of the same run
+    short = 2000
+    got = gpu_run(sw, sw.advance, u0, short, "ks", par)
+    idx = sample_indices(n, plan["tile_w"], 78)
+    want = oracle_mod.ks_points(u0, short, *par, idx)
+    assert np.array_equal(got[idx].view(np.uint8), want.view(np.uint8))
