@@ -152,6 +152,32 @@ int swept_naive_substep_advance(void *u, int64_t nx, int64_t nsteps, int32_t ste
 int swept_set_profiling(int enable);
 int swept_stage_times(double *ms_out, int32_t *kind_out, int64_t cap, int64_t *count);
 
+/*
+ * Gradient by the swept discrete adjoint (SWEPT_HEAT_F64, SWEPT_KS_F64).
+ * For the objective
+ *
+ *   J(u0) = window_weight * sum_{j = window_first}^{nsteps} sum_i (u_i^j)^2
+ *           + sum_i cot_final[i] * u_i^nsteps
+ *
+ * where u^j is the field after j time steps of the stencil, writes dJ/du0 to
+ * grad_u0.  u0, grad_u0 and cot_final (NULL = 0) are DEVICE pointers to nx
+ * elements; window_first > nsteps leaves out the window term.  The
+ * derivative is that of the scheme's sub-timesteps in real arithmetic (each
+ * sub-timestep's transposed Jacobian, applied in reverse order), evaluated
+ * in a fixed order.
+ *
+ * A forward swept pass on a copy of u0 keeps the V edges of every stage (one
+ * checkpoint per sweep, 2*nx points per stage); the stages then run in
+ * reverse, each region recomputing its forward values from its checkpoint
+ * inside the workgroup.  Tiles: W = 2k, k <= 32, W divides nx (tile_w of
+ * swept_set_tuning, if set, caps k at tile_w/2).  Scratch grows to about
+ * 2*nx*(stages)*sizeof(point) bytes (KS: 24-byte points).  Asynchronous on
+ * the current stream, like swept_advance.
+ */
+int swept_adjoint(const void *u0, void *grad_u0, int64_t nx, int64_t nsteps, int32_t stencil_id,
+                  const double *params, int32_t nparams, int64_t window_first,
+                  double window_weight, const void *cot_final);
+
 /* Wait for the current stream; report asynchronous kernel errors. */
 int swept_sync(void);
 

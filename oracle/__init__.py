@@ -60,9 +60,12 @@ def lib() -> ctypes.CDLL:
         L.oracle_heat_f64_points.argtypes = [vp, i64, i64, dbl, vp, i64, vp]
         L.oracle_heat_f32_points.argtypes = [vp, i64, i64, flt, vp, i64, vp]
         L.oracle_ks_f64_points.argtypes = [vp, i64, i64, dbl, dbl, vp, i64, vp]
+        L.oracle_heat_f64_adjoint.argtypes = [vp, i64, i64, dbl, i64, dbl, vp, vp, i32]
+        L.oracle_ks_f64_adjoint.argtypes = [vp, i64, i64, dbl, dbl, i64, dbl, vp, vp, i32]
         for name in ("oracle_heat_f64", "oracle_heat_f32", "oracle_ks_f64",
                      "oracle_heat_f64_points", "oracle_heat_f32_points",
-                     "oracle_ks_f64_points", "oracle_max_threads"):
+                     "oracle_ks_f64_points", "oracle_max_threads", "oracle_heat_f64_adjoint",
+                     "oracle_ks_f64_adjoint"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -129,3 +132,34 @@ def ks_points(u0: np.ndarray, nsteps: int, dt: float, dx: float, idx) -> np.ndar
                                       float(dx), idx.ctypes.data, idx.size, out.ctypes.data),
            "oracle_ks_points")
     return out
+
+
+def _adjoint_args(u0, cot_final):
+    u0 = np.ascontiguousarray(u0, dtype=np.float64)
+    grad = np.empty_like(u0)
+    cot = None if cot_final is None else np.ascontiguousarray(cot_final, dtype=np.float64)
+    return u0, grad, cot
+
+
+def heat_adjoint(u0, nsteps, r, n0, wgt, cot_final=None, threads=0):
+    """dJ/du0 for J = wgt*sum_{j=n0}^{nsteps} |u^j|^2 + <cot_final, u^nsteps>, by
+    the discrete adjoint (transposed sub-timestep Jacobians in reverse order)."""
+    u0, grad, cot = _adjoint_args(u0, cot_final)
+    _check(lib().oracle_heat_f64_adjoint(u0.ctypes.data, u0.size, int(nsteps), float(r), int(n0),
+                                         float(wgt), None if cot is None else cot.ctypes.data,
+                                         grad.ctypes.data, int(threads)), "oracle_heat_f64_adjoint")
+    return grad
+
+
+def ks_adjoint(u0, nsteps, dt, dx, n0, wgt, cot_final=None, threads=0):
+    """dJ/du0 for the KS scheme, same objective as heat_adjoint."""
+    u0, grad, cot = _adjoint_args(u0, cot_final)
+    _check(lib().oracle_ks_f64_adjoint(u0.ctypes.data, u0.size, int(nsteps), float(dt), float(dx),
+                                       int(n0), float(wgt), None if cot is None else cot.ctypes.data,
+                                       grad.ctypes.data, int(threads)), "oracle_ks_f64_adjoint")
+    return grad
+
+
+def window_objective(u_steps, wgt):
+    """J from a list of fields (test helper)."""
+    return wgt * sum(float(np.dot(u, u)) for u in u_steps)

@@ -346,3 +346,215 @@ int oracle_ks_f64_points(const double *u0, int64_t n, int64_t nsteps, double dt,
     }
     return ORACLE_OK;
 }
+
+/* ------------------------------------------------------- discrete adjoints */
+/*
+ * Gradient of a scalar objective with respect to the initial field, by the
+ * discrete adjoint of the schemes above: the transpose of each sub-timestep's
+ * Jacobian, applied in reverse order (in real arithmetic; the operations are
+ * evaluated in the order written below).  Objective:
+ *
+ *   J(u0) = wgt * sum_{j = n0}^{nsteps} sum_i (u_i^j)^2  +  sum_i c_i u_i^nsteps
+ *
+ * where u^j is the field after j time steps and c = cot_final (NULL: 0).
+ * With d2(x)_i = ((x[i-1] + x[i+1]) - 2 x[i]) * c2 and a bar for cotangents:
+ *
+ *   heat (the step matrix is symmetric):  ub = ub' + r*((ub'[i-1] + ub'[i+1]) - 2 ub')
+ *
+ *   KS, reverse of sub3 (u' = u + dt*F(v,z)), g = dt*ub':
+ *     vb = (c1*((g[i+1]*v[i+1]) - (g[i-1]*v[i-1]))) - (g*((v[i+1] - v[i-1])*c1))
+ *     zb = -(g + d2(g))                       ub = ub'
+ *   reverse of sub2 (z = D2(v)):  vb = vb + d2(zb)
+ *   reverse of sub1 (v = u + h*F(u,w)), q = h*vb:
+ *     ub = (ub + vb) + ((c1*((q[i+1]*u[i+1]) - (q[i-1]*u[i-1]))) - (q*((u[i+1] - u[i-1])*c1)))
+ *     wb = -(q + d2(q))
+ *   reverse of sub0 (w = D2(u)):  ub = ub + d2(wb)
+ *
+ * u and v are the forward fields of the same step (u^{j-1} and the midpoint
+ * value).  After the cotangent of u^j is formed, for j >= n0:
+ * ub = ub + (2 wgt) * u^j.  The forward fields are recomputed block by block
+ * from stored copies of u every ADJ_BLOCK steps.
+ */
+#define ADJ_BLOCK 64
+
+static void add_source(double *ub, const double *u, int64_t n, double two_w)
+{
+    int64_t i;
+    for (i = 0; i < n; ++i)
+        ub[i] = ub[i] + two_w * u[i];
+}
+
+/* forward to the end, keeping u^j for j = 0, B, 2B, ... ; returns u^nsteps in fin */
+static int checkpoints(const double *u0, int64_t n, int64_t nsteps, int ks, double r,
+                       double dt, double dx, double **ck_out, double *fin)
+{
+    int64_t nb = nsteps / ADJ_BLOCK + 1, s;
+    double *ck = (double *)malloc((size_t)(nb * n) * sizeof(double));
+    double *cur = (double *)malloc((size_t)n * sizeof(double));
+    if (!ck || !cur) {
+        free(ck); free(cur);
+        return ORACLE_ENOMEM;
+    }
+    memcpy(cur, u0, (size_t)n * sizeof(double));
+    for (s = 0; s < nsteps; ++s) {
+        if (s % ADJ_BLOCK == 0)
+            memcpy(ck + (s / ADJ_BLOCK) * n, cur, (size_t)n * sizeof(double));
+        if (ks)
+            oracle_ks_f64(cur, n, 1, dt, dx, 0);
+        else
+            oracle_heat_f64(cur, n, 1, r, 0);
+    }
+    memcpy(fin, cur, (size_t)n * sizeof(double));
+    free(cur);
+    *ck_out = ck;
+    return ORACLE_OK;
+}
+
+int oracle_heat_f64_adjoint(const double *u0, int64_t n, int64_t nsteps, double r, int64_t n0,
+                            double wgt, const double *cot_final, double *grad, int nthreads)
+{
+    double *ck = NULL, *lev, *ub, *tmp, *fin;
+    const double two_w = 2.0 * wgt;
+    int64_t s, i;
+    int rc;
+    if (!u0 || !grad || n < 3 || nsteps < 0)
+        return ORACLE_EINVAL;
+    set_threads(nthreads);
+    lev = (double *)malloc((size_t)((ADJ_BLOCK + 1) * n) * sizeof(double));
+    ub = (double *)malloc((size_t)n * sizeof(double));
+    tmp = (double *)malloc((size_t)n * sizeof(double));
+    fin = (double *)malloc((size_t)n * sizeof(double));
+    if (!lev || !ub || !tmp || !fin) {
+        free(lev); free(ub); free(tmp); free(fin);
+        return ORACLE_ENOMEM;
+    }
+    rc = checkpoints(u0, n, nsteps, 0, r, 0.0, 1.0, &ck, fin);
+    if (rc) {
+        free(lev); free(ub); free(tmp); free(fin);
+        return rc;
+    }
+    for (i = 0; i < n; ++i)
+        ub[i] = cot_final ? cot_final[i] : 0.0;
+    if (nsteps >= n0)
+        add_source(ub, fin, n, two_w);
+    for (s = nsteps; s > 0;) {
+        const int64_t bs = ((s - 1) / ADJ_BLOCK) * ADJ_BLOCK;
+        int64_t j;
+        memcpy(lev, ck + (bs / ADJ_BLOCK) * n, (size_t)n * sizeof(double));
+        for (j = bs; j < s; ++j)           /* lev[j - bs] = u^j */
+            heat_step_f64(lev + (j - bs) * n, lev + (j - bs + 1) * n, n, r);
+        for (j = s; j > bs; --j) {         /* ub: cotangent of u^j -> of u^{j-1} */
+#pragma omp parallel for schedule(static)
+            for (i = 0; i < n; ++i) {
+                double l = ub[wrap(i - 1, n)], m = ub[i], rr = ub[wrap(i + 1, n)];
+                tmp[i] = m + r * ((l + rr) - 2.0 * m);
+            }
+            memcpy(ub, tmp, (size_t)n * sizeof(double));
+            if (j - 1 >= n0)
+                add_source(ub, lev + (j - 1 - bs) * n, n, two_w);
+        }
+        s = bs;
+    }
+    memcpy(grad, ub, (size_t)n * sizeof(double));
+    free(ck); free(lev); free(ub); free(tmp); free(fin);
+    return ORACLE_OK;
+}
+
+int oracle_ks_f64_adjoint(const double *u0, int64_t n, int64_t nsteps, double dt, double dx,
+                          int64_t n0, double wgt, const double *cot_final, double *grad,
+                          int nthreads)
+{
+    ks_consts k;
+    double *ck = NULL, *U, *V, *ub, *vb, *zb, *wb, *tmp, *fin, *w, *z;
+    const double two_w = 2.0 * wgt;
+    int64_t s, i;
+    int rc;
+    if (!u0 || !grad || n < 3 || nsteps < 0 || !(dx > 0.0))
+        return ORACLE_EINVAL;
+    set_threads(nthreads);
+    k = ks_make(dt, dx);
+    U = (double *)malloc((size_t)((ADJ_BLOCK + 1) * n) * sizeof(double));  /* u^j */
+    V = (double *)malloc((size_t)(ADJ_BLOCK * n) * sizeof(double));        /* midpoint v */
+    ub = (double *)malloc((size_t)n * sizeof(double));
+    vb = (double *)malloc((size_t)n * sizeof(double));
+    zb = (double *)malloc((size_t)n * sizeof(double));
+    wb = (double *)malloc((size_t)n * sizeof(double));
+    tmp = (double *)malloc((size_t)n * sizeof(double));
+    fin = (double *)malloc((size_t)n * sizeof(double));
+    w = (double *)malloc((size_t)n * sizeof(double));
+    z = (double *)malloc((size_t)n * sizeof(double));
+    if (!U || !V || !ub || !vb || !zb || !wb || !tmp || !fin || !w || !z) {
+        free(U); free(V); free(ub); free(vb); free(zb); free(wb); free(tmp); free(fin);
+        free(w); free(z);
+        return ORACLE_ENOMEM;
+    }
+    rc = checkpoints(u0, n, nsteps, 1, 0.0, dt, dx, &ck, fin);
+    if (rc) {
+        free(U); free(V); free(ub); free(vb); free(zb); free(wb); free(tmp); free(fin);
+        free(w); free(z);
+        return rc;
+    }
+    for (i = 0; i < n; ++i)
+        ub[i] = cot_final ? cot_final[i] : 0.0;
+    if (nsteps >= n0)
+        add_source(ub, fin, n, two_w);
+    for (s = nsteps; s > 0;) {
+        const int64_t bs = ((s - 1) / ADJ_BLOCK) * ADJ_BLOCK;
+        int64_t j;
+        memcpy(U, ck + (bs / ADJ_BLOCK) * n, (size_t)n * sizeof(double));
+        for (j = bs; j < s; ++j) {         /* one RK2 step, keeping u^j and v */
+            const double *u = U + (j - bs) * n;
+            double *v = V + (j - bs) * n, *un = U + (j - bs + 1) * n;
+            for (i = 0; i < n; ++i)
+                w[i] = ks_d2(u[wrap(i - 1, n)], u[i], u[wrap(i + 1, n)], &k);
+            for (i = 0; i < n; ++i) {
+                int64_t l = wrap(i - 1, n), r = wrap(i + 1, n);
+                v[i] = u[i] + k.h * ks_rhs(u[l], u[i], u[r], w[l], w[i], w[r], &k);
+            }
+            for (i = 0; i < n; ++i)
+                z[i] = ks_d2(v[wrap(i - 1, n)], v[i], v[wrap(i + 1, n)], &k);
+            for (i = 0; i < n; ++i) {
+                int64_t l = wrap(i - 1, n), r = wrap(i + 1, n);
+                un[i] = u[i] + k.dt * ks_rhs(v[l], v[i], v[r], z[l], z[i], z[r], &k);
+            }
+        }
+        for (j = s; j > bs; --j) {         /* ub: cotangent of u^j -> of u^{j-1} */
+            const double *u = U + (j - 1 - bs) * n, *v = V + (j - 1 - bs) * n;
+            /* reverse of sub3: g = dt*ub */
+#pragma omp parallel for schedule(static)
+            for (i = 0; i < n; ++i) {
+                int64_t l = wrap(i - 1, n), r = wrap(i + 1, n);
+                double gl = k.dt * ub[l], gm = k.dt * ub[i], gr = k.dt * ub[r];
+                vb[i] = (k.c1 * ((gr * v[r]) - (gl * v[l]))) - (gm * ((v[r] - v[l]) * k.c1));
+                zb[i] = -(gm + ks_d2(gl, gm, gr, &k));
+            }
+            /* reverse of sub2 */
+#pragma omp parallel for schedule(static)
+            for (i = 0; i < n; ++i)
+                tmp[i] = vb[i] + ks_d2(zb[wrap(i - 1, n)], zb[i], zb[wrap(i + 1, n)], &k);
+            memcpy(vb, tmp, (size_t)n * sizeof(double));
+            /* reverse of sub1: q = h*vb */
+#pragma omp parallel for schedule(static)
+            for (i = 0; i < n; ++i) {
+                int64_t l = wrap(i - 1, n), r = wrap(i + 1, n);
+                double ql = k.h * vb[l], qm = k.h * vb[i], qr = k.h * vb[r];
+                tmp[i] = (ub[i] + vb[i]) +
+                         ((k.c1 * ((qr * u[r]) - (ql * u[l]))) - (qm * ((u[r] - u[l]) * k.c1)));
+                wb[i] = -(qm + ks_d2(ql, qm, qr, &k));
+            }
+            memcpy(ub, tmp, (size_t)n * sizeof(double));
+            /* reverse of sub0 */
+#pragma omp parallel for schedule(static)
+            for (i = 0; i < n; ++i)
+                tmp[i] = ub[i] + ks_d2(wb[wrap(i - 1, n)], wb[i], wb[wrap(i + 1, n)], &k);
+            memcpy(ub, tmp, (size_t)n * sizeof(double));
+            if (j - 1 >= n0)
+                add_source(ub, U + (j - 1 - bs) * n, n, two_w);
+        }
+        s = bs;
+    }
+    memcpy(grad, ub, (size_t)n * sizeof(double));
+    free(ck); free(U); free(V); free(ub); free(vb); free(zb); free(wb); free(tmp); free(fin);
+    free(w); free(z);
+    return ORACLE_OK;
+}

@@ -28,7 +28,7 @@ _STATUS = {0: "SWEPT_OK", -1: "SWEPT_EINVAL", -2: "SWEPT_ENOTINIT", -3: "SWEPT_E
 
 EXPORTS = ("swept_init", "swept_set_stream", "swept_set_tuning", "swept_plan",
            "swept_advance", "swept_naive_advance", "swept_naive_substep_advance",
-           "swept_set_profiling", "swept_stage_times",
+           "swept_set_profiling", "swept_stage_times", "swept_adjoint",
            "swept_sync", "swept_last_error", "swept_finalize")
 
 
@@ -52,6 +52,7 @@ def _load() -> ctypes.CDLL:
     L.swept_plan.argtypes = [i64, i64, i32, ctypes.POINTER(i64)]
     for f in (L.swept_advance, L.swept_naive_advance, L.swept_naive_substep_advance):
         f.argtypes = [vp, i64, i64, i32, dp, i32]
+    L.swept_adjoint.argtypes = [vp, vp, i64, i64, i32, dp, i32, i64, ctypes.c_double, vp]
     L.swept_set_profiling.argtypes = [ctypes.c_int]
     L.swept_stage_times.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), i64,
                                     ctypes.POINTER(i64)]
@@ -182,6 +183,80 @@ def stage_times():
     kind = (ctypes.c_int32 * max(1, n))()
     _check(_lib.swept_stage_times(ms, kind, n, ctypes.byref(count)), "swept_stage_times")
     return [float(ms[i]) for i in range(n)], [int(kind[i]) for i in range(n)]
+
+
+def adjoint(u0: torch.Tensor, nsteps: int, stencil, params: Sequence[float], *,
+            window_first: int | None = None, window_weight: float = 0.0,
+            cot_final: torch.Tensor | None = None) -> torch.Tensor:
+    """dJ/du0 by the swept discrete adjoint, for
+    J = window_weight * sum_{j=window_first}^{nsteps} |u^j|^2 + <cot_final, u^nsteps>."""
+    sid = stencil_id(stencil, u0.dtype)
+    _prepare(u0, sid)
+    grad = torch.empty_like(u0)
+    cot = None
+    if cot_final is not None:
+        cot = cot_final.contiguous()
+        if cot.shape != u0.shape or cot.dtype != u0.dtype or cot.device != u0.device:
+            raise ValueError("cot_final must match u0")
+    first = nsteps + 1 if window_first is None else int(window_first)
+    p, npar = _params(params)
+    _check(_lib.swept_adjoint(ctypes.c_void_p(u0.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                              u0.numel(), int(nsteps), sid, p, npar, first, float(window_weight),
+                              None if cot is None else ctypes.c_void_p(cot.data_ptr())),
+           "swept_adjoint")
+    return grad
+
+
+class SweptAdvance(torch.autograd.Function):
+    """u = advance(u0, nsteps); backward by the swept adjoint."""
+
+    @staticmethod
+    def forward(ctx, u0, nsteps, stencil, params):
+        u = u0.detach().clone()
+        advance(u, nsteps, stencil, params)
+        ctx.save_for_backward(u0.detach())
+        ctx.args = (nsteps, stencil, tuple(params))
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (u0,) = ctx.saved_tensors
+        nsteps, stencil, params = ctx.args
+        g = adjoint(u0, nsteps, stencil, params, cot_final=grad_out.contiguous())
+        return g, None, None, None
+
+
+def window_mean_square_value(u0: torch.Tensor, nsteps: int, stencil, params, window: int):
+    """J = mean of u^2 over all points and the last `window` time steps
+    (steps nsteps-window+1 .. nsteps), computed by stepping the field."""
+    u = u0.detach().clone()
+    first = nsteps - window + 1
+    if first > 1:
+        advance(u, first - 1, stencil, params)
+    total = torch.zeros((), dtype=torch.float64, device=u.device)
+    for _ in range(window):
+        naive_advance(u, 1, stencil, params)
+        total += torch.dot(u.double(), u.double())
+    return total / (window * u.numel())
+
+
+class WindowMeanSquare(torch.autograd.Function):
+    """J(u0) = mean of u^2 over the final `window` steps; gradient by the
+    swept adjoint with one checkpoint per sweep."""
+
+    @staticmethod
+    def forward(ctx, u0, nsteps, stencil, params, window):
+        ctx.save_for_backward(u0.detach())
+        ctx.args = (nsteps, stencil, tuple(params), window)
+        return window_mean_square_value(u0, nsteps, stencil, params, window)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (u0,) = ctx.saved_tensors
+        nsteps, stencil, params, window = ctx.args
+        g = adjoint(u0, nsteps, stencil, params, window_first=nsteps - window + 1,
+                    window_weight=1.0 / (window * u0.numel()))
+        return g * grad_out, None, None, None, None
 
 
 def sync() -> None:

@@ -43,7 +43,8 @@ template <class S>
 struct StageArgs {
     using Pt = typename S::Pt;
     typename S::T* u;        // the field, n points
-    Pt* re;                  // [tiles][k][2]: kept right edge, own region only
+    const Pt* re;            // [tiles][k][2]: kept right edge of stage s-1, own region only
+    Pt* re_out;              // [tiles][k][2]: kept right edge of this stage (may equal re)
     const Pt* le_in;         // [tiles][k][2]: left edges written by stage s-1
     Pt* le_out;              // [tiles][k][2]: left edges of this stage
     int64_t n;               // grid points
@@ -122,7 +123,8 @@ __global__ __launch_bounds__(64) void swept_stage_kernel(StageArgs<S> g)
     }
     __syncthreads();
 
-    Pt* re = g.re + (size_t)t * k * 2;
+    const Pt* re = g.re + (size_t)t * k * 2;
+    Pt* re_out = g.re_out + (size_t)t * k * 2;
     const int64_t top = g.L - g.b;  // highest relative level of this stage that is <= L
 
     for (int base = 0; base < k; base += 64 * P) {
@@ -219,8 +221,8 @@ __global__ __launch_bounds__(64) void swept_stage_kernel(StageArgs<S> g)
         for (int q = 0; q < P; ++q) {
             const int d = base + elane + q;
             if (elane + q < nvalid) {
-                re[2 * d] = B[q];
-                re[2 * d + 1] = A[q];
+                re_out[2 * d] = B[q];
+                re_out[2 * d + 1] = A[q];
             }
         }
     }
@@ -310,7 +312,8 @@ __device__ __forceinline__ void cont_head_group(int j0, int k, int nb, int cyc,
                                                 typename S::Pt (&An)[P],
                                                 typename S::Pt (&Bn)[P], typename S::Pt& cA,
                                                 typename S::Pt& cB, typename S::Pt* chain,
-                                                typename S::Pt* re, int lane,
+                                                const typename S::Pt* re,
+                                                typename S::Pt* re_out, int lane,
                                                 const typename S::Consts& c)
 {
     if constexpr (I < G) {
@@ -327,14 +330,14 @@ __device__ __forceinline__ void cont_head_group(int j0, int k, int nb, int cyc,
         typename S::Pt* re_store = nullptr;
         const typename S::Pt* re_load = nullptr;
         if constexpr (TRANS) {
-            re_store = re + 2 * ((cyc - 1) * NB + j);
+            re_store = re_out + 2 * ((cyc - 1) * NB + j);
             if (cyc + 1 < nb)
                 re_load = re + 2 * ((cyc + 1) * NB + j);
         }
         cont_step<S, P, PH, MASK, TRANS ? QS : -1>(A, B, An, Bn, cA, cB, chain, lane, j, rs,
                                                    next_slot, wslot, wlast, re_store, re_load, c);
         cont_head_group<S, P, MASK, TRANS, I + 1, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB, chain,
-                                                     re, lane, c);
+                                                     re, re_out, lane, c);
     }
 }
 
@@ -379,7 +382,8 @@ __global__ __launch_bounds__(64) void swept_diamond_cont_kernel(StageArgs<S> g)
     }
     __syncthreads();
 
-    Pt* re = g.re + (size_t)t * k * 2;
+    const Pt* re = g.re + (size_t)t * k * 2;
+    Pt* re_out = g.re_out + (size_t)t * k * 2;
     Pt A[P], B[P], An[P], Bn[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) {
@@ -400,16 +404,16 @@ __global__ __launch_bounds__(64) void swept_diamond_cont_kernel(StageArgs<S> g)
         if (cyc == 0) {
             for (int j0 = 0; j0 < NB; j0 += G)
                 cont_head_group<S, P, 1, false, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
-                                                      chain, re, lane, g.c);
+                                                      chain, re, re_out, lane, g.c);
         } else if (cyc == nb) {
             for (int j0 = 0; j0 < NB; j0 += G)
                 cont_head_group<S, P, 2, false, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
-                                                      chain, re, lane, g.c);
+                                                      chain, re, re_out, lane, g.c);
             break;
         } else {
             for (int j0 = 0; j0 < NB; j0 += G)
                 cont_head_group<S, P, 0, true, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
-                                                     chain, re, lane, g.c);
+                                                     chain, re, re_out, lane, g.c);
         }
         for (int j0 = NB; j0 < k; j0 += U)
             cont_body_group<S, P, 0, U>(j0, k, A, B, An, Bn, cA, cB, chain, lane, g.c);
@@ -418,13 +422,211 @@ __global__ __launch_bounds__(64) void swept_diamond_cont_kernel(StageArgs<S> g)
 #pragma unroll
     for (int q = 0; q < P; ++q) {
         const int e = lane * P + q;
-        re[2 * ((nb - 1) * NB + e)] = B[q];
-        re[2 * ((nb - 1) * NB + e) + 1] = A[q];
+        re_out[2 * ((nb - 1) * NB + e)] = B[q];
+        re_out[2 * ((nb - 1) * NB + e) + 1] = A[q];
     }
     __syncthreads();
     Pt* dst = g.le_out + (size_t)t * k * 2;
     for (int i = lane; i < 2 * k; i += 64)
         dst[i] = chain[i];
+}
+
+// ------------------------------------------------------------ swept adjoint
+// The stages in reverse order, on the same regions as the forward pass
+// (stage s, region t: centre J, base b, tile width 2k; relative level j spans
+// [J-j, J+j-1] for j <= k and [J-2k+j, J+2k-1-j] above; stage 0 is the
+// triangle, whose relative level k is level 0).  A region
+//   1. recomputes its forward values from its checkpoint -- the V kept by the
+//      forward pass for that stage (or u0 for the triangle);
+//   2. takes from the later regions above it (stage s+1: centred at J-k and
+//      J+k) the cotangents of their two outermost points and the forward
+//      value of their outermost point, at each level of their lower half;
+//   3. forms the cotangent of each of its points from the top level down,
+//      each from the three cotangents of the level above and the forward
+//      values of its level (seeded at the target level L, plus the objective
+//      source at step levels in the window);
+//   4. hands the same kind of data to the earlier regions below it, or, for
+//      the triangle, writes the gradient with respect to u0.
+// One wavefront per region, one lane per point of a level (2k <= 64); both
+// the forward and the cotangent values of the region live in LDS.
+
+template <class S>
+struct AdjArgs {
+    using Pt = typename S::Pt;
+    using Ad = typename S::Ad;
+    const typename S::T* u0;   // initial field (triangle)
+    typename S::T* grad;       // d J / d u0 (triangle)
+    const typename S::T* cot;  // cotangent of the final field, or null
+    const Pt* re_in;           // checkpoint: right edges of stage s-1 (own region)
+    const Pt* le_in;           // checkpoint: left edges of stage s-1
+    const Ad* ae_in;           // from stage s+1: [tiles][2 sides][k][2] cotangents
+    const Pt* fh_in;           // from stage s+1: [tiles][2 sides][k] forward values
+    Ad* ae_out;                // to stage s-1
+    Pt* fh_out;
+    int64_t n, L, b, J0;
+    int64_t win_first;         // first time step of the objective window
+    typename S::T two_w;       // 2 * objective weight
+    int k, tiles, tri, has_later;
+    typename S::Consts c;
+};
+
+template <class S, int PH>
+__device__ __forceinline__ typename S::Ad adj_at(const typename S::Ad* ar,
+                                                 const typename S::Pt* fr, int col,
+                                                 const typename S::Consts& c)
+{
+    return S::template adj<PH>(ar[col - 1], ar[col], ar[col + 1], fr[col - 1], fr[col],
+                               fr[col + 1], c);
+}
+
+template <class S>
+__global__ __launch_bounds__(64) void swept_adjoint_kernel(AdjArgs<S> g)
+{
+    using Pt = typename S::Pt;
+    using Ad = typename S::Ad;
+    using T = typename S::T;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int k = g.k;
+    const int C = 2 * k + 4;              // columns: dx = col - (k + 2), dx in [-k-2, k+1]
+    const int R = 2 * k + 1;              // rows: relative levels 0..2k
+    Pt* F = reinterpret_cast<Pt*>(smem_raw);
+    Ad* A = reinterpret_cast<Ad*>(smem_raw + sizeof(Pt) * (size_t)R * C);
+    const int lane = threadIdx.x;
+    const int t = blockIdx.x;
+    const int64_t n = g.n;
+    const int64_t J = wrapn((int64_t)t * (2 * (int64_t)k) + g.J0, n);
+    const int off = k + 2;
+    const int64_t jtop = min((int64_t)(2 * k - 1), g.L - g.b);
+
+    auto lo_of = [&](int j) { return j <= k ? -j : j - 2 * k; };
+    auto hi_of = [&](int j) { return j <= k ? j - 1 : 2 * k - 1 - j; };
+
+    // 1. checkpoint and forward recompute
+    int j0;
+    if (g.tri) {
+        j0 = k;
+        for (int dx = -k + lane; dx < k; dx += 64)
+            F[k * C + dx + off] = S::from_field(g.u0[J + dx]);
+    } else {
+        j0 = 0;
+        const Pt* re = g.re_in + (size_t)t * k * 2;
+        const int tn = (t + 1 == g.tiles) ? 0 : t + 1;
+        const Pt* le = g.le_in + (size_t)tn * k * 2;
+        for (int i = lane; i < k; i += 64) {
+            F[i * C + (-i - 2) + off] = re[2 * i];
+            F[i * C + (-i - 1) + off] = re[2 * i + 1];
+            F[i * C + i + off] = le[2 * i];
+            F[i * C + i + 1 + off] = le[2 * i + 1];
+        }
+    }
+    __syncthreads();
+    for (int j = j0 + 1; j <= (int)jtop; ++j) {
+        const int dx = lo_of(j) + lane;
+        if (dx <= hi_of(j)) {
+            const Pt* pr = F + (j - 1) * C + off;
+            Pt o;
+            switch (phase_of<S::NPHASE>(g.b + j - 1)) {
+            case 0: o = S::template step<0>(pr[dx - 1], pr[dx], pr[dx + 1], g.c); break;
+            case 1: o = S::template step<S::NPHASE == 4 ? 1 : 0>(pr[dx - 1], pr[dx], pr[dx + 1], g.c); break;
+            case 2: o = S::template step<S::NPHASE == 4 ? 2 : 0>(pr[dx - 1], pr[dx], pr[dx + 1], g.c); break;
+            default: o = S::template step<S::NPHASE == 4 ? 3 : 0>(pr[dx - 1], pr[dx], pr[dx + 1], g.c); break;
+            }
+            F[j * C + dx + off] = o;
+        }
+        __syncthreads();
+    }
+
+    // 2. data from the later regions (their relative level jj = our jj + k)
+    if (g.has_later) {
+        const int tl = (t == 0) ? g.tiles - 1 : t - 1;
+        const Ad* aeR = g.ae_in + ((size_t)tl * 2 + 1) * k * 2;   // upper-left region, right side
+        const Ad* aeL = g.ae_in + ((size_t)t * 2 + 0) * k * 2;    // upper-right region, left side
+        const Pt* fhR = g.fh_in + ((size_t)tl * 2 + 1) * k;
+        const Pt* fhL = g.fh_in + ((size_t)t * 2 + 0) * k;
+        for (int jj = lane; jj < k; jj += 64) {    // forward halo at their levels 0..k-1
+            if (jj + k <= (int)jtop) {
+                F[(jj + k) * C + (-k + jj - 1) + off] = fhR[jj];
+                F[(jj + k) * C + (k - jj) + off] = fhL[jj];
+            }
+        }
+        for (int jj = 1 + lane; jj <= k; jj += 64) {  // cotangents at their levels 1..k
+            if (jj + k <= (int)jtop + 1) {
+                A[(jj + k) * C + (-k + jj - 2) + off] = aeR[2 * (jj - 1)];
+                A[(jj + k) * C + (-k + jj - 1) + off] = aeR[2 * (jj - 1) + 1];
+                A[(jj + k) * C + (k - jj) + off] = aeL[2 * (jj - 1)];
+                A[(jj + k) * C + (k - jj + 1) + off] = aeL[2 * (jj - 1) + 1];
+            }
+        }
+    }
+    __syncthreads();
+
+    // 3. cotangents from the top level down
+    const int jbot = g.tri ? k : 1;
+    const int nph = S::NPHASE;
+    for (int j = (int)jtop; j >= jbot; --j) {
+        const int dx = lo_of(j) + lane;
+        const int64_t lev = g.b + j;
+        if (dx <= hi_of(j)) {
+            const int col = dx + off;
+            const Pt fc = F[j * C + col];
+            Ad a;
+            if (lev == g.L) {
+                const int64_t x = wrapn(J + dx, n);
+                a = S::seed(g.cot ? g.cot[x] : T(0), g.two_w, fc, lev / nph >= g.win_first);
+            } else {
+                const Ad* ar = A + (j + 1) * C;
+                const Pt* fr = F + j * C;
+                switch (phase_of<S::NPHASE>(lev)) {
+                case 0: a = adj_at<S, 0>(ar, fr, col, g.c); break;
+                case 1: a = adj_at<S, S::NPHASE == 4 ? 1 : 0>(ar, fr, col, g.c); break;
+                case 2: a = adj_at<S, S::NPHASE == 4 ? 2 : 0>(ar, fr, col, g.c); break;
+                default: a = adj_at<S, S::NPHASE == 4 ? 3 : 0>(ar, fr, col, g.c); break;
+                }
+                if (phase_of<S::NPHASE>(lev) == 0 && lev / nph >= g.win_first)
+                    a = S::source(a, fc, g.two_w);
+            }
+            A[j * C + col] = a;
+        }
+        __syncthreads();
+    }
+
+    // 4. hand down, or write the gradient
+    if (g.tri) {
+        for (int dx = -k + lane; dx < k; dx += 64)
+            g.grad[J + dx] = S::grad(A[k * C + dx + off]);
+    } else {
+        Ad* aeL = g.ae_out + ((size_t)t * 2 + 0) * k * 2;
+        Ad* aeR = g.ae_out + ((size_t)t * 2 + 1) * k * 2;
+        Pt* fhL = g.fh_out + ((size_t)t * 2 + 0) * k;
+        Pt* fhR = g.fh_out + ((size_t)t * 2 + 1) * k;
+        for (int j = 1 + lane; j <= k; j += 64) {
+            if (j <= (int)jtop) {
+                aeL[2 * (j - 1)] = A[j * C + (-j) + off];
+                aeL[2 * (j - 1) + 1] = A[j * C + (-j + 1) + off];
+                aeR[2 * (j - 1)] = A[j * C + (j - 2) + off];
+                aeR[2 * (j - 1) + 1] = A[j * C + (j - 1) + off];
+            }
+        }
+        for (int j = lane; j < k; j += 64) {
+            if (j <= (int)jtop) {
+                fhL[j] = F[j * C + (-j) + off];
+                fhR[j] = F[j * C + (j - 1) + off];
+            }
+        }
+    }
+}
+
+// Zero time steps: the gradient is the seed at level 0.
+template <class S>
+__global__ __launch_bounds__(256) void adjoint_seed_kernel(const typename S::T* __restrict__ u0,
+                                                          const typename S::T* __restrict__ cot,
+                                                          typename S::T* __restrict__ grad,
+                                                          int64_t n, typename S::T two_w, int src)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        grad[i] = S::grad(S::seed(cot ? cot[i] : typename S::T(0), two_w, S::from_field(u0[i]),
+                                  src != 0));
 }
 
 // ------------------------------------------------------------- naive paths

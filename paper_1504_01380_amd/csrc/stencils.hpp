@@ -69,6 +69,30 @@ struct Heat {
         const T lap = (l.u + r.u) - T(2) * c.u;
         return Pt{c.u + k.r * lap};
     }
+
+    // Discrete adjoint.  The heat step matrix is symmetric, so the cotangent
+    // of a level is the same 3-point update applied to the cotangents of the
+    // level above it.
+    struct Ad {
+        T u;
+    };
+    template <int PH>
+    __device__ __forceinline__ static Ad adj(const Ad& l, const Ad& c, const Ad& r, const Pt&,
+                                             const Pt&, const Pt&, const Consts& k)
+    {
+        const T lap = (l.u + r.u) - T(2) * c.u;
+        return Ad{c.u + k.r * lap};
+    }
+    // cotangent at the target level: cot (+ 2w u when that level is in the window)
+    __device__ __forceinline__ static Ad seed(T cot, T two_w, const Pt& f, bool src)
+    {
+        return Ad{src ? cot + two_w * f.u : cot};
+    }
+    __device__ __forceinline__ static Ad source(const Ad& a, const Pt& f, T two_w)
+    {
+        return Ad{a.u + two_w * f.u};
+    }
+    __device__ __forceinline__ static T grad(const Ad& a) { return a.u; }
 };
 
 using HeatF64 = Heat<double>;
@@ -120,6 +144,50 @@ struct KSF64 {
             return Pt{un, un, c.b};
         }
     }
+
+    // Discrete adjoint: the transposed Jacobian of each sub-timestep, in the
+    // pull form (the cotangent of a point from the cotangents of the three
+    // points of the level above that read it).  A cotangent carries
+    // (ub, xb, yb): the cotangents of (u, w) after sub0, (u, v) after sub1,
+    // (u, v, z) after sub2.  PH is the sub-timestep that leaves the level.
+    struct Ad {
+        double u, x, y;
+    };
+    __device__ __forceinline__ static double d2(double l, double m, double r, const Consts& k)
+    {
+        return ((l + r) - 2.0 * m) * k.c2;
+    }
+    template <int PH>
+    __device__ __forceinline__ static Ad adj(const Ad& al, const Ad& ac, const Ad& ar,
+                                             const Pt& fl, const Pt&, const Pt& fr,
+                                             const Consts& k)
+    {
+        if constexpr (PH == 3) {        // reverse of u' = u + dt*F(v, z), g = dt*ub'
+            const double gl = k.dt * al.u, gm = k.dt * ac.u, gr = k.dt * ar.u;
+            const double vb = (k.c1 * ((gr * fr.a) - (gl * fl.a))) - (gm * ((fr.a - fl.a) * k.c1));
+            const double zb = -(gm + d2(gl, gm, gr, k));
+            return Ad{ac.u, vb, zb};
+        } else if constexpr (PH == 2) { // reverse of z = D2(v)
+            return Ad{ac.u, ac.x + d2(al.y, ac.y, ar.y, k), 0.0};
+        } else if constexpr (PH == 1) { // reverse of v = u + h*F(u, w), q = h*vb
+            const double ql = k.h * al.x, qm = k.h * ac.x, qr = k.h * ar.x;
+            const double ub = (ac.u + ac.x) +
+                              ((k.c1 * ((qr * fr.u) - (ql * fl.u))) - (qm * ((fr.u - fl.u) * k.c1)));
+            const double wb = -(qm + d2(ql, qm, qr, k));
+            return Ad{ub, wb, 0.0};
+        } else {                        // reverse of w = D2(u)
+            return Ad{ac.u + d2(al.x, ac.x, ar.x, k), 0.0, 0.0};
+        }
+    }
+    __device__ __forceinline__ static Ad seed(double cot, double two_w, const Pt& f, bool src)
+    {
+        return Ad{src ? cot + two_w * f.u : cot, 0.0, 0.0};
+    }
+    __device__ __forceinline__ static Ad source(const Ad& a, const Pt& f, double two_w)
+    {
+        return Ad{a.u + two_w * f.u, a.x, a.y};
+    }
+    __device__ __forceinline__ static double grad(const Ad& a) { return a.u; }
 };
 
 }  // namespace swept

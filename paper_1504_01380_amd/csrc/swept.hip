@@ -245,6 +245,7 @@ int run_swept(void* u, int64_t nx, int64_t L, const typename S::Consts& c, const
     StageArgs<S> a{};
     a.u = static_cast<typename S::T*>(u);
     a.re = re;
+    a.re_out = re;
     a.n = nx;
     a.L = L;
     a.k = (int)p.k;
@@ -281,13 +282,128 @@ int run_swept(void* u, int64_t nx, int64_t L, const typename S::Consts& c, const
     return SWEPT_OK;
 }
 
-// ------------------------------------------------------------- naive launch
-
 unsigned grid_for(int64_t n, int block)
 {
     const int64_t b = (n + block - 1) / block;
     return (unsigned)std::min<int64_t>(b, 1 << 20);
 }
+
+// ----------------------------------------------------------- swept adjoint
+
+// Tile for the adjoint: one lane per point of a level (2k <= 64) and the
+// region's forward and cotangent values in 64 KB of LDS.
+template <class S>
+size_t adjoint_lds(int64_t k)
+{
+    return (size_t)(2 * k + 1) * (size_t)(2 * k + 4) *
+           (sizeof(typename S::Pt) + sizeof(typename S::Ad));
+}
+
+template <class S>
+int64_t adjoint_depth(int64_t nx, int64_t want)
+{
+    for (int64_t k = std::min<int64_t>(32, want > 0 ? want : 32); k >= 1; --k)
+        if (nx % (2 * k) == 0 && adjoint_lds<S>(k) <= kMaxLds)
+            return k;
+    return 0;
+}
+
+template <class S>
+int run_adjoint(const void* u0v, void* gradv, int64_t nx, int64_t nsteps, const double* params,
+                const typename S::Consts& c, int64_t win_first, double wgt, const void* cotv)
+{
+    using Pt = typename S::Pt;
+    using Ad = typename S::Ad;
+    using T = typename S::T;
+    const T* u0 = static_cast<const T*>(u0v);
+    T* grad = static_cast<T*>(gradv);
+    const T* cot = static_cast<const T*>(cotv);
+    const T two_w = (T)(2.0 * wgt);
+    const int64_t L = nsteps * S::NPHASE;
+    if (L == 0) {
+        hipLaunchKernelGGL((adjoint_seed_kernel<S>), dim3(grid_for(nx, 256)), dim3(256), 0,
+                           g_ctx.stream, u0, cot, grad, nx, two_w, win_first <= 0 ? 1 : 0);
+        HIP_TRY(hipGetLastError());
+        return SWEPT_OK;
+    }
+    const int64_t k = adjoint_depth<S>(nx, g_ctx.tile_w > 0 ? g_ctx.tile_w / 2 : 0);
+    if (k == 0)
+        return fail(SWEPT_EUNSUPPORTED, "nx = %lld has no even tile width for the adjoint",
+                    (long long)nx);
+    const int64_t tiles = nx / (2 * k);
+    const int64_t stages = 1 + (L + k - 1) / k;
+    // checkpoints: right and left edges of every stage; cotangent hand-over buffers
+    const size_t ck = (size_t)stages * nx * sizeof(Pt);
+    const size_t ae = 2 * (size_t)nx * sizeof(Ad);        // tiles * 2 sides * k * 2
+    const size_t fh = (size_t)nx * sizeof(Pt);            // tiles * 2 sides * k
+    const size_t uf = ((size_t)nx * sizeof(T) + 255) / 256 * 256;
+    int rc = ensure_scratch(2 * ck + 2 * ae + 2 * fh + uf);
+    if (rc)
+        return rc;
+    unsigned char* base = static_cast<unsigned char*>(g_ctx.scratch);
+    Pt* ck_re = reinterpret_cast<Pt*>(base);
+    Pt* ck_le = reinterpret_cast<Pt*>(base + ck);
+    Ad* aeb[2] = {reinterpret_cast<Ad*>(base + 2 * ck), reinterpret_cast<Ad*>(base + 2 * ck + ae)};
+    Pt* fhb[2] = {reinterpret_cast<Pt*>(base + 2 * ck + 2 * ae),
+                  reinterpret_cast<Pt*>(base + 2 * ck + 2 * ae + fh)};
+
+    // forward pass on a copy of u0, keeping the edges of every stage
+    T* ufwd = reinterpret_cast<T*>(base + 2 * ck + 2 * ae + 2 * fh);
+    HIP_TRY(hipMemcpyAsync(ufwd, u0, nx * sizeof(T), hipMemcpyDeviceToDevice, g_ctx.stream));
+    StageArgs<S> a{};
+    a.u = ufwd;
+    a.n = nx;
+    a.L = L;
+    a.k = (int)k;
+    a.tiles = (int)tiles;
+    a.c = c;
+    const size_t lds_fwd = (size_t)2 * k * sizeof(Pt);
+    for (int64_t s = 0; s < stages; ++s) {
+        a.tri = s == 0;
+        a.b = (s - 1) * k;
+        a.J0 = (k + s * k) % nx;
+        a.re = s > 0 ? ck_re + (s - 1) * nx : ck_re;
+        a.re_out = ck_re + s * nx;
+        a.le_in = s > 0 ? ck_le + (s - 1) * nx : ck_le;
+        a.le_out = ck_le + s * nx;
+        hipLaunchKernelGGL((swept_stage_kernel<S, 1>), dim3(tiles), dim3(64), lds_fwd,
+                           g_ctx.stream, a);
+    }
+    HIP_TRY(hipGetLastError());
+
+    // reverse pass
+    AdjArgs<S> g{};
+    g.u0 = u0;
+    g.grad = grad;
+    g.cot = cot;
+    g.n = nx;
+    g.L = L;
+    g.win_first = win_first;
+    g.two_w = two_w;
+    g.k = (int)k;
+    g.tiles = (int)tiles;
+    g.c = c;
+    const size_t lds_adj = adjoint_lds<S>(k);
+    for (int64_t s = stages - 1; s >= 0; --s) {
+        g.tri = s == 0;
+        g.b = (s - 1) * k;
+        g.J0 = (k + s * k) % nx;
+        g.re_in = s > 0 ? ck_re + (s - 1) * nx : ck_re;
+        g.le_in = s > 0 ? ck_le + (s - 1) * nx : ck_le;
+        g.has_later = s + 1 < stages;
+        g.ae_in = aeb[(s + 1) & 1];
+        g.fh_in = fhb[(s + 1) & 1];
+        g.ae_out = aeb[s & 1];
+        g.fh_out = fhb[s & 1];
+        hipLaunchKernelGGL((swept_adjoint_kernel<S>), dim3(tiles), dim3(64), lds_adj,
+                           g_ctx.stream, g);
+    }
+    HIP_TRY(hipGetLastError());
+    (void)params;
+    return SWEPT_OK;
+}
+
+// ------------------------------------------------------------- naive launch
 
 template <class S>
 int run_naive_single(void* u, int64_t nx, int64_t nsteps, const typename S::Consts& c)
@@ -513,6 +629,29 @@ int swept_stage_times(double* ms_out, int32_t* kind_out, int64_t cap, int64_t* c
     if (count)
         *count = n;
     return SWEPT_OK;
+}
+
+int swept_adjoint(const void* u0, void* grad_u0, int64_t nx, int64_t nsteps, int32_t stencil_id,
+                  const double* params, int32_t nparams, int64_t window_first,
+                  double window_weight, const void* cot_final)
+{
+    int rc = check_common(u0, nx, nsteps, stencil_id, params, nparams);
+    if (rc)
+        return rc;
+    if (!grad_u0)
+        return fail(SWEPT_EINVAL, "grad_u0 is NULL");
+    if (!std::isfinite(window_weight))
+        return fail(SWEPT_EINVAL, "window weight is not finite");
+    switch (stencil_id) {
+    case SWEPT_HEAT_F64:
+        return run_adjoint<HeatF64>(u0, grad_u0, nx, nsteps, params, heat64_consts(params),
+                                    window_first, window_weight, cot_final);
+    case SWEPT_KS_F64:
+        return run_adjoint<KSF64>(u0, grad_u0, nx, nsteps, params, ks_consts(params), window_first,
+                                  window_weight, cot_final);
+    default:
+        return fail(SWEPT_EUNSUPPORTED, "the adjoint exists for the binary64 stencils only");
+    }
 }
 
 int swept_sync(void)

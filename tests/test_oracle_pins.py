@@ -283,3 +283,76 @@ def test_ks_literal_domain_blows_up(oracle_mod):
     u0 = workloads.smoothed_noise(64, seed=1)
     out = oracle_mod.ks(u0, 5, 0.005, dx)
     assert not np.all(np.isfinite(out))
+
+
+# ------------------------------------------------------------ discrete adjoint
+
+def _window_J(step_fn, u0, nsteps, n0, wgt, cot=None):
+    u = u0.copy()
+    total = wgt * float(np.dot(u, u)) if n0 <= 0 else 0.0
+    for j in range(1, nsteps + 1):
+        u = step_fn(u)
+        if j >= n0:
+            total += wgt * float(np.dot(u, u))
+    if cot is not None:
+        total += float(np.dot(cot, u))
+    return total
+
+
+@pytest.mark.parametrize("stencil", ["heat", "ks"])
+def test_adjoint_matches_finite_differences(oracle_mod, stencil):
+    """<dJ/du0, v> equals the central difference of J along v, computed with
+    the (separately pinned) forward oracle only."""
+    n, nsteps, n0 = 64, 60, 45
+    wgt = 1.0 / (16 * n)
+    if stencil == "heat":
+        u0 = workloads.white_noise(n, seed=31)
+        step = lambda u: oracle_mod.heat(u, 1, 0.3)
+        g = oracle_mod.heat_adjoint(u0, nsteps, 0.3, n0, wgt)
+    else:
+        u0 = 3 * workloads.smoothed_noise(n, seed=32)
+        step = lambda u: oracle_mod.ks(u, 1, 0.005, 0.5)
+        g = oracle_mod.ks_adjoint(u0, nsteps, 0.005, 0.5, n0, wgt)
+    rng = workloads.rng(33)
+    for _ in range(4):
+        v = rng.standard_normal(n)
+        v /= np.linalg.norm(v)
+        eps = 1e-5
+        fd = (_window_J(step, u0 + eps * v, nsteps, n0, wgt) -
+              _window_J(step, u0 - eps * v, nsteps, n0, wgt)) / (2 * eps)
+        assert abs(fd - np.dot(g, v)) <= 1e-7 * abs(fd) + 1e-13
+
+
+def test_heat_adjoint_closed_form(oracle_mod):
+    """For the heat scheme A is symmetric, so dJ/du0 = 2w sum_j A^{2j} u0 +
+    A^n c; in Fourier space every mode m is scaled by g_m = 1 - 4r sin^2(pi m/N)."""
+    n, nsteps, n0, r = 128, 200, 150, 0.25
+    wgt = 1.0 / n
+    u0 = workloads.white_noise(n, seed=34)
+    c = workloads.white_noise(n, seed=35)
+    got = oracle_mod.heat_adjoint(u0, nsteps, r, n0, wgt, c)
+    m = np.arange(n)
+    gm = 1.0 - 4.0 * r * np.sin(np.pi * m / n) ** 2
+    scale = sum(2 * wgt * gm ** (2 * j) for j in range(n0, nsteps + 1))
+    want = np.real(np.fft.ifft(np.fft.fft(u0) * scale + np.fft.fft(c) * gm ** nsteps))
+    assert np.abs(got - want).max() <= 1e-12 * max(1.0, np.abs(want).max())
+
+
+def test_heat_adjoint_is_the_forward_step(oracle_mod):
+    """Self-adjointness: with no window term the adjoint of n heat steps
+    applied to c is n forward steps of c, bit for bit."""
+    n, nsteps = 77, 41
+    c = workloads.white_noise(n, seed=36)
+    got = oracle_mod.heat_adjoint(workloads.white_noise(n, seed=37), nsteps, 0.3, nsteps + 1, 0.0, c)
+    assert np.array_equal(got, oracle_mod.heat(c, nsteps, 0.3))
+
+
+def test_ks_adjoint_linear_regime(oracle_mod):
+    """Around u0 = 0 the KS step is linear and symmetric (R(dt L) with
+    L = -D2 - D2 D2), so the adjoint of a cosine mode is R(dt lam)^n times it."""
+    n, nsteps, m = 64, 100, 5
+    j = np.arange(n)
+    c = np.cos(2 * np.pi * m * j / n)
+    got = oracle_mod.ks_adjoint(np.zeros(n), nsteps, 0.005, 0.5, nsteps + 1, 0.0, c)
+    z = 0.005 * ks_symbol(m, n, 0.5)
+    assert np.abs(got - (1 + z + z * z / 2) ** nsteps * c).max() < 1e-12

@@ -92,3 +92,26 @@ def test_continuous_schedule(oracle_mod, lanes, P, k, nsteps, stencil):
     ok, why = swept_sim.levels_complete(visits, n, L, k)
     assert ok, why
     assert np.array_equal(np.array(got), want)
+
+
+@pytest.mark.parametrize("stencil,n,k,nsteps,n0,cot", [
+    ("heat", 16, 4, 3, 0, True), ("heat", 32, 8, 33, 20, False), ("heat", 8, 4, 13, 3, True),
+    ("heat", 12, 1, 9, 2, True), ("ks", 16, 4, 5, 2, True), ("ks", 32, 4, 9, 6, False),
+    ("ks", 24, 6, 7, 1, True), ("ks", 16, 2, 5, 5, True),
+])
+def test_adjoint_schedule(oracle_mod, stencil, n, k, nsteps, n0, cot):
+    """The swept adjoint schedule (reverse stages, per-region recompute from
+    one checkpoint per stage, boundary hand-over) gives the oracle's discrete
+    adjoint bit for bit."""
+    from tests import swept_adj_sim
+    w = 1.0 / (7 * n)
+    c = workloads.white_noise(n, seed=99) if cot else None
+    if stencil == "heat":
+        u0 = workloads.white_noise(n, seed=n + k)
+        loc, want = swept_adj_sim.heat_local(0.3), oracle_mod.heat_adjoint(u0, nsteps, 0.3, n0, w, c)
+    else:
+        u0 = 3 * workloads.smoothed_noise(n, seed=n + k)
+        loc = swept_adj_sim.ks_local(0.005, 0.5)
+        want = oracle_mod.ks_adjoint(u0, nsteps, 0.005, 0.5, n0, w, c)
+    got = swept_adj_sim.adjoint(list(u0), nsteps, k, loc, n0, w, None if c is None else list(c))
+    assert np.array_equal(np.array(got), want)
