@@ -176,6 +176,49 @@ def other_workloads(sw, torch, workloads):
     return out
 
 
+def ks_adjoint_workload(sw, torch, workloads, directions=16, eps=1e-6):
+    """Gradient of J = mean of u^2 over the final 2,000 of 20,000 KS steps
+    (N = 2^16) by the swept adjoint, timed, and checked against central
+    finite differences of J along seeded random unit directions (eps and a
+    Richardson extrapolation from eps and eps/2)."""
+    w = workloads.WORKLOADS["ks_adjoint"]
+    n, nsteps, par, window = w["n"], w["nsteps"], [w["dt"], w["dx"]], 2000
+    u0 = torch.from_numpy(workloads.initial("ks_adjoint")).cuda()
+    wgt = 1.0 / (window * n)
+    first = nsteps - window + 1
+    sw.adjoint(u0, nsteps, "ks", par, window_first=first, window_weight=wgt)   # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g = sw.adjoint(u0, nsteps, "ks", par, window_first=first, window_weight=wgt)
+    e1.record()
+    e1.synchronize()
+    t_adj = e0.elapsed_time(e1) / 1e3
+    rng = workloads.rng(w["seed"] + 100)
+
+    def J(u):
+        return float(sw.window_mean_square_value(u, nsteps, "ks", par, window))
+
+    errs, errs_rich = [], []
+    for _ in range(directions):
+        v = torch.from_numpy(rng.standard_normal(n)).cuda()
+        v /= torch.linalg.norm(v)
+        d1 = (J(u0 + eps * v) - J(u0 - eps * v)) / (2 * eps)
+        d2 = (J(u0 + 0.5 * eps * v) - J(u0 - 0.5 * eps * v)) / eps
+        ad = float(torch.dot(g, v))
+        errs.append(abs(d1 - ad) / abs(ad))
+        errs_rich.append(abs((4 * d2 - d1) / 3 - ad) / abs(ad))
+    sw.sync()
+    errs.sort()
+    errs_rich.sort()
+    return {"n": n, "time_steps": nsteps, "window": window, "adjoint_ms": t_adj * 1e3,
+            "gradient_point_steps_per_s": n * nsteps / t_adj,
+            "fd_eps": eps, "fd_directions": directions,
+            "fd_rel_err_max": errs[-1], "fd_rel_err_median": errs[len(errs) // 2],
+            "fd_richardson_rel_err_max": errs_rich[-1],
+            "fd_within_1e-6": sum(e <= 1e-6 for e in errs)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -268,6 +311,7 @@ def main():
 
     if not args.no_naive:
         out["workloads"] = other_workloads(sw, torch, workloads)
+        out["workloads"]["ks_adjoint"] = ks_adjoint_workload(sw, torch, workloads)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(u0_np, nsteps, args.cpu_seconds)

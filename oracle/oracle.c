@@ -505,14 +505,18 @@ int oracle_ks_f64_adjoint(const double *u0, int64_t n, int64_t nsteps, double dt
         for (j = bs; j < s; ++j) {         /* one RK2 step, keeping u^j and v */
             const double *u = U + (j - bs) * n;
             double *v = V + (j - bs) * n, *un = U + (j - bs + 1) * n;
+#pragma omp parallel for schedule(static)
             for (i = 0; i < n; ++i)
                 w[i] = ks_d2(u[wrap(i - 1, n)], u[i], u[wrap(i + 1, n)], &k);
+#pragma omp parallel for schedule(static)
             for (i = 0; i < n; ++i) {
                 int64_t l = wrap(i - 1, n), r = wrap(i + 1, n);
                 v[i] = u[i] + k.h * ks_rhs(u[l], u[i], u[r], w[l], w[i], w[r], &k);
             }
+#pragma omp parallel for schedule(static)
             for (i = 0; i < n; ++i)
                 z[i] = ks_d2(v[wrap(i - 1, n)], v[i], v[wrap(i + 1, n)], &k);
+#pragma omp parallel for schedule(static)
             for (i = 0; i < n; ++i) {
                 int64_t l = wrap(i - 1, n), r = wrap(i + 1, n);
                 un[i] = u[i] + k.dt * ks_rhs(v[l], v[i], v[r], z[l], z[i], z[r], &k);

@@ -72,3 +72,39 @@ def test_ks_full_size(sw, oracle_mod):
     idx = sample_indices(n, plan["tile_w"], 78)
     want = oracle_mod.ks_points(u0, short, *par, idx)
     assert np.array_equal(got[idx].view(np.uint8), want.view(np.uint8))
+
+
+def test_ks_adjoint_full_grid(sw, oracle_mod):
+    """The KS adjoint workload's grid (N = 2^16) on a shorter horizon: the
+    swept adjoint equals the oracle's discrete adjoint bit for bit."""
+    import torch
+    w = workloads.WORKLOADS["ks_adjoint"]
+    n, par = w["n"], [w["dt"], w["dx"]]
+    nsteps, window = 600, 100
+    u0 = workloads.initial("ks_adjoint")
+    wgt = 1.0 / (window * n)
+    first = nsteps - window + 1
+    print("ks adjoint N=%d steps=%d" % (n, nsteps), flush=True)
+    g = sw.adjoint(torch.from_numpy(u0).cuda(), nsteps, "ks", par, window_first=first,
+                   window_weight=wgt)
+    torch.cuda.synchronize()
+    want = oracle_mod.ks_adjoint(u0, nsteps, *par, first, wgt)
+    assert np.array_equal(g.cpu().numpy().view(np.uint8), want.view(np.uint8))
+
+
+def test_ks_adjoint_workload_matches_oracle(sw, oracle_mod):
+    """The full adjoint workload: N = 2^16, 20,000 KS steps, J = mean of u^2
+    over the final 2,000 steps.  The swept adjoint's gradient equals the
+    oracle's discrete adjoint bit for bit."""
+    import torch
+    w = workloads.WORKLOADS["ks_adjoint"]
+    n, nsteps, par, window = w["n"], w["nsteps"], [w["dt"], w["dx"]], 2000
+    u0 = workloads.initial("ks_adjoint")
+    wgt = 1.0 / (window * n)
+    first = nsteps - window + 1
+    print("ks adjoint N=%d steps=%d window=%d" % (n, nsteps, window), flush=True)
+    g = sw.adjoint(torch.from_numpy(u0).cuda(), nsteps, "ks", par, window_first=first,
+                   window_weight=wgt)
+    torch.cuda.synchronize()
+    want = oracle_mod.ks_adjoint(u0, nsteps, *par, first, wgt)
+    assert np.array_equal(g.cpu().numpy().view(np.uint8), want.view(np.uint8))
