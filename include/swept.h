@@ -139,6 +139,25 @@ int swept_naive_substep_advance(void *u, int64_t nx, int64_t nsteps, int32_t ste
                                 const double *params, int32_t nparams);
 
 /*
+ * Advance count independent instances at once (binary64 stencils only:
+ * SWEPT_HEAT_F64, SWEPT_KS_F64).  u[j] (a HOST array of DEVICE pointers) is
+ * instance j's field of nx[j] points, advanced in place by nsteps[j] steps of
+ * stencil_id[j] with parameters params[2j], params[2j+1] (heat reads the
+ * first).  Every instance gets exactly the bits its own swept_advance would.
+ *
+ * Each instance is tiled by even widths 2k_t, k_t in {k, k+1} (k = 256, or
+ * tile_w/2 of swept_set_tuning), so any even length tiles without
+ * remainder; the regions of unequal neighbouring tiles are rectangles of
+ * k_t pairs by k_{t+1} steps.  An odd length runs on its two-fold cover
+ * (the field repeated twice, which the scheme keeps repeated).  All tiles of
+ * all instances advance one stage per kernel launch; the launches of a
+ * batch are captured into one HIP graph, which is reused when the same
+ * batch (same sizes, steps, parameters and pointers) is advanced again.
+ */
+int swept_advance_batch(void *const *u, const int64_t *nx, const int64_t *nsteps,
+                        const int32_t *stencil_id, const double *params, int64_t count);
+
+/*
  * Per-stage timing.  With profiling enabled, swept_advance records a HIP
  * event on the current stream before its first and after every stage
  * launch.  swept_stage_times waits for those events and returns, for the

@@ -28,7 +28,7 @@ _STATUS = {0: "SWEPT_OK", -1: "SWEPT_EINVAL", -2: "SWEPT_ENOTINIT", -3: "SWEPT_E
 
 EXPORTS = ("swept_init", "swept_set_stream", "swept_set_tuning", "swept_plan",
            "swept_advance", "swept_naive_advance", "swept_naive_substep_advance",
-           "swept_set_profiling", "swept_stage_times", "swept_adjoint",
+           "swept_set_profiling", "swept_stage_times", "swept_adjoint", "swept_advance_batch",
            "swept_sync", "swept_last_error", "swept_finalize")
 
 
@@ -53,6 +53,8 @@ def _load() -> ctypes.CDLL:
     for f in (L.swept_advance, L.swept_naive_advance, L.swept_naive_substep_advance):
         f.argtypes = [vp, i64, i64, i32, dp, i32]
     L.swept_adjoint.argtypes = [vp, vp, i64, i64, i32, dp, i32, i64, ctypes.c_double, vp]
+    L.swept_advance_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                      ctypes.POINTER(i32), dp, i64]
     L.swept_set_profiling.argtypes = [ctypes.c_int]
     L.swept_stage_times.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), i64,
                                     ctypes.POINTER(i64)]
@@ -167,6 +169,35 @@ def naive_substep_advance(u: torch.Tensor, nsteps: int, stencil, params: Sequenc
     _check(_lib.swept_naive_substep_advance(ctypes.c_void_p(u.data_ptr()), u.numel(), int(nsteps),
                                             sid, p, npar), "swept_naive_substep_advance")
     return u
+
+
+def advance_batch(us: Sequence[torch.Tensor], nsteps: Sequence[int], stencils,
+                  params: Sequence[Sequence[float]]) -> None:
+    """Advance independent float64 fields in place, instance j by nsteps[j]
+    steps of stencils[j] ("heat" or "ks") with params[j], in one batched
+    swept run (one HIP graph)."""
+    count = len(us)
+    if not (len(nsteps) == len(stencils) == len(params) == count):
+        raise ValueError("batch arrays differ in length")
+    if count == 0:
+        return
+    for u in us:
+        if u.dtype != torch.float64:
+            raise TypeError("the batch takes float64 fields")
+    _prepare(us[0], HEAT_F64)
+    for u in us:
+        if not u.is_cuda or not u.is_contiguous() or u.dim() != 1 or u.device != us[0].device:
+            raise ValueError("batch fields must be contiguous 1-D tensors on one device")
+    ptrs = (ctypes.c_void_p * count)(*[u.data_ptr() for u in us])
+    nx = (ctypes.c_int64 * count)(*[u.numel() for u in us])
+    ns = (ctypes.c_int64 * count)(*[int(n) for n in nsteps])
+    ids = (ctypes.c_int32 * count)(*[stencil_id(st, torch.float64) for st in stencils])
+    flat = []
+    for p in params:
+        p = list(p)
+        flat += (p + [0.0, 0.0])[:2]
+    par = (ctypes.c_double * (2 * count))(*flat)
+    _check(_lib.swept_advance_batch(ptrs, nx, ns, ids, par, count), "swept_advance_batch")
 
 
 def set_profiling(enable: bool) -> None:

@@ -99,41 +99,43 @@ __device__ __forceinline__ void band_update(typename S::Pt (&A)[P], typename S::
     }
 }
 
+// One region on the banded schedule.  The region is kp pairs by ks steps
+// (kp = ks for equal tiles; tiles of unequal width make it rectangular):
+// pair d at step m holds A at x = J+m-d and B at x-1, level b+m+d+1.  Inputs:
+// re[2d], re[2d+1] = (B, A) of pair d at step -1 (the left V edge) and
+// le_in[2m], le_in[2m+1] = pair -1 at step m (the right V edge); for the
+// triangle (tri) the pairs start from level 0 of u instead.  Outputs: the
+// final state of every pair (re_out, the new right edge) and the last
+// pair's state at every step (le_out, the new left edge); points that reach
+// level L are written to u.  chain is 2*ks points of LDS.
 template <class S, int P>
-__global__ __launch_bounds__(64) void swept_stage_kernel(StageArgs<S> g)
+__device__ __forceinline__ void banded_region(typename S::T* u, const typename S::Pt* re,
+                                              typename S::Pt* re_out,
+                                              const typename S::Pt* le_in,
+                                              typename S::Pt* le_out, typename S::Pt* chain,
+                                              int64_t n, int64_t L, int64_t b, int64_t J, int kp,
+                                              int ks, bool tri, const typename S::Consts& cst)
 {
     using Pt = typename S::Pt;
     using T = typename S::T;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    Pt* chain = reinterpret_cast<Pt*>(smem_raw);  // [k][2] = (B, A) per step
-
     const int lane = threadIdx.x;
-    const int t = blockIdx.x;
-    const int k = g.k;
-    const int64_t n = g.n;
-    const int64_t J = wrapn((int64_t)t * (2 * (int64_t)k) + g.J0, n);
-    T* u = g.u;
 
-    // right V edge of this diamond = left edge of region t+1 from stage s-1
-    if (!g.tri) {
-        const int tn = (t + 1 == g.tiles) ? 0 : t + 1;
-        const Pt* src = g.le_in + (size_t)tn * k * 2;
-        for (int i = lane; i < 2 * k; i += 64)
-            chain[i] = src[i];
+    // right V edge of this region = left edge of the next tile's region of the previous stage
+    if (!tri) {
+        for (int i = lane; i < 2 * ks; i += 64)
+            chain[i] = le_in[i];
     }
     __syncthreads();
 
-    const Pt* re = g.re + (size_t)t * k * 2;
-    Pt* re_out = g.re_out + (size_t)t * k * 2;
-    const int64_t top = g.L - g.b;  // highest relative level of this stage that is <= L
+    const int64_t top = L - b;  // highest relative level of this stage that is <= L
 
-    for (int base = 0; base < k; base += 64 * P) {
-        const int nvalid = min(64 * P, k - base);
+    for (int base = 0; base < kp; base += 64 * P) {
+        const int nvalid = min(64 * P, kp - base);
         const int elane = lane * P;
-        const int tau_first = g.tri ? (k - base) : 0;
+        const int tau_first = tri ? (ks - base) : 0;
         const int64_t tau_cap = top - base - 1;  // wave step at which the band reaches level L
-        const int64_t tau_end = min((int64_t)(nvalid + k - 2), tau_cap);
-        if (tau_end < tau_first && !g.tri)
+        const int64_t tau_end = min((int64_t)(nvalid + ks - 2), tau_cap);
+        if (tau_end < tau_first && !tri)
             continue;  // the whole band lies above level L (a triangle band
                        // with no step still hands on its level-0 edges)
 
@@ -142,11 +144,11 @@ __global__ __launch_bounds__(64) void swept_stage_kernel(StageArgs<S> g)
         for (int q = 0; q < P; ++q) {
             const int d = base + elane + q;
             if (elane + q < nvalid) {
-                if (g.tri) {  // level 0 of the tile: pair d starts at step k-1-d
-                    const int64_t xa = J + k - 1 - 2 * (int64_t)d;
+                if (tri) {    // level 0 of the tile: pair d starts at step ks-1-d
+                    const int64_t xa = J + ks - 1 - 2 * (int64_t)d;
                     A[q] = S::from_field(u[xa]);
                     B[q] = S::from_field(u[xa - 1]);
-                } else {      // left V edge at relative level d (own right edge of stage s-1)
+                } else {      // left V edge at relative level d
                     B[q] = re[2 * d];
                     A[q] = re[2 * d + 1];
                 }
@@ -158,34 +160,34 @@ __global__ __launch_bounds__(64) void swept_stage_kernel(StageArgs<S> g)
 
         const int eL = nvalid - 1;       // last valid pair of the band
         const int rL = eL / P, qL = eL - rL * P;
-        if (g.tri && lane == rL) {       // its level-0 state is part of the new left edge
+        if (tri && lane == rL) {         // its level-0 state is part of the new left edge
 #pragma unroll
             for (int q = 0; q < P; ++q)
                 if (q == qL) {
-                    const int m = k - 1 - (base + eL);
+                    const int m = ks - 1 - (base + eL);
                     chain[2 * m] = B[q];
                     chain[2 * m + 1] = A[q];
                 }
         }
 
-        int slot = min(tau_first, k - 1);
+        int slot = min(tau_first, ks - 1);
         Pt cA = chain[2 * slot + 1], cB = chain[2 * slot];
         for (int tau = tau_first; tau <= (int)tau_end; ++tau) {
             const Pt inA = S::shr1(A[P - 1], cA);
             const Pt inB = S::shr1(B[P - 1], cB);
-            slot = min(tau + 1, k - 1);  // prefetch pair -1 for the next step
+            slot = min(tau + 1, ks - 1);  // prefetch pair -1 for the next step
             const Pt nA = chain[2 * slot + 1], nB = chain[2 * slot];
 
             const int mlane = tau - elane;
-            const int ph = phase_of<S::NPHASE>(g.b + base + tau);
+            const int ph = phase_of<S::NPHASE>(b + base + tau);
             if constexpr (S::NPHASE == 1) {
-                band_update<S, P, 0>(A, B, inA, inB, mlane, elane, nvalid, k, g.c);
+                band_update<S, P, 0>(A, B, inA, inB, mlane, elane, nvalid, ks, cst);
             } else {
                 switch (ph) {
-                case 0: band_update<S, P, 0>(A, B, inA, inB, mlane, elane, nvalid, k, g.c); break;
-                case 1: band_update<S, P, 1>(A, B, inA, inB, mlane, elane, nvalid, k, g.c); break;
-                case 2: band_update<S, P, 2>(A, B, inA, inB, mlane, elane, nvalid, k, g.c); break;
-                default: band_update<S, P, 3>(A, B, inA, inB, mlane, elane, nvalid, k, g.c); break;
+                case 0: band_update<S, P, 0>(A, B, inA, inB, mlane, elane, nvalid, ks, cst); break;
+                case 1: band_update<S, P, 1>(A, B, inA, inB, mlane, elane, nvalid, ks, cst); break;
+                case 2: band_update<S, P, 2>(A, B, inA, inB, mlane, elane, nvalid, ks, cst); break;
+                default: band_update<S, P, 3>(A, B, inA, inB, mlane, elane, nvalid, ks, cst); break;
                 }
             }
 
@@ -193,7 +195,7 @@ __global__ __launch_bounds__(64) void swept_stage_kernel(StageArgs<S> g)
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
                     const int m = mlane - q;
-                    if ((unsigned)m < (unsigned)k && elane + q < nvalid) {
+                    if ((unsigned)m < (unsigned)ks && elane + q < nvalid) {
                         const int d = base + elane + q;
                         const int64_t xa = wrapn(J + m - d, n);
                         u[xa] = S::to_field(A[q]);
@@ -206,7 +208,7 @@ __global__ __launch_bounds__(64) void swept_stage_kernel(StageArgs<S> g)
                 for (int q = 0; q < P; ++q)
                     if (q == qL) {
                         const int m = tau - eL;
-                        if ((unsigned)m < (unsigned)k) {
+                        if ((unsigned)m < (unsigned)ks) {
                             chain[2 * m] = B[q];
                             chain[2 * m + 1] = A[q];
                         }
@@ -228,9 +230,97 @@ __global__ __launch_bounds__(64) void swept_stage_kernel(StageArgs<S> g)
     }
 
     __syncthreads();
-    Pt* dst = g.le_out + (size_t)t * k * 2;
-    for (int i = lane; i < 2 * k; i += 64)
-        dst[i] = chain[i];
+    for (int i = lane; i < 2 * ks; i += 64)
+        le_out[i] = chain[i];
+}
+
+// Equal tiles: workgroup t, stage s; the region is k x k, centred at
+// J = tW + k + s*k (the tiles drift right by k per stage).
+template <class S, int P>
+__global__ __launch_bounds__(64) void swept_stage_kernel(StageArgs<S> g)
+{
+    using Pt = typename S::Pt;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int t = blockIdx.x;
+    const int k = g.k;
+    const int tn = (t + 1 == g.tiles) ? 0 : t + 1;
+    const int64_t J = wrapn((int64_t)t * (2 * (int64_t)k) + g.J0, g.n);
+    banded_region<S, P>(g.u, g.re + (size_t)t * k * 2, g.re_out + (size_t)t * k * 2,
+                        g.le_in + (size_t)tn * k * 2, g.le_out + (size_t)t * k * 2,
+                        reinterpret_cast<Pt*>(smem_raw), g.n, g.L, g.b, J, k, k, g.tri != 0, g.c);
+}
+
+// ------------------------------------------------------------------ batch
+// Many independent periodic instances, each tiled by even widths 2k_t that
+// need not be equal (k_t in {k, k+1} tiles any even length).  Workgroup t of
+// an instance keeps k_t pairs; at stage s its region is k_t pairs by
+// k_{t+s} steps, centred at J = (X_{t+s} + X_{t+1})/2 with base level
+// b = (X_{t+s} - X_{t+1})/2, where X_t = 2 sum_{t'<t} k_t' is extended
+// periodically (X_{t+T} = X_t + n).  Stage 0 is each tile's triangle; every
+// later region lies above level 0.  Right edges of tile t live at offset
+// X_t of the instance's edge buffer, left edges at offset X_{(t+s) mod T}.
+
+template <class S>
+struct BatchInst {
+    typename S::T* u;    // the instance's field (n points; the two-fold cover for odd rings)
+    int64_t n, L;        // ring length, target level
+    int64_t x_off;       // offset of X_0..X_T in the tile-boundary array
+    int64_t e_off;       // offset of the instance's edges in the edge buffers (n points)
+    int tiles;
+    int pad;
+    typename S::Consts c;
+};
+
+struct BatchTask {
+    int inst, tile;
+};
+
+template <class S>
+struct BatchArgs {
+    const BatchInst<S>* inst;
+    const BatchTask* tasks;     // this stage's tasks are tasks[0 .. gridDim.x)
+    const int64_t* X;           // tile boundaries, per instance X_0 = 0 .. X_T = n
+    typename S::Pt* re;         // right edges, all instances
+    typename S::Pt* le[2];      // left edges, by stage parity
+    int stage;
+};
+
+template <class S, int P>
+__global__ __launch_bounds__(64) void swept_batch_kernel(BatchArgs<S> g)
+{
+    using Pt = typename S::Pt;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const BatchTask task = g.tasks[blockIdx.x];
+    const BatchInst<S> I = g.inst[task.inst];
+    const int s = g.stage;
+    const int t = task.tile;
+    const int64_t* X = g.X + I.x_off;
+    const int T = I.tiles;
+    auto Xp = [&](int64_t i) { return X[i % T] + (i / T) * I.n; };
+    const int64_t xs = Xp((int64_t)t + s), x1 = Xp((int64_t)t + 1);
+    const int64_t b = (xs - x1) / 2;
+    if (s > 0 && b >= I.L)
+        return;                  // this tile's regions are all above the target level
+    const int kp = (int)((X[t + 1] - X[t]) / 2);
+    const int i = (int)(((int64_t)t + s) % T);
+    const int ks = (int)((X[i + 1] - X[i]) / 2);
+    const int64_t J = ((xs + x1) / 2) % I.n;
+    Pt* re = g.re + I.e_off + X[t];
+    banded_region<S, P>(I.u, re, re, g.le[(s + 1) & 1] + I.e_off + X[i],
+                        g.le[s & 1] + I.e_off + X[i], reinterpret_cast<Pt*>(smem_raw), I.n, I.L,
+                        b, J, kp, ks, s == 0, I.c);
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void batch_cover_kernel(const typename S::T* __restrict__ src,
+                                                         typename S::T* __restrict__ dst,
+                                                         int64_t n, int copies)
+{
+    // dst[i] = src[i mod n] for i < copies * n
+    const int64_t total = (int64_t)copies * n;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride)
+        dst[i] = src[i % n];
 }
 
 // ------------------------------------------------- continuous diamond stage

@@ -60,12 +60,15 @@ int hip_fail(hipError_t e, const char* what)
         if (e_ != hipSuccess) return hip_fail(e_, #expr);    \
     } while (0)
 
+void batch_release();
+
 int ensure_scratch(size_t bytes)
 {
     if (bytes <= g_ctx.scratch_bytes)
         return SWEPT_OK;
     if (g_ctx.scratch) {
         HIP_TRY(hipStreamSynchronize(g_ctx.stream));
+        batch_release();
         HIP_TRY(hipFree(g_ctx.scratch));
         g_ctx.scratch = nullptr;
         g_ctx.scratch_bytes = 0;
@@ -403,6 +406,241 @@ int run_adjoint(const void* u0v, void* gradv, int64_t nx, int64_t nsteps, const 
     return SWEPT_OK;
 }
 
+// -------------------------------------------------------------------- batch
+
+// Per-instance tiling for the batch: tiles of width 2k_t, k_t in {base,
+// base+1}, summing to the ring length; odd rings run on their two-fold cover
+// (the same bits: the scheme is translation-equivariant, so a field repeated
+// twice stays repeated).
+struct BatchPlanInst {
+    int64_t n_user, n_ring, L, x_off, e_off, f_off, stages;
+    int tiles, kmax, stencil;
+};
+
+struct BatchCache {
+    std::vector<int64_t> key;       // the batch's defining numbers and pointers
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+BatchCache g_batch;
+
+void batch_release()
+{
+    if (g_batch.exec)
+        (void)hipGraphExecDestroy(g_batch.exec);
+    if (g_batch.graph)
+        (void)hipGraphDestroy(g_batch.graph);
+    g_batch = BatchCache{};
+}
+
+int64_t batch_depth(int id, int64_t nring, int64_t want)
+{
+    // target depth k; tiles never exceed the LDS chain budget
+    const int64_t lim = (int64_t)(kMaxLds / (2 * pt_bytes(id))) - 1;
+    const int64_t k = std::min<int64_t>(want, lim);
+    return std::max<int64_t>(1, std::min<int64_t>(k, nring / 2));
+}
+
+template <class S>
+int launch_batch_stage(const BatchInst<S>* inst, const BatchTask* tasks, const int64_t* X,
+                       typename S::Pt* re, typename S::Pt* le0, typename S::Pt* le1, int stage,
+                       int64_t ntasks, int kmax, hipStream_t st)
+{
+    if (ntasks <= 0)
+        return SWEPT_OK;
+    BatchArgs<S> a{};
+    a.inst = inst;
+    a.tasks = tasks;
+    a.X = X;
+    a.re = re;
+    a.le[0] = le0;
+    a.le[1] = le1;
+    a.stage = stage;
+    const size_t lds = (size_t)2 * kmax * sizeof(typename S::Pt);
+    hipLaunchKernelGGL((swept_batch_kernel<S, 2>), dim3((unsigned)ntasks), dim3(64), lds, st, a);
+    return SWEPT_OK;
+}
+
+int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const int32_t* ids,
+              const double* params, int64_t count)
+{
+    using PtH = HeatF64::Pt;
+    using PtK = KSF64::Pt;
+    // ---- plan
+    std::vector<BatchPlanInst> P((size_t)count);
+    std::vector<int64_t> X;
+    int64_t e_heat = 0, e_ks = 0, f_tot = 0;
+    for (int64_t j = 0; j < count; ++j) {
+        BatchPlanInst& p = P[(size_t)j];
+        p.stencil = ids[j];
+        p.n_user = nx[j];
+        p.n_ring = (nx[j] % 2 == 0) ? nx[j] : 2 * nx[j];
+        p.L = nsteps[j] * substeps_of(ids[j]);
+        const int64_t want = g_ctx.tile_w > 0 ? g_ctx.tile_w / 2 : 256;
+        const int64_t k = batch_depth(ids[j], p.n_ring, want);
+        const int64_t half = p.n_ring / 2;
+        const int64_t T = std::max<int64_t>(1, half / k);
+        const int64_t base = half / T, rem = half % T;
+        p.tiles = (int)T;
+        p.kmax = (int)(base + (rem ? 1 : 0));
+        p.x_off = (int64_t)X.size();
+        X.push_back(0);
+        for (int64_t t = 0; t < T; ++t)
+            X.push_back(X.back() + 2 * (base + (t < rem ? 1 : 0)));
+        // stage s >= 1 of tile t starts at level (X_{t+s} - X_{t+1})/2 >= (s-1)*base
+        p.stages = p.L == 0 ? 0 : 2 + (p.L + base - 1) / base;
+        if (p.stencil == SWEPT_KS_F64) {
+            p.e_off = e_ks;
+            e_ks += p.n_ring;
+        } else {
+            p.e_off = e_heat;
+            e_heat += p.n_ring;
+        }
+        p.f_off = -1;
+        if (p.n_ring != p.n_user) {
+            p.f_off = f_tot;
+            f_tot += p.n_ring;
+        }
+    }
+    // tasks of each stencil, sorted by the instance's stage count (descending),
+    // so that the tasks of stage g are a prefix of the list
+    std::vector<int64_t> order((size_t)count);
+    for (int64_t j = 0; j < count; ++j)
+        order[(size_t)j] = j;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return P[(size_t)a].stages > P[(size_t)b].stages; });
+    std::vector<BatchTask> th, tk;
+    std::vector<int64_t> sh, sk;  // stage count of the instance of each task
+    int kmax_h = 1, kmax_k = 1;
+    for (int64_t j : order) {
+        const BatchPlanInst& p = P[(size_t)j];
+        if (p.L == 0)
+            continue;
+        auto& tv = p.stencil == SWEPT_KS_F64 ? tk : th;
+        auto& sv = p.stencil == SWEPT_KS_F64 ? sk : sh;
+        for (int t = 0; t < p.tiles; ++t) {
+            tv.push_back(BatchTask{(int)j, t});
+            sv.push_back(p.stages);
+        }
+        int& km = p.stencil == SWEPT_KS_F64 ? kmax_k : kmax_h;
+        km = std::max(km, p.kmax);
+    }
+    int64_t smax = 0;
+    for (const auto& p : P)
+        smax = std::max(smax, p.stages);
+
+    // ---- device memory: [inst heat][inst ks][X][tasks h][tasks k][edges h][edges k][fields]
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t b_ih = al(sizeof(BatchInst<HeatF64>) * (size_t)count);
+    const size_t b_ik = al(sizeof(BatchInst<KSF64>) * (size_t)count);
+    const size_t b_x = al(sizeof(int64_t) * X.size());
+    const size_t b_th = al(sizeof(BatchTask) * std::max<size_t>(1, th.size()));
+    const size_t b_tk = al(sizeof(BatchTask) * std::max<size_t>(1, tk.size()));
+    const size_t b_eh = al(3 * (size_t)e_heat * sizeof(PtH));
+    const size_t b_ek = al(3 * (size_t)e_ks * sizeof(PtK));
+    const size_t b_f = al((size_t)f_tot * sizeof(double));
+    int rc = ensure_scratch(b_ih + b_ik + b_x + b_th + b_tk + b_eh + b_ek + b_f);
+    if (rc)
+        return rc;
+    unsigned char* base = static_cast<unsigned char*>(g_ctx.scratch);
+    auto* d_ih = reinterpret_cast<BatchInst<HeatF64>*>(base);
+    auto* d_ik = reinterpret_cast<BatchInst<KSF64>*>(base + b_ih);
+    auto* d_x = reinterpret_cast<int64_t*>(base + b_ih + b_ik);
+    auto* d_th = reinterpret_cast<BatchTask*>(base + b_ih + b_ik + b_x);
+    auto* d_tk = reinterpret_cast<BatchTask*>(base + b_ih + b_ik + b_x + b_th);
+    auto* d_eh = reinterpret_cast<PtH*>(base + b_ih + b_ik + b_x + b_th + b_tk);
+    auto* d_ek = reinterpret_cast<PtK*>(base + b_ih + b_ik + b_x + b_th + b_tk + b_eh);
+    auto* d_f = reinterpret_cast<double*>(base + b_ih + b_ik + b_x + b_th + b_tk + b_eh + b_ek);
+
+    std::vector<BatchInst<HeatF64>> ih((size_t)count);
+    std::vector<BatchInst<KSF64>> ik((size_t)count);
+    for (int64_t j = 0; j < count; ++j) {
+        const BatchPlanInst& p = P[(size_t)j];
+        double* field = p.f_off >= 0 ? d_f + p.f_off : static_cast<double*>(u[j]);
+        if (p.stencil == SWEPT_KS_F64)
+            ik[(size_t)j] = BatchInst<KSF64>{field, p.n_ring, p.L, p.x_off, p.e_off, p.tiles, 0,
+                                            ks_consts(params + 2 * j)};
+        else
+            ih[(size_t)j] = BatchInst<HeatF64>{field, p.n_ring, p.L, p.x_off, p.e_off, p.tiles, 0,
+                                              heat64_consts(params + 2 * j)};
+    }
+    HIP_TRY(hipStreamSynchronize(g_ctx.stream));
+    HIP_TRY(hipMemcpy(d_ih, ih.data(), sizeof(BatchInst<HeatF64>) * (size_t)count, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d_ik, ik.data(), sizeof(BatchInst<KSF64>) * (size_t)count, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d_x, X.data(), sizeof(int64_t) * X.size(), hipMemcpyHostToDevice));
+    if (!th.empty())
+        HIP_TRY(hipMemcpy(d_th, th.data(), sizeof(BatchTask) * th.size(), hipMemcpyHostToDevice));
+    if (!tk.empty())
+        HIP_TRY(hipMemcpy(d_tk, tk.data(), sizeof(BatchTask) * tk.size(), hipMemcpyHostToDevice));
+
+    // ---- the launch sequence (captured once into a graph per batch)
+    std::vector<int64_t> key;
+    key.push_back(count);
+    for (int64_t j = 0; j < count; ++j) {
+        key.push_back(nx[j]);
+        key.push_back(nsteps[j]);
+        key.push_back(ids[j]);
+        key.push_back((int64_t)(intptr_t)u[j]);
+        int64_t pb[2];
+        std::memcpy(pb, params + 2 * j, sizeof pb);
+        key.push_back(pb[0]);
+        key.push_back(pb[1]);
+    }
+    key.push_back((int64_t)(intptr_t)g_ctx.scratch);
+    key.push_back(g_ctx.tile_w);
+    if (g_batch.exec && key == g_batch.key) {
+        HIP_TRY(hipGraphLaunch(g_batch.exec, g_ctx.stream));
+        return SWEPT_OK;
+    }
+    batch_release();
+    hipStream_t cs;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    for (int64_t j = 0; j < count; ++j) {      // odd rings: build the two-fold cover
+        const BatchPlanInst& p = P[(size_t)j];
+        if (p.f_off >= 0)
+            hipLaunchKernelGGL((batch_cover_kernel<HeatF64>), dim3(grid_for(p.n_ring, 256)),
+                               dim3(256), 0, cs, static_cast<const double*>(u[j]), d_f + p.f_off,
+                               p.n_user, 2);
+    }
+    size_t ph = 0, pk = 0;
+    for (int64_t g = 0; g < smax; ++g) {
+        while (ph < sh.size() && sh[ph] > g) ++ph;
+        while (pk < sk.size() && sk[pk] > g) ++pk;
+        launch_batch_stage<HeatF64>(d_ih, d_th, d_x, d_eh, d_eh + e_heat, d_eh + 2 * e_heat,
+                                    (int)g, (int64_t)ph, kmax_h, cs);
+        launch_batch_stage<KSF64>(d_ik, d_tk, d_x, d_ek, d_ek + e_ks, d_ek + 2 * e_ks, (int)g,
+                                  (int64_t)pk, kmax_k, cs);
+    }
+    for (int64_t j = 0; j < count; ++j) {      // odd rings: copy one period back
+        const BatchPlanInst& p = P[(size_t)j];
+        if (p.f_off >= 0)
+            hipLaunchKernelGGL((batch_cover_kernel<HeatF64>), dim3(grid_for(p.n_user, 256)),
+                               dim3(256), 0, cs, d_f + p.f_off, static_cast<double*>(u[j]),
+                               p.n_user, 1);
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    g_batch.key = std::move(key);
+    g_batch.graph = graph;
+    g_batch.exec = exec;
+    HIP_TRY(hipGraphLaunch(exec, g_ctx.stream));
+    return SWEPT_OK;
+}
+
 // ------------------------------------------------------------- naive launch
 
 template <class S>
@@ -598,6 +836,30 @@ int swept_naive_substep_advance(void* u, int64_t nx, int64_t nsteps, int32_t ste
     return run_naive_ks_substep(u, nx, nsteps, ks_consts(params));
 }
 
+int swept_advance_batch(void* const* u, const int64_t* nx, const int64_t* nsteps,
+                        const int32_t* stencil_id, const double* params, int64_t count)
+{
+    if (!g_ctx.ready)
+        return fail(SWEPT_ENOTINIT, "swept_init has not been called");
+    if (count < 0 || (count > 0 && (!u || !nx || !nsteps || !stencil_id || !params)))
+        return fail(SWEPT_EINVAL, "bad batch arrays");
+    for (int64_t j = 0; j < count; ++j) {
+        int rc = check_common(u[j], nx[j], nsteps[j], stencil_id[j], params + 2 * j, 2);
+        if (rc)
+            return fail(rc, "instance %lld: %s", (long long)j, g_err.c_str());
+        if (stencil_id[j] != SWEPT_HEAT_F64 && stencil_id[j] != SWEPT_KS_F64)
+            return fail(SWEPT_EUNSUPPORTED, "instance %lld: the batch takes binary64 stencils",
+                        (long long)j);
+    }
+    if (count == 0)
+        return SWEPT_OK;
+    int rc = run_batch(u, nx, nsteps, stencil_id, params, count);
+    if (rc)
+        return rc;
+    HIP_TRY(hipGetLastError());
+    return SWEPT_OK;
+}
+
 int swept_set_profiling(int enable)
 {
     if (!g_ctx.ready)
@@ -672,6 +934,7 @@ void swept_finalize(void)
     if (g_ctx.scratch)
         (void)hipFree(g_ctx.scratch);
     release_events();
+    batch_release();
     g_ctx = Context{};
 }
 

@@ -203,3 +203,117 @@ def levels_complete(visits, n, L, k):
     if extra:
         return False, ("above L", extra[:3])
     return True, None
+
+
+def simulate_tiles(u0, nsteps, ks_list, P, stencil, lanes=64, track=False):
+    """The swept schedule on tiles of unequal even widths 2*k_t (sum = N).
+    Workgroup t keeps k_t pairs; at stage s its region is the rectangle of
+    k_t pairs by k_{t+s} steps centred at J = (X_{t+s} + X_{t+1}) / 2 with
+    base level b = (X_{t+s} - X_{t+1}) / 2 (X_t = 2*sum_{t'<t} k_t', taken
+    periodically with period N).  Stage 0 is the triangle of each tile.
+    Right edges live at offset X_t, left edges at offset X_{(t+s) mod T}."""
+    step, nph, from_field, to_field = stencil
+    n = len(u0)
+    T = len(ks_list)
+    X = [0]
+    for kt in ks_list:
+        X.append(X[-1] + 2 * kt)
+    assert X[-1] == n
+
+    def Xp(i):  # periodic extension
+        q, r = divmod(i, T)
+        return X[r] + q * n
+
+    L = nsteps * nph
+    u = list(u0)
+    out = list(u0)
+    visits = {} if track else None
+    if L == 0:
+        return u, visits
+    RE = [None] * n
+    LE = [[None] * n, [None] * n]
+    band = lanes * P
+    s = 0
+    while True:
+        active = False
+        le_in, le_out = LE[(s + 1) % 2], LE[s % 2]
+        for t in range(T):
+            kp, ks = ks_list[t], ks_list[(t + s) % T]
+            J2 = Xp(t + s) + Xp(t + 1)
+            assert J2 % 2 == 0
+            J = (J2 // 2) % n
+            b = (Xp(t + s) - Xp(t + 1)) // 2
+            tri = s == 0
+            if not tri and b >= L:
+                continue
+            active = True
+            re_off = X[t]
+            le_off_out = X[(t + s) % T]
+            le_off_in = X[(t + s) % T]   # written by workgroup t+1 at stage s-1
+            chain = [None] * (2 * ks) if tri else list(le_in[le_off_in:le_off_in + 2 * ks])
+            top = L - b
+            for base in range(0, kp, band):
+                nvalid = min(band, kp - base)
+                tau_first = (ks - base) if tri else 0
+                tau_cap = top - base - 1
+                tau_end = min(nvalid + ks - 2, tau_cap)
+                if tau_end < tau_first and not tri:
+                    continue
+                A = [None] * band
+                B = [None] * band
+                for e in range(nvalid):
+                    d = base + e
+                    if tri:
+                        xa = J + ks - 1 - 2 * d
+                        A[e], B[e] = from_field(u[xa % n]), from_field(u[(xa - 1) % n])
+                    else:
+                        B[e], A[e] = RE[re_off + 2 * d], RE[re_off + 2 * d + 1]
+                eL = nvalid - 1
+                if tri:
+                    m = ks - 1 - (base + eL)
+                    chain[2 * m], chain[2 * m + 1] = B[eL], A[eL]
+                slot = min(tau_first, ks - 1)
+                cA, cB = chain[2 * slot + 1], chain[2 * slot]
+                for tau in range(tau_first, tau_end + 1):
+                    inA = [cA] + [A[(r - 1) * P + P - 1] for r in range(1, lanes)]
+                    inB = [cB] + [B[(r - 1) * P + P - 1] for r in range(1, lanes)]
+                    slot = min(tau + 1, ks - 1)
+                    nA, nB = chain[2 * slot + 1], chain[2 * slot]
+                    ph = (b + base + tau) % nph
+                    for r in range(lanes):
+                        for q in range(P - 1, -1, -1):
+                            e = r * P + q
+                            m = tau - e
+                            if not (0 <= m < ks and e < nvalid):
+                                continue
+                            rA = inA[r] if q == 0 else A[e - 1]
+                            cBv = inB[r] if q == 0 else B[e - 1]
+                            nAv = step(ph, A[e], cBv, rA)
+                            nBv = step(ph, B[e], A[e], cBv)
+                            A[e], B[e] = nAv, nBv
+                            if track:
+                                d = base + e
+                                lvl = b + m + d + 1
+                                xa = (J + m - d) % n
+                                for x in (xa, (xa - 1) % n):
+                                    visits[(x, lvl)] = visits.get((x, lvl), 0) + 1
+                    if tau == tau_cap:
+                        for e in range(nvalid):
+                            m = tau - e
+                            if 0 <= m < ks:
+                                d = base + e
+                                xa = (J + m - d) % n
+                                out[xa] = to_field(A[e])
+                                out[(xa - 1) % n] = to_field(B[e])
+                    m = tau - eL
+                    if 0 <= m < ks:
+                        chain[2 * m], chain[2 * m + 1] = B[eL], A[eL]
+                    cA, cB = nA, nB
+                for e in range(nvalid):
+                    d = base + e
+                    RE[re_off + 2 * d], RE[re_off + 2 * d + 1] = B[e], A[e]
+            le_out[le_off_out:le_off_out + 2 * ks] = chain
+        if not active:
+            break
+        s += 1
+    return out, visits

@@ -1,0 +1,80 @@
+"""Batched swept runs: every instance of a batch equals its own oracle run
+bit for bit (odd and even lengths, heat and KS, different step counts, tiles
+of unequal width), also when the captured graph is launched again."""
+import numpy as np
+import pytest
+
+import workloads
+from tests.conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+KS_P = [workloads.KS_DT, workloads.KS_DX]
+
+
+@pytest.fixture(scope="module")
+def sw():
+    import paper_1504_01380_amd as swept
+    swept.init(0)
+    swept.set_tuning(0, 0, swept.MODE_AUTO)
+    yield swept
+    swept.set_tuning(0, 0, swept.MODE_AUTO)
+
+
+def oracle_run(oracle_mod, stencil, u0, nsteps):
+    if stencil == "heat":
+        return oracle_mod.heat(u0, nsteps, 0.25)
+    return oracle_mod.ks(u0, nsteps, *KS_P)
+
+
+@pytest.mark.parametrize("tile", [0, 64, 16])
+def test_mixed_batch_bitwise(sw, oracle_mod, tile):
+    import torch
+    sw.set_tuning(tile, 0, sw.MODE_AUTO)
+    g = workloads.rng(2024 + tile)
+    sizes = [256, 257, 300, 1001, 2048, 3, 4, 999, 4096, 777, 513, 64]
+    insts = []
+    for q, n in enumerate(sizes):
+        stencil = "heat" if q % 2 == 0 else "ks"
+        nsteps = int(g.integers(1, 120 if stencil == "ks" else 400))
+        u0 = g.uniform(-1, 1, size=n)
+        insts.append((stencil, nsteps, u0))
+    insts.append(("ks", 0, g.uniform(-1, 1, size=100)))        # zero steps
+    us = [torch.from_numpy(u0.copy()).cuda() for _, _, u0 in insts]
+    sw.advance_batch(us, [ns for _, ns, _ in insts], [st for st, _, _ in insts],
+                     [[0.25] if st == "heat" else KS_P for st, _, _ in insts])
+    torch.cuda.synchronize()
+    sw.sync()
+    for (st, ns, u0), u in zip(insts, us):
+        want = oracle_run(oracle_mod, st, u0, ns)
+        print(st, u0.size, ns, flush=True)
+        assert np.array_equal(u.cpu().numpy().view(np.uint8), want.view(np.uint8))
+    # the same batch again: the cached graph is launched a second time
+    for (_, _, u0), u in zip(insts, us):
+        u.copy_(torch.from_numpy(u0))
+    sw.advance_batch(us, [ns for _, ns, _ in insts], [st for st, _, _ in insts],
+                     [[0.25] if st == "heat" else KS_P for st, _, _ in insts])
+    torch.cuda.synchronize()
+    for (st, ns, u0), u in zip(insts, us):
+        want = oracle_run(oracle_mod, st, u0, ns)
+        assert np.array_equal(u.cpu().numpy().view(np.uint8), want.view(np.uint8))
+    sw.set_tuning(0, 0, sw.MODE_AUTO)
+
+
+def test_batch_equals_solo_runs(sw):
+    """A sample of the ensemble workload (log-uniform sizes, odd sizes
+    included): each batched instance equals its own swept_advance."""
+    import torch
+    insts = workloads.batch(count=48, seed=7, smin=50, smax=300)
+    us = [torch.from_numpy(i.u0).cuda() for i in insts]
+    solo = []
+    for i in insts:
+        u = torch.from_numpy(i.u0).cuda()
+        sw.advance(u, i.nsteps, i.stencil, [0.25] if i.stencil == "heat" else KS_P)
+        solo.append(u)
+    sw.advance_batch(us, [i.nsteps for i in insts], [i.stencil for i in insts],
+                     [[0.25] if i.stencil == "heat" else KS_P for i in insts])
+    torch.cuda.synchronize()
+    for a, b in zip(us, solo):
+        assert torch.equal(a.view(torch.int64), b.view(torch.int64))
