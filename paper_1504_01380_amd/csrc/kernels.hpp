@@ -35,6 +35,8 @@
 // same sub-timestep, so multi-substep schemes need no divergence.
 #pragma once
 
+#include <type_traits>
+
 #include "stencils.hpp"
 
 namespace swept {
@@ -172,25 +174,16 @@ __device__ __forceinline__ void banded_region(typename S::T* u, const typename S
 
         int slot = min(tau_first, ks - 1);
         Pt cA = chain[2 * slot + 1], cB = chain[2 * slot];
-        for (int tau = tau_first; tau <= (int)tau_end; ++tau) {
+        const int mbase = -elane;
+        // one wave step at sub-timestep phase PH
+        auto wave_step = [&](int tau, auto phc) {
+            constexpr int PH = decltype(phc)::value;
             const Pt inA = S::shr1(A[P - 1], cA);
             const Pt inB = S::shr1(B[P - 1], cB);
-            slot = min(tau + 1, ks - 1);  // prefetch pair -1 for the next step
-            const Pt nA = chain[2 * slot + 1], nB = chain[2 * slot];
-
-            const int mlane = tau - elane;
-            const int ph = phase_of<S::NPHASE>(b + base + tau);
-            if constexpr (S::NPHASE == 1) {
-                band_update<S, P, 0>(A, B, inA, inB, mlane, elane, nvalid, ks, cst);
-            } else {
-                switch (ph) {
-                case 0: band_update<S, P, 0>(A, B, inA, inB, mlane, elane, nvalid, ks, cst); break;
-                case 1: band_update<S, P, 1>(A, B, inA, inB, mlane, elane, nvalid, ks, cst); break;
-                case 2: band_update<S, P, 2>(A, B, inA, inB, mlane, elane, nvalid, ks, cst); break;
-                default: band_update<S, P, 3>(A, B, inA, inB, mlane, elane, nvalid, ks, cst); break;
-                }
-            }
-
+            const int nslot = min(tau + 1, ks - 1);  // prefetch pair -1 for the next step
+            const Pt nA = chain[2 * nslot + 1], nB = chain[2 * nslot];
+            const int mlane = tau + mbase;
+            band_update<S, P, PH>(A, B, inA, inB, mlane, elane, nvalid, ks, cst);
             if (tau == tau_cap) {  // the band is at level L: write it out
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
@@ -216,6 +209,39 @@ __device__ __forceinline__ void banded_region(typename S::T* u, const typename S
             }
             cA = nA;
             cB = nB;
+        };
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        using I3 = std::integral_constant<int, 3>;
+        int tau = tau_first;
+        const int tend = (int)tau_end;
+        if constexpr (S::NPHASE == 1) {
+            for (; tau <= tend; ++tau)
+                wave_step(tau, I0{});
+        } else {
+            static_assert(S::NPHASE == 4, "multi-phase stencils have four sub-timesteps");
+            // the band sits on level b+base+tau+1 at step tau, so the phase of
+            // step tau is (b+base+tau) mod 4: run whole RK2 steps with the
+            // phase known at compile time, the partial ones around them by case
+            auto any_step = [&](int tau) {
+                switch (phase_of<S::NPHASE>(b + base + tau)) {
+                case 0: wave_step(tau, I0{}); break;
+                case 1: wave_step(tau, I1{}); break;
+                case 2: wave_step(tau, I2{}); break;
+                default: wave_step(tau, I3{}); break;
+                }
+            };
+            for (; tau <= tend && phase_of<S::NPHASE>(b + base + tau) != 0; ++tau)
+                any_step(tau);
+            for (; tau + 3 <= tend; tau += 4) {
+                wave_step(tau, I0{});
+                wave_step(tau + 1, I1{});
+                wave_step(tau + 2, I2{});
+                wave_step(tau + 3, I3{});
+            }
+            for (; tau <= tend; ++tau)
+                any_step(tau);
         }
 
         // final states = new right edge (levels above L are never read)

@@ -115,3 +115,49 @@ def test_adjoint_schedule(oracle_mod, stencil, n, k, nsteps, n0, cot):
         want = oracle_mod.ks_adjoint(u0, nsteps, 0.005, 0.5, n0, w, c)
     got = swept_adj_sim.adjoint(list(u0), nsteps, k, loc, n0, w, None if c is None else list(c))
     assert np.array_equal(np.array(got), want)
+
+
+def _split(half, k):
+    """The batch plan's tiling of a ring of 2*half points: T = max(1, half//k)
+    tiles, half-widths base or base+1 (the first half % T get base+1)."""
+    T = max(1, half // k)
+    base, rem = divmod(half, T)
+    return [base + (1 if t < rem else 0) for t in range(T)]
+
+
+@pytest.mark.parametrize("ks_list,nsteps,stencil", [
+    ([4, 5, 4, 5], 23, "heat"),       # alternating widths
+    ([3, 7, 2, 5, 6], 40, "heat"),    # arbitrary widths
+    ([6], 30, "heat"),                # one tile
+    ([1, 1, 2], 9, "heat"),           # k = 1 tiles
+    (_split(50, 8), 61, "heat"),      # the plan's split: 6 tiles of 8 or 9
+    ([4, 5, 4], 7, "ks"),
+    (_split(21, 4), 6, "ks"),
+])
+def test_unequal_tiles(oracle_mod, ks_list, nsteps, stencil):
+    """Tiles of unequal even widths (the batch path): every (point, level)
+    exactly once, the oracle's bits."""
+    n = 2 * sum(ks_list)
+    if stencil == "heat":
+        u0 = workloads.white_noise(n, seed=n)
+        st, L, want = swept_sim.heat_step(0.25), nsteps, oracle_mod.heat(u0, nsteps, 0.25)
+    else:
+        u0 = workloads.smoothed_noise(n, seed=n)
+        st, L, want = swept_sim.ks_step(0.005, 0.5), 4 * nsteps, oracle_mod.ks(u0, nsteps, 0.005, 0.5)
+    got, visits = swept_sim.simulate_tiles(list(u0), nsteps, ks_list, 1, st, lanes=2, track=True)
+    ok, why = swept_sim.levels_complete(visits, n, L, 0)
+    assert ok, why
+    assert np.array_equal(np.array(got), want)
+
+
+@pytest.mark.parametrize("n,k,nsteps", [(17, 4, 30), (9, 2, 11), (3, 8, 5), (101, 16, 70)])
+def test_odd_ring_on_two_fold_cover(oracle_mod, n, k, nsteps):
+    """An odd ring of n points run on its 2n-point cover: the first period of
+    the result is the n-point run (the scheme commutes with translation)."""
+    u0 = workloads.white_noise(n, seed=n)
+    cover = list(u0) + list(u0)
+    got, _ = swept_sim.simulate_tiles(cover, nsteps, _split(n, k), 1, swept_sim.heat_step(0.25),
+                                      lanes=4)
+    want = oracle_mod.heat(u0, nsteps, 0.25)
+    assert np.array_equal(np.array(got[:n]), want)
+    assert np.array_equal(np.array(got[n:]), want)
