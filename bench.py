@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-naive", action="store_true", help="skip the naive and f32 legs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the untuned plans (no autotuner in the warm-up)")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: a plain copy of u (calibration), then the "
                          "timed swept runs only")
@@ -127,9 +129,10 @@ def cpu_baseline(u0_np, nsteps_full, seconds):
 KS_OPS_PER_STEP = 30  # per point-step: 4 sub-timesteps (4 + 11 + 4 + 11 flops, no FMA)
 
 
-def other_workloads(sw, torch, workloads):
-    """The other two single-GPU workloads: heat N=4096 (launch-latency bound
-    when stepped naively) and KS N=2^20 (four sub-timesteps per step)."""
+def other_workloads(sw, torch, workloads, tune=True):
+    """The other two single-field workloads: heat N=4096 (launch-latency
+    bound when stepped naively) and KS N=2^20 (four sub-timesteps per step),
+    each after the autotuner has chosen its tiling."""
     out = {}
     cases = [("heat_small", "heat", workloads.WORKLOADS["heat_small"], [0.25],
               HEAT_OPS_PER_UPDATE, 16),
@@ -138,9 +141,11 @@ def other_workloads(sw, torch, workloads):
     for name, st, w, par, ops, naive_bytes in cases:
         u0 = torch.from_numpy(workloads.initial(name)).cuda()
         n, nsteps = u0.numel(), w["nsteps"]
+        tuned = sw.autotune(n, nsteps, st, par) if tune else None
         plan = sw.plan(n, nsteps, st)
         rec = {"n": n, "time_steps": nsteps, "tile_w": plan["tile_w"],
-               "pairs_per_lane": plan["pairs_per_lane"], "stages": plan["stages"]}
+               "pairs_per_lane": plan["pairs_per_lane"], "stages": plan["stages"],
+               "tuning": tuned}
         for label, fn, reps in (("swept", sw.advance, 3), ("naive", sw.naive_advance, 1)):
             u = u0.clone()
             fn(u, nsteps, st, par)           # warm-up
@@ -174,6 +179,62 @@ def other_workloads(sw, torch, workloads):
         sw.sync()
         out[name] = rec
     return out
+
+
+def batch_workload(sw, torch, workloads, tune=True):
+    """The ensemble: 4096 independent instances (half heat, half KS, N
+    log-uniform in [256, 65536], 1,000-20,000 steps) in one batched swept
+    run, against the batched naive schedule (one launch per time step over
+    all instances still running).  Rates count each instance's own N x steps
+    (the two-fold cover of an odd ring is overhead, not work)."""
+    insts = workloads.batch()
+    ns = [i.nsteps for i in insts]
+    kinds = [i.stencil for i in insts]
+    pars = [[0.25] if k == "heat" else [workloads.KS_DT, workloads.KS_DX] for k in kinds]
+    u0 = [torch.from_numpy(i.u0).cuda() for i in insts]
+    us = [u.clone() for u in u0]
+    work = float(sum(i.n * i.nsteps for i in insts))
+    rec = {"instances": len(insts), "total_points": sum(i.n for i in insts),
+           "point_steps": work, "odd_instances": sum(i.n % 2 for i in insts)}
+    if tune:
+        t0 = time.perf_counter()
+        rec["tuned_depth"] = sw.autotune_batch([i.n for i in insts], ns, kinds, pars)
+        rec["tune_s"] = time.perf_counter() - t0
+
+    def restore():
+        for a, b in zip(us, u0):
+            a.copy_(b)
+        torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    sw.advance_batch(us, ns, kinds, pars)         # warm-up: plan, capture the graph
+    torch.cuda.synchronize()
+    rec["first_call_s"] = time.perf_counter() - t0
+    ts = []
+    for _ in range(3):
+        restore()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sw.advance_batch(us, ns, kinds, pars)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    t = sorted(ts)[1]
+    rec["swept"] = work / t
+    rec["swept_ms"] = t * 1e3
+    sw.naive_advance_batch(us[:64], [min(x, 4) for x in ns[:64]], kinds[:64], pars[:64])
+    restore()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sw.naive_advance_batch(us, ns, kinds, pars)
+    e1.record()
+    e1.synchronize()
+    tn = e0.elapsed_time(e1) / 1e3
+    rec["naive"] = work / tn
+    rec["naive_ms"] = tn * 1e3
+    rec["speedup_vs_naive"] = rec["swept"] / rec["naive"]
+    sw.sync()
+    return rec
 
 
 def ks_adjoint_workload(sw, torch, workloads, directions=16, eps=1e-6):
@@ -232,9 +293,16 @@ def main():
 
     sw.init(0)
     sw.set_tuning(0, 0, sw.MODE_AUTO)
+    sw.clear_tuning()
     n, nsteps = args.n, args.nsteps
     u0_np = workloads.white_noise(n, seed=workloads.WORKLOADS["heat_large"]["seed"])
     u0 = torch.from_numpy(u0_np).cuda()
+    tuning = None
+    if not args.no_tune:
+        # warm-up: the autotuner (Eq. (1) prior + timed probes) picks the tiling
+        t0 = time.perf_counter()
+        tuning = sw.autotune(n, nsteps, "heat", [0.25], torch.float64)
+        tuning["tune_s"] = time.perf_counter() - t0
     plan = sw.plan(n, nsteps, "heat", torch.float64)
 
     if args.profile:
@@ -246,12 +314,15 @@ def main():
     # The stage launches of every timed run are bracketed by HIP events on
     # the library's stream (torch's current stream).
     sw.set_profiling(True)
-    cont_ms, stage_ms = [], []
+    k = plan["depth_k"]
+    full = [s for s in range(1, plan["stages"]) if (s - 1) * k + 2 * k - 1 <= nsteps]
+    diamond_ms, stage_ms, kinds = [], [], set()
 
     def record():
         ms, kind = sw.stage_times()
         stage_ms.append(sum(ms))
-        cont_ms.extend(m for m, kd in zip(ms, kind) if kd == 1)
+        diamond_ms.extend(ms[s] for s in full)
+        kinds.update(kind[s] for s in full)
 
     times, _ = timed_runs(sw, torch, sw.advance, u0, nsteps, [0.25], args.steps, args.warmup,
                           after=record)
@@ -260,19 +331,21 @@ def main():
     updates = float(n) * nsteps
     value = updates / t
 
-    # Dominant kernel: the continuous-band diamond kernel, one launch per full
-    # diamond stage; each launch computes 2k^2 point-updates per tile.
-    k, tiles = plan["depth_k"], plan["tiles"]
-    kname = "swept_diamond_cont_kernel<Heat<double>,%d>" % plan["pairs_per_lane"]
+    # Dominant kernel: the one that runs the full diamond stages (the
+    # continuous-band kernel when k is a multiple of its band), one launch per
+    # stage; each launch computes 2k^2 point-updates per tile.
+    tiles = plan["tiles"]
+    kname = ("swept_diamond_cont_kernel<Heat<double>,%d>" if kinds == {1} else
+             "swept_stage_kernel<Heat<double>,%d>") % plan["pairs_per_lane"]
     updates_per_launch = float(tiles) * 2 * k * k
     flops_per_launch = HEAT_OPS_PER_UPDATE * updates_per_launch
-    avg_launch = (sum(cont_ms) / len(cont_ms) / 1e3) if cont_ms else float("nan")
+    avg_launch = (sum(diamond_ms) / len(diamond_ms) / 1e3) if diamond_ms else float("nan")
     achieved = flops_per_launch / avg_launch
     edge_bytes = float(tiles) * 4 * 2 * k * 8   # RE in/out + LE in/out, 2k values each
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANE_OPS / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / VALU_LANE_OPS,
                 "traffic": measured_traffic(kname),
-                "kernel": kname, "launches_per_step": len(cont_ms) // max(1, args.steps),
+                "kernel": kname, "launches_per_step": len(diamond_ms) // max(1, args.steps),
                 "stages_per_step": plan["stages"], "avg_launch_ms": avg_launch * 1e3,
                 "flops_per_launch": flops_per_launch, "ops_per_update": HEAT_OPS_PER_UPDATE,
                 "stage_sum_ms": sum(stage_ms) / max(1, len(stage_ms)),
@@ -287,7 +360,7 @@ def main():
         "config": {"workload": "heat N=2^24 f64 r=0.25 20000 steps, u0~U[-1,1] seed 1001",
                    "n": n, "time_steps": nsteps, "tile_w": plan["tile_w"],
                    "depth_k": plan["depth_k"], "tiles": plan["tiles"], "stages": plan["stages"],
-                   "pairs_per_lane": plan["pairs_per_lane"]},
+                   "pairs_per_lane": plan["pairs_per_lane"], "tuning": tuning},
         "roofline": roofline,
     }
 
@@ -301,16 +374,21 @@ def main():
                         "hbm_frac": naive * HEAT_NAIVE_BYTES[8] / HBM_PEAK}
         out["speedup_vs_naive"] = value / naive
         u32 = u0.float()
+        tune32 = None if args.no_tune else sw.autotune(n, nsteps, "heat", [0.25], torch.float32)
+        plan32 = sw.plan(n, nsteps, "heat", torch.float32)
         st, _ = timed_runs(sw, torch, sw.advance, u32, nsteps, [0.25], 2, 1)
         nt32, _ = timed_runs(sw, torch, sw.naive_advance, u32, nsteps, [0.25], 1, 1)
         s32 = updates / (sum(st) / len(st))
         n32 = updates / nt32[0]
         out["f32"] = {"swept": s32, "naive": n32, "speedup_vs_naive": s32 / n32,
                       "swept_frac_alu": HEAT_OPS_PER_UPDATE * s32 / VALU_LANE_OPS_F32,
-                      "naive_hbm_frac": n32 * HEAT_NAIVE_BYTES[4] / HBM_PEAK}
+                      "naive_hbm_frac": n32 * HEAT_NAIVE_BYTES[4] / HBM_PEAK,
+                      "tile_w": plan32["tile_w"], "pairs_per_lane": plan32["pairs_per_lane"],
+                      "tuning": tune32}
 
     if not args.no_naive:
-        out["workloads"] = other_workloads(sw, torch, workloads)
+        out["workloads"] = other_workloads(sw, torch, workloads, tune=not args.no_tune)
+        out["workloads"]["batch"] = batch_workload(sw, torch, workloads, tune=not args.no_tune)
         out["workloads"]["ks_adjoint"] = ks_adjoint_workload(sw, torch, workloads)
 
     if not args.no_cpu:

@@ -145,8 +145,9 @@ int swept_naive_substep_advance(void *u, int64_t nx, int64_t nsteps, int32_t ste
  * stencil_id[j] with parameters params[2j], params[2j+1] (heat reads the
  * first).  Every instance gets exactly the bits its own swept_advance would.
  *
- * Each instance is tiled by even widths 2k_t, k_t in {k, k+1} (k = 256, or
- * tile_w/2 of swept_set_tuning), so any even length tiles without
+ * Each instance is tiled by even widths 2k_t, k_t in {k, k+1} (k = tile_w/2
+ * of swept_set_tuning if set, else the depth swept_autotune_batch chose for
+ * the stencil, else 128), so any even length tiles without
  * remainder; the regions of unequal neighbouring tiles are rectangles of
  * k_t pairs by k_{t+1} steps.  An odd length runs on its two-fold cover
  * (the field repeated twice, which the scheme keeps repeated).  All tiles of
@@ -156,6 +157,62 @@ int swept_naive_substep_advance(void *u, int64_t nx, int64_t nsteps, int32_t ste
  */
 int swept_advance_batch(void *const *u, const int64_t *nx, const int64_t *nsteps,
                         const int32_t *stencil_id, const double *params, int64_t count);
+
+/*
+ * The naive schedule for a batch, the baseline of swept_advance_batch: one
+ * launch per time step and stencil advances every instance that still has
+ * steps to go (heat: one thread per point; KS: the fused RK2 step of
+ * swept_naive_advance, per block of 256 points of one instance).  Same
+ * arguments and same bits as swept_advance_batch.  Uses library scratch for
+ * a second copy of every field (8 bytes per point) and synchronizes the
+ * stream once to upload its tables.
+ */
+int swept_naive_advance_batch(void *const *u, const int64_t *nx, const int64_t *nsteps,
+                              const int32_t *stencil_id, const double *params, int64_t count);
+
+/*
+ * Autotuner for swept_advance (paper, Section 4: Eq. (1) and its optimum
+ * n* = sqrt(2 tau / s)).  With W-point tiles a sub-timestep costs
+ * max(W s1, nx s_full) + 2 tau / W, where tau is the cost of a stage
+ * boundary (end of a launch, edge round trip, next launch), s1 the time one
+ * wavefront alone spends per point-substep and s_full the whole GPU's time
+ * per point-substep; all three are measured with short runs of the stencil
+ * on zero fields.  The prior W0 = max(nx s_full / s1, sqrt(2 tau / s1))
+ * centres the candidates: the valid tile widths (even, dividing nx, within
+ * the LDS budget) nearest W0/8, W0/4, W0/2, W0, 2 W0 and 4 W0 (the model
+ * leaves out that wider tiles hold more LDS and so share a CU with fewer
+ * others) and the width the untuned plan would take, each with 1, 2 or 4
+ * pairs per lane (64 x pairs <= W/2), and the naive schedule.  Each tiling
+ * is timed (best of three) over sixteen of its stages (at most
+ * nsteps steps) on as many of its tiles as fill the GPU four times over (at
+ * most nx points), the naive schedule over at most 256 steps of all nx
+ * points, and the highest rate in point-steps per second is kept.  Later
+ * swept_advance calls of the same stencil with floor(log2 nx) equal to this
+ * one's, in SWEPT_MODE_AUTO with tile width and pairs per lane left at 0,
+ * use it whenever the chosen width divides their nx.  Results never depend
+ * on the choice.
+ *
+ * report (host, may be NULL) receives 8 doubles: tau [s], s1 [s], s_full [s],
+ * n* = sqrt(2 tau / s1) [points], W0 [points], the chosen W (0 = naive), the
+ * chosen pairs per lane, the fastest probe's rate [point-steps/s].  The call
+ * allocates and frees its own probe fields and synchronizes the stream.
+ */
+int swept_autotune(int64_t nx, int64_t nsteps, int32_t stencil_id, const double *params,
+                   int32_t nparams, double *report);
+
+/*
+ * Autotuner for swept_advance_batch: for each binary64 stencil present, times
+ * the batch's own shapes (zero fields, each instance's steps cut to at most
+ * 3072 sub-timesteps) at depths k = 32, 64, 128, 256 and keeps the fastest
+ * for later batches.  depth_out (host, 3 entries indexed by stencil id)
+ * receives the chosen depth, 0 for a stencil not in the batch.  Allocates
+ * and frees its own probe fields; synchronizes the stream.
+ */
+int swept_autotune_batch(const int64_t *nx, const int64_t *nsteps, const int32_t *stencil_id,
+                         const double *params, int64_t count, int64_t *depth_out);
+
+/* Forget every choice made by swept_autotune and swept_autotune_batch. */
+int swept_clear_tuning(void);
 
 /*
  * Per-stage timing.  With profiling enabled, swept_advance records a HIP

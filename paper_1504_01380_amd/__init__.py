@@ -29,6 +29,8 @@ _STATUS = {0: "SWEPT_OK", -1: "SWEPT_EINVAL", -2: "SWEPT_ENOTINIT", -3: "SWEPT_E
 EXPORTS = ("swept_init", "swept_set_stream", "swept_set_tuning", "swept_plan",
            "swept_advance", "swept_naive_advance", "swept_naive_substep_advance",
            "swept_set_profiling", "swept_stage_times", "swept_adjoint", "swept_advance_batch",
+           "swept_naive_advance_batch", "swept_autotune", "swept_autotune_batch",
+           "swept_clear_tuning",
            "swept_sync", "swept_last_error", "swept_finalize")
 
 
@@ -55,6 +57,11 @@ def _load() -> ctypes.CDLL:
     L.swept_adjoint.argtypes = [vp, vp, i64, i64, i32, dp, i32, i64, ctypes.c_double, vp]
     L.swept_advance_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(i64),
                                       ctypes.POINTER(i32), dp, i64]
+    L.swept_naive_advance_batch.argtypes = L.swept_advance_batch.argtypes
+    L.swept_autotune.argtypes = [i64, i64, i32, dp, i32, dp]
+    L.swept_autotune_batch.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32),
+                                       dp, i64, ctypes.POINTER(i64)]
+    L.swept_clear_tuning.argtypes = []
     L.swept_set_profiling.argtypes = [ctypes.c_int]
     L.swept_stage_times.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), i64,
                                     ctypes.POINTER(i64)]
@@ -171,16 +178,10 @@ def naive_substep_advance(u: torch.Tensor, nsteps: int, stencil, params: Sequenc
     return u
 
 
-def advance_batch(us: Sequence[torch.Tensor], nsteps: Sequence[int], stencils,
-                  params: Sequence[Sequence[float]]) -> None:
-    """Advance independent float64 fields in place, instance j by nsteps[j]
-    steps of stencils[j] ("heat" or "ks") with params[j], in one batched
-    swept run (one HIP graph)."""
+def _batch_args(us, nsteps, stencils, params):
     count = len(us)
     if not (len(nsteps) == len(stencils) == len(params) == count):
         raise ValueError("batch arrays differ in length")
-    if count == 0:
-        return
     for u in us:
         if u.dtype != torch.float64:
             raise TypeError("the batch takes float64 fields")
@@ -194,10 +195,72 @@ def advance_batch(us: Sequence[torch.Tensor], nsteps: Sequence[int], stencils,
     ids = (ctypes.c_int32 * count)(*[stencil_id(st, torch.float64) for st in stencils])
     flat = []
     for p in params:
-        p = list(p)
-        flat += (p + [0.0, 0.0])[:2]
+        flat += (list(p) + [0.0, 0.0])[:2]
     par = (ctypes.c_double * (2 * count))(*flat)
-    _check(_lib.swept_advance_batch(ptrs, nx, ns, ids, par, count), "swept_advance_batch")
+    return ptrs, nx, ns, ids, par, count
+
+
+def advance_batch(us: Sequence[torch.Tensor], nsteps: Sequence[int], stencils,
+                  params: Sequence[Sequence[float]]) -> None:
+    """Advance independent float64 fields in place, instance j by nsteps[j]
+    steps of stencils[j] ("heat" or "ks") with params[j], in one batched
+    swept run (one HIP graph)."""
+    if len(us) == 0:
+        return
+    _check(_lib.swept_advance_batch(*_batch_args(us, nsteps, stencils, params)),
+           "swept_advance_batch")
+
+
+def naive_advance_batch(us: Sequence[torch.Tensor], nsteps: Sequence[int], stencils,
+                        params: Sequence[Sequence[float]]) -> None:
+    """The same as advance_batch with the naive schedule (one launch per time
+    step over all instances still running)."""
+    if len(us) == 0:
+        return
+    _check(_lib.swept_naive_advance_batch(*_batch_args(us, nsteps, stencils, params)),
+           "swept_naive_advance_batch")
+
+
+def autotune(nx: int, nsteps: int, stencil, params: Sequence[float],
+             dtype: torch.dtype | None = None) -> dict:
+    """Measure tau, s1 and s_full, form the prior tile width of Eq. (1) and
+    keep the fastest of the timed candidates for later automatic advances of
+    this stencil and size class.  Returns the model and the choice."""
+    arr, npar = _params(params)
+    rep = (ctypes.c_double * 8)()
+    _check(_lib.swept_autotune(int(nx), int(nsteps), stencil_id(stencil, dtype), arr, npar, rep),
+           "swept_autotune")
+    keys = ("tau", "s1", "s_full", "n_star", "w0", "tile_w", "pairs_per_lane", "probe_rate")
+    out = dict(zip(keys, list(rep)))
+    out["tile_w"] = int(out["tile_w"])
+    out["pairs_per_lane"] = int(out["pairs_per_lane"])
+    return out
+
+
+def autotune_batch(sizes: Sequence[int], nsteps: Sequence[int], stencils,
+                   params: Sequence[Sequence[float]]) -> dict:
+    """Choose the batch depth per stencil from timed probes of this batch's
+    shapes; returns {"heat": k, "ks": k} for the stencils present."""
+    count = len(sizes)
+    nx = (ctypes.c_int64 * max(1, count))(*[int(n) for n in sizes])
+    ns = (ctypes.c_int64 * max(1, count))(*[int(n) for n in nsteps])
+    ids = (ctypes.c_int32 * max(1, count))(*[stencil_id(st, torch.float64) for st in stencils])
+    flat = []
+    for p in params:
+        flat += (list(p) + [0.0, 0.0])[:2]
+    par = (ctypes.c_double * max(2, len(flat)))(*flat)
+    out = (ctypes.c_int64 * 3)()
+    _check(_lib.swept_autotune_batch(nx, ns, ids, par, count, out), "swept_autotune_batch")
+    res = {}
+    if out[HEAT_F64]:
+        res["heat"] = int(out[HEAT_F64])
+    if out[KS_F64]:
+        res["ks"] = int(out[KS_F64])
+    return res
+
+
+def clear_tuning() -> None:
+    _check(_lib.swept_clear_tuning(), "swept_clear_tuning")
 
 
 def set_profiling(enable: bool) -> None:

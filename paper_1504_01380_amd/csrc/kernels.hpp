@@ -769,14 +769,13 @@ __global__ __launch_bounds__(256) void naive_step_kernel(const typename S::T* __
 // intermediate levels on its halo (the same per-point operations, so the
 // same bits).
 template <class S, int NB>
-__global__ __launch_bounds__(NB) void naive_fused_kernel(const typename S::T* __restrict__ in,
-                                                        typename S::T* __restrict__ out,
-                                                        int64_t n, typename S::Consts c)
+__device__ __forceinline__ void fused_block(const typename S::T* __restrict__ in,
+                                            typename S::T* __restrict__ out, int64_t n,
+                                            int64_t i0, const typename S::Consts& c)
 {
     using Pt = typename S::Pt;
     static_assert(S::NPHASE == 4, "four-substep schemes only");
     __shared__ Pt s0[NB + 8], s1[NB + 6], s2[NB + 4], s3[NB + 2];
-    const int64_t i0 = (int64_t)blockIdx.x * NB;
     const int tid = threadIdx.x;
     for (int j = tid; j < NB + 8; j += NB) {
         int64_t x = (i0 - 4 + j) % n;
@@ -796,6 +795,52 @@ __global__ __launch_bounds__(NB) void naive_fused_kernel(const typename S::T* __
     const int64_t i = i0 + tid;
     if (i < n)
         out[i] = S::to_field(S::template step<3>(s3[tid], s3[tid + 1], s3[tid + 2], c));
+}
+
+template <class S, int NB>
+__global__ __launch_bounds__(NB) void naive_fused_kernel(const typename S::T* __restrict__ in,
+                                                        typename S::T* __restrict__ out,
+                                                        int64_t n, typename S::Consts c)
+{
+    fused_block<S, NB>(in, out, n, (int64_t)blockIdx.x * NB, c);
+}
+
+// Naive batch: one launch per time step advances every block of NB points of
+// every instance that still has steps to go.  Blocks never straddle two
+// instances; an instance's field alternates between buf[0] and buf[1].
+template <class S>
+struct NaiveInst {
+    typename S::T* buf[2];
+    int64_t n;
+    typename S::Consts c;
+};
+
+struct NaiveBlock {
+    int32_t inst;
+    int32_t pad;
+    int64_t x0;
+};
+
+template <class S, int NB>
+__global__ __launch_bounds__(NB) void naive_batch_kernel(const NaiveInst<S>* __restrict__ inst,
+                                                        const NaiveBlock* __restrict__ blocks,
+                                                        int parity)
+{
+    const NaiveBlock bk = blocks[blockIdx.x];
+    const NaiveInst<S> I = inst[bk.inst];
+    const typename S::T* in = I.buf[parity];
+    typename S::T* out = I.buf[parity ^ 1];
+    if constexpr (S::NPHASE == 1) {
+        const int64_t i = bk.x0 + threadIdx.x;
+        if (i < I.n) {
+            const int64_t il = i == 0 ? I.n - 1 : i - 1;
+            const int64_t ir = i == I.n - 1 ? 0 : i + 1;
+            out[i] = S::to_field(S::template step<0>(S::from_field(in[il]), S::from_field(in[i]),
+                                                     S::from_field(in[ir]), I.c));
+        }
+    } else {
+        fused_block<S, NB>(in, out, I.n, bk.x0, I.c);
+    }
 }
 
 // KS: one launch per sub-timestep (the paper's straight decomposition that

@@ -10,7 +10,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "swept.h"
@@ -97,13 +99,10 @@ size_t pt_bytes(int id)
     }
 }
 
-int check_common(const void* u, int64_t nx, int64_t nsteps, int32_t id, const double* params,
-                 int32_t nparams)
+int check_problem(int64_t nx, int64_t nsteps, int32_t id, const double* params, int32_t nparams)
 {
     if (!g_ctx.ready)
         return fail(SWEPT_ENOTINIT, "swept_init has not been called");
-    if (!u)
-        return fail(SWEPT_EINVAL, "u is NULL");
     if (nx < 3)
         return fail(SWEPT_EINVAL, "nx = %lld: need at least 3 points", (long long)nx);
     if (nsteps < 0)
@@ -119,6 +118,14 @@ int check_common(const void* u, int64_t nx, int64_t nsteps, int32_t id, const do
     if (id == SWEPT_KS_F64 && !(params[1] > 0.0))
         return fail(SWEPT_EINVAL, "KS needs dx > 0");
     return SWEPT_OK;
+}
+
+int check_common(const void* u, int64_t nx, int64_t nsteps, int32_t id, const double* params,
+                 int32_t nparams)
+{
+    if (g_ctx.ready && !u)
+        return fail(SWEPT_EINVAL, "u is NULL");
+    return check_problem(nx, nsteps, id, params, nparams);
 }
 
 HeatF64::Consts heat64_consts(const double* p) { return HeatF64::Consts{p[0]}; }
@@ -152,6 +159,24 @@ bool tile_fits(int id, int64_t nx, int64_t W)
     return W >= 2 && W % 2 == 0 && nx % W == 0 && (size_t)W * pt_bytes(id) <= kMaxLds;
 }
 
+// Tilings chosen by swept_autotune, per stencil and size class floor(log2 nx).
+struct Tuned {
+    int64_t W;
+    int P;
+};
+std::map<std::pair<int, int>, Tuned> g_tuned;
+// Batch depth per stencil id chosen by swept_autotune_batch (0 = default).
+int64_t g_batch_want[3] = {0, 0, 0};
+constexpr int64_t kBatchWantDefault = 128;
+
+std::pair<int, int> tune_key(int id, int64_t nx)
+{
+    int b = 0;
+    while ((int64_t(1) << (b + 1)) <= nx)
+        ++b;
+    return {id, b};
+}
+
 // Tiles of W = 2k points (paper, Section 3: each node owns an even number of
 // points); stages 0..ceil(L/k).
 int make_plan(int64_t nx, int64_t nsteps, int32_t id, Plan* p)
@@ -163,7 +188,21 @@ int make_plan(int64_t nx, int64_t nsteps, int32_t id, Plan* p)
         return SWEPT_OK;
     }
     int64_t W = 0;
-    if (g_ctx.tile_w > 0) {
+    int tunedP = 0;
+    if (g_ctx.tile_w == 0 && g_ctx.ppl == 0 && g_ctx.mode == SWEPT_MODE_AUTO) {
+        const auto it = g_tuned.find(tune_key(id, nx));
+        if (it != g_tuned.end() && it->second.W < 0) {
+            p->mode = SWEPT_MODE_NAIVE;   // the naive schedule was fastest
+            return SWEPT_OK;
+        }
+        if (it != g_tuned.end() && tile_fits(id, nx, it->second.W)) {
+            W = it->second.W;
+            tunedP = it->second.P;
+        }
+    }
+    if (W > 0) {
+        // tuned for this stencil and size class
+    } else if (g_ctx.tile_w > 0) {
         if (!tile_fits(id, nx, g_ctx.tile_w))
             return fail(SWEPT_EINVAL,
                         "tile width %d must be even, divide nx = %lld and fit 64 KB of LDS",
@@ -187,7 +226,7 @@ int make_plan(int64_t nx, int64_t nsteps, int32_t id, Plan* p)
     p->k = W / 2;
     p->tiles = nx / W;
     p->stages = L == 0 ? 0 : 1 + (L + p->k - 1) / p->k;
-    p->P = g_ctx.ppl > 0 ? g_ctx.ppl : auto_ppl(id, p->k);
+    p->P = g_ctx.ppl > 0 ? g_ctx.ppl : (tunedP > 0 ? tunedP : auto_ppl(id, p->k));
     p->mode = SWEPT_MODE_STAGE;
     return SWEPT_OK;
 }
@@ -433,6 +472,11 @@ void batch_release()
     g_batch = BatchCache{};
 }
 
+int64_t batch_want(int id)
+{
+    return g_batch_want[id] > 0 ? g_batch_want[id] : kBatchWantDefault;
+}
+
 int64_t batch_depth(int id, int64_t nring, int64_t want)
 {
     // target depth k; tiles never exceed the LDS chain budget
@@ -476,7 +520,7 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
         p.n_user = nx[j];
         p.n_ring = (nx[j] % 2 == 0) ? nx[j] : 2 * nx[j];
         p.L = nsteps[j] * substeps_of(ids[j]);
-        const int64_t want = g_ctx.tile_w > 0 ? g_ctx.tile_w / 2 : 256;
+        const int64_t want = g_ctx.tile_w > 0 ? g_ctx.tile_w / 2 : batch_want(ids[j]);
         const int64_t k = batch_depth(ids[j], p.n_ring, want);
         const int64_t half = p.n_ring / 2;
         const int64_t T = std::max<int64_t>(1, half / k);
@@ -588,6 +632,8 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
     }
     key.push_back((int64_t)(intptr_t)g_ctx.scratch);
     key.push_back(g_ctx.tile_w);
+    for (int64_t w : g_batch_want)
+        key.push_back(w);
     if (g_batch.exec && key == g_batch.key) {
         HIP_TRY(hipGraphLaunch(g_batch.exec, g_ctx.stream));
         return SWEPT_OK;
@@ -723,6 +769,423 @@ int naive_dispatch(void* u, int64_t nx, int64_t nsteps, int32_t id, const double
     }
 }
 
+// The naive schedule for a batch: per time step, one launch per stencil over
+// the blocks of the instances that still have steps to go (instances sorted
+// by step count, so those blocks are a prefix of the block list).
+template <class S>
+int naive_batch_tables(const std::vector<int64_t>& order, void* const* u, const int64_t* nx,
+                       const int64_t* nsteps, const int32_t* ids, const double* params,
+                       int32_t id, typename S::T* spare, const std::vector<int64_t>& spare_off,
+                       typename S::Consts (*consts)(const double*), std::vector<NaiveInst<S>>& inst,
+                       std::vector<NaiveBlock>& blocks, std::vector<int64_t>& block_steps)
+{
+    constexpr int NB = 256;
+    for (int64_t j : order) {
+        if (ids[j] != id || nsteps[j] == 0)
+            continue;
+        NaiveInst<S> I{};
+        I.buf[0] = static_cast<typename S::T*>(u[j]);
+        I.buf[1] = spare + spare_off[(size_t)j];
+        I.n = nx[j];
+        I.c = consts(params + 2 * j);
+        const int32_t q = (int32_t)inst.size();
+        inst.push_back(I);
+        for (int64_t x0 = 0; x0 < nx[j]; x0 += NB) {
+            blocks.push_back(NaiveBlock{q, 0, x0});
+            block_steps.push_back(nsteps[j]);
+        }
+    }
+    return SWEPT_OK;
+}
+
+int run_naive_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const int32_t* ids,
+                    const double* params, int64_t count)
+{
+    constexpr int NB = 256;
+    std::vector<int64_t> order((size_t)count), spare_off((size_t)count);
+    size_t total = 0;
+    int64_t smax = 0;
+    for (int64_t j = 0; j < count; ++j) {
+        order[(size_t)j] = j;
+        spare_off[(size_t)j] = (int64_t)total;
+        total += (size_t)nx[j];
+        smax = std::max(smax, nsteps[j]);
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return nsteps[a] > nsteps[b]; });
+    std::vector<NaiveInst<HeatF64>> ih;
+    std::vector<NaiveInst<KSF64>> ik;
+    std::vector<NaiveBlock> bh, bk;
+    std::vector<int64_t> sh, sk;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t b_f = al(total * sizeof(double));
+    const size_t cap_i = al(sizeof(NaiveInst<KSF64>) * (size_t)std::max<int64_t>(1, count));
+    size_t nblocks = 0;
+    for (int64_t j = 0; j < count; ++j)
+        nblocks += (size_t)((nx[j] + NB - 1) / NB);
+    const size_t b_b = al(sizeof(NaiveBlock) * std::max<size_t>(1, nblocks));
+    int rc = ensure_scratch(b_f + 2 * cap_i + 2 * b_b);
+    if (rc)
+        return rc;
+    unsigned char* base = static_cast<unsigned char*>(g_ctx.scratch);
+    double* spare = reinterpret_cast<double*>(base);
+    auto* d_ih = reinterpret_cast<NaiveInst<HeatF64>*>(base + b_f);
+    auto* d_ik = reinterpret_cast<NaiveInst<KSF64>*>(base + b_f + cap_i);
+    auto* d_bh = reinterpret_cast<NaiveBlock*>(base + b_f + 2 * cap_i);
+    auto* d_bk = reinterpret_cast<NaiveBlock*>(base + b_f + 2 * cap_i + b_b);
+    naive_batch_tables<HeatF64>(order, u, nx, nsteps, ids, params, SWEPT_HEAT_F64, spare,
+                                spare_off, heat64_consts, ih, bh, sh);
+    naive_batch_tables<KSF64>(order, u, nx, nsteps, ids, params, SWEPT_KS_F64, spare, spare_off,
+                              ks_consts, ik, bk, sk);
+    HIP_TRY(hipStreamSynchronize(g_ctx.stream));
+    if (!ih.empty()) {
+        HIP_TRY(hipMemcpy(d_ih, ih.data(), sizeof(ih[0]) * ih.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(d_bh, bh.data(), sizeof(bh[0]) * bh.size(), hipMemcpyHostToDevice));
+    }
+    if (!ik.empty()) {
+        HIP_TRY(hipMemcpy(d_ik, ik.data(), sizeof(ik[0]) * ik.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(d_bk, bk.data(), sizeof(bk[0]) * bk.size(), hipMemcpyHostToDevice));
+    }
+    size_t ph = bh.size(), pk = bk.size();
+    for (int64_t s = 0; s < smax; ++s) {
+        while (ph > 0 && sh[ph - 1] <= s) --ph;
+        while (pk > 0 && sk[pk - 1] <= s) --pk;
+        if (ph)
+            hipLaunchKernelGGL((naive_batch_kernel<HeatF64, NB>), dim3((unsigned)ph), dim3(NB), 0,
+                               g_ctx.stream, d_ih, d_bh, (int)(s & 1));
+        if (pk)
+            hipLaunchKernelGGL((naive_batch_kernel<KSF64, NB>), dim3((unsigned)pk), dim3(NB), 0,
+                               g_ctx.stream, d_ik, d_bk, (int)(s & 1));
+    }
+    // an odd step count leaves the result in the spare buffer
+    for (int64_t j = 0; j < count; ++j)
+        if (nsteps[j] % 2 == 1)
+            HIP_TRY(hipMemcpyAsync(u[j], spare + spare_off[(size_t)j], (size_t)nx[j] * sizeof(double),
+                                   hipMemcpyDeviceToDevice, g_ctx.stream));
+    HIP_TRY(hipGetLastError());
+    return SWEPT_OK;
+}
+
+// swept_advance after validation: plan, then the swept or the naive schedule
+int advance_dispatch(void* u, int64_t nx, int64_t nsteps, int32_t id, const double* params)
+{
+    if (nsteps == 0)
+        return SWEPT_OK;
+    Plan p;
+    int rc = make_plan(nx, nsteps, id, &p);
+    if (rc)
+        return rc;
+    if (p.mode == SWEPT_MODE_NAIVE)
+        return naive_dispatch(u, nx, nsteps, id, params);
+    const int64_t L = nsteps * substeps_of(id);
+    switch (id) {
+    case SWEPT_HEAT_F64: return run_swept<HeatF64>(u, nx, L, heat64_consts(params), p);
+    case SWEPT_HEAT_F32: return run_swept<HeatF32>(u, nx, L, heat32_consts(params), p);
+    default: return run_swept<KSF64>(u, nx, L, ks_consts(params), p);
+    }
+}
+
+// ----------------------------------------------------------------- autotuner
+//
+// The paper's model (Section 4, Eq. (1)): with n points per node, a swept
+// cycle computes for n^2 s and communicates twice, for 2 tau, while it
+// advances n sub-timesteps, so a sub-timestep costs n s + 2 tau / n, least at
+// n* = sqrt(2 tau / s).  On one GPU a node is a workgroup and tau is the cost
+// of a stage boundary: the end of one launch, the edge round trip through
+// memory, the start of the next.  s1 is the time one wavefront spends per
+// point-substep when it runs alone.  Because the tiles share the chip, a
+// sub-timestep also takes at least N s_full, s_full being the whole GPU's
+// time per point-substep, so with W-point tiles
+//     t(W) = max(W s1, N s_full) + 2 tau / W,
+// least at W0 = max(N s_full / s1, sqrt(2 tau / s1)).  W0 centres the
+// candidates; short timed runs choose among them.
+
+struct DeviceBuffer {
+    void* p = nullptr;
+    ~DeviceBuffer()
+    {
+        if (p)
+            (void)hipFree(p);
+    }
+    int alloc(size_t bytes)
+    {
+        hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 256));
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return fail(SWEPT_ENOMEM, "hipMalloc of %zu bytes for the tuner failed", bytes);
+        }
+        e = hipMemsetAsync(p, 0, bytes, g_ctx.stream);
+        return e == hipSuccess ? SWEPT_OK : hip_fail(e, "hipMemsetAsync");
+    }
+};
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair()
+    {
+        if (a)
+            (void)hipEventDestroy(a);
+        if (b)
+            (void)hipEventDestroy(b);
+    }
+};
+
+// Saves the tuning knobs and restores them on scope exit.
+struct KnobGuard {
+    int tile_w = g_ctx.tile_w, ppl = g_ctx.ppl, mode = g_ctx.mode;
+    bool profiling = g_ctx.profiling;
+    KnobGuard() { g_ctx.profiling = false; }
+    ~KnobGuard()
+    {
+        g_ctx.tile_w = tile_w;
+        g_ctx.ppl = ppl;
+        g_ctx.mode = mode;
+        g_ctx.profiling = profiling;
+    }
+};
+
+// Best of `reps` timings (seconds) of fn() on the stream, after one untimed call.
+template <class F>
+int time_best(F&& fn, int reps, double* sec)
+{
+    int rc = fn();
+    if (rc)
+        return rc;
+    EventPair ev;
+    HIP_TRY(hipEventCreate(&ev.a));
+    HIP_TRY(hipEventCreate(&ev.b));
+    double best = 1e30;
+    for (int r = 0; r < reps; ++r) {
+        HIP_TRY(hipEventRecord(ev.a, g_ctx.stream));
+        rc = fn();
+        if (rc)
+            return rc;
+        HIP_TRY(hipEventRecord(ev.b, g_ctx.stream));
+        HIP_TRY(hipEventSynchronize(ev.b));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
+        best = std::min(best, 1e-3 * (double)ms);
+    }
+    *sec = best;
+    return SWEPT_OK;
+}
+
+size_t field_bytes(int id) { return id == SWEPT_HEAT_F32 ? sizeof(float) : sizeof(double); }
+
+// One swept run of `nsteps` steps on the zero field f with the given tiling;
+// returns its time and its number of stages.
+int timed_swept(void* f, int64_t nx, int64_t nsteps, int id, const double* params, int64_t W,
+                int P, int reps, double* sec, int64_t* stages)
+{
+    g_ctx.tile_w = (int)W;
+    g_ctx.ppl = P;
+    g_ctx.mode = SWEPT_MODE_STAGE;
+    Plan p;
+    int rc = make_plan(nx, nsteps, id, &p);
+    if (rc)
+        return rc;
+    if (stages)
+        *stages = p.stages;
+    return time_best([&] { return advance_dispatch(f, nx, nsteps, id, params); }, reps, sec);
+}
+
+// tau, s1 and s_full of the stencil on this GPU
+int measure_model(int id, const double* params, double* tau, double* s1, double* sfull)
+{
+    const int S = substeps_of(id);
+    const int64_t nbig = int64_t(1) << 20;
+    DeviceBuffer f;
+    int rc = f.alloc((size_t)nbig * field_bytes(id));
+    if (rc)
+        return rc;
+    double t;
+    int64_t st;
+    // tau: 64 tiles of 4 points over 64 stages with next to no work in them
+    rc = timed_swept(f.p, 256, 128 / S, id, params, 4, 1, 3, &t, &st);
+    if (rc)
+        return rc;
+    *tau = t / (double)st;
+    // s1: a single 512-point tile, 2048 sub-timesteps, one workgroup
+    const int64_t Ls = 2048;
+    rc = timed_swept(f.p, 512, Ls / S, id, params, 512, 2, 2, &t, &st);
+    if (rc)
+        return rc;
+    *s1 = std::max(1e-15, (t - (double)st * *tau) / (512.0 * (double)Ls));
+    // s_full: 2^20 points in 512-point tiles
+    rc = timed_swept(f.p, nbig, Ls / S, id, params, 512, 2, 2, &t, &st);
+    if (rc)
+        return rc;
+    *sfull = std::max(1e-18, (t - (double)st * *tau) / ((double)nbig * (double)Ls));
+    return SWEPT_OK;
+}
+
+// Even tile widths that divide nx and fit the LDS budget, nearest (in ratio)
+// to each of the targets.
+std::vector<int64_t> tile_candidates(int id, int64_t nx, const std::vector<double>& targets)
+{
+    std::vector<int64_t> valid;
+    for (int64_t d = 1; d * d <= nx; ++d)
+        if (nx % d == 0)
+            for (int64_t w : {d, nx / d})
+                if (w >= 4 && tile_fits(id, nx, w))
+                    valid.push_back(w);
+    std::vector<int64_t> out;
+    for (double tg : targets) {
+        int64_t best = 0;
+        double bd = 1e30;
+        for (int64_t w : valid) {
+            const double dist = std::fabs(std::log((double)w / tg));
+            if (dist < bd) {
+                bd = dist;
+                best = w;
+            }
+        }
+        if (best && std::find(out.begin(), out.end(), best) == out.end())
+            out.push_back(best);
+    }
+    std::sort(out.begin(), out.end());
+    return out;
+}
+
+int autotune(int64_t nx, int64_t nsteps, int id, const double* params, double* report)
+{
+    KnobGuard guard;
+    double tau = 0, s1 = 0, sfull = 0;
+    int rc = measure_model(id, params, &tau, &s1, &sfull);
+    if (rc)
+        return rc;
+    const double nstar = std::sqrt(2.0 * tau / s1);
+    const double w0 = std::max((double)nx * sfull / s1, nstar);
+    // The model leaves out that wider tiles hold more LDS, so fewer of them
+    // share a CU to hide latency: the candidates reach well below W0.
+    std::vector<int64_t> Ws =
+        tile_candidates(id, nx, {w0 / 8, w0 / 4, w0 / 2, w0, 2 * w0, 4 * w0});
+    {   // the untuned plan's width is always among the candidates
+        g_ctx.tile_w = 0;
+        g_ctx.ppl = 0;
+        g_ctx.mode = SWEPT_MODE_STAGE;
+        Plan dflt;
+        if (make_plan(nx, nsteps, id, &dflt) == SWEPT_OK && dflt.W >= 4 &&
+            std::find(Ws.begin(), Ws.end(), dflt.W) == Ws.end())
+            Ws.push_back(dflt.W);
+        g_err.clear();
+    }
+    const int S = substeps_of(id);
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g_ctx.device));
+    DeviceBuffer f;
+    rc = f.alloc((size_t)nx * field_bytes(id));
+    if (rc)
+        return rc;
+    // the naive schedule costs the same every step: time a few
+    const int64_t nn = std::min<int64_t>(nsteps, 256);
+    double t;
+    g_ctx.mode = SWEPT_MODE_NAIVE;
+    rc = time_best([&] { return naive_dispatch(f.p, nx, nn, id, params); }, 2, &t);
+    if (rc)
+        return rc;
+    double best_rate = (double)nx * (double)nn / t;
+    Tuned best{-1, 0};
+    for (int64_t W : Ws) {
+        // Once the tiles fill the chip the rate per point no longer depends
+        // on their number: time four rounds of the workgroups that fit at
+        // once (64-lane workgroups, at most 32 per CU, LDS of W points
+        // each), over sixteen stages.
+        const int64_t per_cu =
+            std::max<int64_t>(1, std::min<int64_t>(32, (160 * 1024) / ((int64_t)W * pt_bytes(id))));
+        const int64_t npts = W * std::min(nx / W, 4 * (int64_t)cus * per_cu);
+        const int64_t Lp = std::min(nsteps * S, std::max<int64_t>(16 * (W / 2), 64));
+        const int64_t np = std::max<int64_t>(1, (Lp + S - 1) / S);
+        for (int P : {1, 2, 4}) {
+            if (P > 1 && 64 * P > W / 2)
+                continue;
+            rc = timed_swept(f.p, npts, np, id, params, W, P, 3, &t, nullptr);
+            if (rc)
+                return rc;
+            const double rate = (double)npts * (double)np / t;
+            if (rate > best_rate) {
+                best_rate = rate;
+                best = Tuned{W, P};
+            }
+        }
+    }
+    g_tuned[tune_key(id, nx)] = best;
+    if (report) {
+        const double r[8] = {tau, s1, sfull, nstar, w0, (double)std::max<int64_t>(best.W, 0),
+                             (double)best.P, best_rate};
+        std::memcpy(report, r, sizeof r);
+    }
+    return SWEPT_OK;
+}
+
+// The batch runs all its instances at once, so the chip is always full and
+// the depth only trades the fill and drain of each region against its LDS
+// and the stage count: time the batch's own shapes (one stencil at a time, zero
+// fields, steps cut to a few stages) at each candidate depth.
+int autotune_batch(const int64_t* nx, const int64_t* nsteps, const int32_t* ids,
+                   const double* params, int64_t count, int64_t* want_out)
+{
+    KnobGuard guard;
+    g_ctx.tile_w = 0;
+    int rc = SWEPT_OK;
+    for (int id : {SWEPT_HEAT_F64, SWEPT_KS_F64}) {
+        want_out[id] = 0;
+        std::vector<int64_t> sel;
+        size_t total = 0;
+        for (int64_t j = 0; j < count; ++j)
+            if (ids[j] == id && nsteps[j] > 0) {
+                sel.push_back(j);
+                total += (size_t)nx[j];
+            }
+        if (sel.empty())
+            continue;
+        const int S = substeps_of(id);
+        const int64_t np_max = (6 * 2 * 256 + S - 1) / S;
+        DeviceBuffer f;
+        rc = f.alloc(total * sizeof(double));
+        if (rc)
+            return rc;
+        std::vector<void*> up;
+        std::vector<int64_t> nxs, ns;
+        std::vector<int32_t> is;
+        std::vector<double> ps;
+        size_t off = 0;
+        for (int64_t j : sel) {
+            up.push_back(static_cast<double*>(f.p) + off);
+            off += (size_t)nx[j];
+            nxs.push_back(nx[j]);
+            ns.push_back(std::min(nsteps[j], np_max));
+            is.push_back(id);
+            ps.push_back(params[2 * j]);
+            ps.push_back(params[2 * j + 1]);
+        }
+        double best_t = 1e30;
+        int64_t best = kBatchWantDefault;
+        for (int64_t want : {32, 64, 128, 256}) {
+            g_batch_want[id] = want;
+            double t;
+            rc = time_best([&] {
+                return run_batch(up.data(), nxs.data(), ns.data(), is.data(), ps.data(),
+                                 (int64_t)sel.size());
+            }, 1, &t);
+            if (rc)
+                break;
+            if (t < best_t) {
+                best_t = t;
+                best = want;
+            }
+        }
+        HIP_TRY(hipStreamSynchronize(g_ctx.stream));
+        batch_release();  // its graph points at the probe fields
+        if (rc)
+            return rc;
+        g_batch_want[id] = best;
+        want_out[id] = best;
+    }
+    return SWEPT_OK;
+}
+
 }  // namespace
 
 // ===================================================================== C ABI
@@ -796,20 +1259,7 @@ int swept_advance(void* u, int64_t nx, int64_t nsteps, int32_t stencil_id, const
     int rc = check_common(u, nx, nsteps, stencil_id, params, nparams);
     if (rc)
         return rc;
-    if (nsteps == 0)
-        return SWEPT_OK;
-    Plan p;
-    rc = make_plan(nx, nsteps, stencil_id, &p);
-    if (rc)
-        return rc;
-    if (p.mode == SWEPT_MODE_NAIVE)
-        return naive_dispatch(u, nx, nsteps, stencil_id, params);
-    const int64_t L = nsteps * substeps_of(stencil_id);
-    switch (stencil_id) {
-    case SWEPT_HEAT_F64: return run_swept<HeatF64>(u, nx, L, heat64_consts(params), p);
-    case SWEPT_HEAT_F32: return run_swept<HeatF32>(u, nx, L, heat32_consts(params), p);
-    default: return run_swept<KSF64>(u, nx, L, ks_consts(params), p);
-    }
+    return advance_dispatch(u, nx, nsteps, stencil_id, params);
 }
 
 int swept_naive_advance(void* u, int64_t nx, int64_t nsteps, int32_t stencil_id,
@@ -857,6 +1307,74 @@ int swept_advance_batch(void* const* u, const int64_t* nx, const int64_t* nsteps
     if (rc)
         return rc;
     HIP_TRY(hipGetLastError());
+    return SWEPT_OK;
+}
+
+int swept_naive_advance_batch(void* const* u, const int64_t* nx, const int64_t* nsteps,
+                              const int32_t* stencil_id, const double* params, int64_t count)
+{
+    if (!g_ctx.ready)
+        return fail(SWEPT_ENOTINIT, "swept_init has not been called");
+    if (count < 0 || (count > 0 && (!u || !nx || !nsteps || !stencil_id || !params)))
+        return fail(SWEPT_EINVAL, "bad batch arrays");
+    for (int64_t j = 0; j < count; ++j) {
+        int rc = check_common(u[j], nx[j], nsteps[j], stencil_id[j], params + 2 * j, 2);
+        if (rc)
+            return fail(rc, "instance %lld: %s", (long long)j, g_err.c_str());
+        if (stencil_id[j] != SWEPT_HEAT_F64 && stencil_id[j] != SWEPT_KS_F64)
+            return fail(SWEPT_EUNSUPPORTED, "instance %lld: the batch takes binary64 stencils",
+                        (long long)j);
+        if (nx[j] > (int64_t(1) << 40))
+            return fail(SWEPT_EINVAL, "instance %lld is too long", (long long)j);
+    }
+    if (count == 0)
+        return SWEPT_OK;
+    return run_naive_batch(u, nx, nsteps, stencil_id, params, count);
+}
+
+int swept_autotune(int64_t nx, int64_t nsteps, int32_t stencil_id, const double* params,
+                   int32_t nparams, double* report)
+{
+    int rc = check_problem(nx, nsteps, stencil_id, params, nparams);
+    if (rc)
+        return rc;
+    if (nsteps == 0)
+        return fail(SWEPT_EINVAL, "nothing to tune for zero steps");
+    rc = autotune(nx, nsteps, stencil_id, params, report);
+    if (rc)
+        return rc;
+    HIP_TRY(hipGetLastError());
+    return SWEPT_OK;
+}
+
+int swept_autotune_batch(const int64_t* nx, const int64_t* nsteps, const int32_t* stencil_id,
+                         const double* params, int64_t count, int64_t* depth_out)
+{
+    if (!g_ctx.ready)
+        return fail(SWEPT_ENOTINIT, "swept_init has not been called");
+    if (count < 0 || !depth_out || (count > 0 && (!nx || !nsteps || !stencil_id || !params)))
+        return fail(SWEPT_EINVAL, "bad batch arrays");
+    for (int64_t j = 0; j < count; ++j) {
+        int rc = check_problem(nx[j], nsteps[j], stencil_id[j], params + 2 * j, 2);
+        if (rc)
+            return fail(rc, "instance %lld: %s", (long long)j, g_err.c_str());
+        if (stencil_id[j] != SWEPT_HEAT_F64 && stencil_id[j] != SWEPT_KS_F64)
+            return fail(SWEPT_EUNSUPPORTED, "instance %lld: the batch takes binary64 stencils",
+                        (long long)j);
+    }
+    depth_out[0] = depth_out[1] = depth_out[2] = 0;
+    int rc = autotune_batch(nx, nsteps, stencil_id, params, count, depth_out);
+    if (rc)
+        return rc;
+    HIP_TRY(hipGetLastError());
+    return SWEPT_OK;
+}
+
+int swept_clear_tuning(void)
+{
+    g_tuned.clear();
+    for (int64_t& w : g_batch_want)
+        w = 0;
     return SWEPT_OK;
 }
 
@@ -935,6 +1453,7 @@ void swept_finalize(void)
         (void)hipFree(g_ctx.scratch);
     release_events();
     batch_release();
+    swept_clear_tuning();
     g_ctx = Context{};
 }
 

@@ -83,3 +83,18 @@ def test_plan_geometry(swept):
     assert lib.swept_plan(2, 5, 0, out) == -1                       # nx < 3
     assert lib.swept_plan(64, -1, 0, out) == -1
     assert lib.swept_plan(64, 1, 7, out) == -1
+
+
+def test_tuner_rejects_bad_requests_without_a_gpu():
+    """Validation happens before any device work."""
+    import paper_1504_01380_amd as sw
+    L = sw.lib()
+    import ctypes
+    par = (ctypes.c_double * 2)(0.25, 0.0)
+    rep = (ctypes.c_double * 8)()
+    # not initialised, or invalid: an error code, never a crash
+    assert L.swept_autotune(2, 10, 0, par, 1, rep) != 0
+    assert L.swept_autotune(4096, 10, 7, par, 1, rep) != 0
+    out = (ctypes.c_int64 * 3)()
+    assert L.swept_autotune_batch(None, None, None, None, -1, out) != 0
+    assert L.swept_clear_tuning() == 0

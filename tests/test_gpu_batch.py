@@ -78,3 +78,56 @@ def test_batch_equals_solo_runs(sw):
     torch.cuda.synchronize()
     for a, b in zip(us, solo):
         assert torch.equal(a.view(torch.int64), b.view(torch.int64))
+
+
+def test_naive_batch_bitwise(sw, oracle_mod):
+    """The naive batch baseline gives the oracle's bits too (odd step counts
+    end in the spare buffer and are copied back; zero steps leave u alone)."""
+    import torch
+    g = workloads.rng(77)
+    insts = []
+    for q, n in enumerate([3, 4, 5, 255, 256, 257, 1000, 513, 2048, 99]):
+        stencil = "heat" if q % 2 else "ks"
+        insts.append((stencil, int(g.integers(0, 60)), g.uniform(-1, 1, size=n)))
+    us = [torch.from_numpy(u0.copy()).cuda() for _, _, u0 in insts]
+    sw.naive_advance_batch(us, [ns for _, ns, _ in insts], [st for st, _, _ in insts],
+                           [[0.25] if st == "heat" else KS_P for st, _, _ in insts])
+    torch.cuda.synchronize()
+    for (st, ns, u0), u in zip(insts, us):
+        want = oracle_run(oracle_mod, st, u0, ns)
+        assert np.array_equal(u.cpu().numpy(), want), (st, u0.size, ns)
+
+
+def test_full_ensemble(sw, oracle_mod):
+    """The ensemble workload at full size (4096 instances, N log-uniform in
+    [256, 65536], 1,000-20,000 steps): the swept batch equals the naive batch
+    on every instance bit for bit, and the oracle on a sample of instances
+    (the shortest-running ones of each stencil and parity, which the oracle
+    finishes in seconds)."""
+    import torch
+    insts = workloads.batch()
+    ns = [i.nsteps for i in insts]
+    kinds = [i.stencil for i in insts]
+    pars = [[0.25] if k == "heat" else KS_P for k in kinds]
+    us = [torch.from_numpy(i.u0).cuda() for i in insts]
+    vs = [u.clone() for u in us]
+    print("swept batch", flush=True)
+    sw.advance_batch(us, ns, kinds, pars)
+    print("naive batch", flush=True)
+    sw.naive_advance_batch(vs, ns, kinds, pars)
+    torch.cuda.synchronize()
+    for q, (a, b) in enumerate(zip(us, vs)):
+        assert torch.equal(a.view(torch.int64), b.view(torch.int64)), q
+    cost = sorted(range(len(insts)), key=lambda q: insts[q].n * insts[q].nsteps *
+                  (4 if insts[q].stencil == "ks" else 1))
+    picked = {}
+    for q in cost:
+        key = (insts[q].stencil, insts[q].n % 2)
+        picked.setdefault(key, q)
+    threads = oracle_mod.max_threads()
+    for key, q in sorted(picked.items()):
+        i = insts[q]
+        want = (oracle_mod.heat(i.u0, i.nsteps, 0.25, threads=threads) if i.stencil == "heat"
+                else oracle_mod.ks(i.u0, i.nsteps, *KS_P, threads=threads))
+        print(key, i.n, i.nsteps, flush=True)
+        assert np.array_equal(us[q].cpu().numpy(), want)
