@@ -99,8 +99,10 @@ int swept_set_stream(void *hip_stream);
 
 /*
  * Tuning of the swept path.  tile_w: points per tile W (even, W divides nx);
- * 0 = automatic.  pairs_per_lane: 1, 2, 4 or 8 (0 = automatic); each lane of
- * a tile's wavefront carries that many adjacent point pairs.  mode: one of
+ * 0 = automatic.  pairs_per_lane: 1, 2, 4 or 8 (0 = automatic; the KS
+ * stencil takes at most 4, and swept_advance fails with SWEPT_EUNSUPPORTED
+ * for 8); each lane of a tile's wavefront carries that many adjacent point
+ * pairs.  mode: one of
  * SWEPT_MODE_*.  The values persist until changed.  Results do not depend on
  * the tuning, bit for bit.
  */

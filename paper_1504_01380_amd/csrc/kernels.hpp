@@ -805,41 +805,57 @@ __global__ __launch_bounds__(NB) void naive_fused_kernel(const typename S::T* __
     fused_block<S, NB>(in, out, n, (int64_t)blockIdx.x * NB, c);
 }
 
-// Naive batch: one launch per time step advances every block of NB points of
-// every instance that still has steps to go.  Blocks never straddle two
-// instances; an instance's field alternates between buf[0] and buf[1].
+// Naive batch: one launch per time step advances every block of NB points
+// (heat: NB = 4 x 256, four points per thread; KS: NB = 256, the fused step
+// above) of every instance that still has steps to go.  Blocks never
+// straddle two instances; an instance's field alternates between buf[0] and
+// buf[1].  A block's record holds all it needs besides the constants, so its
+// loads of field values wait on one table read only.
 template <class S>
 struct NaiveInst {
-    typename S::T* buf[2];
-    int64_t n;
     typename S::Consts c;
 };
 
+template <class S>
 struct NaiveBlock {
-    int32_t inst;
-    int32_t pad;
-    int64_t x0;
+    typename S::T* buf[2];
+    int64_t n, x0;
+    int64_t inst;
 };
 
 template <class S, int NB>
-__global__ __launch_bounds__(NB) void naive_batch_kernel(const NaiveInst<S>* __restrict__ inst,
-                                                        const NaiveBlock* __restrict__ blocks,
-                                                        int parity)
+__global__ __launch_bounds__(256) void naive_batch_kernel(const NaiveInst<S>* __restrict__ inst,
+                                                         const NaiveBlock<S>* __restrict__ blocks,
+                                                         int parity)
 {
-    const NaiveBlock bk = blocks[blockIdx.x];
-    const NaiveInst<S> I = inst[bk.inst];
-    const typename S::T* in = I.buf[parity];
-    typename S::T* out = I.buf[parity ^ 1];
+    const NaiveBlock<S> bk = blocks[blockIdx.x];
+    const typename S::Consts c = inst[bk.inst].c;
+    // a select, not bk.buf[parity]: an indexed record would live in memory
+    const typename S::T* in = parity ? bk.buf[1] : bk.buf[0];
+    typename S::T* out = parity ? bk.buf[0] : bk.buf[1];
     if constexpr (S::NPHASE == 1) {
-        const int64_t i = bk.x0 + threadIdx.x;
-        if (i < I.n) {
-            const int64_t il = i == 0 ? I.n - 1 : i - 1;
-            const int64_t ir = i == I.n - 1 ? 0 : i + 1;
-            out[i] = S::to_field(S::template step<0>(S::from_field(in[il]), S::from_field(in[i]),
-                                                     S::from_field(in[ir]), I.c));
+        static_assert(NB % 256 == 0, "whole points per thread");
+        constexpr int PER = NB / 256;
+        typename S::T v[PER];
+        int64_t xs[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int64_t i = bk.x0 + threadIdx.x + 256 * q;
+            xs[q] = i;
+            if (i < bk.n) {
+                const int64_t il = i == 0 ? bk.n - 1 : i - 1;
+                const int64_t ir = i == bk.n - 1 ? 0 : i + 1;
+                v[q] = S::to_field(S::template step<0>(S::from_field(in[il]), S::from_field(in[i]),
+                                                       S::from_field(in[ir]), c));
+            }
         }
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            if (xs[q] < bk.n)
+                out[xs[q]] = v[q];
     } else {
-        fused_block<S, NB>(in, out, I.n, bk.x0, I.c);
+        static_assert(NB == 256, "one point per thread");
+        fused_block<S, NB>(in, out, bk.n, bk.x0, c);
     }
 }
 

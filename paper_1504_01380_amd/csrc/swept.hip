@@ -310,7 +310,13 @@ int run_swept(void* u, int64_t nx, int64_t L, const typename S::Consts& c, const
         case 1: launch_stage<S, 1>(a, lds, g_ctx.stream, (int)p.tiles, cont); break;
         case 2: launch_stage<S, 2>(a, lds, g_ctx.stream, (int)p.tiles, cont); break;
         case 4: launch_stage<S, 4>(a, lds, g_ctx.stream, (int)p.tiles, cont); break;
-        case 8: launch_stage<S, 8>(a, lds, g_ctx.stream, (int)p.tiles, cont); break;
+        case 8:
+            // eight KS pairs (48 values) per lane exceed the register file
+            if constexpr (S::NPHASE == 1)
+                launch_stage<S, 8>(a, lds, g_ctx.stream, (int)p.tiles, cont);
+            else
+                return fail(SWEPT_EUNSUPPORTED, "the KS stencil takes at most 4 pairs per lane");
+            break;
         default: return fail(SWEPT_EINVAL, "pairs per lane %d not in {1,2,4,8}", p.P);
         }
         if (g_ctx.profiling) {
@@ -772,36 +778,36 @@ int naive_dispatch(void* u, int64_t nx, int64_t nsteps, int32_t id, const double
 // The naive schedule for a batch: per time step, one launch per stencil over
 // the blocks of the instances that still have steps to go (instances sorted
 // by step count, so those blocks are a prefix of the block list).
-template <class S>
-int naive_batch_tables(const std::vector<int64_t>& order, void* const* u, const int64_t* nx,
-                       const int64_t* nsteps, const int32_t* ids, const double* params,
-                       int32_t id, typename S::T* spare, const std::vector<int64_t>& spare_off,
-                       typename S::Consts (*consts)(const double*), std::vector<NaiveInst<S>>& inst,
-                       std::vector<NaiveBlock>& blocks, std::vector<int64_t>& block_steps)
+template <class S, int NB>
+void naive_batch_tables(const std::vector<int64_t>& order, void* const* u, const int64_t* nx,
+                        const int64_t* nsteps, const int32_t* ids, const double* params,
+                        int32_t id, typename S::T* spare, const std::vector<int64_t>& spare_off,
+                        typename S::Consts (*consts)(const double*),
+                        std::vector<NaiveInst<S>>& inst, std::vector<NaiveBlock<S>>& blocks,
+                        std::vector<int64_t>& block_steps)
 {
-    constexpr int NB = 256;
     for (int64_t j : order) {
         if (ids[j] != id || nsteps[j] == 0)
             continue;
-        NaiveInst<S> I{};
-        I.buf[0] = static_cast<typename S::T*>(u[j]);
-        I.buf[1] = spare + spare_off[(size_t)j];
-        I.n = nx[j];
-        I.c = consts(params + 2 * j);
-        const int32_t q = (int32_t)inst.size();
-        inst.push_back(I);
+        const int64_t q = (int64_t)inst.size();
+        inst.push_back(NaiveInst<S>{consts(params + 2 * j)});
         for (int64_t x0 = 0; x0 < nx[j]; x0 += NB) {
-            blocks.push_back(NaiveBlock{q, 0, x0});
+            NaiveBlock<S> b{};
+            b.buf[0] = static_cast<typename S::T*>(u[j]);
+            b.buf[1] = spare + spare_off[(size_t)j];
+            b.n = nx[j];
+            b.x0 = x0;
+            b.inst = q;
+            blocks.push_back(b);
             block_steps.push_back(nsteps[j]);
         }
     }
-    return SWEPT_OK;
 }
 
 int run_naive_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const int32_t* ids,
                     const double* params, int64_t count)
 {
-    constexpr int NB = 256;
+    constexpr int NBH = 1024, NBK = 256;
     std::vector<int64_t> order((size_t)count), spare_off((size_t)count);
     size_t total = 0;
     int64_t smax = 0;
@@ -815,15 +821,16 @@ int run_naive_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, co
                      [&](int64_t a, int64_t b) { return nsteps[a] > nsteps[b]; });
     std::vector<NaiveInst<HeatF64>> ih;
     std::vector<NaiveInst<KSF64>> ik;
-    std::vector<NaiveBlock> bh, bk;
+    std::vector<NaiveBlock<HeatF64>> bh;
+    std::vector<NaiveBlock<KSF64>> bk;
     std::vector<int64_t> sh, sk;
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     const size_t b_f = al(total * sizeof(double));
     const size_t cap_i = al(sizeof(NaiveInst<KSF64>) * (size_t)std::max<int64_t>(1, count));
     size_t nblocks = 0;
     for (int64_t j = 0; j < count; ++j)
-        nblocks += (size_t)((nx[j] + NB - 1) / NB);
-    const size_t b_b = al(sizeof(NaiveBlock) * std::max<size_t>(1, nblocks));
+        nblocks += (size_t)((nx[j] + NBK - 1) / NBK);
+    const size_t b_b = al(sizeof(NaiveBlock<KSF64>) * std::max<size_t>(1, nblocks));
     int rc = ensure_scratch(b_f + 2 * cap_i + 2 * b_b);
     if (rc)
         return rc;
@@ -831,12 +838,12 @@ int run_naive_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, co
     double* spare = reinterpret_cast<double*>(base);
     auto* d_ih = reinterpret_cast<NaiveInst<HeatF64>*>(base + b_f);
     auto* d_ik = reinterpret_cast<NaiveInst<KSF64>*>(base + b_f + cap_i);
-    auto* d_bh = reinterpret_cast<NaiveBlock*>(base + b_f + 2 * cap_i);
-    auto* d_bk = reinterpret_cast<NaiveBlock*>(base + b_f + 2 * cap_i + b_b);
-    naive_batch_tables<HeatF64>(order, u, nx, nsteps, ids, params, SWEPT_HEAT_F64, spare,
-                                spare_off, heat64_consts, ih, bh, sh);
-    naive_batch_tables<KSF64>(order, u, nx, nsteps, ids, params, SWEPT_KS_F64, spare, spare_off,
-                              ks_consts, ik, bk, sk);
+    auto* d_bh = reinterpret_cast<NaiveBlock<HeatF64>*>(base + b_f + 2 * cap_i);
+    auto* d_bk = reinterpret_cast<NaiveBlock<KSF64>*>(base + b_f + 2 * cap_i + b_b);
+    naive_batch_tables<HeatF64, NBH>(order, u, nx, nsteps, ids, params, SWEPT_HEAT_F64, spare,
+                                     spare_off, heat64_consts, ih, bh, sh);
+    naive_batch_tables<KSF64, NBK>(order, u, nx, nsteps, ids, params, SWEPT_KS_F64, spare,
+                                   spare_off, ks_consts, ik, bk, sk);
     HIP_TRY(hipStreamSynchronize(g_ctx.stream));
     if (!ih.empty()) {
         HIP_TRY(hipMemcpy(d_ih, ih.data(), sizeof(ih[0]) * ih.size(), hipMemcpyHostToDevice));
@@ -851,10 +858,10 @@ int run_naive_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, co
         while (ph > 0 && sh[ph - 1] <= s) --ph;
         while (pk > 0 && sk[pk - 1] <= s) --pk;
         if (ph)
-            hipLaunchKernelGGL((naive_batch_kernel<HeatF64, NB>), dim3((unsigned)ph), dim3(NB), 0,
-                               g_ctx.stream, d_ih, d_bh, (int)(s & 1));
+            hipLaunchKernelGGL((naive_batch_kernel<HeatF64, NBH>), dim3((unsigned)ph), dim3(256),
+                               0, g_ctx.stream, d_ih, d_bh, (int)(s & 1));
         if (pk)
-            hipLaunchKernelGGL((naive_batch_kernel<KSF64, NB>), dim3((unsigned)pk), dim3(NB), 0,
+            hipLaunchKernelGGL((naive_batch_kernel<KSF64, NBK>), dim3((unsigned)pk), dim3(256), 0,
                                g_ctx.stream, d_ik, d_bk, (int)(s & 1));
     }
     // an odd step count leaves the result in the spare buffer

@@ -190,3 +190,12 @@ def test_banded_and_continuous_kernels_agree(sw, oracle_mod, stencil, n, W, P, n
     assert same_bits(run(sw, sw.advance, u0, nsteps, stencil, par), want)
     sw.set_tuning(W, P, sw.MODE_STAGE_BANDED)
     assert same_bits(run(sw, sw.advance, u0, nsteps, stencil, par), want)
+
+
+def test_ks_rejects_eight_pairs_per_lane(sw):
+    import paper_1504_01380_amd as swmod
+    sw.set_tuning(2048, 8, sw.MODE_STAGE)
+    u = __import__("torch").zeros(4096, dtype=__import__("torch").float64, device="cuda")
+    with pytest.raises(swmod.SweptError):
+        sw.advance(u, 10, "ks", KS_P)
+    sw.set_tuning(0, 0, sw.MODE_AUTO)
