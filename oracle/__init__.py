@@ -62,10 +62,11 @@ def lib() -> ctypes.CDLL:
         L.oracle_ks_f64_points.argtypes = [vp, i64, i64, dbl, dbl, vp, i64, vp]
         L.oracle_heat_f64_adjoint.argtypes = [vp, i64, i64, dbl, i64, dbl, vp, vp, i32]
         L.oracle_ks_f64_adjoint.argtypes = [vp, i64, i64, dbl, dbl, i64, dbl, vp, vp, i32]
+        L.oracle_euler_f64.argtypes = [vp, i64, i64, dbl, dbl, dbl, i32]
         for name in ("oracle_heat_f64", "oracle_heat_f32", "oracle_ks_f64",
                      "oracle_heat_f64_points", "oracle_heat_f32_points",
                      "oracle_ks_f64_points", "oracle_max_threads", "oracle_heat_f64_adjoint",
-                     "oracle_ks_f64_adjoint"):
+                     "oracle_ks_f64_adjoint", "oracle_euler_f64"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -103,6 +104,20 @@ def ks(u0: np.ndarray, nsteps: int, dt: float, dx: float, threads: int = 0) -> n
     _check(lib().oracle_ks_f64(u.ctypes.data, u.size, int(nsteps), float(dt), float(dx),
                                int(threads)), "oracle_ks_f64")
     return u
+
+
+def euler(q0: np.ndarray, nsteps: int, dt: float, dx: float, gamma: float,
+          threads: int = 0) -> np.ndarray:
+    """1D Euler equations, paper Section 7 (second-order finite volume, minmod
+    limiter, scalar dissipation by the Roe spectral radius, midpoint RK2) as
+    four radius-1 sub-timesteps (Section 2).  q0 has shape (N, 3): rho, m, E
+    per cell; float64."""
+    q = np.array(q0, dtype=np.float64, copy=True, order="C")
+    if q.ndim != 2 or q.shape[1] != 3:
+        raise ValueError("q0 must have shape (N, 3)")
+    _check(lib().oracle_euler_f64(q.ctypes.data, q.shape[0], int(nsteps), float(dt), float(dx),
+                                  float(gamma), int(threads)), "oracle_euler_f64")
+    return q
 
 
 def heat_points(u0: np.ndarray, nsteps: int, r: float, idx) -> np.ndarray:

@@ -356,3 +356,230 @@ def test_ks_adjoint_linear_regime(oracle_mod):
     got = oracle_mod.ks_adjoint(np.zeros(n), nsteps, 0.005, 0.5, nsteps + 1, 0.0, c)
     z = 0.005 * ks_symbol(m, n, 0.5)
     assert np.abs(got - (1 + z + z * z / 2) ** nsteps * c).max() < 1e-12
+
+
+def _ks_jvp(u0, v, nsteps, dt, dx, n0, wgt, cot):
+    """J and its derivative along v by forward-mode (dual-number) stepping of
+    the KS scheme written out here: per RK2 step w = D2 u, p = u + (dt/2) F(u,w),
+    z = D2 p, u' = u + dt F(p,z), F(a,b) = -(a D1 a + b + D2 b)."""
+    c1, c2 = 1.0 / (2.0 * dx), 1.0 / (dx * dx)
+
+    def d1(a):
+        return (np.roll(a, -1) - np.roll(a, 1)) * c1
+
+    def d2(a):
+        return ((np.roll(a, 1) + np.roll(a, -1)) - 2.0 * a) * c2
+
+    def F(a, da, b, db):
+        return (-(a * d1(a) + b + d2(b)),
+                -(da * d1(a) + a * d1(da) + db + d2(db)))
+
+    u, du = u0.copy(), v.copy()
+    J = dJ = 0.0
+    if n0 <= 0:
+        J += wgt * np.dot(u, u)
+        dJ += 2 * wgt * np.dot(u, du)
+    for j in range(1, nsteps + 1):
+        w, dw = d2(u), d2(du)
+        f, df = F(u, du, w, dw)
+        p, dp = u + 0.5 * dt * f, du + 0.5 * dt * df
+        z, dz = d2(p), d2(dp)
+        f, df = F(p, dp, z, dz)
+        u, du = u + dt * f, du + dt * df
+        if j >= n0:
+            J += wgt * np.dot(u, u)
+            dJ += 2 * wgt * np.dot(u, du)
+    if cot is not None:
+        J += np.dot(cot, u)
+        dJ += np.dot(cot, du)
+    return J, dJ
+
+
+@pytest.mark.parametrize("n,nsteps,n0,with_cot", [(16, 5, 2, True), (40, 30, 20, False),
+                                                  (9, 12, 0, True)])
+def test_ks_adjoint_matches_forward_mode(oracle_mod, n, nsteps, n0, with_cot):
+    """Reverse mode (the oracle's adjoint) against forward mode (dual numbers
+    through the scheme, no truncation error): <dJ/du0, v> = dJ(u0; v) to
+    rounding, for random directions v."""
+    u0 = 3 * workloads.smoothed_noise(n, seed=n + 5)
+    cot = workloads.white_noise(n, seed=n + 6) if with_cot else None
+    wgt = 1.0 / (5 * n)
+    g = oracle_mod.ks_adjoint(u0, nsteps, 0.005, 0.5, n0, wgt, cot)
+    rng = workloads.rng(n + 7)
+    for _ in range(5):
+        v = rng.standard_normal(n)
+        _, dJ = _ks_jvp(u0, v, nsteps, 0.005, 0.5, n0, wgt, cot)
+        assert abs(np.dot(g, v) - dJ) <= 1e-11 * (abs(dJ) + np.abs(g).sum() * np.abs(v).max())
+
+
+# ------------------------------------------------------------------- Euler
+GAMMA = 1.4
+
+
+def euler_state(rho, u, p, gamma=GAMMA):
+    rho, u, p = np.broadcast_arrays(np.asarray(rho, float), np.asarray(u, float),
+                                    np.asarray(p, float))
+    return np.stack([rho, rho * u, p / (gamma - 1) + 0.5 * rho * u * u], axis=-1)
+
+
+def euler_primitive(q, gamma=GAMMA):
+    rho = q[:, 0]
+    u = q[:, 1] / rho
+    return rho, u, (gamma - 1) * (q[:, 2] - 0.5 * rho * u * u)
+
+
+def exact_riemann(left, right, xi, gamma=GAMMA):
+    """Exact solution of the 1D Riemann problem (left/right = (rho, u, p)) at
+    similarity coordinates xi = x/t: the star pressure from the two-rarefaction
+    / two-shock pressure functions (found by bisection), then the wave pattern
+    sampled at each xi (the textbook construction, e.g. Toro, Riemann Solvers
+    and Numerical Methods for Fluid Dynamics, ch. 4)."""
+    g = gamma
+    rl, ul, pl = left
+    rr, ur, pr = right
+    cl, cr = np.sqrt(g * pl / rl), np.sqrt(g * pr / rr)
+
+    def fk(p, rk, pk, ck):
+        if p > pk:       # shock
+            A, B = 2 / ((g + 1) * rk), (g - 1) / (g + 1) * pk
+            return (p - pk) * np.sqrt(A / (p + B))
+        return 2 * ck / (g - 1) * ((p / pk) ** ((g - 1) / (2 * g)) - 1)
+
+    def fsum(p):
+        return fk(p, rl, pl, cl) + fk(p, rr, pr, cr) + (ur - ul)
+
+    lo, hi = 1e-12, 10 * max(pl, pr)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if fsum(mid) > 0:
+            hi = mid
+        else:
+            lo = mid
+    ps = 0.5 * (lo + hi)
+    us = 0.5 * (ul + ur) + 0.5 * (fk(ps, rr, pr, cr) - fk(ps, rl, pl, cl))
+
+    def side(xi_, rk, uk, pk, ck, sgn):
+        # sgn = -1 for the left wave, +1 for the right wave; xi_ measured as is
+        if ps > pk:      # shock
+            rs = rk * ((ps / pk + (g - 1) / (g + 1)) / ((g - 1) / (g + 1) * ps / pk + 1))
+            S = uk + sgn * ck * np.sqrt((g + 1) / (2 * g) * ps / pk + (g - 1) / (2 * g))
+            if sgn * (xi_ - S) > 0:
+                return rk, uk, pk
+            return rs, us, ps
+        rs = rk * (ps / pk) ** (1 / g)
+        cs = ck * (ps / pk) ** ((g - 1) / (2 * g))
+        head, tail = uk + sgn * ck, us + sgn * cs
+        if sgn * (xi_ - head) > 0:
+            return rk, uk, pk
+        if sgn * (xi_ - tail) < 0:
+            return rs, us, ps
+        # inside the fan
+        u = 2 / (g + 1) * (-sgn * ck + (g - 1) / 2 * uk + xi_)
+        c = sgn * (xi_ - u)
+        rho = rk * (c / ck) ** (2 / (g - 1))
+        return rho, u, pk * (c / ck) ** (2 * g / (g - 1))
+
+    out = np.empty((len(xi), 3))
+    for j, x in enumerate(xi):
+        out[j] = side(x, rl, ul, pl, cl, -1) if x < us else side(x, rr, ur, pr, cr, +1)
+    return out
+
+
+def mirrored_sod(n):
+    """The periodic Sod problem: rho = 0.125, u = 0, p = 0.1 on the left half
+    of [0, 1), rho = 1, u = 0, p = 1 on the right half."""
+    x = (np.arange(n) + 0.5) / n
+    lowside = x < 0.5
+    return euler_state(np.where(lowside, 0.125, 1.0), 0.0, np.where(lowside, 0.1, 1.0))
+
+
+def test_euler_uniform_state_is_exact(oracle_mod):
+    q0 = np.tile(euler_state(0.8, 0.7, 1.3), (37, 1))
+    assert np.array_equal(oracle_mod.euler(q0, 60, 0.01, 1 / 37, GAMMA), q0)
+
+
+def test_euler_conservation(oracle_mod):
+    n = 256
+    x = (np.arange(n) + 0.5) / n
+    q0 = euler_state(1 + 0.3 * np.sin(2 * np.pi * x), 0.5 * np.cos(4 * np.pi * x),
+                     1 + 0.2 * np.sin(6 * np.pi * x))
+    q = oracle_mod.euler(q0, 200, 0.2 / n, 1 / n, GAMMA)
+    assert np.allclose(q.sum(axis=0), q0.sum(axis=0), rtol=1e-13, atol=1e-12)
+    assert not np.allclose(q, q0)
+
+
+def test_euler_mirror_symmetry_is_exact(oracle_mod):
+    """Reflection about x = 1/4 (cell i <-> cell n/2-1-i) with u -> -u maps
+    the mirrored Sod problem to itself; every operation of the scheme commutes
+    with it exactly, so the result is symmetric bit for bit."""
+    n = 96
+    q = oracle_mod.euler(mirrored_sod(n), 120, 0.2 / n, 1 / n, GAMMA)
+    j = (n // 2 - 1 - np.arange(n)) % n
+    assert np.array_equal(q[:, 0], q[j, 0])
+    assert np.array_equal(q[:, 1], -q[j, 1])
+    assert np.array_equal(q[:, 2], q[j, 2])
+    assert np.abs(q[:, 1]).max() > 0.1
+
+
+def test_euler_translation_is_exact(oracle_mod):
+    n = 64
+    q0 = mirrored_sod(n)
+    a = oracle_mod.euler(np.roll(q0, 11, axis=0), 50, 0.2 / n, 1 / n, GAMMA)
+    b = np.roll(oracle_mod.euler(q0, 50, 0.2 / n, 1 / n, GAMMA), 11, axis=0)
+    assert np.array_equal(a, b)
+
+
+def _sod_error(oracle_mod, n, t=0.1, cfl=0.2):
+    dx = 1 / n
+    nsteps = int(round(t / (cfl * dx)))
+    dt = t / nsteps
+    q = oracle_mod.euler(mirrored_sod(n), nsteps, dt, dx, GAMMA)
+    x = (np.arange(n) + 0.5) / n
+    # two Riemann problems: at x = 1/2 (low | high) and at x = 0 = 1 (high | low)
+    low, high = (0.125, 0.0, 0.1), (1.0, 0.0, 1.0)
+    near_half = np.abs(x - 0.5) < 0.25
+    want = np.empty((n, 3))
+    want[near_half] = exact_riemann(low, high, (x[near_half] - 0.5) / t)
+    xd = np.where(x[~near_half] > 0.5, x[~near_half] - 1.0, x[~near_half])
+    want[~near_half] = exact_riemann(high, low, xd / t)
+    rho, u, p = euler_primitive(q)
+    return (np.abs(rho - want[:, 0]).mean(), np.abs(u - want[:, 1]).mean(),
+            np.abs(p - want[:, 2]).mean())
+
+
+def test_euler_sod_against_exact_riemann(oracle_mod):
+    """Density, velocity and pressure at t = 0.1 against the exact solutions
+    of the two Riemann problems (they have not met yet), with the L1 error
+    falling as the grid is refined."""
+    e200 = _sod_error(oracle_mod, 200)
+    e800 = _sod_error(oracle_mod, 800)
+    assert e800[0] < 4e-3 and e800[1] < 1e-2 and e800[2] < 4e-3
+    for a, b in zip(e200, e800):
+        assert b < a / 2.2
+
+
+def test_euler_smooth_convergence(oracle_mod):
+    """An entropy wave (rho = 1 + 0.2 sin 2 pi x, u = 1, p = 1) is carried
+    unchanged at speed 1; the scheme converges at about second order (minmod
+    clips the extrema, so the L1 order is a little below 2)."""
+    errs = []
+    for n in (64, 128, 256):
+        x = (np.arange(n) + 0.5) / n
+        t, nsteps = 0.25, n
+        q0 = euler_state(1 + 0.2 * np.sin(2 * np.pi * x), 1.0, 1.0)
+        q = oracle_mod.euler(q0, nsteps, t / nsteps, 1 / n, GAMMA)
+        # exact cell averages of the translated wave
+        xa, xb = x - 0.5 / n - t, x + 0.5 / n - t
+        avg = 1 + 0.2 * (np.cos(2 * np.pi * xa) - np.cos(2 * np.pi * xb)) / (2 * np.pi / n)
+        errs.append(np.abs(q[:, 0] - avg).mean())
+    assert errs[0] / errs[1] > 2.8 and errs[1] / errs[2] > 2.8
+
+
+def test_exact_riemann_reference_values():
+    """The test's exact Riemann solver reproduces the published star state of
+    Sod's problem (rho, u, p) = (1, 0, 1) | (0.125, 0, 0.1), gamma = 1.4:
+    p* = 0.30313, u* = 0.92745, rho*L = 0.42632, rho*R = 0.26557."""
+    left, right = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    a, b = exact_riemann(left, right, np.array([0.9, 1.0]))
+    assert abs(a[2] - 0.30313) < 1e-5 and abs(a[1] - 0.92745) < 1e-5
+    assert abs(a[0] - 0.42632) < 1e-5 and abs(b[0] - 0.26557) < 1e-5

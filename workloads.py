@@ -23,6 +23,11 @@ Workloads (sizes and distributions of the five benchmark configurations):
   dx=0.5), N log-uniform in [256, 65536] (odd N occurs), steps uniform in
   [1000, 20000], u0 ~ U[-1, 1].
 * ``ks_adjoint``   KS at N=2**16, 20,000 steps, u0 as for ``ks``.
+* ``euler``        1D Euler equations, N=2**20 cells on [0, 1) (dx = 1/N),
+  gamma = 1.4, dt = 0.2 dx, 10,000 midpoint steps; the periodic Sod problem:
+  rho = 0.125, u = 0, p = 0.1 on the left half, rho = 1, u = 0, p = 1 on the
+  right half (no randomness).  Parity tests also use ``euler_smooth``: seeded
+  random Fourier modes in rho, u, p around (1, 0, 1).
 """
 from __future__ import annotations
 
@@ -95,12 +100,47 @@ def batch(count: int = 4096, seed: int = 1003, nmin: int = 256, nmax: int = 6553
     return out
 
 
+EULER_GAMMA = 1.4
+EULER_CFL = 0.2
+
+
+def euler_state(rho, u, p, gamma: float = EULER_GAMMA) -> np.ndarray:
+    """Conserved variables (rho, rho u, E) per cell, shape (N, 3)."""
+    rho, u, p = np.broadcast_arrays(np.asarray(rho, float), np.asarray(u, float),
+                                    np.asarray(p, float))
+    return np.ascontiguousarray(np.stack([rho, rho * u, p / (gamma - 1) + 0.5 * rho * u * u],
+                                         axis=-1))
+
+
+def euler_mirrored_sod(n: int) -> np.ndarray:
+    """The periodic Sod problem on n cells of [0, 1)."""
+    x = (np.arange(n) + 0.5) / n
+    low = x < 0.5
+    return euler_state(np.where(low, 0.125, 1.0), 0.0, np.where(low, 0.1, 1.0))
+
+
+def euler_smooth(n: int, seed: int, modes: int = 6) -> np.ndarray:
+    """rho, u, p = (1, 0, 1) plus seeded random low Fourier modes (rho and p
+    stay within [0.5, 1.5])."""
+    g = rng(seed)
+    x = (np.arange(n) + 0.5) / n
+    fields = []
+    for base, amp in ((1.0, 0.5), (0.0, 0.5), (1.0, 0.5)):
+        f = np.zeros(n)
+        for m in g.choice(np.arange(1, 9), size=modes, replace=True):
+            f += g.uniform(-1, 1) * np.sin(2 * np.pi * m * x + g.uniform(0, 2 * np.pi))
+        fields.append(base + amp * f / max(1.0, np.abs(f).max()))
+    return euler_state(*fields)
+
+
 WORKLOADS = {
     "heat_small": dict(stencil="heat", n=4096, nsteps=10_000, r=HEAT_R, seed=1000),
     "heat_large": dict(stencil="heat", n=1 << 24, nsteps=20_000, r=HEAT_R, seed=1001),
     "ks": dict(stencil="ks", n=1 << 20, nsteps=50_000, dt=KS_DT, dx=KS_DX, seed=1002),
     "batch": dict(count=4096, seed=1003),
     "ks_adjoint": dict(stencil="ks", n=1 << 16, nsteps=20_000, dt=KS_DT, dx=KS_DX, seed=1004),
+    "euler": dict(stencil="euler", n=1 << 20, nsteps=10_000, gamma=EULER_GAMMA, cfl=EULER_CFL,
+                  seed=1005),
 }
 
 
@@ -114,4 +154,6 @@ def initial(name: str, dtype=np.float64, n: int | None = None) -> np.ndarray:
         return white_noise(size, w["seed"], dtype)
     if name in ("ks", "ks_adjoint"):
         return smoothed_noise(size, w["seed"]).astype(dtype)
+    if name == "euler":
+        return euler_mirrored_sod(size)
     raise KeyError(name)
