@@ -71,11 +71,26 @@ typedef enum {
  *   with D2(a) = ((a[i-1]+a[i+1]) - 2a[i])*c2, D1(a) = (a[i+1]-a[i-1])*c1,
  *   F(a,b) = -(((a*D1(a)) + b) + D2(b)), c1 = 1/(2dx), c2 = 1/(dx*dx),
  *   h = dt/2, all in binary64.  params = { dt, dx } (nparams >= 2, dx > 0).
+ *
+ * SWEPT_EULER_F64: the 1D Euler equations of gas dynamics by second-order
+ *   finite volumes (paper, Section 7: minmod limiter, interface flux with
+ *   scalar dissipation proportional to the spectral radius of the Roe
+ *   matrix, midpoint Runge-Kutta; Section 2: a slope sub-timestep and a
+ *   flux-difference sub-timestep per Runge-Kutta stage), four sub-timesteps
+ *   per step:  s = slope(q);  r = q - ch*dF(q,s);  s = slope(r);
+ *   q' = q - cf*dF(r,s),  ch = (dt/2)/dx, cf = dt/dx.  slope is the minmod of
+ *   the one-sided differences; dF the difference of the two face fluxes
+ *   F = (f(qL) + f(qR))/2 - (|u| + c)/2 (qR - qL), u and c at the Roe average
+ *   of the states qL = v[i] + s[i]/2, qR = v[i+1] - s[i+1]/2.  A cell is
+ *   three binary64 values (rho, rho*u, E), interleaved: u points to 3*nx
+ *   doubles.  params = { dt, dx, gamma } (nparams >= 3, dx > 0, gamma > 1).
+ *   Not available in swept_advance_batch or swept_adjoint.
  */
 enum {
     SWEPT_HEAT_F64 = 0,
     SWEPT_HEAT_F32 = 1,
-    SWEPT_KS_F64 = 2
+    SWEPT_KS_F64 = 2,
+    SWEPT_EULER_F64 = 3
 };
 
 /* Schedules for swept_set_tuning. */

@@ -20,7 +20,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libswept.so")
 
-HEAT_F64, HEAT_F32, KS_F64 = 0, 1, 2
+HEAT_F64, HEAT_F32, KS_F64, EULER_F64 = 0, 1, 2, 3
 MODE_AUTO, MODE_STAGE, MODE_NAIVE, MODE_STAGE_BANDED = 0, 1, 2, 3
 
 _STATUS = {0: "SWEPT_OK", -1: "SWEPT_EINVAL", -2: "SWEPT_ENOTINIT", -3: "SWEPT_ENOMEM",
@@ -94,7 +94,7 @@ def _check(rc: int, what: str) -> None:
 
 
 def stencil_id(stencil, dtype: torch.dtype | None = None) -> int:
-    """'heat' (float64 or float32 by dtype), 'ks', or an integer id."""
+    """'heat' (float64 or float32 by dtype), 'ks', 'euler', or an integer id."""
     if isinstance(stencil, int):
         return stencil
     s = stencil.lower()
@@ -102,6 +102,8 @@ def stencil_id(stencil, dtype: torch.dtype | None = None) -> int:
         return HEAT_F32 if dtype == torch.float32 else HEAT_F64
     if s == "ks":
         return KS_F64
+    if s == "euler":
+        return EULER_F64
     raise ValueError("unknown stencil %r" % (stencil,))
 
 
@@ -110,7 +112,7 @@ def dtype_of(sid: int) -> torch.dtype:
 
 
 def substeps(sid: int) -> int:
-    return 4 if sid == KS_F64 else 1
+    return 4 if sid in (KS_F64, EULER_F64) else 1
 
 
 def init(device: int = 0) -> None:
@@ -119,17 +121,23 @@ def init(device: int = 0) -> None:
     _device = int(device)
 
 
-def _prepare(u: torch.Tensor, sid: int) -> None:
+def _prepare(u: torch.Tensor, sid: int) -> int:
+    """Check u for the stencil, bind the library to u's device and torch's
+    current stream; returns the number of grid points (cells)."""
     if not u.is_cuda:
         raise ValueError("u must be a device tensor")
     if u.dtype != dtype_of(sid):
         raise TypeError("stencil %d needs %s, got %s" % (sid, dtype_of(sid), u.dtype))
-    if not u.is_contiguous() or u.dim() != 1:
+    if sid == EULER_F64:
+        if not u.is_contiguous() or u.dim() != 2 or u.shape[1] != 3:
+            raise ValueError("Euler fields are contiguous (N, 3) tensors of (rho, m, E)")
+    elif not u.is_contiguous() or u.dim() != 1:
         raise ValueError("u must be a contiguous 1-D tensor")
     if _device != u.device.index:
         init(u.device.index)
     _check(_lib.swept_set_stream(ctypes.c_void_p(torch.cuda.current_stream(u.device).cuda_stream)),
            "swept_set_stream")
+    return u.shape[0]
 
 
 def _params(params: Sequence[float]):
@@ -151,9 +159,9 @@ def plan(nx: int, nsteps: int, stencil, dtype: torch.dtype | None = None) -> dic
 def advance(u: torch.Tensor, nsteps: int, stencil, params: Sequence[float]) -> torch.Tensor:
     """Advance u in place by nsteps time steps with the swept rule."""
     sid = stencil_id(stencil, u.dtype)
-    _prepare(u, sid)
+    nx = _prepare(u, sid)
     p, npar = _params(params)
-    _check(_lib.swept_advance(ctypes.c_void_p(u.data_ptr()), u.numel(), int(nsteps), sid, p, npar),
+    _check(_lib.swept_advance(ctypes.c_void_p(u.data_ptr()), nx, int(nsteps), sid, p, npar),
            "swept_advance")
     return u
 
@@ -161,19 +169,19 @@ def advance(u: torch.Tensor, nsteps: int, stencil, params: Sequence[float]) -> t
 def naive_advance(u: torch.Tensor, nsteps: int, stencil, params: Sequence[float]) -> torch.Tensor:
     """Advance u in place with one kernel launch per time step."""
     sid = stencil_id(stencil, u.dtype)
-    _prepare(u, sid)
+    nx = _prepare(u, sid)
     p, npar = _params(params)
-    _check(_lib.swept_naive_advance(ctypes.c_void_p(u.data_ptr()), u.numel(), int(nsteps), sid,
+    _check(_lib.swept_naive_advance(ctypes.c_void_p(u.data_ptr()), nx, int(nsteps), sid,
                                     p, npar), "swept_naive_advance")
     return u
 
 
 def naive_substep_advance(u: torch.Tensor, nsteps: int, stencil, params: Sequence[float]):
-    """KS only: one kernel launch per sub-timestep."""
+    """KS and Euler: one kernel launch per sub-timestep."""
     sid = stencil_id(stencil, u.dtype)
-    _prepare(u, sid)
+    nx = _prepare(u, sid)
     p, npar = _params(params)
-    _check(_lib.swept_naive_substep_advance(ctypes.c_void_p(u.data_ptr()), u.numel(), int(nsteps),
+    _check(_lib.swept_naive_substep_advance(ctypes.c_void_p(u.data_ptr()), nx, int(nsteps),
                                             sid, p, npar), "swept_naive_substep_advance")
     return u
 

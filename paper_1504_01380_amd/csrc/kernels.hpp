@@ -155,8 +155,8 @@ __device__ __forceinline__ void banded_region(typename S::T* u, const typename S
                     A[q] = re[2 * d + 1];
                 }
             } else {
-                A[q] = S::from_field(T(0));
-                B[q] = S::from_field(T(0));
+                A[q] = S::from_field(T{});
+                B[q] = S::from_field(T{});
             }
         }
 

@@ -190,4 +190,128 @@ struct KSF64 {
     __device__ __forceinline__ static double grad(const Ad& a) { return a.u; }
 };
 
+// ---------------------------------------------------------------- Euler
+// 1D Euler equations of gas dynamics (paper, Section 7): second-order
+// finite volume with the minmod limiter, interface flux with scalar
+// dissipation proportional to the spectral radius of the Roe matrix, and the
+// midpoint Runge-Kutta rule; as in Section 2, each Runge-Kutta stage is a
+// slope sub-timestep and a flux-difference sub-timestep:
+//   sub0  s = slope(q)               sub1  r  = q - ch*dF(q, s)
+//   sub2  s = slope(r)               sub3  q' = q - cf*dF(r, s)
+// slope = minmod of the one-sided differences, per conserved variable;
+// dF(v, s) = F[i+1/2] - F[i-1/2], each face flux from the states
+// reconstructed on its two sides, F = (f(qL) + f(qR))/2 - (lam/2)(qR - qL),
+// lam = |u| + c at the Roe average.  ch = (dt/2)/dx, cf = dt/dx.  A cell's
+// field value is (rho, m = rho u, E); a point carries q, r and s.
+struct Cons {
+    double r, m, e;
+};
+
+struct EulerF64 {
+    using T = Cons;
+    struct Pt {
+        double q[3], r[3], s[3];
+    };
+    struct Consts {
+        double gm1, ch, cf;
+    };
+    static constexpr int NPHASE = 4;
+
+    __device__ __forceinline__ static Pt from_field(const Cons& v)
+    {
+        return Pt{{v.r, v.m, v.e}, {v.r, v.m, v.e}, {0.0, 0.0, 0.0}};
+    }
+    __device__ __forceinline__ static Cons to_field(const Pt& p)
+    {
+        return Cons{p.q[0], p.q[1], p.q[2]};
+    }
+    __device__ __forceinline__ static Pt shr1(const Pt& v, const Pt& old)
+    {
+        Pt o;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            o.q[c] = dpp_shr1(v.q[c], old.q[c]);
+            o.r[c] = dpp_shr1(v.r[c], old.r[c]);
+            o.s[c] = dpp_shr1(v.s[c], old.s[c]);
+        }
+        return o;
+    }
+    __device__ __forceinline__ static double minmod(double a, double b)
+    {
+        if (a > 0.0 && b > 0.0)
+            return a < b ? a : b;
+        if (a < 0.0 && b < 0.0)
+            return a > b ? a : b;
+        return 0.0;
+    }
+    // physical flux f(q); returns the total enthalpy (E + p)/rho
+    __device__ __forceinline__ static double flux(const double (&q)[3], double gm1, double (&f)[3])
+    {
+        const double u = q[1] / q[0];
+        const double p = gm1 * (q[2] - (0.5 * (q[1] * u)));
+        f[0] = q[1];
+        f[1] = (q[1] * u) + p;
+        f[2] = (q[2] + p) * u;
+        return (q[2] + p) / q[0];
+    }
+    // the face flux from the values v and slopes s of the cells on its two sides
+    __device__ __forceinline__ static void face(const double (&vl)[3], const double (&sl)[3],
+                                                const double (&vr)[3], const double (&sr)[3],
+                                                double gm1, double (&F)[3])
+    {
+        double qL[3], qR[3], fL[3], fR[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            qL[c] = vl[c] + (0.5 * sl[c]);
+            qR[c] = vr[c] - (0.5 * sr[c]);
+        }
+        const double HL = flux(qL, gm1, fL);
+        const double HR = flux(qR, gm1, fR);
+        const double a = sqrt(qL[0]), b = sqrt(qR[0]);
+        const double uL = qL[1] / qL[0], uR = qR[1] / qR[0];
+        const double ur = ((a * uL) + (b * uR)) / (a + b);
+        const double Hr = ((a * HL) + (b * HR)) / (a + b);
+        const double cr2 = gm1 * (Hr - (0.5 * (ur * ur)));
+        const double lam = fabs(ur) + (cr2 > 0.0 ? sqrt(cr2) : 0.0);
+        const double hl = 0.5 * lam;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            F[c] = (0.5 * (fL[c] + fR[c])) - (hl * (qR[c] - qL[c]));
+    }
+    template <int PH>
+    __device__ __forceinline__ static Pt step(const Pt& l, const Pt& c, const Pt& r,
+                                              const Consts& k)
+    {
+        Pt o = c;
+        if constexpr (PH == 0 || PH == 2) {   // limited slopes of q (sub0) or r (sub2)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double vl = PH == 0 ? l.q[j] : l.r[j];
+                const double vc = PH == 0 ? c.q[j] : c.r[j];
+                const double vr = PH == 0 ? r.q[j] : r.r[j];
+                o.s[j] = minmod(vc - vl, vr - vc);
+            }
+        } else {                              // flux differences of (q, s) or (r, s)
+            double FL[3], FR[3];
+            if constexpr (PH == 1) {
+                face(l.q, l.s, c.q, c.s, k.gm1, FL);
+                face(c.q, c.s, r.q, r.s, k.gm1, FR);
+            } else {
+                face(l.r, l.s, c.r, c.s, k.gm1, FL);
+                face(c.r, c.s, r.r, r.s, k.gm1, FR);
+            }
+            const double coef = PH == 1 ? k.ch : k.cf;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double v = c.q[j] - (coef * (FR[j] - FL[j]));
+                if constexpr (PH == 1)
+                    o.r[j] = v;
+                else
+                    o.q[j] = o.r[j] = v;
+            }
+        }
+        return o;
+    }
+};
+
 }  // namespace swept

@@ -88,13 +88,14 @@ int ensure_scratch(size_t bytes)
 
 // ------------------------------------------------------------------ stencils
 
-int substeps_of(int id) { return id == SWEPT_KS_F64 ? 4 : 1; }
+int substeps_of(int id) { return (id == SWEPT_KS_F64 || id == SWEPT_EULER_F64) ? 4 : 1; }
 
 size_t pt_bytes(int id)
 {
     switch (id) {
     case SWEPT_HEAT_F64: return sizeof(HeatF64::Pt);
     case SWEPT_HEAT_F32: return sizeof(HeatF32::Pt);
+    case SWEPT_EULER_F64: return sizeof(EulerF64::Pt);
     default: return sizeof(KSF64::Pt);
     }
 }
@@ -107,16 +108,19 @@ int check_problem(int64_t nx, int64_t nsteps, int32_t id, const double* params, 
         return fail(SWEPT_EINVAL, "nx = %lld: need at least 3 points", (long long)nx);
     if (nsteps < 0)
         return fail(SWEPT_EINVAL, "nsteps = %lld is negative", (long long)nsteps);
-    if (id != SWEPT_HEAT_F64 && id != SWEPT_HEAT_F32 && id != SWEPT_KS_F64)
+    if (id != SWEPT_HEAT_F64 && id != SWEPT_HEAT_F32 && id != SWEPT_KS_F64 &&
+        id != SWEPT_EULER_F64)
         return fail(SWEPT_EINVAL, "unknown stencil id %d", id);
-    const int need = id == SWEPT_KS_F64 ? 2 : 1;
+    const int need = id == SWEPT_EULER_F64 ? 3 : (id == SWEPT_KS_F64 ? 2 : 1);
     if (!params || nparams < need)
         return fail(SWEPT_EINVAL, "stencil %d needs %d parameter(s)", id, need);
     for (int i = 0; i < need; ++i)
         if (!std::isfinite(params[i]))
             return fail(SWEPT_EINVAL, "parameter %d is not finite", i);
-    if (id == SWEPT_KS_F64 && !(params[1] > 0.0))
-        return fail(SWEPT_EINVAL, "KS needs dx > 0");
+    if ((id == SWEPT_KS_F64 || id == SWEPT_EULER_F64) && !(params[1] > 0.0))
+        return fail(SWEPT_EINVAL, "stencil %d needs dx > 0", id);
+    if (id == SWEPT_EULER_F64 && !(params[2] > 1.0))
+        return fail(SWEPT_EINVAL, "Euler needs gamma > 1");
     return SWEPT_OK;
 }
 
@@ -130,6 +134,11 @@ int check_common(const void* u, int64_t nx, int64_t nsteps, int32_t id, const do
 
 HeatF64::Consts heat64_consts(const double* p) { return HeatF64::Consts{p[0]}; }
 HeatF32::Consts heat32_consts(const double* p) { return HeatF32::Consts{(float)p[0]}; }
+EulerF64::Consts euler_consts(const double* p)
+{
+    const double dt = p[0], dx = p[1], gamma = p[2];
+    return EulerF64::Consts{gamma - 1.0, (0.5 * dt) / dx, dt / dx};
+}
 KSF64::Consts ks_consts(const double* p)
 {
     const double dt = p[0], dx = p[1];
@@ -152,7 +161,27 @@ constexpr size_t kMaxLds = 64 * 1024;
 // CU); small grids keep at least 16 tiles so that more CUs take part.
 int64_t target_tile(int /*id*/) { return 1024; }
 
-int auto_ppl(int /*id*/, int64_t k) { return k >= 512 ? 4 : (k >= 128 ? 2 : 1); }
+// Pairs per lane a stencil's point fits in registers with: heat 8; KS
+// (three values a point) 4; Euler (nine values a point) 2.
+template <class S>
+constexpr int pmax_of()
+{
+    return S::NPHASE == 1 ? 8 : (sizeof(typename S::Pt) <= 3 * sizeof(double) ? 4 : 2);
+}
+
+int pmax(int id)
+{
+    switch (id) {
+    case SWEPT_KS_F64: return pmax_of<KSF64>();
+    case SWEPT_EULER_F64: return pmax_of<EulerF64>();
+    default: return 8;
+    }
+}
+
+int auto_ppl(int id, int64_t k)
+{
+    return std::min(pmax(id) == 2 ? 1 : 4, k >= 512 ? 4 : (k >= 128 ? 2 : 1));
+}
 
 bool tile_fits(int id, int64_t nx, int64_t W)
 {
@@ -306,16 +335,24 @@ int run_swept(void* u, int64_t nx, int64_t L, const typename S::Consts& c, const
         a.le_in = le[(s + 1) & 1];
         a.le_out = le[s & 1];
         const bool cont = use_continuous(p, s, L);
+        // pairs per lane beyond the register budget of a point are not built
+        constexpr int PMAX = pmax_of<S>();
         switch (p.P) {
         case 1: launch_stage<S, 1>(a, lds, g_ctx.stream, (int)p.tiles, cont); break;
         case 2: launch_stage<S, 2>(a, lds, g_ctx.stream, (int)p.tiles, cont); break;
-        case 4: launch_stage<S, 4>(a, lds, g_ctx.stream, (int)p.tiles, cont); break;
+        case 4:
+            if constexpr (PMAX >= 4)
+                launch_stage<S, 4>(a, lds, g_ctx.stream, (int)p.tiles, cont);
+            else
+                return fail(SWEPT_EUNSUPPORTED, "this stencil takes at most %d pairs per lane",
+                            PMAX);
+            break;
         case 8:
-            // eight KS pairs (48 values) per lane exceed the register file
-            if constexpr (S::NPHASE == 1)
+            if constexpr (PMAX >= 8)
                 launch_stage<S, 8>(a, lds, g_ctx.stream, (int)p.tiles, cont);
             else
-                return fail(SWEPT_EUNSUPPORTED, "the KS stencil takes at most 4 pairs per lane");
+                return fail(SWEPT_EUNSUPPORTED, "this stencil takes at most %d pairs per lane",
+                            PMAX);
             break;
         default: return fail(SWEPT_EINVAL, "pairs per lane %d not in {1,2,4,8}", p.P);
         }
@@ -717,51 +754,53 @@ int run_naive_single(void* u, int64_t nx, int64_t nsteps, const typename S::Cons
     return SWEPT_OK;
 }
 
-int run_naive_ks_fused(void* u, int64_t nx, int64_t nsteps, const KSF64::Consts& c)
+template <class S, int NB>
+int run_naive_fused(void* u, int64_t nx, int64_t nsteps, const typename S::Consts& c)
 {
-    int rc = ensure_scratch((size_t)nx * sizeof(double));
+    using T = typename S::T;
+    int rc = ensure_scratch((size_t)nx * sizeof(T));
     if (rc)
         return rc;
-    double* a = static_cast<double*>(u);
-    double* b = static_cast<double*>(g_ctx.scratch);
-    constexpr int NB = 256;
+    T* a = static_cast<T*>(u);
+    T* b = static_cast<T*>(g_ctx.scratch);
     const unsigned grid = (unsigned)((nx + NB - 1) / NB);
     for (int64_t s = 0; s < nsteps; ++s) {
-        hipLaunchKernelGGL((naive_fused_kernel<KSF64, NB>), dim3(grid), dim3(NB), 0,
-                           g_ctx.stream, a, b, nx, c);
+        hipLaunchKernelGGL((naive_fused_kernel<S, NB>), dim3(grid), dim3(NB), 0, g_ctx.stream, a,
+                           b, nx, c);
         std::swap(a, b);
     }
     if (a != u)
-        HIP_TRY(hipMemcpyAsync(u, a, (size_t)nx * sizeof(double), hipMemcpyDeviceToDevice,
+        HIP_TRY(hipMemcpyAsync(u, a, (size_t)nx * sizeof(T), hipMemcpyDeviceToDevice,
                                g_ctx.stream));
     HIP_TRY(hipGetLastError());
     return SWEPT_OK;
 }
 
-int run_naive_ks_substep(void* u, int64_t nx, int64_t nsteps, const KSF64::Consts& c)
+template <class S>
+int run_naive_substep(void* u, int64_t nx, int64_t nsteps, const typename S::Consts& c)
 {
-    using Pt = KSF64::Pt;
+    using Pt = typename S::Pt;
+    using T = typename S::T;
     int rc = ensure_scratch(2 * (size_t)nx * sizeof(Pt));
     if (rc)
         return rc;
     Pt* a = static_cast<Pt*>(g_ctx.scratch);
     Pt* b = a + nx;
     const unsigned grid = grid_for(nx, 256);
-    double* uf = static_cast<double*>(u);
-    hipLaunchKernelGGL((field_to_pt_kernel<KSF64>), dim3(grid), dim3(256), 0, g_ctx.stream, uf,
-                       a, nx);
+    T* uf = static_cast<T*>(u);
+    hipLaunchKernelGGL((field_to_pt_kernel<S>), dim3(grid), dim3(256), 0, g_ctx.stream, uf, a, nx);
     for (int64_t s = 0; s < nsteps; ++s) {
-        hipLaunchKernelGGL((naive_substep_kernel<KSF64, 0>), dim3(grid), dim3(256), 0,
-                           g_ctx.stream, a, b, nx, c);
-        hipLaunchKernelGGL((naive_substep_kernel<KSF64, 1>), dim3(grid), dim3(256), 0,
-                           g_ctx.stream, b, a, nx, c);
-        hipLaunchKernelGGL((naive_substep_kernel<KSF64, 2>), dim3(grid), dim3(256), 0,
-                           g_ctx.stream, a, b, nx, c);
-        hipLaunchKernelGGL((naive_substep_kernel<KSF64, 3>), dim3(grid), dim3(256), 0,
-                           g_ctx.stream, b, a, nx, c);
+        hipLaunchKernelGGL((naive_substep_kernel<S, 0>), dim3(grid), dim3(256), 0, g_ctx.stream,
+                           a, b, nx, c);
+        hipLaunchKernelGGL((naive_substep_kernel<S, 1>), dim3(grid), dim3(256), 0, g_ctx.stream,
+                           b, a, nx, c);
+        hipLaunchKernelGGL((naive_substep_kernel<S, 2>), dim3(grid), dim3(256), 0, g_ctx.stream,
+                           a, b, nx, c);
+        hipLaunchKernelGGL((naive_substep_kernel<S, 3>), dim3(grid), dim3(256), 0, g_ctx.stream,
+                           b, a, nx, c);
     }
-    hipLaunchKernelGGL((pt_to_field_kernel<KSF64>), dim3(grid), dim3(256), 0, g_ctx.stream, a,
-                       uf, nx);
+    hipLaunchKernelGGL((pt_to_field_kernel<S>), dim3(grid), dim3(256), 0, g_ctx.stream, a, uf,
+                       nx);
     HIP_TRY(hipGetLastError());
     return SWEPT_OK;
 }
@@ -771,7 +810,9 @@ int naive_dispatch(void* u, int64_t nx, int64_t nsteps, int32_t id, const double
     switch (id) {
     case SWEPT_HEAT_F64: return run_naive_single<HeatF64>(u, nx, nsteps, heat64_consts(params));
     case SWEPT_HEAT_F32: return run_naive_single<HeatF32>(u, nx, nsteps, heat32_consts(params));
-    default: return run_naive_ks_fused(u, nx, nsteps, ks_consts(params));
+    case SWEPT_EULER_F64:
+        return run_naive_fused<EulerF64, 128>(u, nx, nsteps, euler_consts(params));
+    default: return run_naive_fused<KSF64, 256>(u, nx, nsteps, ks_consts(params));
     }
 }
 
@@ -888,6 +929,7 @@ int advance_dispatch(void* u, int64_t nx, int64_t nsteps, int32_t id, const doub
     switch (id) {
     case SWEPT_HEAT_F64: return run_swept<HeatF64>(u, nx, L, heat64_consts(params), p);
     case SWEPT_HEAT_F32: return run_swept<HeatF32>(u, nx, L, heat32_consts(params), p);
+    case SWEPT_EULER_F64: return run_swept<EulerF64>(u, nx, L, euler_consts(params), p);
     default: return run_swept<KSF64>(u, nx, L, ks_consts(params), p);
     }
 }
@@ -926,6 +968,18 @@ struct DeviceBuffer {
         return e == hipSuccess ? SWEPT_OK : hip_fail(e, "hipMemsetAsync");
     }
 };
+
+// Probe fields hold zeros; Euler probes need a physical state (rho = 1,
+// u = 0, p = 1 at gamma = 1.4: E = 2.5) so that no flux divides by zero.
+int fill_probe_field(int id, void* p, size_t cells)
+{
+    if (id != SWEPT_EULER_F64)
+        return SWEPT_OK;
+    std::vector<Cons> h(cells, Cons{1.0, 0.0, 2.5});
+    HIP_TRY(hipMemcpyAsync(p, h.data(), cells * sizeof(Cons), hipMemcpyHostToDevice, g_ctx.stream));
+    HIP_TRY(hipStreamSynchronize(g_ctx.stream));
+    return SWEPT_OK;
+}
 
 struct EventPair {
     hipEvent_t a = nullptr, b = nullptr;
@@ -978,7 +1032,14 @@ int time_best(F&& fn, int reps, double* sec)
     return SWEPT_OK;
 }
 
-size_t field_bytes(int id) { return id == SWEPT_HEAT_F32 ? sizeof(float) : sizeof(double); }
+size_t field_bytes(int id)
+{
+    switch (id) {
+    case SWEPT_HEAT_F32: return sizeof(float);
+    case SWEPT_EULER_F64: return sizeof(Cons);
+    default: return sizeof(double);
+    }
+}
 
 // One swept run of `nsteps` steps on the zero field f with the given tiling;
 // returns its time and its number of stages.
@@ -1004,6 +1065,8 @@ int measure_model(int id, const double* params, double* tau, double* s1, double*
     const int64_t nbig = int64_t(1) << 20;
     DeviceBuffer f;
     int rc = f.alloc((size_t)nbig * field_bytes(id));
+    if (!rc)
+        rc = fill_probe_field(id, f.p, (size_t)nbig);
     if (rc)
         return rc;
     double t;
@@ -1083,6 +1146,8 @@ int autotune(int64_t nx, int64_t nsteps, int id, const double* params, double* r
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g_ctx.device));
     DeviceBuffer f;
     rc = f.alloc((size_t)nx * field_bytes(id));
+    if (!rc)
+        rc = fill_probe_field(id, f.p, (size_t)nx);
     if (rc)
         return rc;
     // the naive schedule costs the same every step: time a few
@@ -1105,7 +1170,7 @@ int autotune(int64_t nx, int64_t nsteps, int id, const double* params, double* r
         const int64_t Lp = std::min(nsteps * S, std::max<int64_t>(16 * (W / 2), 64));
         const int64_t np = std::max<int64_t>(1, (Lp + S - 1) / S);
         for (int P : {1, 2, 4}) {
-            if (P > 1 && 64 * P > W / 2)
+            if ((P > 1 && 64 * P > W / 2) || P > pmax(id))
                 continue;
             rc = timed_swept(f.p, npts, np, id, params, W, P, 3, &t, nullptr);
             if (rc)
@@ -1245,7 +1310,7 @@ int swept_plan(int64_t nx, int64_t nsteps, int32_t stencil_id, int64_t* out)
 {
     if (!out || nx < 3 || nsteps < 0 ||
         (stencil_id != SWEPT_HEAT_F64 && stencil_id != SWEPT_HEAT_F32 &&
-         stencil_id != SWEPT_KS_F64))
+         stencil_id != SWEPT_KS_F64 && stencil_id != SWEPT_EULER_F64))
         return fail(SWEPT_EINVAL, "invalid plan request");
     Plan p;
     int rc = make_plan(nx, nsteps, stencil_id, &p);
@@ -1286,11 +1351,14 @@ int swept_naive_substep_advance(void* u, int64_t nx, int64_t nsteps, int32_t ste
     int rc = check_common(u, nx, nsteps, stencil_id, params, nparams);
     if (rc)
         return rc;
-    if (stencil_id != SWEPT_KS_F64)
-        return fail(SWEPT_EINVAL, "per-sub-timestep launches exist for the KS stencil only");
+    if (stencil_id != SWEPT_KS_F64 && stencil_id != SWEPT_EULER_F64)
+        return fail(SWEPT_EINVAL,
+                    "per-sub-timestep launches exist for the four-sub-timestep stencils only");
     if (nsteps == 0)
         return SWEPT_OK;
-    return run_naive_ks_substep(u, nx, nsteps, ks_consts(params));
+    if (stencil_id == SWEPT_EULER_F64)
+        return run_naive_substep<EulerF64>(u, nx, nsteps, euler_consts(params));
+    return run_naive_substep<KSF64>(u, nx, nsteps, ks_consts(params));
 }
 
 int swept_advance_batch(void* const* u, const int64_t* nx, const int64_t* nsteps,
@@ -1437,7 +1505,7 @@ int swept_adjoint(const void* u0, void* grad_u0, int64_t nx, int64_t nsteps, int
         return run_adjoint<KSF64>(u0, grad_u0, nx, nsteps, params, ks_consts(params), window_first,
                                   window_weight, cot_final);
     default:
-        return fail(SWEPT_EUNSUPPORTED, "the adjoint exists for the binary64 stencils only");
+        return fail(SWEPT_EUNSUPPORTED, "the adjoint exists for the heat and KS binary64 stencils only");
     }
 }
 
