@@ -52,6 +52,11 @@ def parse():
     return ap.parse_args()
 
 
+def progress(msg: str) -> None:
+    """One line on stderr per finished leg (the JSON result goes to stdout)."""
+    print("[bench] %s" % msg, file=sys.stderr, flush=True)
+
+
 def timed_runs(sw, torch, fn, u0, nsteps, params, reps, warmup, after=None):
     """Run fn `reps` times on copies of u0; HIP events on the stream the
     library launches on (torch's current stream) bracket each run.  `after`
@@ -127,20 +132,28 @@ def cpu_baseline(u0_np, nsteps_full, seconds):
 
 
 KS_OPS_PER_STEP = 30  # per point-step: 4 sub-timesteps (4 + 11 + 4 + 11 flops, no FMA)
+# Euler, per cell-step: two slope sub-timesteps (9 each) and two flux-difference
+# sub-timesteps (151 each: two faces of 71 and the 9-flop update), counting a
+# division, a square root, |x| and a min/max as one flop each.
+EULER_OPS_PER_STEP = 320
 
 
 def other_workloads(sw, torch, workloads, tune=True):
-    """The other two single-field workloads: heat N=4096 (launch-latency
-    bound when stepped naively) and KS N=2^20 (four sub-timesteps per step),
-    each after the autotuner has chosen its tiling."""
+    """The other single-field workloads: heat N=4096 (launch-latency bound
+    when stepped naively), KS N=2^20 and Euler N=2^20 cells (four
+    sub-timesteps per step), each after the autotuner has chosen its
+    tiling."""
     out = {}
+    we = workloads.WORKLOADS["euler"]
     cases = [("heat_small", "heat", workloads.WORKLOADS["heat_small"], [0.25],
               HEAT_OPS_PER_UPDATE, 16),
              ("ks", "ks", workloads.WORKLOADS["ks"],
-              [workloads.KS_DT, workloads.KS_DX], KS_OPS_PER_STEP, 16)]
+              [workloads.KS_DT, workloads.KS_DX], KS_OPS_PER_STEP, 16),
+             ("euler", "euler", we, [we["cfl"] / we["n"], 1.0 / we["n"], we["gamma"]],
+              EULER_OPS_PER_STEP, 48)]
     for name, st, w, par, ops, naive_bytes in cases:
         u0 = torch.from_numpy(workloads.initial(name)).cuda()
-        n, nsteps = u0.numel(), w["nsteps"]
+        n, nsteps = u0.shape[0], w["nsteps"]
         tuned = sw.autotune(n, nsteps, st, par) if tune else None
         plan = sw.plan(n, nsteps, st)
         rec = {"n": n, "time_steps": nsteps, "tile_w": plan["tile_w"],
@@ -165,7 +178,7 @@ def other_workloads(sw, torch, workloads, tune=True):
         rec["speedup_vs_naive"] = rec["swept"] / rec["naive"]
         rec["swept_frac_alu"] = ops * rec["swept"] / VALU_LANE_OPS
         rec["naive_GBps"] = naive_bytes * rec["naive"] / 1e9
-        if st == "ks":
+        if st in ("ks", "euler"):
             u = u0.clone()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -178,6 +191,7 @@ def other_workloads(sw, torch, workloads, tune=True):
             rec["speedup_vs_naive_substep"] = rec["swept"] / rec["naive_substep"]
         sw.sync()
         out[name] = rec
+        progress("%s done" % name)
     return out
 
 
@@ -304,6 +318,7 @@ def main():
         tuning = sw.autotune(n, nsteps, "heat", [0.25], torch.float64)
         tuning["tune_s"] = time.perf_counter() - t0
     plan = sw.plan(n, nsteps, "heat", torch.float64)
+    progress("tuned: %s" % (plan,))
 
     if args.profile:
         # a plain device copy of known size, for scaling the HBM counters
@@ -327,6 +342,7 @@ def main():
     times, _ = timed_runs(sw, torch, sw.advance, u0, nsteps, [0.25], args.steps, args.warmup,
                           after=record)
     sw.set_profiling(False)
+    progress("heat f64 swept runs done")
     t = sum(times) / len(times)
     updates = float(n) * nsteps
     value = updates / t
@@ -373,6 +389,7 @@ def main():
                         "hbm_GBps": naive * HEAT_NAIVE_BYTES[8] / 1e9,
                         "hbm_frac": naive * HEAT_NAIVE_BYTES[8] / HBM_PEAK}
         out["speedup_vs_naive"] = value / naive
+        progress("heat f64 naive done")
         u32 = u0.float()
         tune32 = None if args.no_tune else sw.autotune(n, nsteps, "heat", [0.25], torch.float32)
         plan32 = sw.plan(n, nsteps, "heat", torch.float32)
@@ -387,9 +404,12 @@ def main():
                       "tuning": tune32}
 
     if not args.no_naive:
+        progress("heat f32 done")
         out["workloads"] = other_workloads(sw, torch, workloads, tune=not args.no_tune)
         out["workloads"]["batch"] = batch_workload(sw, torch, workloads, tune=not args.no_tune)
+        progress("batch done")
         out["workloads"]["ks_adjoint"] = ks_adjoint_workload(sw, torch, workloads)
+        progress("ks adjoint done")
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(u0_np, nsteps, args.cpu_seconds)
