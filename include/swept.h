@@ -162,9 +162,11 @@ int swept_naive_substep_advance(void *u, int64_t nx, int64_t nsteps, int32_t ste
  * stencil_id[j] with parameters params[2j], params[2j+1] (heat reads the
  * first).  Every instance gets exactly the bits its own swept_advance would.
  *
- * Each instance is tiled by even widths 2k_t, k_t in {k, k+1} (k = tile_w/2
- * of swept_set_tuning if set, else the depth swept_autotune_batch chose for
- * the stencil, else 128), so any even length tiles without
+ * Each instance of 2h points (h = nx/2 for even nx) is tiled by T = ceil(h/k)
+ * tiles of even widths 2k_t, k_t in {floor(h/T), floor(h/T)+1}, all <= k
+ * (k = tile_w/2 of swept_set_tuning if set, else the depth
+ * swept_autotune_batch chose for the stencil, else 256), so any even length
+ * tiles without
  * remainder; the regions of unequal neighbouring tiles are rectangles of
  * k_t pairs by k_{t+1} steps.  An odd length runs on its two-fold cover
  * (the field repeated twice, which the scheme keeps repeated).  All tiles of
@@ -220,7 +222,7 @@ int swept_autotune(int64_t nx, int64_t nsteps, int32_t stencil_id, const double 
 /*
  * Autotuner for swept_advance_batch: for each binary64 stencil present, times
  * the batch's own shapes (zero fields, each instance's steps cut to at most
- * 3072 sub-timesteps) at depths k = 32, 64, 128, 256 and keeps the fastest
+ * 3072 sub-timesteps) at depths k = 128, 192, 256, 384 and keeps the fastest
  * for later batches.  depth_out (host, 3 entries indexed by stencil id)
  * receives the chosen depth, 0 for a stencil not in the batch.  Allocates
  * and frees its own probe fields; synchronizes the stream.
@@ -270,6 +272,19 @@ int swept_stage_times(double *ms_out, int32_t *kind_out, int64_t cap, int64_t *c
 int swept_adjoint(const void *u0, void *grad_u0, int64_t nx, int64_t nsteps, int32_t stencil_id,
                   const double *params, int32_t nparams, int64_t window_first,
                   double window_weight, const void *cot_final);
+
+/*
+ * The same gradient by the straight decomposition of the discrete adjoint,
+ * the baseline of swept_adjoint: a forward pass of one launch per time step
+ * that keeps the field of every step, then one launch per time step
+ * backwards (each recomputes that step's sub-timestep levels on a halo and
+ * applies their transposes).  Same arguments and same bits as
+ * swept_adjoint.  Scratch: (nsteps + 3) fields of nx points (KS at 2^16
+ * points and 20,000 steps: 10.5 GB); SWEPT_ENOMEM if that cannot be had.
+ */
+int swept_naive_adjoint(const void *u0, void *grad_u0, int64_t nx, int64_t nsteps,
+                        int32_t stencil_id, const double *params, int32_t nparams,
+                        int64_t window_first, double window_weight, const void *cot_final);
 
 /* Wait for the current stream; report asynchronous kernel errors. */
 int swept_sync(void);

@@ -28,7 +28,8 @@ _STATUS = {0: "SWEPT_OK", -1: "SWEPT_EINVAL", -2: "SWEPT_ENOTINIT", -3: "SWEPT_E
 
 EXPORTS = ("swept_init", "swept_set_stream", "swept_set_tuning", "swept_plan",
            "swept_advance", "swept_naive_advance", "swept_naive_substep_advance",
-           "swept_set_profiling", "swept_stage_times", "swept_adjoint", "swept_advance_batch",
+           "swept_set_profiling", "swept_stage_times", "swept_adjoint", "swept_naive_adjoint",
+           "swept_advance_batch",
            "swept_naive_advance_batch", "swept_autotune", "swept_autotune_batch",
            "swept_clear_tuning",
            "swept_sync", "swept_last_error", "swept_finalize")
@@ -55,6 +56,7 @@ def _load() -> ctypes.CDLL:
     for f in (L.swept_advance, L.swept_naive_advance, L.swept_naive_substep_advance):
         f.argtypes = [vp, i64, i64, i32, dp, i32]
     L.swept_adjoint.argtypes = [vp, vp, i64, i64, i32, dp, i32, i64, ctypes.c_double, vp]
+    L.swept_naive_adjoint.argtypes = L.swept_adjoint.argtypes
     L.swept_advance_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(i64),
                                       ctypes.POINTER(i32), dp, i64]
     L.swept_naive_advance_batch.argtypes = L.swept_advance_batch.argtypes
@@ -287,13 +289,9 @@ def stage_times():
     return [float(ms[i]) for i in range(n)], [int(kind[i]) for i in range(n)]
 
 
-def adjoint(u0: torch.Tensor, nsteps: int, stencil, params: Sequence[float], *,
-            window_first: int | None = None, window_weight: float = 0.0,
-            cot_final: torch.Tensor | None = None) -> torch.Tensor:
-    """dJ/du0 by the swept discrete adjoint, for
-    J = window_weight * sum_{j=window_first}^{nsteps} |u^j|^2 + <cot_final, u^nsteps>."""
+def _adjoint_call(fn, what, u0, nsteps, stencil, params, window_first, window_weight, cot_final):
     sid = stencil_id(stencil, u0.dtype)
-    _prepare(u0, sid)
+    nx = _prepare(u0, sid)
     grad = torch.empty_like(u0)
     cot = None
     if cot_final is not None:
@@ -302,11 +300,28 @@ def adjoint(u0: torch.Tensor, nsteps: int, stencil, params: Sequence[float], *,
             raise ValueError("cot_final must match u0")
     first = nsteps + 1 if window_first is None else int(window_first)
     p, npar = _params(params)
-    _check(_lib.swept_adjoint(ctypes.c_void_p(u0.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
-                              u0.numel(), int(nsteps), sid, p, npar, first, float(window_weight),
-                              None if cot is None else ctypes.c_void_p(cot.data_ptr())),
-           "swept_adjoint")
+    _check(fn(ctypes.c_void_p(u0.data_ptr()), ctypes.c_void_p(grad.data_ptr()), nx, int(nsteps),
+              sid, p, npar, first, float(window_weight),
+              None if cot is None else ctypes.c_void_p(cot.data_ptr())), what)
     return grad
+
+
+def adjoint(u0: torch.Tensor, nsteps: int, stencil, params: Sequence[float], *,
+            window_first: int | None = None, window_weight: float = 0.0,
+            cot_final: torch.Tensor | None = None) -> torch.Tensor:
+    """dJ/du0 by the swept discrete adjoint, for
+    J = window_weight * sum_{j=window_first}^{nsteps} |u^j|^2 + <cot_final, u^nsteps>."""
+    return _adjoint_call(_lib.swept_adjoint, "swept_adjoint", u0, nsteps, stencil, params,
+                         window_first, window_weight, cot_final)
+
+
+def naive_adjoint(u0: torch.Tensor, nsteps: int, stencil, params: Sequence[float], *,
+                  window_first: int | None = None, window_weight: float = 0.0,
+                  cot_final: torch.Tensor | None = None) -> torch.Tensor:
+    """The same gradient by the straight decomposition (one launch per step
+    forward, keeping every step, and one per step backward)."""
+    return _adjoint_call(_lib.swept_naive_adjoint, "swept_naive_adjoint", u0, nsteps, stencil,
+                         params, window_first, window_weight, cot_final)
 
 
 class SweptAdvance(torch.autograd.Function):

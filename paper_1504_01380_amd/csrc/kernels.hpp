@@ -745,6 +745,79 @@ __global__ __launch_bounds__(256) void adjoint_seed_kernel(const typename S::T* 
                                   src != 0));
 }
 
+// Naive adjoint (the straight decomposition run backwards): one launch per
+// time step turns the cotangent of step j+1 into that of step j, from the
+// forward field of step j kept by the forward pass.  A block of NB points
+// recomputes the step's forward levels on a halo of 7 (KS: levels 4j..4j+3
+// over [i0-7+l, i0+NB+7-l)), applies the transposed sub-timesteps 3, 2, 1, 0
+// (each one point narrower), and adds the window source at the step level.
+template <class S, int NB>
+__global__ __launch_bounds__(NB) void naive_adjoint_kernel(const typename S::T* __restrict__ uj,
+                                                          const typename S::T* __restrict__ ub_in,
+                                                          typename S::T* __restrict__ ub_out,
+                                                          int64_t n, typename S::Consts c,
+                                                          typename S::T two_w, int src)
+{
+    using Pt = typename S::Pt;
+    using Ad = typename S::Ad;
+    using T = typename S::T;
+    const int64_t i0 = (int64_t)blockIdx.x * NB;
+    const int tid = threadIdx.x;
+    auto at = [&](int64_t x) {
+        x %= n;
+        return x < 0 ? x + n : x;
+    };
+    auto cot = [&](int64_t x) { return S::seed(ub_in[at(x)], T(0), Pt{}, false); };
+    if constexpr (S::NPHASE == 1) {
+        const int64_t i = i0 + tid;
+        if (i < n) {
+            const Pt fl = S::from_field(uj[at(i - 1)]), fc = S::from_field(uj[i]),
+                     fr = S::from_field(uj[at(i + 1)]);
+            Ad a = S::template adj<0>(cot(i - 1), cot(i), cot(i + 1), fl, fc, fr, c);
+            if (src)
+                a = S::source(a, fc, two_w);
+            ub_out[i] = S::grad(a);
+        }
+    } else {
+        static_assert(S::NPHASE == 4, "one or four sub-timesteps");
+        __shared__ Pt f0[NB + 14], f1[NB + 12], f2[NB + 10], f3[NB + 8];
+        __shared__ Ad a4[NB + 8], a3[NB + 6], a2[NB + 4], a1[NB + 2];
+        for (int j = tid; j < NB + 14; j += NB)
+            f0[j] = S::from_field(uj[at(i0 - 7 + j)]);          // x = i0-7+j
+        for (int j = tid; j < NB + 8; j += NB)
+            a4[j] = cot(i0 - 4 + j);                            // x = i0-4+j
+        __syncthreads();
+        for (int j = tid; j < NB + 12; j += NB)                 // x = i0-6+j
+            f1[j] = S::template step<0>(f0[j], f0[j + 1], f0[j + 2], c);
+        __syncthreads();
+        for (int j = tid; j < NB + 10; j += NB)                 // x = i0-5+j
+            f2[j] = S::template step<1>(f1[j], f1[j + 1], f1[j + 2], c);
+        __syncthreads();
+        for (int j = tid; j < NB + 8; j += NB)                  // x = i0-4+j
+            f3[j] = S::template step<2>(f2[j], f2[j + 1], f2[j + 2], c);
+        __syncthreads();
+        for (int j = tid; j < NB + 6; j += NB)                  // x = i0-3+j
+            a3[j] = S::template adj<3>(a4[j], a4[j + 1], a4[j + 2], f3[j], f3[j + 1], f3[j + 2], c);
+        __syncthreads();
+        for (int j = tid; j < NB + 4; j += NB)                  // x = i0-2+j
+            a2[j] = S::template adj<2>(a3[j], a3[j + 1], a3[j + 2], f2[j + 2], f2[j + 3],
+                                       f2[j + 4], c);
+        __syncthreads();
+        for (int j = tid; j < NB + 2; j += NB)                  // x = i0-1+j
+            a1[j] = S::template adj<1>(a2[j], a2[j + 1], a2[j + 2], f1[j + 4], f1[j + 5],
+                                       f1[j + 6], c);
+        __syncthreads();
+        const int64_t i = i0 + tid;                             // x = i0+tid
+        if (i < n) {
+            Ad a = S::template adj<0>(a1[tid], a1[tid + 1], a1[tid + 2], f0[tid + 6], f0[tid + 7],
+                                      f0[tid + 8], c);
+            if (src)
+                a = S::source(a, f0[tid + 7], two_w);
+            ub_out[i] = S::grad(a);
+        }
+    }
+}
+
 // ------------------------------------------------------------- naive paths
 // The straight decomposition: every sub-timestep of every point, one launch
 // per time step, from two full fields.

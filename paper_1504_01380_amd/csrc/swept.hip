@@ -196,7 +196,7 @@ struct Tuned {
 std::map<std::pair<int, int>, Tuned> g_tuned;
 // Batch depth per stencil id chosen by swept_autotune_batch (0 = default).
 int64_t g_batch_want[3] = {0, 0, 0};
-constexpr int64_t kBatchWantDefault = 128;
+constexpr int64_t kBatchWantDefault = 256;
 
 std::pair<int, int> tune_key(int id, int64_t nx)
 {
@@ -490,8 +490,9 @@ int run_adjoint(const void* u0v, void* gradv, int64_t nx, int64_t nsteps, const 
 
 // -------------------------------------------------------------------- batch
 
-// Per-instance tiling for the batch: tiles of width 2k_t, k_t in {base,
-// base+1}, summing to the ring length; odd rings run on their two-fold cover
+// Per-instance tiling for the batch: T = ceil(h/k) tiles of half-widths
+// k_t in {base, base+1} <= k summing to the half ring length h (so the
+// deepest tile, which sets every workgroup's LDS, never exceeds the target); odd rings run on their two-fold cover
 // (the same bits: the scheme is translation-equivariant, so a field repeated
 // twice stays repeated).
 struct BatchPlanInst {
@@ -566,7 +567,7 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
         const int64_t want = g_ctx.tile_w > 0 ? g_ctx.tile_w / 2 : batch_want(ids[j]);
         const int64_t k = batch_depth(ids[j], p.n_ring, want);
         const int64_t half = p.n_ring / 2;
-        const int64_t T = std::max<int64_t>(1, half / k);
+        const int64_t T = std::max<int64_t>(1, (half + k - 1) / k);   // half-widths <= k
         const int64_t base = half / T, rem = half % T;
         p.tiles = (int)T;
         p.kmax = (int)(base + (rem ? 1 : 0));
@@ -914,6 +915,48 @@ int run_naive_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, co
     return SWEPT_OK;
 }
 
+// The straight decomposition of the discrete adjoint: a forward pass of one
+// launch per step that keeps every step's field, then one launch per step
+// backwards.  Scratch: (nsteps + 1) fields and two cotangent fields.
+template <class S, int NB, class StepFn>
+int run_naive_adjoint(const void* u0v, void* gradv, int64_t nx, int64_t nsteps,
+                      const typename S::Consts& c, int64_t win_first, double wgt,
+                      const void* cotv, StepFn forward_step)
+{
+    using T = typename S::T;
+    const T* u0 = static_cast<const T*>(u0v);
+    T* grad = static_cast<T*>(gradv);
+    const T* cot = static_cast<const T*>(cotv);
+    const T two_w = (T)(2.0 * wgt);
+    const size_t field = ((size_t)nx * sizeof(T) + 255) / 256 * 256;
+    if ((double)(nsteps + 3) * (double)field > 1.5e14)
+        return fail(SWEPT_ENOMEM, "the naive adjoint would keep %lld fields", (long long)nsteps + 1);
+    int rc = ensure_scratch((size_t)(nsteps + 3) * field);
+    if (rc)
+        return rc;
+    unsigned char* base = static_cast<unsigned char*>(g_ctx.scratch);
+    auto slot = [&](int64_t j) { return reinterpret_cast<T*>(base + (size_t)j * field); };
+    T* ub[2] = {reinterpret_cast<T*>(base + (size_t)(nsteps + 1) * field),
+                reinterpret_cast<T*>(base + (size_t)(nsteps + 2) * field)};
+    HIP_TRY(hipMemcpyAsync(slot(0), u0, (size_t)nx * sizeof(T), hipMemcpyDeviceToDevice,
+                           g_ctx.stream));
+    for (int64_t j = 0; j < nsteps; ++j)
+        forward_step(slot(j), slot(j + 1));
+    T* out = nsteps == 0 ? grad : ub[0];
+    hipLaunchKernelGGL((adjoint_seed_kernel<S>), dim3(grid_for(nx, 256)), dim3(256), 0,
+                       g_ctx.stream, slot(nsteps), cot, out, nx, two_w,
+                       nsteps >= win_first ? 1 : 0);
+    const unsigned grid = (unsigned)((nx + NB - 1) / NB);
+    for (int64_t j = nsteps - 1; j >= 0; --j) {
+        const int in = (int)((nsteps - 1 - j) & 1);
+        T* dst = j == 0 ? grad : ub[in ^ 1];
+        hipLaunchKernelGGL((naive_adjoint_kernel<S, NB>), dim3(grid), dim3(NB), 0, g_ctx.stream,
+                           slot(j), ub[in], dst, nx, c, two_w, j >= win_first ? 1 : 0);
+    }
+    HIP_TRY(hipGetLastError());
+    return SWEPT_OK;
+}
+
 // swept_advance after validation: plan, then the swept or the naive schedule
 int advance_dispatch(void* u, int64_t nx, int64_t nsteps, int32_t id, const double* params)
 {
@@ -1234,7 +1277,7 @@ int autotune_batch(const int64_t* nx, const int64_t* nsteps, const int32_t* ids,
         }
         double best_t = 1e30;
         int64_t best = kBatchWantDefault;
-        for (int64_t want : {32, 64, 128, 256}) {
+        for (int64_t want : {128, 192, 256, 384}) {
             g_batch_want[id] = want;
             double t;
             rc = time_best([&] {
@@ -1504,6 +1547,43 @@ int swept_adjoint(const void* u0, void* grad_u0, int64_t nx, int64_t nsteps, int
     case SWEPT_KS_F64:
         return run_adjoint<KSF64>(u0, grad_u0, nx, nsteps, params, ks_consts(params), window_first,
                                   window_weight, cot_final);
+    default:
+        return fail(SWEPT_EUNSUPPORTED, "the adjoint exists for the heat and KS binary64 stencils only");
+    }
+}
+
+int swept_naive_adjoint(const void* u0, void* grad_u0, int64_t nx, int64_t nsteps,
+                        int32_t stencil_id, const double* params, int32_t nparams,
+                        int64_t window_first, double window_weight, const void* cot_final)
+{
+    int rc = check_common(u0, nx, nsteps, stencil_id, params, nparams);
+    if (rc)
+        return rc;
+    if (!grad_u0)
+        return fail(SWEPT_EINVAL, "grad_u0 is NULL");
+    if (!std::isfinite(window_weight))
+        return fail(SWEPT_EINVAL, "window weight is not finite");
+    switch (stencil_id) {
+    case SWEPT_HEAT_F64: {
+        const HeatF64::Consts c = heat64_consts(params);
+        const unsigned grid = grid_for(nx, 256);
+        return run_naive_adjoint<HeatF64, 256>(
+            u0, grad_u0, nx, nsteps, c, window_first, window_weight, cot_final,
+            [&](const double* a, double* b) {
+                hipLaunchKernelGGL((naive_step_kernel<HeatF64>), dim3(grid), dim3(256), 0,
+                                   g_ctx.stream, a, b, nx, c);
+            });
+    }
+    case SWEPT_KS_F64: {
+        const KSF64::Consts c = ks_consts(params);
+        const unsigned grid = (unsigned)((nx + 255) / 256);
+        return run_naive_adjoint<KSF64, 128>(
+            u0, grad_u0, nx, nsteps, c, window_first, window_weight, cot_final,
+            [&](const double* a, double* b) {
+                hipLaunchKernelGGL((naive_fused_kernel<KSF64, 256>), dim3(grid), dim3(256), 0,
+                                   g_ctx.stream, a, b, nx, c);
+            });
+    }
     default:
         return fail(SWEPT_EUNSUPPORTED, "the adjoint exists for the heat and KS binary64 stencils only");
     }

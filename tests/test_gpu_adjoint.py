@@ -93,3 +93,28 @@ def test_window_objective_fd(sw):
         fd = float((jp - jm) / (2 * eps))
         ad = float(torch.dot(g, v))
         assert abs(fd - ad) <= 1e-6 * abs(ad) + 1e-12
+
+
+@pytest.mark.parametrize("stencil,n,nsteps,first,with_cot", [
+    ("heat", 64, 37, 20, True), ("heat", 1001, 50, 0, False), ("heat", 5, 9, 3, True),
+    ("heat", 128, 0, 0, True), ("ks", 64, 9, 5, True), ("ks", 1000, 40, 1, False),
+    ("ks", 7, 6, 2, True), ("ks", 4096, 120, 100, True), ("ks", 300, 25, 26, True),
+])
+def test_naive_adjoint_bitwise(sw, oracle_mod, stencil, n, nsteps, first, with_cot):
+    """The straight-decomposition adjoint (the baseline) gives the oracle's
+    bits too, on any grid (it needs no tiling: odd and tiny n included)."""
+    import torch
+    if stencil == "heat":
+        u0, par = workloads.white_noise(n, seed=n + 1), [0.3]
+        want = lambda c: oracle_mod.heat_adjoint(u0, nsteps, 0.3, first, w, c)
+    else:
+        u0, par = workloads.smoothed_noise(n, seed=n + 1) * 5, KS_P
+        want = lambda c: oracle_mod.ks_adjoint(u0, nsteps, *KS_P, first, w, c)
+    w = 1.0 / (n * 10)
+    cot = workloads.white_noise(n, seed=9) if with_cot else None
+    u = torch.from_numpy(u0).cuda()
+    c = None if cot is None else torch.from_numpy(cot).cuda()
+    g = sw.naive_adjoint(u, nsteps, stencil, par, window_first=first, window_weight=w,
+                         cot_final=c)
+    torch.cuda.synchronize()
+    assert np.array_equal(g.cpu().numpy().view(np.uint8), want(cot).view(np.uint8))

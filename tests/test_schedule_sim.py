@@ -118,9 +118,9 @@ def test_adjoint_schedule(oracle_mod, stencil, n, k, nsteps, n0, cot):
 
 
 def _split(half, k):
-    """The batch plan's tiling of a ring of 2*half points: T = max(1, half//k)
-    tiles, half-widths base or base+1 (the first half % T get base+1)."""
-    T = max(1, half // k)
+    """The batch plan's tiling of a ring of 2*half points: T = ceil(half/k)
+    tiles, half-widths base or base+1 <= k (the first half % T get base+1)."""
+    T = max(1, -(-half // k))
     base, rem = divmod(half, T)
     return [base + (1 if t < rem else 0) for t in range(T)]
 
