@@ -274,6 +274,19 @@ def ks_adjoint_workload(sw, torch, workloads, directions=16, eps=1e-6):
     def J(u):
         return float(sw.window_mean_square_value(u, nsteps, "ks", par, window))
 
+    # the straight-decomposition adjoint (one launch per step each way,
+    # every step's field kept) on the same objective
+    gn = sw.naive_adjoint(u0, nsteps, "ks", par, window_first=first, window_weight=wgt)
+    torch.cuda.synchronize()
+    e0.record()
+    gn = sw.naive_adjoint(u0, nsteps, "ks", par, window_first=first, window_weight=wgt)
+    e1.record()
+    e1.synchronize()
+    t_naive = e0.elapsed_time(e1) / 1e3
+    same = bool(torch.equal(gn.view(torch.int64), g.view(torch.int64)))
+    del gn
+    torch.cuda.empty_cache()
+
     errs, errs_rich = [], []
     for _ in range(directions):
         v = torch.from_numpy(rng.standard_normal(n)).cuda()
@@ -288,6 +301,8 @@ def ks_adjoint_workload(sw, torch, workloads, directions=16, eps=1e-6):
     errs_rich.sort()
     return {"n": n, "time_steps": nsteps, "window": window, "adjoint_ms": t_adj * 1e3,
             "gradient_point_steps_per_s": n * nsteps / t_adj,
+            "naive_adjoint_ms": t_naive * 1e3, "naive_gradient_point_steps_per_s": n * nsteps / t_naive,
+            "speedup_vs_naive": t_naive / t_adj, "naive_equals_swept_bitwise": same,
             "fd_eps": eps, "fd_directions": directions,
             "fd_rel_err_max": errs[-1], "fd_rel_err_median": errs[len(errs) // 2],
             "fd_richardson_rel_err_max": errs_rich[-1],

@@ -583,18 +583,39 @@ struct AdjArgs {
     int64_t win_first;         // first time step of the objective window
     typename S::T two_w;       // 2 * objective weight
     int k, tiles, tri, has_later;
+    int lanes_per_region;      // LW: 64/LW regions per workgroup
+    int region_bytes;          // LDS per region
     typename S::Consts c;
 };
 
-template <class S, int PH>
-__device__ __forceinline__ typename S::Ad adj_at(const typename S::Ad* ar,
-                                                 const typename S::Pt* fr, int col,
-                                                 const typename S::Consts& c)
-{
-    return S::template adj<PH>(ar[col - 1], ar[col], ar[col + 1], fr[col - 1], fr[col],
-                               fr[col + 1], c);
-}
+// LDS layout of a region.  Forward values: row j (relative level) holds the
+// columns its points and the reverse pass read, dx in [-j-2, j+1] below the
+// middle level (the V edges sit at -j-2, -j-1, j, j+1) and [j-2k-1, 2k-j]
+// from it up (the later regions' forward halo at both ends): 2k^2 + 6k + 2
+// values.  Cotangents: a ring of two rows, dx in [-k-2, k+1], since row j is
+// formed from row j+1 only; the cotangents handed over by the later regions
+// (4 per row of their lower half) are staged first and put into the ring
+// just before the row below reads them.
+struct AdjLayout {
+    int k;
+    __device__ __forceinline__ int frow(int j) const
+    {
+        return j < k ? j * j + 3 * j : k * k + 3 * k + (j - k) * (3 * k + 3 - j);
+    }
+    __device__ __forceinline__ int fidx(int j, int dx) const
+    {
+        return frow(j) + dx - (j < k ? -j - 2 : j - 2 * k - 1);
+    }
+    __device__ __forceinline__ int fsize() const { return 2 * k * k + 6 * k + 2; }
+    __device__ __forceinline__ int acol(int dx) const { return dx + k + 2; }
+    __device__ __forceinline__ int awidth() const { return 2 * k + 4; }
+};
 
+// A workgroup of 64 lanes takes 64/LW regions (tiles t = blockIdx*64/LW +
+// lane/LW), LW lanes each (LW >= 2k, a power of two): the regions of a stage
+// share their level structure, so they keep one barrier per level, and at
+// small k no lane idles.  Each region has its own LDS block of
+// adjoint_region_bytes.
 template <class S>
 __global__ __launch_bounds__(64) void swept_adjoint_kernel(AdjArgs<S> g)
 {
@@ -603,130 +624,142 @@ __global__ __launch_bounds__(64) void swept_adjoint_kernel(AdjArgs<S> g)
     using T = typename S::T;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int k = g.k;
-    const int C = 2 * k + 4;              // columns: dx = col - (k + 2), dx in [-k-2, k+1]
-    const int R = 2 * k + 1;              // rows: relative levels 0..2k
-    Pt* F = reinterpret_cast<Pt*>(smem_raw);
-    Ad* A = reinterpret_cast<Ad*>(smem_raw + sizeof(Pt) * (size_t)R * C);
-    const int lane = threadIdx.x;
-    const int t = blockIdx.x;
+    const AdjLayout ly{k};
+    const int LW = g.lanes_per_region;
+    const int lane = threadIdx.x % LW;
+    const int t = blockIdx.x * (64 / LW) + threadIdx.x / LW;
+    unsigned char* mine = smem_raw + (size_t)(threadIdx.x / LW) * g.region_bytes;
+    Pt* F = reinterpret_cast<Pt*>(mine);
+    Ad* Aring = reinterpret_cast<Ad*>(mine + sizeof(Pt) * (size_t)ly.fsize());
+    Ad* Ain = Aring + 2 * ly.awidth();    // [2 sides][k][2] from the later regions
+    const bool live = t < g.tiles;        // the last workgroup may hold fewer regions
     const int64_t n = g.n;
-    const int64_t J = wrapn((int64_t)t * (2 * (int64_t)k) + g.J0, n);
-    const int off = k + 2;
-    const int64_t jtop = min((int64_t)(2 * k - 1), g.L - g.b);
+    const int tc = live ? t : g.tiles - 1;  // a spare region recomputes the last one, writes nothing
+    const int64_t J = wrapn((int64_t)tc * (2 * (int64_t)k) + g.J0, n);
+    const int jtop = (int)min((int64_t)(2 * k - 1), g.L - g.b);
 
     auto lo_of = [&](int j) { return j <= k ? -j : j - 2 * k; };
     auto hi_of = [&](int j) { return j <= k ? j - 1 : 2 * k - 1 - j; };
+    auto arow = [&](int j) { return Aring + (j & 1) * ly.awidth(); };
 
-    // 1. checkpoint and forward recompute
+    // 1. checkpoint, the later regions' data, and the forward recompute
     int j0;
     if (g.tri) {
         j0 = k;
-        for (int dx = -k + lane; dx < k; dx += 64)
-            F[k * C + dx + off] = S::from_field(g.u0[J + dx]);
+        for (int dx = -k + lane; dx < k; dx += LW)
+            F[ly.fidx(k, dx)] = S::from_field(g.u0[J + dx]);
     } else {
         j0 = 0;
-        const Pt* re = g.re_in + (size_t)t * k * 2;
-        const int tn = (t + 1 == g.tiles) ? 0 : t + 1;
+        const Pt* re = g.re_in + (size_t)tc * k * 2;
+        const int tn = (tc + 1 == g.tiles) ? 0 : tc + 1;
         const Pt* le = g.le_in + (size_t)tn * k * 2;
-        for (int i = lane; i < k; i += 64) {
-            F[i * C + (-i - 2) + off] = re[2 * i];
-            F[i * C + (-i - 1) + off] = re[2 * i + 1];
-            F[i * C + i + off] = le[2 * i];
-            F[i * C + i + 1 + off] = le[2 * i + 1];
+        for (int i = lane; i < k; i += LW) {
+            F[ly.fidx(i, -i - 2)] = re[2 * i];
+            F[ly.fidx(i, -i - 1)] = re[2 * i + 1];
+            F[ly.fidx(i, i)] = le[2 * i];
+            F[ly.fidx(i, i + 1)] = le[2 * i + 1];
+        }
+    }
+    if (g.has_later) {   // their relative level jj is our level jj + k
+        const int tl = (tc == 0) ? g.tiles - 1 : tc - 1;
+        const Ad* aeR = g.ae_in + ((size_t)tl * 2 + 1) * k * 2;   // upper-left region, right side
+        const Ad* aeL = g.ae_in + ((size_t)tc * 2 + 0) * k * 2;   // upper-right region, left side
+        const Pt* fhR = g.fh_in + ((size_t)tl * 2 + 1) * k;
+        const Pt* fhL = g.fh_in + ((size_t)tc * 2 + 0) * k;
+        for (int jj = lane; jj < k; jj += LW) {    // forward halo at their levels 0..k-1
+            if (jj + k <= jtop) {
+                F[ly.fidx(jj + k, -k + jj - 1)] = fhR[jj];
+                F[ly.fidx(jj + k, k - jj)] = fhL[jj];
+            }
+        }
+        for (int i = lane; i < 2 * k; i += LW) {   // cotangents at their levels 1..k
+            Ain[i] = aeR[i];
+            Ain[2 * k + i] = aeL[i];
         }
     }
     __syncthreads();
-    for (int j = j0 + 1; j <= (int)jtop; ++j) {
+    for (int j = j0 + 1; j <= jtop; ++j) {
         const int dx = lo_of(j) + lane;
         if (dx <= hi_of(j)) {
-            const Pt* pr = F + (j - 1) * C + off;
+            const Pt* pl = F + ly.fidx(j - 1, dx - 1);   // dx-1, dx, dx+1 are adjacent
             Pt o;
             switch (phase_of<S::NPHASE>(g.b + j - 1)) {
-            case 0: o = S::template step<0>(pr[dx - 1], pr[dx], pr[dx + 1], g.c); break;
-            case 1: o = S::template step<S::NPHASE == 4 ? 1 : 0>(pr[dx - 1], pr[dx], pr[dx + 1], g.c); break;
-            case 2: o = S::template step<S::NPHASE == 4 ? 2 : 0>(pr[dx - 1], pr[dx], pr[dx + 1], g.c); break;
-            default: o = S::template step<S::NPHASE == 4 ? 3 : 0>(pr[dx - 1], pr[dx], pr[dx + 1], g.c); break;
+            case 0: o = S::template step<0>(pl[0], pl[1], pl[2], g.c); break;
+            case 1: o = S::template step<S::NPHASE == 4 ? 1 : 0>(pl[0], pl[1], pl[2], g.c); break;
+            case 2: o = S::template step<S::NPHASE == 4 ? 2 : 0>(pl[0], pl[1], pl[2], g.c); break;
+            default: o = S::template step<S::NPHASE == 4 ? 3 : 0>(pl[0], pl[1], pl[2], g.c); break;
             }
-            F[j * C + dx + off] = o;
+            F[ly.fidx(j, dx)] = o;
         }
         __syncthreads();
     }
 
-    // 2. data from the later regions (their relative level jj = our jj + k)
-    if (g.has_later) {
-        const int tl = (t == 0) ? g.tiles - 1 : t - 1;
-        const Ad* aeR = g.ae_in + ((size_t)tl * 2 + 1) * k * 2;   // upper-left region, right side
-        const Ad* aeL = g.ae_in + ((size_t)t * 2 + 0) * k * 2;    // upper-right region, left side
-        const Pt* fhR = g.fh_in + ((size_t)tl * 2 + 1) * k;
-        const Pt* fhL = g.fh_in + ((size_t)t * 2 + 0) * k;
-        for (int jj = lane; jj < k; jj += 64) {    // forward halo at their levels 0..k-1
-            if (jj + k <= (int)jtop) {
-                F[(jj + k) * C + (-k + jj - 1) + off] = fhR[jj];
-                F[(jj + k) * C + (k - jj) + off] = fhL[jj];
-            }
+    // the later regions' cotangents of row r (= jj + k, jj in 1..k) go into
+    // the ring once row r itself is there
+    auto put_incoming = [&](int r) {
+        const int jj = r - k;
+        if (g.has_later && jj >= 1 && jj <= k && lane < 4) {   // LW >= 4
+            Ad* ar = arow(r);
+            const int side = lane >> 1, h = lane & 1;
+            const int dx = side == 0 ? (-k + jj - 2 + h) : (k - jj + h);
+            ar[ly.acol(dx)] = Ain[side * 2 * k + 2 * (jj - 1) + h];
         }
-        for (int jj = 1 + lane; jj <= k; jj += 64) {  // cotangents at their levels 1..k
-            if (jj + k <= (int)jtop + 1) {
-                A[(jj + k) * C + (-k + jj - 2) + off] = aeR[2 * (jj - 1)];
-                A[(jj + k) * C + (-k + jj - 1) + off] = aeR[2 * (jj - 1) + 1];
-                A[(jj + k) * C + (k - jj) + off] = aeL[2 * (jj - 1)];
-                A[(jj + k) * C + (k - jj + 1) + off] = aeL[2 * (jj - 1) + 1];
-            }
-        }
-    }
-    __syncthreads();
+    };
 
-    // 3. cotangents from the top level down
+    // 2. cotangents from the top level down
     const int jbot = g.tri ? k : 1;
     const int nph = S::NPHASE;
-    for (int j = (int)jtop; j >= jbot; --j) {
+    Ad* aeLo = g.ae_out + ((size_t)tc * 2 + 0) * k * 2;
+    Ad* aeRo = g.ae_out + ((size_t)tc * 2 + 1) * k * 2;
+    put_incoming(jtop + 1);
+    __syncthreads();
+    for (int j = jtop; j >= jbot; --j) {
         const int dx = lo_of(j) + lane;
         const int64_t lev = g.b + j;
         if (dx <= hi_of(j)) {
-            const int col = dx + off;
-            const Pt fc = F[j * C + col];
+            const Pt* fr = F + ly.fidx(j, dx - 1);
             Ad a;
             if (lev == g.L) {
                 const int64_t x = wrapn(J + dx, n);
-                a = S::seed(g.cot ? g.cot[x] : T(0), g.two_w, fc, lev / nph >= g.win_first);
+                a = S::seed(g.cot ? g.cot[x] : T(0), g.two_w, fr[1], lev / nph >= g.win_first);
             } else {
-                const Ad* ar = A + (j + 1) * C;
-                const Pt* fr = F + j * C;
+                const Ad* ar = arow(j + 1) + ly.acol(dx - 1);
                 switch (phase_of<S::NPHASE>(lev)) {
-                case 0: a = adj_at<S, 0>(ar, fr, col, g.c); break;
-                case 1: a = adj_at<S, S::NPHASE == 4 ? 1 : 0>(ar, fr, col, g.c); break;
-                case 2: a = adj_at<S, S::NPHASE == 4 ? 2 : 0>(ar, fr, col, g.c); break;
-                default: a = adj_at<S, S::NPHASE == 4 ? 3 : 0>(ar, fr, col, g.c); break;
+                case 0: a = S::template adj<0>(ar[0], ar[1], ar[2], fr[0], fr[1], fr[2], g.c); break;
+                case 1: a = S::template adj<S::NPHASE == 4 ? 1 : 0>(ar[0], ar[1], ar[2], fr[0], fr[1], fr[2], g.c); break;
+                case 2: a = S::template adj<S::NPHASE == 4 ? 2 : 0>(ar[0], ar[1], ar[2], fr[0], fr[1], fr[2], g.c); break;
+                default: a = S::template adj<S::NPHASE == 4 ? 3 : 0>(ar[0], ar[1], ar[2], fr[0], fr[1], fr[2], g.c); break;
                 }
                 if (phase_of<S::NPHASE>(lev) == 0 && lev / nph >= g.win_first)
-                    a = S::source(a, fc, g.two_w);
+                    a = S::source(a, fr[1], g.two_w);
             }
-            A[j * C + col] = a;
+            arow(j)[ly.acol(dx)] = a;
+            // 3. hand down the two outermost cotangents of each side (levels 1..k)
+            if (!g.tri && j <= k && live) {
+                if (dx == -j) aeLo[2 * (j - 1)] = a;
+                if (dx == -j + 1) aeLo[2 * (j - 1) + 1] = a;
+                if (dx == j - 2) aeRo[2 * (j - 1)] = a;
+                if (dx == j - 1) aeRo[2 * (j - 1) + 1] = a;
+            }
         }
+        put_incoming(j);
         __syncthreads();
     }
 
-    // 4. hand down, or write the gradient
+    // 4. the forward halo handed down, or the gradient
+    if (!live)
+        return;
     if (g.tri) {
-        for (int dx = -k + lane; dx < k; dx += 64)
-            g.grad[J + dx] = S::grad(A[k * C + dx + off]);
+        const Ad* ar = arow(k);
+        for (int dx = -k + lane; dx < k; dx += LW)
+            g.grad[J + dx] = S::grad(ar[ly.acol(dx)]);
     } else {
-        Ad* aeL = g.ae_out + ((size_t)t * 2 + 0) * k * 2;
-        Ad* aeR = g.ae_out + ((size_t)t * 2 + 1) * k * 2;
-        Pt* fhL = g.fh_out + ((size_t)t * 2 + 0) * k;
-        Pt* fhR = g.fh_out + ((size_t)t * 2 + 1) * k;
-        for (int j = 1 + lane; j <= k; j += 64) {
-            if (j <= (int)jtop) {
-                aeL[2 * (j - 1)] = A[j * C + (-j) + off];
-                aeL[2 * (j - 1) + 1] = A[j * C + (-j + 1) + off];
-                aeR[2 * (j - 1)] = A[j * C + (j - 2) + off];
-                aeR[2 * (j - 1) + 1] = A[j * C + (j - 1) + off];
-            }
-        }
-        for (int j = lane; j < k; j += 64) {
-            if (j <= (int)jtop) {
-                fhL[j] = F[j * C + (-j) + off];
-                fhR[j] = F[j * C + (j - 1) + off];
+        Pt* fhL = g.fh_out + ((size_t)tc * 2 + 0) * k;
+        Pt* fhR = g.fh_out + ((size_t)tc * 2 + 1) * k;
+        for (int j = lane; j < k; j += LW) {
+            if (j <= jtop) {
+                fhL[j] = F[ly.fidx(j, -j)];
+                fhR[j] = F[ly.fidx(j, j - 1)];
             }
         }
     }
