@@ -108,3 +108,72 @@ def test_ks_adjoint_workload_matches_oracle(sw, oracle_mod):
     torch.cuda.synchronize()
     want = oracle_mod.ks_adjoint(u0, nsteps, *par, first, wgt)
     assert np.array_equal(g.cpu().numpy().view(np.uint8), want.view(np.uint8))
+
+
+def _device_equal(a, b):
+    import torch
+    return bool(torch.equal(a.view(torch.int64), b.view(torch.int64)))
+
+
+def test_heat_maximum_size(sw, oracle_mod):
+    """2^28 points (2 GiB binary64, 262,144 tiles at W = 1024), 256 steps:
+    sampled outputs against the oracle's cones of dependence (tile edges, the
+    wrap-around, random points) and the whole field against the naive
+    schedule, compared on the device."""
+    import torch
+    n, nsteps = 1 << 28, 256
+    u0 = workloads.white_noise(n, seed=2028)
+    plan = sw.plan(n, nsteps, "heat")
+    print("heat N=2^28 plan=%s" % (plan,), flush=True)
+    a = torch.from_numpy(u0).cuda()
+    b = a.clone()
+    sw.advance(a, nsteps, "heat", [0.25])
+    sw.naive_advance(b, nsteps, "heat", [0.25])
+    torch.cuda.synchronize()
+    sw.sync()
+    assert _device_equal(a, b)
+    idx = sample_indices(n, plan["tile_w"], 88)
+    want = oracle_mod.heat_points(u0, nsteps, 0.25, idx)
+    got = a[torch.from_numpy(idx).cuda()].cpu().numpy()
+    assert np.array_equal(got.view(np.uint8), want.view(np.uint8))
+
+
+def test_ks_maximum_size(sw, oracle_mod):
+    """KS at 2^26 points (512 MiB), 100 steps: sampled outputs against the
+    oracle and the whole field against the naive schedule."""
+    import torch
+    n, nsteps, par = 1 << 26, 100, [workloads.KS_DT, workloads.KS_DX]
+    u0 = workloads.smoothed_noise(n, seed=2026)
+    plan = sw.plan(n, nsteps, "ks")
+    print("ks N=2^26 plan=%s" % (plan,), flush=True)
+    a = torch.from_numpy(u0).cuda()
+    b = a.clone()
+    sw.advance(a, nsteps, "ks", par)
+    sw.naive_advance(b, nsteps, "ks", par)
+    torch.cuda.synchronize()
+    sw.sync()
+    assert _device_equal(a, b)
+    idx = sample_indices(n, plan["tile_w"], 89)
+    want = oracle_mod.ks_points(u0, nsteps, *par, idx)
+    got = a[torch.from_numpy(idx).cuda()].cpu().numpy()
+    assert np.array_equal(got.view(np.uint8), want.view(np.uint8))
+
+
+def test_euler_large_size(sw):
+    """Euler at 2^24 cells (400 MB of state), 50 steps from the periodic Sod
+    problem: the swept and naive schedules agree bit for bit and the totals
+    of mass, momentum and energy are conserved to rounding (the oracle's
+    parity is established at the smaller sizes and the full workload)."""
+    import torch
+    n, nsteps = 1 << 24, 50
+    par = [workloads.EULER_CFL / n, 1.0 / n, workloads.EULER_GAMMA]
+    q0 = torch.from_numpy(workloads.euler_mirrored_sod(n)).cuda()
+    a = q0.clone()
+    b = q0.clone()
+    sw.advance(a, nsteps, "euler", par)
+    sw.naive_advance(b, nsteps, "euler", par)
+    torch.cuda.synchronize()
+    sw.sync()
+    assert _device_equal(a, b)
+    s0, s1 = q0.sum(dim=0), a.sum(dim=0)
+    assert torch.allclose(s1, s0, rtol=1e-12, atol=1e-9)
