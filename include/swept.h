@@ -23,16 +23,23 @@
  *    aborts or throws across the ABI; swept_last_error() returns a message
  *    for the last failure of the calling thread.
  *  - Pointers named u are DEVICE pointers to nx contiguous elements of the
- *    stencil's type (double for *_F64, float for *_F32), owned by the caller.
- *    They are updated in place to the state after nsteps full time steps.
+ *    stencil's type (double for *_F64, float for *_F32, three interleaved
+ *    doubles per cell for SWEPT_EULER_F64), owned by the caller.  They are
+ *    updated in place to the state after nsteps full time steps.
  *  - Work is enqueued on the library's current stream (swept_set_stream) and
  *    is asynchronous: the caller keeps u alive until that stream is
  *    synchronised.  Errors raised by kernels that are still running surface
  *    at swept_sync().
  *  - params points to HOST memory and is read during the call only.
  *  - The library owns its scratch (edge buffers of the swept path, a second
- *    field for the naive path).  It grows on demand, synchronising the
- *    current stream first, and is released by swept_finalize().
+ *    field for the naive path, checkpoints of the adjoints, the tables of a
+ *    batch).  It grows on demand, synchronising the current stream first,
+ *    and is released by swept_finalize().  Work still running on another
+ *    stream when the scratch grows is the caller's to finish first.
+ *  - The library keeps one context per process (device, stream, tuning,
+ *    scratch): calls from several host threads must be serialised by the
+ *    caller.  Calls that overlap on the device (two streams) must not share
+ *    the library's scratch, so use one stream at a time.
  */
 #ifndef SWEPT_H
 #define SWEPT_H
