@@ -870,45 +870,82 @@ __global__ __launch_bounds__(256) void naive_step_kernel(const typename S::T* __
     }
 }
 
-// KS: the four sub-timesteps of one RK2 step in one launch.  Each block of
-// NB points stages u on [i0-4, i0+NB+4) in LDS and recomputes the
-// intermediate levels on its halo (the same per-point operations, so the
-// same bits).
-template <class S, int NB>
+// The same step, V = 16 / sizeof(T) consecutive points per thread: one
+// aligned 16-byte load and store of the thread's points plus its two outer
+// neighbours (nx a multiple of V, 16-byte aligned fields).
+template <class S>
+__global__ __launch_bounds__(256) void naive_step_vec_kernel(const typename S::T* __restrict__ in,
+                                                            typename S::T* __restrict__ out,
+                                                            int64_t n, typename S::Consts c)
+{
+    static_assert(S::NPHASE == 1, "single-substep schemes only");
+    using T = typename S::T;
+    constexpr int V = 16 / sizeof(T);
+    struct alignas(16) Vec {
+        T v[V];
+    };
+    const int64_t nv = n / V;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
+        const Vec x = reinterpret_cast<const Vec*>(in)[i];
+        const T l = in[i == 0 ? n - 1 : i * V - 1];
+        const T r = in[i == nv - 1 ? 0 : i * V + V];
+        Vec y;
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+            const T xl = q == 0 ? l : x.v[q - 1];
+            const T xr = q == V - 1 ? r : x.v[q + 1];
+            y.v[q] = S::to_field(S::template step<0>(S::from_field(xl), S::from_field(x.v[q]),
+                                                     S::from_field(xr), c));
+        }
+        reinterpret_cast<Vec*>(out)[i] = y;
+    }
+}
+
+// Four-sub-timestep schemes (KS, Euler): one RK2 step in one launch.  Each
+// block of NB points (NT threads) stages u on [i0-4, i0+NB+4) in LDS and
+// recomputes the intermediate levels on its halo (the same per-point
+// operations, so the same bits).  Measured on MI355X: NB = 1024 on 512
+// threads for KS, 256 on 256 for Euler.
+template <class S, int NB, int NT>
 __device__ __forceinline__ void fused_block(const typename S::T* __restrict__ in,
                                             typename S::T* __restrict__ out, int64_t n,
                                             int64_t i0, const typename S::Consts& c)
 {
     using Pt = typename S::Pt;
     static_assert(S::NPHASE == 4, "four-substep schemes only");
-    __shared__ Pt s0[NB + 8], s1[NB + 6], s2[NB + 4], s3[NB + 2];
+    // NB points on NT threads; the levels alternate between two buffers:
+    // level l of the step holds points i0-4+l+j at index j
+    __shared__ Pt b0[NB + 8], b1[NB + 8];
     const int tid = threadIdx.x;
-    for (int j = tid; j < NB + 8; j += NB) {
+    for (int j = tid; j < NB + 8; j += NT) {
         int64_t x = (i0 - 4 + j) % n;
         if (x < 0) x += n;
-        s0[j] = S::from_field(in[x]);
+        b0[j] = S::from_field(in[x]);
     }
     __syncthreads();
-    for (int j = tid; j < NB + 6; j += NB)
-        s1[j] = S::template step<0>(s0[j], s0[j + 1], s0[j + 2], c);
+    for (int j = tid; j < NB + 6; j += NT)
+        b1[j] = S::template step<0>(b0[j], b0[j + 1], b0[j + 2], c);
     __syncthreads();
-    for (int j = tid; j < NB + 4; j += NB)
-        s2[j] = S::template step<1>(s1[j], s1[j + 1], s1[j + 2], c);
+    for (int j = tid; j < NB + 4; j += NT)
+        b0[j] = S::template step<1>(b1[j], b1[j + 1], b1[j + 2], c);
     __syncthreads();
-    for (int j = tid; j < NB + 2; j += NB)
-        s3[j] = S::template step<2>(s2[j], s2[j + 1], s2[j + 2], c);
+    for (int j = tid; j < NB + 2; j += NT)
+        b1[j] = S::template step<2>(b0[j], b0[j + 1], b0[j + 2], c);
     __syncthreads();
-    const int64_t i = i0 + tid;
-    if (i < n)
-        out[i] = S::to_field(S::template step<3>(s3[tid], s3[tid + 1], s3[tid + 2], c));
+    for (int j = tid; j < NB; j += NT) {
+        const int64_t i = i0 + j;
+        if (i < n)
+            out[i] = S::to_field(S::template step<3>(b1[j], b1[j + 1], b1[j + 2], c));
+    }
 }
 
-template <class S, int NB>
-__global__ __launch_bounds__(NB) void naive_fused_kernel(const typename S::T* __restrict__ in,
+template <class S, int NB, int NT>
+__global__ __launch_bounds__(NT) void naive_fused_kernel(const typename S::T* __restrict__ in,
                                                         typename S::T* __restrict__ out,
                                                         int64_t n, typename S::Consts c)
 {
-    fused_block<S, NB>(in, out, n, (int64_t)blockIdx.x * NB, c);
+    fused_block<S, NB, NT>(in, out, n, (int64_t)blockIdx.x * NB, c);
 }
 
 // Naive batch: one launch per time step advances every block of NB points
@@ -961,7 +998,7 @@ __global__ __launch_bounds__(256) void naive_batch_kernel(const NaiveInst<S>* __
                 out[xs[q]] = v[q];
     } else {
         static_assert(NB == 256, "one point per thread");
-        fused_block<S, NB>(in, out, bk.n, bk.x0, c);
+        fused_block<S, NB, NB>(in, out, bk.n, bk.x0, c);
     }
 }
 

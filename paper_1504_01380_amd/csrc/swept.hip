@@ -770,10 +770,17 @@ int run_naive_single(void* u, int64_t nx, int64_t nsteps, const typename S::Cons
         return rc;
     T* a = static_cast<T*>(u);
     T* b = static_cast<T*>(g_ctx.scratch);
-    const unsigned grid = grid_for(nx, 256);
+    // 16 bytes of points per thread where the length and the field allow
+    constexpr int V = 16 / sizeof(T);
+    const bool vec = nx % V == 0 && reinterpret_cast<uintptr_t>(u) % 16 == 0;
+    const unsigned grid = grid_for(vec ? nx / V : nx, 256);
     for (int64_t s = 0; s < nsteps; ++s) {
-        hipLaunchKernelGGL((naive_step_kernel<S>), dim3(grid), dim3(256), 0, g_ctx.stream, a, b,
-                           nx, c);
+        if (vec)
+            hipLaunchKernelGGL((naive_step_vec_kernel<S>), dim3(grid), dim3(256), 0, g_ctx.stream,
+                               a, b, nx, c);
+        else
+            hipLaunchKernelGGL((naive_step_kernel<S>), dim3(grid), dim3(256), 0, g_ctx.stream, a,
+                               b, nx, c);
         std::swap(a, b);
     }
     if (a != u)
@@ -783,7 +790,7 @@ int run_naive_single(void* u, int64_t nx, int64_t nsteps, const typename S::Cons
     return SWEPT_OK;
 }
 
-template <class S, int NB>
+template <class S, int NB, int NT>
 int run_naive_fused(void* u, int64_t nx, int64_t nsteps, const typename S::Consts& c)
 {
     using T = typename S::T;
@@ -794,8 +801,8 @@ int run_naive_fused(void* u, int64_t nx, int64_t nsteps, const typename S::Const
     T* b = static_cast<T*>(g_ctx.scratch);
     const unsigned grid = (unsigned)((nx + NB - 1) / NB);
     for (int64_t s = 0; s < nsteps; ++s) {
-        hipLaunchKernelGGL((naive_fused_kernel<S, NB>), dim3(grid), dim3(NB), 0, g_ctx.stream, a,
-                           b, nx, c);
+        hipLaunchKernelGGL((naive_fused_kernel<S, NB, NT>), dim3(grid), dim3(NT), 0, g_ctx.stream,
+                           a, b, nx, c);
         std::swap(a, b);
     }
     if (a != u)
@@ -839,9 +846,15 @@ int naive_dispatch(void* u, int64_t nx, int64_t nsteps, int32_t id, const double
     switch (id) {
     case SWEPT_HEAT_F64: return run_naive_single<HeatF64>(u, nx, nsteps, heat64_consts(params));
     case SWEPT_HEAT_F32: return run_naive_single<HeatF32>(u, nx, nsteps, heat32_consts(params));
+    // large blocks where the grid still has at least 512 of them (two per CU)
     case SWEPT_EULER_F64:
-        return run_naive_fused<EulerF64, 128>(u, nx, nsteps, euler_consts(params));
-    default: return run_naive_fused<KSF64, 256>(u, nx, nsteps, ks_consts(params));
+        return nx >= 256 * 512
+                   ? run_naive_fused<EulerF64, 256, 256>(u, nx, nsteps, euler_consts(params))
+                   : run_naive_fused<EulerF64, 128, 128>(u, nx, nsteps, euler_consts(params));
+    default:
+        return nx >= 1024 * 512
+                   ? run_naive_fused<KSF64, 1024, 512>(u, nx, nsteps, ks_consts(params))
+                   : run_naive_fused<KSF64, 256, 256>(u, nx, nsteps, ks_consts(params));
     }
 }
 
@@ -1604,12 +1617,17 @@ int swept_naive_adjoint(const void* u0, void* grad_u0, int64_t nx, int64_t nstep
     }
     case SWEPT_KS_F64: {
         const KSF64::Consts c = ks_consts(params);
-        const unsigned grid = (unsigned)((nx + 255) / 256);
+        const bool big = nx >= 1024 * 512;   // as in the forward naive path
+        const unsigned grid = (unsigned)(big ? (nx + 1023) / 1024 : (nx + 255) / 256);
         return run_naive_adjoint<KSF64, 128>(
             u0, grad_u0, nx, nsteps, c, window_first, window_weight, cot_final,
             [&](const double* a, double* b) {
-                hipLaunchKernelGGL((naive_fused_kernel<KSF64, 256>), dim3(grid), dim3(256), 0,
-                                   g_ctx.stream, a, b, nx, c);
+                if (big)
+                    hipLaunchKernelGGL((naive_fused_kernel<KSF64, 1024, 512>), dim3(grid),
+                                       dim3(512), 0, g_ctx.stream, a, b, nx, c);
+                else
+                    hipLaunchKernelGGL((naive_fused_kernel<KSF64, 256, 256>), dim3(grid),
+                                       dim3(256), 0, g_ctx.stream, a, b, nx, c);
             });
     }
     default:
