@@ -76,6 +76,16 @@ __device__ __forceinline__ int phase_of(int64_t level)
     }
 }
 
+// A stencil may set kChainPrefetch = false: lane 0 then reads pair -1 from
+// the LDS chain at the step that uses it instead of one step ahead, which
+// frees the registers of two points (for every lane) where a wave step is
+// long enough to cover the LDS latency.
+template <class S, class = void>
+struct chain_prefetch : std::true_type {};
+template <class S>
+struct chain_prefetch<S, std::void_t<decltype(S::kChainPrefetch)>>
+    : std::integral_constant<bool, S::kChainPrefetch> {};
+
 // One wave step of a band: every active pair advances one level.  Pairs are
 // visited from the last to the first so that pair q still reads pair q-1's
 // state from the previous step.
@@ -178,10 +188,18 @@ __device__ __forceinline__ void banded_region(typename S::T* u, const typename S
         // one wave step at sub-timestep phase PH
         auto wave_step = [&](int tau, auto phc) {
             constexpr int PH = decltype(phc)::value;
-            const Pt inA = S::shr1(A[P - 1], cA);
-            const Pt inB = S::shr1(B[P - 1], cB);
-            const int nslot = min(tau + 1, ks - 1);  // prefetch pair -1 for the next step
-            const Pt nA = chain[2 * nslot + 1], nB = chain[2 * nslot];
+            Pt inA, inB, nA, nB;
+            if constexpr (chain_prefetch<S>::value) {
+                inA = S::shr1(A[P - 1], cA);
+                inB = S::shr1(B[P - 1], cB);
+                const int nslot = min(tau + 1, ks - 1);  // prefetch pair -1 for the next step
+                nA = chain[2 * nslot + 1];
+                nB = chain[2 * nslot];
+            } else {
+                const int cslot = min(tau, ks - 1);
+                inA = S::shr1(A[P - 1], chain[2 * cslot + 1]);
+                inB = S::shr1(B[P - 1], chain[2 * cslot]);
+            }
             const int mlane = tau + mbase;
             band_update<S, P, PH>(A, B, inA, inB, mlane, elane, nvalid, ks, cst);
             if (tau == tau_cap) {  // the band is at level L: write it out
@@ -207,8 +225,10 @@ __device__ __forceinline__ void banded_region(typename S::T* u, const typename S
                         }
                     }
             }
-            cA = nA;
-            cB = nB;
+            if constexpr (chain_prefetch<S>::value) {
+                cA = nA;
+                cB = nB;
+            }
         };
         using I0 = std::integral_constant<int, 0>;
         using I1 = std::integral_constant<int, 1>;
@@ -375,10 +395,16 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
                                           const typename S::Consts& c)
 {
     using Pt = typename S::Pt;
-    const Pt inA = S::shr1(A[P - 1], cA);
-    const Pt inB = S::shr1(B[P - 1], cB);
-    const Pt nA = chain[2 * next_slot + 1];
-    const Pt nB = chain[2 * next_slot];
+    Pt inA, inB, nA, nB;
+    if constexpr (chain_prefetch<S>::value) {
+        inA = S::shr1(A[P - 1], cA);
+        inB = S::shr1(B[P - 1], cB);
+        nA = chain[2 * next_slot + 1];
+        nB = chain[2 * next_slot];
+    } else {   // slot 0 is at step j of its band: pair -1 of step j
+        inA = S::shr1(A[P - 1], chain[2 * j + 1]);
+        inB = S::shr1(B[P - 1], chain[2 * j]);
+    }
 #pragma unroll
     for (int q = P - 1; q >= 0; --q) {
         if (QS == q) {     // folded at compile time after unrolling
@@ -409,8 +435,10 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
         chain[2 * wslot] = B[P - 1];
         chain[2 * wslot + 1] = A[P - 1];
     }
-    cA = nA;
-    cB = nB;
+    if constexpr (chain_prefetch<S>::value) {
+        cA = nA;
+        cB = nB;
+    }
 }
 
 // Wave steps are issued in statically unrolled groups.  Every cycle starts at
