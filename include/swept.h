@@ -40,6 +40,13 @@
  *    scratch): calls from several host threads must be serialised by the
  *    caller.  Calls that overlap on the device (two streams) must not share
  *    the library's scratch, so use one stream at a time.
+ *  - swept_advance and swept_naive_advance enqueue only kernels (and, on the
+ *    naive path, one device copy) once the scratch is large enough, so a
+ *    caller may capture them into a HIP graph after one eager call of the
+ *    same size and replay the graph; the captured kernels keep the scratch
+ *    addresses of that moment, so the graph must not outlive a later call
+ *    that grows the scratch, nor swept_finalize().  Capture with stage
+ *    profiling off.
  */
 #ifndef SWEPT_H
 #define SWEPT_H
