@@ -577,8 +577,8 @@ __global__ __launch_bounds__(64) void swept_diamond_cont_kernel(StageArgs<S> g)
 
 // ------------------------------------------------------------ swept adjoint
 // The stages in reverse order, on the same regions as the forward pass
-// (stage s, region t: centre J, base b, tile width 2k; relative level j spans
-// [J-j, J+j-1] for j <= k and [J-2k+j, J+2k-1-j] above; stage 0 is the
+// (stage s, region t: centre J, base b, tile width 2k; relative level j
+// spans [J-j, J+j-1] for j <= k and [J-2k+j, J+2k-1-j] above; stage 0 is the
 // triangle, whose relative level k is level 0).  A region
 //   1. recomputes its forward values from its checkpoint -- the V kept by the
 //      forward pass for that stage (or u0 for the triangle);
@@ -591,8 +591,17 @@ __global__ __launch_bounds__(64) void swept_diamond_cont_kernel(StageArgs<S> g)
 //      source at step levels in the window);
 //   4. hands the same kind of data to the earlier regions below it, or, for
 //      the triangle, writes the gradient with respect to u0.
-// One wavefront per region, one lane per point of a level (2k <= 64); both
-// the forward and the cotangent values of the region live in LDS.
+//
+// One wavefront per region, in a fixed frame: lane l holds column
+// dx = l - k - 1 (the region and its V edges span dx in [-k-1, k], so
+// 2k + 2 <= 64).  Both sweeps keep one level per lane in registers and take
+// the neighbours' values with one DPP wave shift per 32-bit word, so a level
+// costs a few VALU operations and no LDS round trip.  Values that enter from
+// outside the region -- the V edges on the way up, the later regions'
+// cotangents on the way down -- each reach a column at two consecutive
+// levels, so every lane holds its two in registers and selects them at those
+// levels.  LDS keeps the forward values (written on the way up, read on the
+// way down with the later regions' forward halo at the ends of each level).
 
 template <class S>
 struct AdjArgs {
@@ -611,185 +620,323 @@ struct AdjArgs {
     int64_t win_first;         // first time step of the objective window
     typename S::T two_w;       // 2 * objective weight
     int k, tiles, tri, has_later;
-    int lanes_per_region;      // LW: 64/LW regions per workgroup
-    int region_bytes;          // LDS per region
     typename S::Consts c;
 };
 
-// LDS layout of a region.  Forward values: row j (relative level) holds the
-// columns its points and the reverse pass read, dx in [-j-2, j+1] below the
-// middle level (the V edges sit at -j-2, -j-1, j, j+1) and [j-2k-1, 2k-j]
-// from it up (the later regions' forward halo at both ends): 2k^2 + 6k + 2
-// values.  Cotangents: a ring of two rows, dx in [-k-2, k+1], since row j is
-// formed from row j+1 only; the cotangents handed over by the later regions
-// (4 per row of their lower half) are staged first and put into the ring
-// just before the row below reads them.
+// LDS layout of a region's forward values.  Row j (relative level) holds the
+// columns the reverse sweep reads, dx in [-j-2, j+1] below the middle level
+// (the V edges sit at -j-2, -j-1, j, j+1) and [j-2k-1, 2k-j] from it up (the
+// later regions' forward halo at both ends): 2k^2 + 6k + 2 values.
 struct AdjLayout {
     int k;
     __device__ __forceinline__ int frow(int j) const
     {
         return j < k ? j * j + 3 * j : k * k + 3 * k + (j - k) * (3 * k + 3 - j);
     }
-    __device__ __forceinline__ int fidx(int j, int dx) const
-    {
-        return frow(j) + dx - (j < k ? -j - 2 : j - 2 * k - 1);
-    }
+    __device__ __forceinline__ int lo(int j) const { return j < k ? -j - 2 : j - 2 * k - 1; }
+    __device__ __forceinline__ int hi(int j) const { return j < k ? j + 1 : 2 * k - j; }
+    __device__ __forceinline__ int fidx(int j, int dx) const { return frow(j) + dx - lo(j); }
     __device__ __forceinline__ int fsize() const { return 2 * k * k + 6 * k + 2; }
-    __device__ __forceinline__ int acol(int dx) const { return dx + k + 2; }
-    __device__ __forceinline__ int awidth() const { return 2 * k + 4; }
+    // the same per half, without a branch: index of (j, dx) = base + dx
+    template <bool UP>
+    __device__ __forceinline__ int lo_h(int j) const { return UP ? j - 2 * k - 1 : -j - 2; }
+    template <bool UP>
+    __device__ __forceinline__ int hi_h(int j) const { return UP ? 2 * k - j : j + 1; }
+    template <bool UP>
+    __device__ __forceinline__ int base_h(int j) const
+    {
+        return UP ? k * k + 3 * k + (j - k) * (3 * k + 3 - j) - (j - 2 * k - 1) : j * j + 4 * j + 2;
+    }
 };
 
-// A workgroup of 64 lanes takes 64/LW regions (tiles t = blockIdx*64/LW +
-// lane/LW), LW lanes each (LW >= 2k, a power of two): the regions of a stage
-// share their level structure, so they keep one barrier per level, and at
-// small k no lane idles.  Each region has its own LDS block of
-// adjoint_region_bytes.
+// DPP wave shifts of a whole record, one v_mov_b32_dpp per 32-bit word:
+// kWaveShr1 -- lane i receives lane i-1; kWaveShl1 -- lane i receives lane
+// i+1; the lane with no source receives 0 (bound_ctrl).
+constexpr int kWaveShl1 = 0x130;
+constexpr int kWaveShr1 = 0x138;
+template <int CTRL, class V>
+__device__ __forceinline__ V dpp_record(const V& src)
+{
+    static_assert(sizeof(V) % 4 == 0, "records of 32-bit words");
+    constexpr int NW = (int)(sizeof(V) / 4);
+    int w[NW];
+    __builtin_memcpy(w, &src, sizeof(V));
+#pragma unroll
+    for (int i = 0; i < NW; ++i)
+        w[i] = __builtin_amdgcn_mov_dpp(w[i], CTRL, 0xF, 0xF, true);
+    V out;
+    __builtin_memcpy(&out, w, sizeof(V));
+    return out;
+}
+
+// c ? x : y for a whole record, word by word (a select between the records
+// themselves would make the compiler keep them in scratch memory).
+template <class V>
+__device__ __forceinline__ V pick(bool c, const V& x, const V& y)
+{
+    constexpr int NW = (int)(sizeof(V) / 4);
+    int wx[NW], wy[NW];
+    __builtin_memcpy(wx, &x, sizeof(V));
+    __builtin_memcpy(wy, &y, sizeof(V));
+#pragma unroll
+    for (int i = 0; i < NW; ++i)
+        wx[i] = c ? wx[i] : wy[i];
+    V out;
+    __builtin_memcpy(&out, wx, sizeof(V));
+    return out;
+}
+
+template <int N>
+using Phase = std::integral_constant<int, N>;
+
+// fn(j, Phase<p>) for j = j_first, j_first+1, ..., j_last with
+// p = phase_of(base + j): single levels until the phase is 0, then groups of
+// NPHASE levels whose phases are compile-time constants, then single levels.
+template <int NPH, class Fn>
+__device__ __forceinline__ void levels_up(int64_t base, int j_first, int j_last, Fn&& fn)
+{
+    static_assert(NPH == 1 || NPH == 4, "one or four sub-timesteps per step");
+    int j = j_first;
+    if constexpr (NPH == 1) {
+        for (; j <= j_last; ++j)
+            fn(j, Phase<0>{});
+    } else {
+        auto one = [&](int jj) {
+            switch (phase_of<4>(base + jj)) {
+            case 0: fn(jj, Phase<0>{}); break;
+            case 1: fn(jj, Phase<1>{}); break;
+            case 2: fn(jj, Phase<2>{}); break;
+            default: fn(jj, Phase<3>{}); break;
+            }
+        };
+        for (; j <= j_last && phase_of<4>(base + j) != 0; ++j)
+            one(j);
+        for (; j + 3 <= j_last; j += 4) {
+            fn(j, Phase<0>{});
+            fn(j + 1, Phase<1>{});
+            fn(j + 2, Phase<2>{});
+            fn(j + 3, Phase<3>{});
+        }
+        for (; j <= j_last; ++j)
+            one(j);
+    }
+}
+
+// The same for j = j_first, j_first-1, ..., j_last (j_first >= j_last).
+template <int NPH, class Fn>
+__device__ __forceinline__ void levels_down(int64_t base, int j_first, int j_last, Fn&& fn)
+{
+    static_assert(NPH == 1 || NPH == 4, "one or four sub-timesteps per step");
+    int j = j_first;
+    if constexpr (NPH == 1) {
+        for (; j >= j_last; --j)
+            fn(j, Phase<0>{});
+    } else {
+        auto one = [&](int jj) {
+            switch (phase_of<4>(base + jj)) {
+            case 0: fn(jj, Phase<0>{}); break;
+            case 1: fn(jj, Phase<1>{}); break;
+            case 2: fn(jj, Phase<2>{}); break;
+            default: fn(jj, Phase<3>{}); break;
+            }
+        };
+        for (; j >= j_last && phase_of<4>(base + j) != 3; --j)
+            one(j);
+        for (; j - 3 >= j_last; j -= 4) {
+            fn(j, Phase<3>{});
+            fn(j - 1, Phase<2>{});
+            fn(j - 2, Phase<1>{});
+            fn(j - 3, Phase<0>{});
+        }
+        for (; j >= j_last; --j)
+            one(j);
+    }
+}
+
 template <class S>
 __global__ __launch_bounds__(64) void swept_adjoint_kernel(AdjArgs<S> g)
 {
     using Pt = typename S::Pt;
     using Ad = typename S::Ad;
     using T = typename S::T;
+    constexpr int NPH = S::NPHASE;
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    Pt* F = reinterpret_cast<Pt*>(smem_raw);
     const int k = g.k;
     const AdjLayout ly{k};
-    const int LW = g.lanes_per_region;
-    const int lane = threadIdx.x % LW;
-    const int t = blockIdx.x * (64 / LW) + threadIdx.x / LW;
-    unsigned char* mine = smem_raw + (size_t)(threadIdx.x / LW) * g.region_bytes;
-    Pt* F = reinterpret_cast<Pt*>(mine);
-    Ad* Aring = reinterpret_cast<Ad*>(mine + sizeof(Pt) * (size_t)ly.fsize());
-    Ad* Ain = Aring + 2 * ly.awidth();    // [2 sides][k][2] from the later regions
-    const bool live = t < g.tiles;        // the last workgroup may hold fewer regions
+    const int dump = ly.fsize();               // one spare slot: lanes with nothing to store
+    const int dx = (int)threadIdx.x - k - 1;   // this lane's column
+    const int t = blockIdx.x;
     const int64_t n = g.n;
-    const int tc = live ? t : g.tiles - 1;  // a spare region recomputes the last one, writes nothing
-    const int64_t J = wrapn((int64_t)tc * (2 * (int64_t)k) + g.J0, n);
+    const int64_t J = wrapn((int64_t)t * (2 * (int64_t)k) + g.J0, n);
     const int jtop = (int)min((int64_t)(2 * k - 1), g.L - g.b);
+    const bool act_k = dx >= -k && dx <= k - 1;   // the middle level's points
 
-    auto lo_of = [&](int j) { return j <= k ? -j : j - 2 * k; };
-    auto hi_of = [&](int j) { return j <= k ? j - 1 : 2 * k - 1 - j; };
-    auto arow = [&](int j) { return Aring + (j & 1) * ly.awidth(); };
-
-    // 1. checkpoint, the later regions' data, and the forward recompute
-    int j0;
+    // 1. checkpoint, the later regions' data, and the forward recompute.
+    // The V edge reaches this column at rows iA and iB: -dx-2 and -dx-1 on
+    // the left (the kept right edge of the stage before), dx and dx-1 on the
+    // right (the left edge of the next region of the stage before).
+    Pt v{}, eA{}, eB{};
+    const int iA = dx < 0 ? -dx - 2 : dx, iB = dx < 0 ? -dx - 1 : dx - 1;
+    int j0 = k;
     if (g.tri) {
-        j0 = k;
-        for (int dx = -k + lane; dx < k; dx += LW)
-            F[ly.fidx(k, dx)] = S::from_field(g.u0[J + dx]);
+        if (act_k) {
+            v = S::from_field(g.u0[J + dx]);
+            F[ly.fidx(k, dx)] = v;
+        }
     } else {
         j0 = 0;
-        const Pt* re = g.re_in + (size_t)tc * k * 2;
-        const int tn = (tc + 1 == g.tiles) ? 0 : tc + 1;
+        const Pt* re = g.re_in + (size_t)t * k * 2;
+        const int tn = (t + 1 == g.tiles) ? 0 : t + 1;
         const Pt* le = g.le_in + (size_t)tn * k * 2;
-        for (int i = lane; i < k; i += LW) {
-            F[ly.fidx(i, -i - 2)] = re[2 * i];
-            F[ly.fidx(i, -i - 1)] = re[2 * i + 1];
-            F[ly.fidx(i, i)] = le[2 * i];
-            F[ly.fidx(i, i + 1)] = le[2 * i + 1];
-        }
+        if (iA >= 0 && iA < k)
+            eA = dx < 0 ? re[2 * iA] : le[2 * iA];
+        if (iB >= 0 && iB < k)
+            eB = dx < 0 ? re[2 * iB + 1] : le[2 * iB + 1];
+        v = pick(iA == 0, eA, eB);   // row 0 holds only edges
+        if (dx >= -2 && dx <= 1)
+            F[ly.fidx(0, dx)] = v;
     }
     if (g.has_later) {   // their relative level jj is our level jj + k
-        const int tl = (tc == 0) ? g.tiles - 1 : tc - 1;
-        const Ad* aeR = g.ae_in + ((size_t)tl * 2 + 1) * k * 2;   // upper-left region, right side
-        const Ad* aeL = g.ae_in + ((size_t)tc * 2 + 0) * k * 2;   // upper-right region, left side
-        const Pt* fhR = g.fh_in + ((size_t)tl * 2 + 1) * k;
-        const Pt* fhL = g.fh_in + ((size_t)tc * 2 + 0) * k;
-        for (int jj = lane; jj < k; jj += LW) {    // forward halo at their levels 0..k-1
+        const int tl = (t == 0) ? g.tiles - 1 : t - 1;
+        const Pt* fhR = g.fh_in + ((size_t)tl * 2 + 1) * k;   // upper-left region, right side
+        const Pt* fhL = g.fh_in + ((size_t)t * 2 + 0) * k;    // upper-right region, left side
+        for (int jj = threadIdx.x; jj < k; jj += 64) {       // forward halo at their levels 0..k-1
             if (jj + k <= jtop) {
                 F[ly.fidx(jj + k, -k + jj - 1)] = fhR[jj];
                 F[ly.fidx(jj + k, k - jj)] = fhL[jj];
             }
         }
-        for (int i = lane; i < 2 * k; i += LW) {   // cotangents at their levels 1..k
-            Ain[i] = aeR[i];
-            Ain[2 * k + i] = aeL[i];
-        }
     }
-    __syncthreads();
-    for (int j = j0 + 1; j <= jtop; ++j) {
-        const int dx = lo_of(j) + lane;
-        if (dx <= hi_of(j)) {
-            const Pt* pl = F + ly.fidx(j - 1, dx - 1);   // dx-1, dx, dx+1 are adjacent
-            Pt o;
-            switch (phase_of<S::NPHASE>(g.b + j - 1)) {
-            case 0: o = S::template step<0>(pl[0], pl[1], pl[2], g.c); break;
-            case 1: o = S::template step<S::NPHASE == 4 ? 1 : 0>(pl[0], pl[1], pl[2], g.c); break;
-            case 2: o = S::template step<S::NPHASE == 4 ? 2 : 0>(pl[0], pl[1], pl[2], g.c); break;
-            default: o = S::template step<S::NPHASE == 4 ? 3 : 0>(pl[0], pl[1], pl[2], g.c); break;
-            }
-            F[ly.fidx(j, dx)] = o;
-        }
-        __syncthreads();
+    // 2 (issued early). The later regions' cotangents reach this column at
+    // rows rA and rB (their levels 1..k are our rows k+1..2k): dx+2k+2 and
+    // dx+2k+1 on the left (the upper-left region's right side), 2k-dx and
+    // 2k-dx+1 on the right (the upper-right region's left side).
+    Ad inA{}, inB{};
+    const int rA = dx < 0 ? dx + 2 * k + 2 : 2 * k - dx;
+    const int rB = dx < 0 ? dx + 2 * k + 1 : 2 * k - dx + 1;
+    if (g.has_later) {
+        const int tl = (t == 0) ? g.tiles - 1 : t - 1;
+        const Ad* in = dx < 0 ? g.ae_in + ((size_t)tl * 2 + 1) * k * 2
+                              : g.ae_in + ((size_t)t * 2 + 0) * k * 2;
+        if (rA > k && rA <= 2 * k)
+            inA = in[2 * (rA - k - 1)];
+        if (rB > k && rB <= 2 * k)
+            inB = in[2 * (rB - k - 1) + 1];
     }
 
-    // the later regions' cotangents of row r (= jj + k, jj in 1..k) go into
-    // the ring once row r itself is there
-    auto put_incoming = [&](int r) {
-        const int jj = r - k;
-        if (g.has_later && jj >= 1 && jj <= k && lane < 4) {   // LW >= 4
-            Ad* ar = arow(r);
-            const int side = lane >> 1, h = lane & 1;
-            const int dx = side == 0 ? (-k + jj - 2 + h) : (k - jj + h);
-            ar[ly.acol(dx)] = Ain[side * 2 * k + 2 * (jj - 1) + h];
-        }
-    };
+    // LDS byte addresses in 32 bits: the lane's column times the record size
+    // plus a per-row offset
+    constexpr unsigned PB = sizeof(Pt);
+    unsigned char* const Fb = smem_raw;
+    const unsigned dump_b = (unsigned)dump * PB;
+    // rows below the middle: the V edge enters at rows iA and iB; every row
+    // is stored with its edges (dx in [-j-2, j+1])
+    levels_up<NPH>(g.b - 1, j0 + 1, min(k - 1, jtop), [&](int j, auto ph) {
+        constexpr int PH = decltype(ph)::value;
+        const Pt l = dpp_record<kWaveShr1>(v), r = dpp_record<kWaveShl1>(v);
+        v = pick(iA == j, eA, pick(iB == j, eB, S::template step<PH>(l, v, r, g.c)));
+        const bool in_row = (unsigned)(dx + j + 2) <= (unsigned)(2 * j + 3);
+        const unsigned at = (unsigned)(ly.template base_h<false>(j) + dx) * PB;
+        *reinterpret_cast<Pt*>(Fb + (in_row ? at : dump_b)) = v;
+    });
+    // from the middle row up: only the region's own points are stored
+    // (dx in [j-2k, 2k-1-j]; the ends of these rows hold the later regions'
+    // forward halo)
+    levels_up<NPH>(g.b - 1, max(k, j0 + 1), jtop, [&](int j, auto ph) {
+        constexpr int PH = decltype(ph)::value;
+        const Pt l = dpp_record<kWaveShr1>(v), r = dpp_record<kWaveShl1>(v);
+        v = S::template step<PH>(l, v, r, g.c);
+        const bool own = (unsigned)(dx - (j - 2 * k)) <= (unsigned)(4 * k - 1 - 2 * j);
+        const unsigned at = (unsigned)(ly.template base_h<true>(j) + dx) * PB;
+        *reinterpret_cast<Pt*>(Fb + (own ? at : dump_b)) = v;
+    });
+    __syncthreads();
 
     // 2. cotangents from the top level down
+    Ad a = pick(rA == jtop + 1, inA, inB);
+    // the cotangents this column hands down (rows 1..k): it is one of the
+    // four outermost columns of rows -dx and 1-dx (left) or dx+1 and dx+2
+    // (right); row cA's value is kept in capA, row cB's in capB
+    const int cA = dx < 0 ? -dx : dx + 1, cB = cA + 1;
+    Ad capA{}, capB{};
     const int jbot = g.tri ? k : 1;
-    const int nph = S::NPHASE;
-    Ad* aeLo = g.ae_out + ((size_t)tc * 2 + 0) * k * 2;
-    Ad* aeRo = g.ae_out + ((size_t)tc * 2 + 1) * k * 2;
-    put_incoming(jtop + 1);
-    __syncthreads();
-    for (int j = jtop; j >= jbot; --j) {
-        const int dx = lo_of(j) + lane;
-        const int64_t lev = g.b + j;
-        if (dx <= hi_of(j)) {
-            const Pt* fr = F + ly.fidx(j, dx - 1);
-            Ad a;
-            if (lev == g.L) {
-                const int64_t x = wrapn(J + dx, n);
-                a = S::seed(g.cot ? g.cot[x] : T(0), g.two_w, fr[1], lev / nph >= g.win_first);
-            } else {
-                const Ad* ar = arow(j + 1) + ly.acol(dx - 1);
-                switch (phase_of<S::NPHASE>(lev)) {
-                case 0: a = S::template adj<0>(ar[0], ar[1], ar[2], fr[0], fr[1], fr[2], g.c); break;
-                case 1: a = S::template adj<S::NPHASE == 4 ? 1 : 0>(ar[0], ar[1], ar[2], fr[0], fr[1], fr[2], g.c); break;
-                case 2: a = S::template adj<S::NPHASE == 4 ? 2 : 0>(ar[0], ar[1], ar[2], fr[0], fr[1], fr[2], g.c); break;
-                default: a = S::template adj<S::NPHASE == 4 ? 3 : 0>(ar[0], ar[1], ar[2], fr[0], fr[1], fr[2], g.c); break;
-                }
-                if (phase_of<S::NPHASE>(lev) == 0 && lev / nph >= g.win_first)
-                    a = S::source(a, fr[1], g.two_w);
-            }
-            arow(j)[ly.acol(dx)] = a;
-            // 3. hand down the two outermost cotangents of each side (levels 1..k)
-            if (!g.tri && j <= k && live) {
-                if (dx == -j) aeLo[2 * (j - 1)] = a;
-                if (dx == -j + 1) aeLo[2 * (j - 1) + 1] = a;
-                if (dx == j - 2) aeRo[2 * (j - 1)] = a;
-                if (dx == j - 1) aeRo[2 * (j - 1) + 1] = a;
-            }
+    // the objective's source enters at step levels from row jw up
+    const int jw = (int)max((int64_t)-1, min((int64_t)(2 * k + 1), g.win_first * NPH - g.b));
+    // forward values of row j at dx-1, dx, dx+1, the column clamped into the
+    // row for the lanes outside it (whose results are never used)
+    auto fwd3 = [&](int j, auto up) {
+        constexpr bool UP = decltype(up)::value;
+        const int col = min(max(dx, ly.template lo_h<UP>(j) + 1), ly.template hi_h<UP>(j) - 1);
+        return reinterpret_cast<const Pt*>(Fb + (unsigned)(ly.template base_h<UP>(j) + col - 1) * PB);
+    };
+    // one level: UP selects the layout half (rows >= k), MERGE takes the
+    // later regions' cotangents (rows > k), otherwise the hand-down rows are
+    // captured
+    auto level = [&](int j, auto ph, auto up, auto merge) {
+        constexpr int PH = decltype(ph)::value;
+        const Pt* fr = fwd3(j, up);
+        const Ad al = dpp_record<kWaveShr1>(a), ar = dpp_record<kWaveShl1>(a);
+        Ad o = S::template adj<PH>(al, a, ar, fr[0], fr[1], fr[2], g.c);
+        if (PH == 0 && j >= jw)
+            o = S::source(o, fr[1], g.two_w);
+        if constexpr (decltype(merge)::value) {
+            a = pick(rA == j, inA, pick(rB == j, inB, o));
+        } else {
+            a = o;
+            capA = pick(cA == j, a, capA);
+            capB = pick(cB == j, a, capB);
         }
-        put_incoming(j);
-        __syncthreads();
+    };
+    using Yes = std::true_type;
+    using No = std::false_type;
+    int jstart = jtop;
+    if (g.b + jtop == g.L) {   // the target level: the seed
+        const Pt* fr = jtop >= k ? fwd3(jtop, Yes{}) : fwd3(jtop, No{});
+        T c0 = T(0);
+        if (g.cot && (jtop <= k ? (dx >= -jtop && dx <= jtop - 1)
+                                : (dx >= jtop - 2 * k && dx <= 2 * k - 1 - jtop)))
+            c0 = g.cot[wrapn(J + dx, n)];
+        const Ad o = S::seed(c0, g.two_w, fr[1], g.L / NPH >= g.win_first);
+        if (jtop > k) {
+            a = pick(rA == jtop, inA, pick(rB == jtop, inB, o));
+        } else {
+            a = o;
+            capA = pick(cA == jtop, a, capA);
+            capB = pick(cB == jtop, a, capB);
+        }
+        --jstart;
     }
+    levels_down<NPH>(g.b, jstart, max(k + 1, jbot),
+                     [&](int j, auto ph) { level(j, ph, Yes{}, Yes{}); });
+    if (jstart >= k && k >= jbot)   // the middle row: upper layout, lower cotangent rule
+        levels_down<NPH>(g.b, k, k, [&](int j, auto ph) { level(j, ph, Yes{}, No{}); });
+    levels_down<NPH>(g.b, min(jstart, k - 1), jbot,
+                     [&](int j, auto ph) { level(j, ph, No{}, No{}); });
 
-    // 4. the forward halo handed down, or the gradient
-    if (!live)
-        return;
+    // 3. the gradient, or the hand-down to the earlier regions
     if (g.tri) {
-        const Ad* ar = arow(k);
-        for (int dx = -k + lane; dx < k; dx += LW)
-            g.grad[J + dx] = S::grad(ar[ly.acol(dx)]);
-    } else {
-        Pt* fhL = g.fh_out + ((size_t)tc * 2 + 0) * k;
-        Pt* fhR = g.fh_out + ((size_t)tc * 2 + 1) * k;
-        for (int j = lane; j < k; j += LW) {
-            if (j <= jtop) {
-                fhL[j] = F[ly.fidx(j, -j)];
-                fhR[j] = F[ly.fidx(j, j - 1)];
-            }
-        }
+        if (act_k)
+            g.grad[J + dx] = S::grad(a);
+        return;
+    }
+    Ad* aeLo = g.ae_out + ((size_t)t * 2 + 0) * k * 2;
+    Ad* aeRo = g.ae_out + ((size_t)t * 2 + 1) * k * 2;
+    auto hand_down = [&](int j, const Ad& val) {
+        if (j < 1 || j > k || j > jtop)
+            return;
+        if (dx == -j) aeLo[2 * (j - 1)] = val;
+        if (dx == -j + 1) aeLo[2 * (j - 1) + 1] = val;
+        if (dx == j - 2) aeRo[2 * (j - 1)] = val;
+        if (dx == j - 1) aeRo[2 * (j - 1) + 1] = val;
+    };
+    hand_down(cA, capA);
+    hand_down(cB, capB);
+    Pt* fhL = g.fh_out + ((size_t)t * 2 + 0) * k;
+    Pt* fhR = g.fh_out + ((size_t)t * 2 + 1) * k;
+    for (int j = threadIdx.x; j < k && j <= jtop; j += 64) {
+        fhL[j] = F[ly.fidx(j, -j)];
+        fhR[j] = F[ly.fidx(j, j - 1)];
     }
 }
 

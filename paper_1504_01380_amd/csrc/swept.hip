@@ -375,41 +375,23 @@ unsigned grid_for(int64_t n, int block)
 
 // ----------------------------------------------------------- swept adjoint
 
-// Tile for the adjoint: one lane per point of a level (2k <= 64) and the
-// region's forward and cotangent values in 64 KB of LDS.
-// Tile for the adjoint: one lane per point of a level (2k <= 64); the
-// region's forward values (2k^2 + 6k + 2 points), a two-row ring of
-// cotangents and the later regions' 4k cotangents in LDS.
+// Tile for the adjoint: one wavefront per region, whose lanes are the
+// columns [-k-1, k] of the region and its V edges (2k + 2 <= 64); the
+// region's forward values (2k^2 + 6k + 2 points, and one spare) in LDS.
 template <class S>
 size_t adjoint_lds(int64_t k)
 {
-    return (size_t)(2 * k * k + 6 * k + 2) * sizeof(typename S::Pt) +
-           (size_t)(2 * (2 * k + 4) + 4 * k) * sizeof(typename S::Ad);
+    return (size_t)(2 * k * k + 6 * k + 3) * sizeof(typename S::Pt);
 }
 
-int adjoint_lanes(int64_t k)
-{
-    int lw = 4;
-    while (lw < 2 * k)
-        lw *= 2;
-    return lw;
-}
-
-template <class S>
-size_t adjoint_region_bytes(int64_t k)
-{
-    return (adjoint_lds<S>(k) + 15) / 16 * 16;
-}
-
-// Depth: the largest k <= want (16 by default: with small regions a CU holds
-// many, and the reverse stage is latency-bound per region) dividing nx/2
-// whose workgroup (64/LW regions) fits the LDS budget.
+// Depth: the largest k <= want (16 by default: the reverse stage is a chain
+// of about 4k dependent levels, and small regions keep it short) dividing
+// nx/2 with 2k + 2 <= 64.
 template <class S>
 int64_t adjoint_depth(int64_t nx, int64_t want)
 {
-    for (int64_t k = std::min<int64_t>(32, want > 0 ? want : 16); k >= 1; --k)
-        if (nx % (2 * k) == 0 &&
-            (size_t)(64 / adjoint_lanes(k)) * adjoint_region_bytes<S>(k) <= kMaxLds)
+    for (int64_t k = std::min<int64_t>(31, want > 0 ? want : 16); k >= 1; --k)
+        if (nx % (2 * k) == 0 && adjoint_lds<S>(k) <= kMaxLds)
             return k;
     return 0;
 }
@@ -489,14 +471,7 @@ int run_adjoint(const void* u0v, void* gradv, int64_t nx, int64_t nsteps, const 
     g.k = (int)k;
     g.tiles = (int)tiles;
     g.c = c;
-    // 64/LW regions per workgroup, LW lanes each (LW: the smallest power of
-    // two >= 2k, at least 4), each with its own LDS block
-    const int lw = adjoint_lanes(k);
-    const int per_wg = 64 / lw;
-    g.lanes_per_region = lw;
-    g.region_bytes = (int)adjoint_region_bytes<S>(k);
-    const size_t lds_adj = (size_t)per_wg * g.region_bytes;
-    const unsigned groups = (unsigned)((tiles + per_wg - 1) / per_wg);
+    const size_t lds_adj = adjoint_lds<S>(k);
     for (int64_t s = stages - 1; s >= 0; --s) {
         g.tri = s == 0;
         g.b = (s - 1) * k;
@@ -508,7 +483,7 @@ int run_adjoint(const void* u0v, void* gradv, int64_t nx, int64_t nsteps, const 
         g.fh_in = fhb[(s + 1) & 1];
         g.ae_out = aeb[s & 1];
         g.fh_out = fhb[s & 1];
-        hipLaunchKernelGGL((swept_adjoint_kernel<S>), dim3(groups), dim3(64), lds_adj,
+        hipLaunchKernelGGL((swept_adjoint_kernel<S>), dim3(tiles), dim3(64), lds_adj,
                            g_ctx.stream, g);
     }
     HIP_TRY(hipGetLastError());
