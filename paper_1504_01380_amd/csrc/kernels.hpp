@@ -940,6 +940,72 @@ __global__ __launch_bounds__(64) void swept_adjoint_kernel(AdjArgs<S> g)
     }
 }
 
+// Forward pass of the swept adjoint: each stage's regions in the same lane
+// frame as the reverse kernel, keeping only what the next stage and the
+// reverse pass read -- the new V edges, the two outermost points on each
+// side of rows k..2k-1 (the field itself is not written).  g.u is read, for
+// the triangle, and nothing else of it is touched.
+template <class S>
+__global__ __launch_bounds__(64) void swept_checkpoint_kernel(StageArgs<S> g)
+{
+    using Pt = typename S::Pt;
+    constexpr int NPH = S::NPHASE;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int k = g.k;
+    const AdjLayout ly{k};
+    const int dx = (int)threadIdx.x - k - 1;
+    const int t = blockIdx.x;
+    const int64_t J = wrapn((int64_t)t * (2 * (int64_t)k) + g.J0, g.n);
+    const int jtop = (int)min((int64_t)(2 * k - 1), g.L - g.b);
+    constexpr unsigned PB = sizeof(Pt);
+    unsigned char* const Fb = smem_raw;
+    const unsigned dump_b = (unsigned)ly.fsize() * PB;
+
+    Pt v{}, eA{}, eB{};
+    const int iA = dx < 0 ? -dx - 2 : dx, iB = dx < 0 ? -dx - 1 : dx - 1;
+    int j0 = k;
+    if (g.tri) {
+        if (dx >= -k && dx <= k - 1) {
+            v = S::from_field(g.u[J + dx]);
+            *reinterpret_cast<Pt*>(Fb + (unsigned)ly.fidx(k, dx) * PB) = v;
+        }
+    } else {
+        j0 = 0;
+        const Pt* re = g.re + (size_t)t * k * 2;
+        const int tn = (t + 1 == g.tiles) ? 0 : t + 1;
+        const Pt* le = g.le_in + (size_t)tn * k * 2;
+        if (iA >= 0 && iA < k)
+            eA = dx < 0 ? re[2 * iA] : le[2 * iA];
+        if (iB >= 0 && iB < k)
+            eB = dx < 0 ? re[2 * iB + 1] : le[2 * iB + 1];
+        v = pick(iA == 0, eA, eB);
+    }
+    levels_up<NPH>(g.b - 1, j0 + 1, min(k - 1, jtop), [&](int j, auto ph) {
+        constexpr int PH = decltype(ph)::value;
+        const Pt l = dpp_record<kWaveShr1>(v), r = dpp_record<kWaveShl1>(v);
+        v = pick(iA == j, eA, pick(iB == j, eB, S::template step<PH>(l, v, r, g.c)));
+    });
+    levels_up<NPH>(g.b - 1, max(k, j0 + 1), jtop, [&](int j, auto ph) {
+        constexpr int PH = decltype(ph)::value;
+        const Pt l = dpp_record<kWaveShr1>(v), r = dpp_record<kWaveShl1>(v);
+        v = S::template step<PH>(l, v, r, g.c);
+        const bool own = (unsigned)(dx - (j - 2 * k)) <= (unsigned)(4 * k - 1 - 2 * j);
+        const unsigned at = (unsigned)(ly.template base_h<true>(j) + dx) * PB;
+        *reinterpret_cast<Pt*>(Fb + (own ? at : dump_b)) = v;
+    });
+    __syncthreads();
+    const Pt* F = reinterpret_cast<const Pt*>(smem_raw);
+    Pt* re_out = g.re_out + (size_t)t * k * 2;
+    Pt* le_out = g.le_out + (size_t)t * k * 2;
+    for (int j = k + (int)threadIdx.x; j <= jtop; j += 64) {
+        const int i = j - k;
+        re_out[2 * i] = F[ly.fidx(j, 2 * k - 2 - j)];
+        re_out[2 * i + 1] = F[ly.fidx(j, 2 * k - 1 - j)];
+        le_out[2 * i] = F[ly.fidx(j, j - 2 * k)];
+        le_out[2 * i + 1] = F[ly.fidx(j, j - 2 * k + 1)];
+    }
+}
+
 // Zero time steps: the gradient is the seed at level 0.
 template <class S>
 __global__ __launch_bounds__(256) void adjoint_seed_kernel(const typename S::T* __restrict__ u0,

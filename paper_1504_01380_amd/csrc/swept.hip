@@ -424,8 +424,7 @@ int run_adjoint(const void* u0v, void* gradv, int64_t nx, int64_t nsteps, const 
     const size_t ck = (size_t)stages * nx * sizeof(Pt);
     const size_t ae = 2 * (size_t)nx * sizeof(Ad);        // tiles * 2 sides * k * 2
     const size_t fh = (size_t)nx * sizeof(Pt);            // tiles * 2 sides * k
-    const size_t uf = ((size_t)nx * sizeof(T) + 255) / 256 * 256;
-    int rc = ensure_scratch(2 * ck + 2 * ae + 2 * fh + uf);
+    int rc = ensure_scratch(2 * ck + 2 * ae + 2 * fh);
     if (rc)
         return rc;
     unsigned char* base = static_cast<unsigned char*>(g_ctx.scratch);
@@ -435,17 +434,15 @@ int run_adjoint(const void* u0v, void* gradv, int64_t nx, int64_t nsteps, const 
     Pt* fhb[2] = {reinterpret_cast<Pt*>(base + 2 * ck + 2 * ae),
                   reinterpret_cast<Pt*>(base + 2 * ck + 2 * ae + fh)};
 
-    // forward pass on a copy of u0, keeping the edges of every stage
-    T* ufwd = reinterpret_cast<T*>(base + 2 * ck + 2 * ae + 2 * fh);
-    HIP_TRY(hipMemcpyAsync(ufwd, u0, nx * sizeof(T), hipMemcpyDeviceToDevice, g_ctx.stream));
+    // forward pass, keeping the V edges of every stage (the field is not written)
     StageArgs<S> a{};
-    a.u = ufwd;
+    a.u = const_cast<T*>(u0);   // read only, by the triangle
     a.n = nx;
     a.L = L;
     a.k = (int)k;
     a.tiles = (int)tiles;
     a.c = c;
-    const size_t lds_fwd = (size_t)2 * k * sizeof(Pt);
+    const size_t lds_adj = adjoint_lds<S>(k);
     for (int64_t s = 0; s < stages; ++s) {
         a.tri = s == 0;
         a.b = (s - 1) * k;
@@ -454,7 +451,7 @@ int run_adjoint(const void* u0v, void* gradv, int64_t nx, int64_t nsteps, const 
         a.re_out = ck_re + s * nx;
         a.le_in = s > 0 ? ck_le + (s - 1) * nx : ck_le;
         a.le_out = ck_le + s * nx;
-        hipLaunchKernelGGL((swept_stage_kernel<S, 1>), dim3(tiles), dim3(64), lds_fwd,
+        hipLaunchKernelGGL((swept_checkpoint_kernel<S>), dim3(tiles), dim3(64), lds_adj,
                            g_ctx.stream, a);
     }
     HIP_TRY(hipGetLastError());
@@ -471,7 +468,6 @@ int run_adjoint(const void* u0v, void* gradv, int64_t nx, int64_t nsteps, const 
     g.k = (int)k;
     g.tiles = (int)tiles;
     g.c = c;
-    const size_t lds_adj = adjoint_lds<S>(k);
     for (int64_t s = stages - 1; s >= 0; --s) {
         g.tri = s == 0;
         g.b = (s - 1) * k;
