@@ -275,13 +275,14 @@ int swept_stage_times(double *ms_out, int32_t *kind_out, int64_t cap, int64_t *c
  * sub-timestep's transposed Jacobian, applied in reverse order), evaluated
  * in a fixed order.
  *
- * A forward swept pass on a copy of u0 keeps the V edges of every stage (one
- * checkpoint per sweep, 2*nx points per stage); the stages then run in
+ * A forward swept pass keeps the V edges of every stage (one checkpoint per
+ * sweep, 2*nx points per stage; u0 is only read); the stages then run in
  * reverse, each region recomputing its forward values from its checkpoint
- * inside the workgroup.  Tiles: W = 2k, k <= 32, W divides nx (tile_w of
- * swept_set_tuning, if set, caps k at tile_w/2).  Scratch grows to about
- * 2*nx*(stages)*sizeof(point) bytes (KS: 24-byte points).  Asynchronous on
- * the current stream, like swept_advance.
+ * inside its wavefront.  Tiles: W = 2k, the largest k <= 32 with W dividing
+ * nx (tile_w of swept_set_tuning, if set, caps k at tile_w/2).  Scratch
+ * grows to about 2*nx*(stages)*sizeof(point) bytes, stages = 1 +
+ * ceil(4*nsteps/k) for KS (24-byte points; 2^16 points and 20,000 steps at
+ * k = 32: 7.9 GB).  Asynchronous on the current stream, like swept_advance.
  */
 int swept_adjoint(const void *u0, void *grad_u0, int64_t nx, int64_t nsteps, int32_t stencil_id,
                   const double *params, int32_t nparams, int64_t window_first,

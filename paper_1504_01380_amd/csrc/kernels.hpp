@@ -592,30 +592,35 @@ __global__ __launch_bounds__(64) void swept_diamond_cont_kernel(StageArgs<S> g)
 //   4. hands the same kind of data to the earlier regions below it, or, for
 //      the triangle, writes the gradient with respect to u0.
 //
-// One wavefront per region, in a fixed frame: lane l holds column
-// dx = l - k - 1 (the region and its V edges span dx in [-k-1, k], so
-// 2k + 2 <= 64).  Both sweeps keep one level per lane in registers and take
-// the neighbours' values with one DPP wave shift per 32-bit word, so a level
-// costs a few VALU operations and no LDS round trip.  Values that enter from
-// outside the region -- the V edges on the way up, the later regions'
-// cotangents on the way down -- each reach a column at two consecutive
-// levels, so every lane holds its two in registers and selects them at those
-// levels.  LDS keeps the forward values (written on the way up, read on the
-// way down with the later regions' forward halo at the ends of each level).
+// One wavefront per region, in a fixed frame: lane l holds column dx = l - o.
+// The region and its V edges span dx in [-k-1, k]; o = k + 1 covers them for
+// k <= 31.  For k = 32, o = 32 and the two outermost columns lie outside the
+// wave; only row k reads them (the V edge of row k-1 on the way up, the later
+// regions' cotangents of row k+1 on the way down), and there they enter the
+// boundary lanes' DPP moves as the value a lane keeps when it has no source.
+// Both sweeps keep one level per lane in registers and take the neighbours'
+// values with one DPP wave shift per 32-bit word, so a level costs a few VALU
+// operations and no LDS round trip.  Values that enter from outside the
+// region -- the V edges on the way up, the later regions' cotangents on the
+// way down -- each reach a column at two consecutive levels, so every lane
+// holds its two in registers and selects them at those levels.  LDS keeps,
+// per point, the one forward value the reverse sweep reads there (S::keep),
+// with the later regions' forward halo at the ends of the upper levels.
 
 template <class S>
 struct AdjArgs {
     using Pt = typename S::Pt;
     using Ad = typename S::Ad;
+    using Kept = typename S::Kept;
     const typename S::T* u0;   // initial field (triangle)
     typename S::T* grad;       // d J / d u0 (triangle)
     const typename S::T* cot;  // cotangent of the final field, or null
     const Pt* re_in;           // checkpoint: right edges of stage s-1 (own region)
     const Pt* le_in;           // checkpoint: left edges of stage s-1
     const Ad* ae_in;           // from stage s+1: [tiles][2 sides][k][2] cotangents
-    const Pt* fh_in;           // from stage s+1: [tiles][2 sides][k] forward values
+    const Kept* fh_in;         // from stage s+1: [tiles][2 sides][k] kept forward values
     Ad* ae_out;                // to stage s-1
-    Pt* fh_out;
+    Kept* fh_out;
     int64_t n, L, b, J0;
     int64_t win_first;         // first time step of the objective window
     typename S::T two_w;       // 2 * objective weight
@@ -626,7 +631,8 @@ struct AdjArgs {
 // LDS layout of a region's forward values.  Row j (relative level) holds the
 // columns the reverse sweep reads, dx in [-j-2, j+1] below the middle level
 // (the V edges sit at -j-2, -j-1, j, j+1) and [j-2k-1, 2k-j] from it up (the
-// later regions' forward halo at both ends): 2k^2 + 6k + 2 values.
+// later regions' forward halo at both ends): 2k^2 + 6k + 2 values, the
+// k^2 + 3k rows below the middle level first.
 struct AdjLayout {
     int k;
     __device__ __forceinline__ int frow(int j) const
@@ -634,9 +640,9 @@ struct AdjLayout {
         return j < k ? j * j + 3 * j : k * k + 3 * k + (j - k) * (3 * k + 3 - j);
     }
     __device__ __forceinline__ int lo(int j) const { return j < k ? -j - 2 : j - 2 * k - 1; }
-    __device__ __forceinline__ int hi(int j) const { return j < k ? j + 1 : 2 * k - j; }
     __device__ __forceinline__ int fidx(int j, int dx) const { return frow(j) + dx - lo(j); }
     __device__ __forceinline__ int fsize() const { return 2 * k * k + 6 * k + 2; }
+    __device__ __forceinline__ int lower_size() const { return k * k + 3 * k; }
     // the same per half, without a branch: index of (j, dx) = base + dx
     template <bool UP>
     __device__ __forceinline__ int lo_h(int j) const { return UP ? j - 2 * k - 1 : -j - 2; }
@@ -649,9 +655,13 @@ struct AdjLayout {
     }
 };
 
+// lane frame: lane l holds column l - adj_frame(k)
+__device__ __forceinline__ int adj_frame(int k) { return k + 1 < 32 ? k + 1 : 32; }
+
 // DPP wave shifts of a whole record, one v_mov_b32_dpp per 32-bit word:
 // kWaveShr1 -- lane i receives lane i-1; kWaveShl1 -- lane i receives lane
-// i+1; the lane with no source receives 0 (bound_ctrl).
+// i+1.  dpp_record: the lane with no source receives 0; dpp_record_keep: it
+// receives `old`.
 constexpr int kWaveShl1 = 0x130;
 constexpr int kWaveShr1 = 0x138;
 template <int CTRL, class V>
@@ -664,6 +674,21 @@ __device__ __forceinline__ V dpp_record(const V& src)
 #pragma unroll
     for (int i = 0; i < NW; ++i)
         w[i] = __builtin_amdgcn_mov_dpp(w[i], CTRL, 0xF, 0xF, true);
+    V out;
+    __builtin_memcpy(&out, w, sizeof(V));
+    return out;
+}
+template <int CTRL, class V>
+__device__ __forceinline__ V dpp_record_keep(const V& src, const V& old)
+{
+    static_assert(sizeof(V) % 4 == 0, "records of 32-bit words");
+    constexpr int NW = (int)(sizeof(V) / 4);
+    int w[NW], o[NW];
+    __builtin_memcpy(w, &src, sizeof(V));
+    __builtin_memcpy(o, &old, sizeof(V));
+#pragma unroll
+    for (int i = 0; i < NW; ++i)
+        w[i] = __builtin_amdgcn_update_dpp(o[i], w[i], CTRL, 0xF, 0xF, false);
     V out;
     __builtin_memcpy(&out, w, sizeof(V));
     return out;
@@ -753,36 +778,59 @@ __device__ __forceinline__ void levels_down(int64_t base, int j_first, int j_las
     }
 }
 
+// S::keep for a phase known at run time
+template <class S>
+__device__ __forceinline__ typename S::Kept keep_at(int64_t level, const typename S::Pt& p)
+{
+    if constexpr (S::NPHASE == 1) {
+        return S::template keep<0>(p);
+    } else {
+        switch (phase_of<4>(level)) {
+        case 0: return S::template keep<0>(p);
+        case 1: return S::template keep<1>(p);
+        case 2: return S::template keep<2>(p);
+        default: return S::template keep<3>(p);
+        }
+    }
+}
+
 template <class S>
 __global__ __launch_bounds__(64) void swept_adjoint_kernel(AdjArgs<S> g)
 {
     using Pt = typename S::Pt;
     using Ad = typename S::Ad;
+    using Kept = typename S::Kept;
     using T = typename S::T;
     constexpr int NPH = S::NPHASE;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    Pt* F = reinterpret_cast<Pt*>(smem_raw);
     const int k = g.k;
     const AdjLayout ly{k};
-    const int dump = ly.fsize();               // one spare slot: lanes with nothing to store
-    const int dx = (int)threadIdx.x - k - 1;   // this lane's column
+    const int dx = (int)threadIdx.x - adj_frame(k);   // this lane's column
+    const bool wide = adj_frame(k) == k;              // columns -k-1 and k outside the wave
     const int t = blockIdx.x;
     const int64_t n = g.n;
     const int64_t J = wrapn((int64_t)t * (2 * (int64_t)k) + g.J0, n);
     const int jtop = (int)min((int64_t)(2 * k - 1), g.L - g.b);
     const bool act_k = dx >= -k && dx <= k - 1;   // the middle level's points
+    // LDS byte addresses in 32 bits: a per-row offset plus the lane's column
+    constexpr unsigned KB = sizeof(Kept);
+    unsigned char* const Fb = smem_raw;
+    const unsigned dump_b = (unsigned)ly.fsize() * KB;   // a spare slot for lanes with nothing to store
+    auto F = [&](int idx) -> Kept& { return *reinterpret_cast<Kept*>(Fb + (unsigned)idx * KB); };
 
     // 1. checkpoint, the later regions' data, and the forward recompute.
     // The V edge reaches this column at rows iA and iB: -dx-2 and -dx-1 on
     // the left (the kept right edge of the stage before), dx and dx-1 on the
-    // right (the left edge of the next region of the stage before).
-    Pt v{}, eA{}, eB{};
+    // right (the left edge of the next region of the stage before).  The
+    // stored forward value of row j is the one read by the sub-timestep that
+    // leaves level b + j.
+    Pt v{}, eA{}, eB{}, oL{}, oR{};
     const int iA = dx < 0 ? -dx - 2 : dx, iB = dx < 0 ? -dx - 1 : dx - 1;
     int j0 = k;
     if (g.tri) {
         if (act_k) {
             v = S::from_field(g.u0[J + dx]);
-            F[ly.fidx(k, dx)] = v;
+            F(ly.fidx(k, dx)) = keep_at<S>(g.b + k, v);
         }
     } else {
         j0 = 0;
@@ -793,43 +841,47 @@ __global__ __launch_bounds__(64) void swept_adjoint_kernel(AdjArgs<S> g)
             eA = dx < 0 ? re[2 * iA] : le[2 * iA];
         if (iB >= 0 && iB < k)
             eB = dx < 0 ? re[2 * iB + 1] : le[2 * iB + 1];
+        if (wide) {   // columns -k-1 and k of row k-1
+            oL = re[2 * (k - 1)];
+            oR = le[2 * (k - 1) + 1];
+        }
         v = pick(iA == 0, eA, eB);   // row 0 holds only edges
         if (dx >= -2 && dx <= 1)
-            F[ly.fidx(0, dx)] = v;
+            F(ly.fidx(0, dx)) = keep_at<S>(g.b, v);
     }
     if (g.has_later) {   // their relative level jj is our level jj + k
         const int tl = (t == 0) ? g.tiles - 1 : t - 1;
-        const Pt* fhR = g.fh_in + ((size_t)tl * 2 + 1) * k;   // upper-left region, right side
-        const Pt* fhL = g.fh_in + ((size_t)t * 2 + 0) * k;    // upper-right region, left side
-        for (int jj = threadIdx.x; jj < k; jj += 64) {       // forward halo at their levels 0..k-1
+        const Kept* fhR = g.fh_in + ((size_t)tl * 2 + 1) * k;   // upper-left region, right side
+        const Kept* fhL = g.fh_in + ((size_t)t * 2 + 0) * k;    // upper-right region, left side
+        for (int jj = threadIdx.x; jj < k; jj += 64) {         // forward halo at their levels 0..k-1
             if (jj + k <= jtop) {
-                F[ly.fidx(jj + k, -k + jj - 1)] = fhR[jj];
-                F[ly.fidx(jj + k, k - jj)] = fhL[jj];
+                F(ly.fidx(jj + k, -k + jj - 1)) = fhR[jj];
+                F(ly.fidx(jj + k, k - jj)) = fhL[jj];
             }
         }
     }
-    // 2 (issued early). The later regions' cotangents reach this column at
-    // rows rA and rB (their levels 1..k are our rows k+1..2k): dx+2k+2 and
-    // dx+2k+1 on the left (the upper-left region's right side), 2k-dx and
-    // 2k-dx+1 on the right (the upper-right region's left side).
-    Ad inA{}, inB{};
+    // (issued early) The later regions' cotangents reach this column at rows
+    // rA and rB (their levels 1..k are our rows k+1..2k): dx+2k+2 and dx+2k+1
+    // on the left (the upper-left region's right side), 2k-dx and 2k-dx+1 on
+    // the right (the upper-right region's left side).
+    Ad inA{}, inB{}, iL{}, iR{};
     const int rA = dx < 0 ? dx + 2 * k + 2 : 2 * k - dx;
     const int rB = dx < 0 ? dx + 2 * k + 1 : 2 * k - dx + 1;
     if (g.has_later) {
         const int tl = (t == 0) ? g.tiles - 1 : t - 1;
-        const Ad* in = dx < 0 ? g.ae_in + ((size_t)tl * 2 + 1) * k * 2
-                              : g.ae_in + ((size_t)t * 2 + 0) * k * 2;
+        const Ad* inl = g.ae_in + ((size_t)tl * 2 + 1) * k * 2;
+        const Ad* inr = g.ae_in + ((size_t)t * 2 + 0) * k * 2;
+        const Ad* in = dx < 0 ? inl : inr;
         if (rA > k && rA <= 2 * k)
             inA = in[2 * (rA - k - 1)];
         if (rB > k && rB <= 2 * k)
             inB = in[2 * (rB - k - 1) + 1];
+        if (wide) {   // columns -k-1 and k of row k+1
+            iL = inl[0];
+            iR = inr[1];
+        }
     }
 
-    // LDS byte addresses in 32 bits: the lane's column times the record size
-    // plus a per-row offset
-    constexpr unsigned PB = sizeof(Pt);
-    unsigned char* const Fb = smem_raw;
-    const unsigned dump_b = (unsigned)dump * PB;
     // rows below the middle: the V edge enters at rows iA and iB; every row
     // is stored with its edges (dx in [-j-2, j+1])
     levels_up<NPH>(g.b - 1, j0 + 1, min(k - 1, jtop), [&](int j, auto ph) {
@@ -837,20 +889,31 @@ __global__ __launch_bounds__(64) void swept_adjoint_kernel(AdjArgs<S> g)
         const Pt l = dpp_record<kWaveShr1>(v), r = dpp_record<kWaveShl1>(v);
         v = pick(iA == j, eA, pick(iB == j, eB, S::template step<PH>(l, v, r, g.c)));
         const bool in_row = (unsigned)(dx + j + 2) <= (unsigned)(2 * j + 3);
-        const unsigned at = (unsigned)(ly.template base_h<false>(j) + dx) * PB;
-        *reinterpret_cast<Pt*>(Fb + (in_row ? at : dump_b)) = v;
+        const unsigned at = (unsigned)(ly.template base_h<false>(j) + dx) * KB;
+        *reinterpret_cast<Kept*>(Fb + (in_row ? at : dump_b)) =
+            S::template keep<(PH + 1) % NPH>(v);
     });
     // from the middle row up: only the region's own points are stored
     // (dx in [j-2k, 2k-1-j]; the ends of these rows hold the later regions'
-    // forward halo)
-    levels_up<NPH>(g.b - 1, max(k, j0 + 1), jtop, [&](int j, auto ph) {
+    // forward halo).  The middle row of a diamond reads columns -k-1 and k.
+    auto up_level = [&](int j, auto ph, auto outer) {
         constexpr int PH = decltype(ph)::value;
-        const Pt l = dpp_record<kWaveShr1>(v), r = dpp_record<kWaveShl1>(v);
+        Pt l, r;
+        if constexpr (decltype(outer)::value) {
+            l = dpp_record_keep<kWaveShr1>(v, oL);
+            r = dpp_record_keep<kWaveShl1>(v, oR);
+        } else {
+            l = dpp_record<kWaveShr1>(v);
+            r = dpp_record<kWaveShl1>(v);
+        }
         v = S::template step<PH>(l, v, r, g.c);
         const bool own = (unsigned)(dx - (j - 2 * k)) <= (unsigned)(4 * k - 1 - 2 * j);
-        const unsigned at = (unsigned)(ly.template base_h<true>(j) + dx) * PB;
-        *reinterpret_cast<Pt*>(Fb + (own ? at : dump_b)) = v;
-    });
+        const unsigned at = (unsigned)(ly.template base_h<true>(j) + dx) * KB;
+        *reinterpret_cast<Kept*>(Fb + (own ? at : dump_b)) = S::template keep<(PH + 1) % NPH>(v);
+    };
+    if (!g.tri && jtop >= k)
+        levels_up<NPH>(g.b - 1, k, k, [&](int j, auto ph) { up_level(j, ph, std::true_type{}); });
+    levels_up<NPH>(g.b - 1, k + 1, jtop, [&](int j, auto ph) { up_level(j, ph, std::false_type{}); });
     __syncthreads();
 
     // 2. cotangents from the top level down
@@ -863,20 +926,27 @@ __global__ __launch_bounds__(64) void swept_adjoint_kernel(AdjArgs<S> g)
     const int jbot = g.tri ? k : 1;
     // the objective's source enters at step levels from row jw up
     const int jw = (int)max((int64_t)-1, min((int64_t)(2 * k + 1), g.win_first * NPH - g.b));
-    // forward values of row j at dx-1, dx, dx+1, the column clamped into the
-    // row for the lanes outside it (whose results are never used)
+    // kept forward values of row j at dx-1, dx, dx+1, the column clamped
+    // into the row for the lanes outside it (whose results are never used)
     auto fwd3 = [&](int j, auto up) {
         constexpr bool UP = decltype(up)::value;
         const int col = min(max(dx, ly.template lo_h<UP>(j) + 1), ly.template hi_h<UP>(j) - 1);
-        return reinterpret_cast<const Pt*>(Fb + (unsigned)(ly.template base_h<UP>(j) + col - 1) * PB);
+        return reinterpret_cast<const Kept*>(Fb + (unsigned)(ly.template base_h<UP>(j) + col - 1) * KB);
     };
     // one level: UP selects the layout half (rows >= k), MERGE takes the
     // later regions' cotangents (rows > k), otherwise the hand-down rows are
-    // captured
-    auto level = [&](int j, auto ph, auto up, auto merge) {
+    // captured; OUTER (the middle row) reads columns -k-1 and k of row k+1
+    auto level = [&](int j, auto ph, auto up, auto merge, auto outer) {
         constexpr int PH = decltype(ph)::value;
-        const Pt* fr = fwd3(j, up);
-        const Ad al = dpp_record<kWaveShr1>(a), ar = dpp_record<kWaveShl1>(a);
+        const Kept* fr = fwd3(j, up);
+        Ad al, ar;
+        if constexpr (decltype(outer)::value) {
+            al = dpp_record_keep<kWaveShr1>(a, iL);
+            ar = dpp_record_keep<kWaveShl1>(a, iR);
+        } else {
+            al = dpp_record<kWaveShr1>(a);
+            ar = dpp_record<kWaveShl1>(a);
+        }
         Ad o = S::template adj<PH>(al, a, ar, fr[0], fr[1], fr[2], g.c);
         if (PH == 0 && j >= jw)
             o = S::source(o, fr[1], g.two_w);
@@ -892,7 +962,7 @@ __global__ __launch_bounds__(64) void swept_adjoint_kernel(AdjArgs<S> g)
     using No = std::false_type;
     int jstart = jtop;
     if (g.b + jtop == g.L) {   // the target level: the seed
-        const Pt* fr = jtop >= k ? fwd3(jtop, Yes{}) : fwd3(jtop, No{});
+        const Kept* fr = jtop >= k ? fwd3(jtop, Yes{}) : fwd3(jtop, No{});
         T c0 = T(0);
         if (g.cot && (jtop <= k ? (dx >= -jtop && dx <= jtop - 1)
                                 : (dx >= jtop - 2 * k && dx <= 2 * k - 1 - jtop)))
@@ -908,11 +978,11 @@ __global__ __launch_bounds__(64) void swept_adjoint_kernel(AdjArgs<S> g)
         --jstart;
     }
     levels_down<NPH>(g.b, jstart, max(k + 1, jbot),
-                     [&](int j, auto ph) { level(j, ph, Yes{}, Yes{}); });
+                     [&](int j, auto ph) { level(j, ph, Yes{}, Yes{}, No{}); });
     if (jstart >= k && k >= jbot)   // the middle row: upper layout, lower cotangent rule
-        levels_down<NPH>(g.b, k, k, [&](int j, auto ph) { level(j, ph, Yes{}, No{}); });
+        levels_down<NPH>(g.b, k, k, [&](int j, auto ph) { level(j, ph, Yes{}, No{}, Yes{}); });
     levels_down<NPH>(g.b, min(jstart, k - 1), jbot,
-                     [&](int j, auto ph) { level(j, ph, No{}, No{}); });
+                     [&](int j, auto ph) { level(j, ph, No{}, No{}, No{}); });
 
     // 3. the gradient, or the hand-down to the earlier regions
     if (g.tri) {
@@ -932,11 +1002,11 @@ __global__ __launch_bounds__(64) void swept_adjoint_kernel(AdjArgs<S> g)
     };
     hand_down(cA, capA);
     hand_down(cB, capB);
-    Pt* fhL = g.fh_out + ((size_t)t * 2 + 0) * k;
-    Pt* fhR = g.fh_out + ((size_t)t * 2 + 1) * k;
+    Kept* fhL = g.fh_out + ((size_t)t * 2 + 0) * k;
+    Kept* fhR = g.fh_out + ((size_t)t * 2 + 1) * k;
     for (int j = threadIdx.x; j < k && j <= jtop; j += 64) {
-        fhL[j] = F[ly.fidx(j, -j)];
-        fhR[j] = F[ly.fidx(j, j - 1)];
+        fhL[j] = F(ly.fidx(j, -j));
+        fhR[j] = F(ly.fidx(j, j - 1));
     }
 }
 
@@ -944,7 +1014,8 @@ __global__ __launch_bounds__(64) void swept_adjoint_kernel(AdjArgs<S> g)
 // frame as the reverse kernel, keeping only what the next stage and the
 // reverse pass read -- the new V edges, the two outermost points on each
 // side of rows k..2k-1 (the field itself is not written).  g.u is read, for
-// the triangle, and nothing else of it is touched.
+// the triangle, and nothing else of it is touched.  LDS holds the rows from
+// the middle level up (the upper half of the adjoint layout).
 template <class S>
 __global__ __launch_bounds__(64) void swept_checkpoint_kernel(StageArgs<S> g)
 {
@@ -953,21 +1024,26 @@ __global__ __launch_bounds__(64) void swept_checkpoint_kernel(StageArgs<S> g)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int k = g.k;
     const AdjLayout ly{k};
-    const int dx = (int)threadIdx.x - k - 1;
+    const int dx = (int)threadIdx.x - adj_frame(k);
+    const bool wide = adj_frame(k) == k;
     const int t = blockIdx.x;
     const int64_t J = wrapn((int64_t)t * (2 * (int64_t)k) + g.J0, g.n);
     const int jtop = (int)min((int64_t)(2 * k - 1), g.L - g.b);
     constexpr unsigned PB = sizeof(Pt);
     unsigned char* const Fb = smem_raw;
-    const unsigned dump_b = (unsigned)ly.fsize() * PB;
+    const int low = ly.lower_size();
+    const unsigned dump_b = (unsigned)(ly.fsize() - low) * PB;
+    auto U = [&](int j, int col) -> Pt& {
+        return *reinterpret_cast<Pt*>(Fb + (unsigned)(ly.fidx(j, col) - low) * PB);
+    };
 
-    Pt v{}, eA{}, eB{};
+    Pt v{}, eA{}, eB{}, oL{}, oR{};
     const int iA = dx < 0 ? -dx - 2 : dx, iB = dx < 0 ? -dx - 1 : dx - 1;
     int j0 = k;
     if (g.tri) {
         if (dx >= -k && dx <= k - 1) {
             v = S::from_field(g.u[J + dx]);
-            *reinterpret_cast<Pt*>(Fb + (unsigned)ly.fidx(k, dx) * PB) = v;
+            U(k, dx) = v;
         }
     } else {
         j0 = 0;
@@ -978,6 +1054,10 @@ __global__ __launch_bounds__(64) void swept_checkpoint_kernel(StageArgs<S> g)
             eA = dx < 0 ? re[2 * iA] : le[2 * iA];
         if (iB >= 0 && iB < k)
             eB = dx < 0 ? re[2 * iB + 1] : le[2 * iB + 1];
+        if (wide) {
+            oL = re[2 * (k - 1)];
+            oR = le[2 * (k - 1) + 1];
+        }
         v = pick(iA == 0, eA, eB);
     }
     levels_up<NPH>(g.b - 1, j0 + 1, min(k - 1, jtop), [&](int j, auto ph) {
@@ -985,24 +1065,33 @@ __global__ __launch_bounds__(64) void swept_checkpoint_kernel(StageArgs<S> g)
         const Pt l = dpp_record<kWaveShr1>(v), r = dpp_record<kWaveShl1>(v);
         v = pick(iA == j, eA, pick(iB == j, eB, S::template step<PH>(l, v, r, g.c)));
     });
-    levels_up<NPH>(g.b - 1, max(k, j0 + 1), jtop, [&](int j, auto ph) {
+    auto up_level = [&](int j, auto ph, auto outer) {
         constexpr int PH = decltype(ph)::value;
-        const Pt l = dpp_record<kWaveShr1>(v), r = dpp_record<kWaveShl1>(v);
+        Pt l, r;
+        if constexpr (decltype(outer)::value) {
+            l = dpp_record_keep<kWaveShr1>(v, oL);
+            r = dpp_record_keep<kWaveShl1>(v, oR);
+        } else {
+            l = dpp_record<kWaveShr1>(v);
+            r = dpp_record<kWaveShl1>(v);
+        }
         v = S::template step<PH>(l, v, r, g.c);
         const bool own = (unsigned)(dx - (j - 2 * k)) <= (unsigned)(4 * k - 1 - 2 * j);
-        const unsigned at = (unsigned)(ly.template base_h<true>(j) + dx) * PB;
+        const unsigned at = (unsigned)(ly.template base_h<true>(j) + dx - low) * PB;
         *reinterpret_cast<Pt*>(Fb + (own ? at : dump_b)) = v;
-    });
+    };
+    if (!g.tri && jtop >= k)
+        levels_up<NPH>(g.b - 1, k, k, [&](int j, auto ph) { up_level(j, ph, std::true_type{}); });
+    levels_up<NPH>(g.b - 1, k + 1, jtop, [&](int j, auto ph) { up_level(j, ph, std::false_type{}); });
     __syncthreads();
-    const Pt* F = reinterpret_cast<const Pt*>(smem_raw);
     Pt* re_out = g.re_out + (size_t)t * k * 2;
     Pt* le_out = g.le_out + (size_t)t * k * 2;
     for (int j = k + (int)threadIdx.x; j <= jtop; j += 64) {
         const int i = j - k;
-        re_out[2 * i] = F[ly.fidx(j, 2 * k - 2 - j)];
-        re_out[2 * i + 1] = F[ly.fidx(j, 2 * k - 1 - j)];
-        le_out[2 * i] = F[ly.fidx(j, j - 2 * k)];
-        le_out[2 * i + 1] = F[ly.fidx(j, j - 2 * k + 1)];
+        re_out[2 * i] = U(j, 2 * k - 2 - j);
+        re_out[2 * i + 1] = U(j, 2 * k - 1 - j);
+        le_out[2 * i] = U(j, j - 2 * k);
+        le_out[2 * i + 1] = U(j, j - 2 * k + 1);
     }
 }
 
@@ -1015,8 +1104,8 @@ __global__ __launch_bounds__(256) void adjoint_seed_kernel(const typename S::T* 
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        grad[i] = S::grad(S::seed(cot ? cot[i] : typename S::T(0), two_w, S::from_field(u0[i]),
-                                  src != 0));
+        grad[i] = S::grad(S::seed(cot ? cot[i] : typename S::T(0), two_w,
+                                  S::template keep<0>(S::from_field(u0[i])), src != 0));
 }
 
 // Naive adjoint (the straight decomposition run backwards): one launch per
@@ -1041,15 +1130,16 @@ __global__ __launch_bounds__(NB) void naive_adjoint_kernel(const typename S::T* 
         x %= n;
         return x < 0 ? x + n : x;
     };
-    auto cot = [&](int64_t x) { return S::seed(ub_in[at(x)], T(0), Pt{}, false); };
+    auto cot = [&](int64_t x) { return S::seed(ub_in[at(x)], T(0), typename S::Kept{}, false); };
     if constexpr (S::NPHASE == 1) {
         const int64_t i = i0 + tid;
         if (i < n) {
             const Pt fl = S::from_field(uj[at(i - 1)]), fc = S::from_field(uj[i]),
                      fr = S::from_field(uj[at(i + 1)]);
-            Ad a = S::template adj<0>(cot(i - 1), cot(i), cot(i + 1), fl, fc, fr, c);
+            Ad a = S::template adj<0>(cot(i - 1), cot(i), cot(i + 1), S::template keep<0>(fl),
+                                      S::template keep<0>(fc), S::template keep<0>(fr), c);
             if (src)
-                a = S::source(a, fc, two_w);
+                a = S::source(a, S::template keep<0>(fc), two_w);
             ub_out[i] = S::grad(a);
         }
     } else {
@@ -1071,22 +1161,23 @@ __global__ __launch_bounds__(NB) void naive_adjoint_kernel(const typename S::T* 
             f3[j] = S::template step<2>(f2[j], f2[j + 1], f2[j + 2], c);
         __syncthreads();
         for (int j = tid; j < NB + 6; j += NB)                  // x = i0-3+j
-            a3[j] = S::template adj<3>(a4[j], a4[j + 1], a4[j + 2], f3[j], f3[j + 1], f3[j + 2], c);
+            a3[j] = S::template adj<3>(a4[j], a4[j + 1], a4[j + 2], S::template keep<3>(f3[j]),
+                                       S::template keep<3>(f3[j + 1]), S::template keep<3>(f3[j + 2]), c);
         __syncthreads();
         for (int j = tid; j < NB + 4; j += NB)                  // x = i0-2+j
-            a2[j] = S::template adj<2>(a3[j], a3[j + 1], a3[j + 2], f2[j + 2], f2[j + 3],
-                                       f2[j + 4], c);
+            a2[j] = S::template adj<2>(a3[j], a3[j + 1], a3[j + 2], S::template keep<2>(f2[j + 2]),
+                                       S::template keep<2>(f2[j + 3]), S::template keep<2>(f2[j + 4]), c);
         __syncthreads();
         for (int j = tid; j < NB + 2; j += NB)                  // x = i0-1+j
-            a1[j] = S::template adj<1>(a2[j], a2[j + 1], a2[j + 2], f1[j + 4], f1[j + 5],
-                                       f1[j + 6], c);
+            a1[j] = S::template adj<1>(a2[j], a2[j + 1], a2[j + 2], S::template keep<1>(f1[j + 4]),
+                                       S::template keep<1>(f1[j + 5]), S::template keep<1>(f1[j + 6]), c);
         __syncthreads();
         const int64_t i = i0 + tid;                             // x = i0+tid
         if (i < n) {
-            Ad a = S::template adj<0>(a1[tid], a1[tid + 1], a1[tid + 2], f0[tid + 6], f0[tid + 7],
-                                      f0[tid + 8], c);
+            Ad a = S::template adj<0>(a1[tid], a1[tid + 1], a1[tid + 2], S::template keep<0>(f0[tid + 6]),
+                                      S::template keep<0>(f0[tid + 7]), S::template keep<0>(f0[tid + 8]), c);
             if (src)
-                a = S::source(a, f0[tid + 7], two_w);
+                a = S::source(a, S::template keep<0>(f0[tid + 7]), two_w);
             ub_out[i] = S::grad(a);
         }
     }

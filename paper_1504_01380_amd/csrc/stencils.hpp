@@ -76,21 +76,29 @@ struct Heat {
     struct Ad {
         T u;
     };
+    // the forward value the reverse sweep reads at a level (the objective's
+    // source needs u; the update itself needs none)
+    using Kept = T;
     template <int PH>
-    __device__ __forceinline__ static Ad adj(const Ad& l, const Ad& c, const Ad& r, const Pt&,
-                                             const Pt&, const Pt&, const Consts& k)
+    __device__ __forceinline__ static Kept keep(const Pt& p)
+    {
+        return p.u;
+    }
+    template <int PH>
+    __device__ __forceinline__ static Ad adj(const Ad& l, const Ad& c, const Ad& r, Kept, Kept,
+                                             Kept, const Consts& k)
     {
         const T lap = (l.u + r.u) - T(2) * c.u;
         return Ad{c.u + k.r * lap};
     }
     // cotangent at the target level: cot (+ 2w u when that level is in the window)
-    __device__ __forceinline__ static Ad seed(T cot, T two_w, const Pt& f, bool src)
+    __device__ __forceinline__ static Ad seed(T cot, T two_w, Kept u, bool src)
     {
-        return Ad{src ? cot + two_w * f.u : cot};
+        return Ad{src ? cot + two_w * u : cot};
     }
-    __device__ __forceinline__ static Ad source(const Ad& a, const Pt& f, T two_w)
+    __device__ __forceinline__ static Ad source(const Ad& a, Kept u, T two_w)
     {
-        return Ad{a.u + two_w * f.u};
+        return Ad{a.u + two_w * u};
     }
     __device__ __forceinline__ static T grad(const Ad& a) { return a.u; }
 };
@@ -153,39 +161,48 @@ struct KSF64 {
     struct Ad {
         double u, x, y;
     };
+    // The one forward value each transposed sub-timestep reads at a point:
+    // v (held in a) for sub3, u for sub1 and for the objective's source at
+    // step levels; sub2 reads none.  PH is the sub-timestep that leaves the
+    // level.
+    using Kept = double;
+    template <int PH>
+    __device__ __forceinline__ static Kept keep(const Pt& p)
+    {
+        return PH == 3 ? p.a : p.u;
+    }
     __device__ __forceinline__ static double d2(double l, double m, double r, const Consts& k)
     {
         return ((l + r) - 2.0 * m) * k.c2;
     }
     template <int PH>
-    __device__ __forceinline__ static Ad adj(const Ad& al, const Ad& ac, const Ad& ar,
-                                             const Pt& fl, const Pt&, const Pt& fr,
-                                             const Consts& k)
+    __device__ __forceinline__ static Ad adj(const Ad& al, const Ad& ac, const Ad& ar, Kept fl,
+                                             Kept, Kept fr, const Consts& k)
     {
-        if constexpr (PH == 3) {        // reverse of u' = u + dt*F(v, z), g = dt*ub'
+        if constexpr (PH == 3) {        // reverse of u' = u + dt*F(v, z), g = dt*ub'; fl, fr = v
             const double gl = k.dt * al.u, gm = k.dt * ac.u, gr = k.dt * ar.u;
-            const double vb = (k.c1 * ((gr * fr.a) - (gl * fl.a))) - (gm * ((fr.a - fl.a) * k.c1));
+            const double vb = (k.c1 * ((gr * fr) - (gl * fl))) - (gm * ((fr - fl) * k.c1));
             const double zb = -(gm + d2(gl, gm, gr, k));
             return Ad{ac.u, vb, zb};
         } else if constexpr (PH == 2) { // reverse of z = D2(v)
             return Ad{ac.u, ac.x + d2(al.y, ac.y, ar.y, k), 0.0};
-        } else if constexpr (PH == 1) { // reverse of v = u + h*F(u, w), q = h*vb
+        } else if constexpr (PH == 1) { // reverse of v = u + h*F(u, w), q = h*vb; fl, fr = u
             const double ql = k.h * al.x, qm = k.h * ac.x, qr = k.h * ar.x;
             const double ub = (ac.u + ac.x) +
-                              ((k.c1 * ((qr * fr.u) - (ql * fl.u))) - (qm * ((fr.u - fl.u) * k.c1)));
+                              ((k.c1 * ((qr * fr) - (ql * fl))) - (qm * ((fr - fl) * k.c1)));
             const double wb = -(qm + d2(ql, qm, qr, k));
             return Ad{ub, wb, 0.0};
         } else {                        // reverse of w = D2(u)
             return Ad{ac.u + d2(al.x, ac.x, ar.x, k), 0.0, 0.0};
         }
     }
-    __device__ __forceinline__ static Ad seed(double cot, double two_w, const Pt& f, bool src)
+    __device__ __forceinline__ static Ad seed(double cot, double two_w, Kept u, bool src)
     {
-        return Ad{src ? cot + two_w * f.u : cot, 0.0, 0.0};
+        return Ad{src ? cot + two_w * u : cot, 0.0, 0.0};
     }
-    __device__ __forceinline__ static Ad source(const Ad& a, const Pt& f, double two_w)
+    __device__ __forceinline__ static Ad source(const Ad& a, Kept u, double two_w)
     {
-        return Ad{a.u + two_w * f.u, a.x, a.y};
+        return Ad{a.u + two_w * u, a.x, a.y};
     }
     __device__ __forceinline__ static double grad(const Ad& a) { return a.u; }
 };

@@ -376,22 +376,32 @@ unsigned grid_for(int64_t n, int block)
 // ----------------------------------------------------------- swept adjoint
 
 // Tile for the adjoint: one wavefront per region, whose lanes are the
-// columns [-k-1, k] of the region and its V edges (2k + 2 <= 64); the
-// region's forward values (2k^2 + 6k + 2 points, and one spare) in LDS.
+// columns of the region and its V edges (the two outermost ones excepted at
+// k = 32).  LDS of the reverse kernel: one kept forward value per point of
+// the region's layout (2k^2 + 6k + 2, and one spare); of the checkpoint
+// kernel: the full points of the rows from the middle level up (k^2 + 3k + 2,
+// and one spare).
 template <class S>
 size_t adjoint_lds(int64_t k)
 {
-    return (size_t)(2 * k * k + 6 * k + 3) * sizeof(typename S::Pt);
+    return (size_t)(2 * k * k + 6 * k + 3) * sizeof(typename S::Kept);
 }
 
-// Depth: the largest k <= want (16 by default: the reverse stage is a chain
-// of about 4k dependent levels, and small regions keep it short) dividing
-// nx/2 with 2k + 2 <= 64.
+template <class S>
+size_t checkpoint_lds(int64_t k)
+{
+    return (size_t)(k * k + 3 * k + 3) * sizeof(typename S::Pt);
+}
+
+// Depth: the largest k <= want (32 by default: a stage costs a launch and
+// its edge traffic plus a chain of about 4k dependent levels, so deeper
+// stages are cheaper per level up to the lane frame's k <= 32) dividing nx/2,
+// with both kernels' LDS in budget.
 template <class S>
 int64_t adjoint_depth(int64_t nx, int64_t want)
 {
-    for (int64_t k = std::min<int64_t>(31, want > 0 ? want : 16); k >= 1; --k)
-        if (nx % (2 * k) == 0 && adjoint_lds<S>(k) <= kMaxLds)
+    for (int64_t k = std::min<int64_t>(32, want > 0 ? want : 32); k >= 1; --k)
+        if (nx % (2 * k) == 0 && adjoint_lds<S>(k) <= kMaxLds && checkpoint_lds<S>(k) <= kMaxLds)
             return k;
     return 0;
 }
@@ -402,6 +412,7 @@ int run_adjoint(const void* u0v, void* gradv, int64_t nx, int64_t nsteps, const 
 {
     using Pt = typename S::Pt;
     using Ad = typename S::Ad;
+    using Kept = typename S::Kept;
     using T = typename S::T;
     const T* u0 = static_cast<const T*>(u0v);
     T* grad = static_cast<T*>(gradv);
@@ -423,7 +434,7 @@ int run_adjoint(const void* u0v, void* gradv, int64_t nx, int64_t nsteps, const 
     // checkpoints: right and left edges of every stage; cotangent hand-over buffers
     const size_t ck = (size_t)stages * nx * sizeof(Pt);
     const size_t ae = 2 * (size_t)nx * sizeof(Ad);        // tiles * 2 sides * k * 2
-    const size_t fh = (size_t)nx * sizeof(Pt);            // tiles * 2 sides * k
+    const size_t fh = (size_t)nx * sizeof(Kept);          // tiles * 2 sides * k
     int rc = ensure_scratch(2 * ck + 2 * ae + 2 * fh);
     if (rc)
         return rc;
@@ -431,8 +442,8 @@ int run_adjoint(const void* u0v, void* gradv, int64_t nx, int64_t nsteps, const 
     Pt* ck_re = reinterpret_cast<Pt*>(base);
     Pt* ck_le = reinterpret_cast<Pt*>(base + ck);
     Ad* aeb[2] = {reinterpret_cast<Ad*>(base + 2 * ck), reinterpret_cast<Ad*>(base + 2 * ck + ae)};
-    Pt* fhb[2] = {reinterpret_cast<Pt*>(base + 2 * ck + 2 * ae),
-                  reinterpret_cast<Pt*>(base + 2 * ck + 2 * ae + fh)};
+    Kept* fhb[2] = {reinterpret_cast<Kept*>(base + 2 * ck + 2 * ae),
+                    reinterpret_cast<Kept*>(base + 2 * ck + 2 * ae + fh)};
 
     // forward pass, keeping the V edges of every stage (the field is not written)
     StageArgs<S> a{};
@@ -442,7 +453,7 @@ int run_adjoint(const void* u0v, void* gradv, int64_t nx, int64_t nsteps, const 
     a.k = (int)k;
     a.tiles = (int)tiles;
     a.c = c;
-    const size_t lds_adj = adjoint_lds<S>(k);
+    const size_t lds_ck = checkpoint_lds<S>(k);
     for (int64_t s = 0; s < stages; ++s) {
         a.tri = s == 0;
         a.b = (s - 1) * k;
@@ -451,7 +462,7 @@ int run_adjoint(const void* u0v, void* gradv, int64_t nx, int64_t nsteps, const 
         a.re_out = ck_re + s * nx;
         a.le_in = s > 0 ? ck_le + (s - 1) * nx : ck_le;
         a.le_out = ck_le + s * nx;
-        hipLaunchKernelGGL((swept_checkpoint_kernel<S>), dim3(tiles), dim3(64), lds_adj,
+        hipLaunchKernelGGL((swept_checkpoint_kernel<S>), dim3(tiles), dim3(64), lds_ck,
                            g_ctx.stream, a);
     }
     HIP_TRY(hipGetLastError());
@@ -468,6 +479,7 @@ int run_adjoint(const void* u0v, void* gradv, int64_t nx, int64_t nsteps, const 
     g.k = (int)k;
     g.tiles = (int)tiles;
     g.c = c;
+    const size_t lds_adj = adjoint_lds<S>(k);
     for (int64_t s = stages - 1; s >= 0; --s) {
         g.tri = s == 0;
         g.b = (s - 1) * k;

@@ -39,6 +39,7 @@ def gpu_adjoint(sw, u0, nsteps, stencil, params, first, wgt, cot=None, tile=0):
 @pytest.mark.parametrize("n,nsteps,first,tile,with_cot", [
     (64, 1, 0, 0, True), (64, 37, 20, 0, True), (128, 100, 1, 0, False), (96, 50, 51, 32, True),
     (1024, 333, 300, 0, True), (64, 0, 0, 0, True), (4096, 1000, 900, 64, False),
+    (64, 37, 20, 64, True), (640, 45, 44, 64, False),
 ])
 def test_heat_adjoint_bitwise(sw, oracle_mod, n, nsteps, first, tile, with_cot):
     u0 = workloads.white_noise(n, seed=n + nsteps)
@@ -52,6 +53,8 @@ def test_heat_adjoint_bitwise(sw, oracle_mod, n, nsteps, first, tile, with_cot):
 @pytest.mark.parametrize("n,nsteps,first,tile,with_cot", [
     (64, 1, 0, 0, True), (64, 9, 5, 0, True), (128, 40, 1, 0, False), (96, 25, 20, 8, True),
     (1024, 120, 100, 0, True), (4096, 300, 250, 16, False), (256, 50, 51, 4, True),
+    (4096, 300, 250, 64, True), (128, 77, 30, 64, False), (64, 21, 1, 64, True),
+    (192, 33, 7, 64, True),
 ])
 def test_ks_adjoint_bitwise(sw, oracle_mod, n, nsteps, first, tile, with_cot):
     u0 = workloads.smoothed_noise(n, seed=n + nsteps) * 5
