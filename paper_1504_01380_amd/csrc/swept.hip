@@ -273,10 +273,14 @@ void launch_stage(const StageArgs<S>& a, size_t lds, hipStream_t st, int tiles, 
 
 // Full diamonds (below the target level, k a multiple of the band 64P) run
 // on the continuous kernel; the triangle and capped stages on the banded one.
+// The continuous kernel writes no field value, so it takes only the stages
+// whose diamond lies strictly below the target level (its apex, level
+// b + 2k - 1, below L); a stage whose apex reaches L goes to the banded
+// kernel, which writes the points that reach L.
 bool use_continuous(const Plan& p, int64_t s, int64_t L)
 {
     const int64_t b = (s - 1) * p.k;
-    return g_ctx.mode != SWEPT_MODE_STAGE_BANDED && s > 0 && b + 2 * p.k - 1 <= L &&
+    return g_ctx.mode != SWEPT_MODE_STAGE_BANDED && s > 0 && b + 2 * p.k - 1 < L &&
            p.k % (64 * p.P) == 0;
 }
 

@@ -123,7 +123,7 @@ def simulate(u0, nsteps, k, P, stencil, lanes=64, track=False, cont=False):
             J = (t * W + J0) % n
             chain = list(le_in[(t + 1) % T]) if not tri else [None] * (2 * k)
             top = L - b
-            if cont and not tri and b + 2 * k - 1 <= L and k % (lanes * P) == 0:
+            if cont and not tri and b + 2 * k - 1 < L and k % (lanes * P) == 0:
                 _cont_stage(t, J, b, k, P, lanes, RE, chain, step, nph, n, visits)
                 le_out[t] = chain
                 continue

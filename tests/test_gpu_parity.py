@@ -56,6 +56,9 @@ def same_bits(a, b):
     (1000, 200, 1, 401),    # k = 100 > 64: two bands, the second partial
     (40, 2, 1, 23),         # k = 1
     (30, 10, 1, 60),
+    # the apex of a full diamond at the target level (nsteps = k - 1 mod k):
+    # that stage must write the field, so it is not a continuous-kernel stage
+    (512, 128, 1, 127), (512, 128, 1, 191), (2048, 512, 4, 767), (4096, 1024, 4, 1535),
 ])
 def test_heat_f64_swept_bitwise(sw, oracle_mod, n, W, P, nsteps):
     sw.set_tuning(W, P, sw.MODE_STAGE)
@@ -93,7 +96,8 @@ def test_heat_small_workload_full(sw, oracle_mod):
 # ---------------------------------------------------------------- heat f32
 
 @pytest.mark.parametrize("n,W,P,nsteps", [(64, 16, 1, 9), (1024, 256, 2, 600),
-                                          (8192, 4096, 4, 2500), (8192, 1024, 8, 999)])
+                                          (8192, 4096, 4, 2500), (8192, 1024, 8, 999),
+                                          (1024, 256, 2, 383)])
 def test_heat_f32_swept_bitwise(sw, oracle_mod, n, W, P, nsteps):
     sw.set_tuning(W, P, sw.MODE_STAGE)
     u0 = workloads.white_noise(n, seed=W, dtype=np.float32)

@@ -94,6 +94,21 @@ def test_continuous_schedule(oracle_mod, lanes, P, k, nsteps, stencil):
     assert np.array_equal(np.array(got), want)
 
 
+@pytest.mark.parametrize("nsteps", range(1, 26))
+def test_continuous_schedule_every_cap(oracle_mod, nsteps):
+    """The continuous schedule at every target level modulo k (k = 4): a
+    diamond whose apex reaches the target level writes that level, so it
+    must not run on the continuous kernel, which writes no field value
+    (nsteps = 7, 11, ... once failed here)."""
+    k, n = 4, 16
+    u0 = workloads.white_noise(n, seed=nsteps)
+    got, visits = swept_sim.simulate(list(u0), nsteps, k, 4, swept_sim.heat_step(0.3), lanes=1,
+                                     track=True, cont=True)
+    ok, why = swept_sim.levels_complete(visits, n, nsteps, k)
+    assert ok, why
+    assert np.array_equal(np.array(got), oracle_mod.heat(u0, nsteps, 0.3))
+
+
 @pytest.mark.parametrize("stencil,n,k,nsteps,n0,cot", [
     ("heat", 16, 4, 3, 0, True), ("heat", 32, 8, 33, 20, False), ("heat", 8, 4, 13, 3, True),
     ("heat", 12, 1, 9, 2, True), ("ks", 16, 4, 5, 2, True), ("ks", 32, 4, 9, 6, False),
