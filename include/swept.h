@@ -177,12 +177,13 @@ int swept_naive_substep_advance(void *u, int64_t nx, int64_t nsteps, int32_t ste
  * first).  Every instance gets exactly the bits its own swept_advance would.
  *
  * Each instance of 2h points (h = nx/2 for even nx) is tiled by T = ceil(h/k)
- * tiles of even widths 2k_t, k_t in {floor(h/T), floor(h/T)+1}, all <= k
- * (k = tile_w/2 of swept_set_tuning if set, else the depth
- * swept_autotune_batch chose for the stencil, else 256), so any even length
- * tiles without
- * remainder; the regions of unequal neighbouring tiles are rectangles of
- * k_t pairs by k_{t+1} steps.  An odd length runs on its two-fold cover
+ * tiles: T-1 of width 2k and one of the remainder 2(h - (T-1)k) (k =
+ * tile_w/2 of swept_set_tuning if set, else the depth swept_autotune_batch
+ * chose for the stencil, else 256), so any even length tiles without
+ * remainder.  The regions between two full tiles are k x k squares (those
+ * below the target level run on the continuous-band schedule); the regions
+ * next to the short tile are rectangles of k_t pairs by k_{t+s} steps.  An
+ * odd length runs on its two-fold cover
  * (the field repeated twice, which the scheme keeps repeated).  All tiles of
  * all instances advance one stage per kernel launch; the launches of a
  * batch are captured into one HIP graph, which is reused when the same

@@ -352,9 +352,26 @@ __global__ __launch_bounds__(64) void swept_batch_kernel(BatchArgs<S> g)
     const int ks = (int)((X[i + 1] - X[i]) / 2);
     const int64_t J = ((xs + x1) / 2) % I.n;
     Pt* re = g.re + I.e_off + X[t];
-    banded_region<S, P>(I.u, re, re, g.le[(s + 1) & 1] + I.e_off + X[i],
-                        g.le[s & 1] + I.e_off + X[i], reinterpret_cast<Pt*>(smem_raw), I.n, I.L,
-                        b, J, kp, ks, s == 0, I.c);
+    const Pt* le_in = g.le[(s + 1) & 1] + I.e_off + X[i];
+    Pt* le_out = g.le[s & 1] + I.e_off + X[i];
+    Pt* chain = reinterpret_cast<Pt*>(smem_raw);
+    if (s > 0 && kp == ks && kp % (64 * P) == 0 && b + 2 * (int64_t)kp - 1 < I.L) {
+        // a full square diamond strictly below the target level: the
+        // continuous-band schedule, whose cycles start at phase b mod NPHASE
+        if constexpr (S::NPHASE == 1) {
+            cont_region<S, P, 0>(re, re, le_in, le_out, chain, kp, I.c);
+        } else {
+            static_assert(S::NPHASE == 4, "one or four sub-timesteps per step");
+            switch ((int)(b % 4)) {
+            case 0: cont_region<S, P, 0>(re, re, le_in, le_out, chain, kp, I.c); break;
+            case 1: cont_region<S, P, 1>(re, re, le_in, le_out, chain, kp, I.c); break;
+            case 2: cont_region<S, P, 2>(re, re, le_in, le_out, chain, kp, I.c); break;
+            default: cont_region<S, P, 3>(re, re, le_in, le_out, chain, kp, I.c); break;
+            }
+        }
+        return;
+    }
+    banded_region<S, P>(I.u, re, re, le_in, le_out, chain, I.n, I.L, b, J, kp, ks, s == 0, I.c);
 }
 
 template <class S>
@@ -442,15 +459,15 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
 }
 
 // Wave steps are issued in statically unrolled groups.  Every cycle starts at
-// a step sigma = cyc*k with b + sigma = 0 mod 4 (k and 64P are multiples of
-// 4), so inside a group the sub-timestep of step i is i mod NPHASE, known at
-// compile time.
+// a step sigma = cyc*k with b + sigma = b mod 4 (k and 64P are multiples of
+// 4), so inside a group the sub-timestep of step i is (PH0 + i) mod NPHASE
+// with PH0 = b mod NPHASE, known at compile time.
 
 // Head of a cycle, steps j = j0 .. j0+G-1 (G = max(P, NPHASE) divides 64P):
 // step j = rs*P + QS is the one at which slot j changes band (cycles
 // 1..nb-1), or a step of the pipeline fill (cycle 0) or drain (after the
 // last band).
-template <class S, int P, int MASK, bool TRANS, int I, int G>
+template <class S, int P, int PH0, int MASK, bool TRANS, int I, int G>
 __device__ __forceinline__ void cont_head_group(int j0, int k, int nb, int cyc,
                                                 typename S::Pt (&A)[P], typename S::Pt (&B)[P],
                                                 typename S::Pt (&An)[P],
@@ -463,7 +480,7 @@ __device__ __forceinline__ void cont_head_group(int j0, int k, int nb, int cyc,
     if constexpr (I < G) {
         constexpr int NB = 64 * P;
         constexpr int QS = I % P;
-        constexpr int PH = I % S::NPHASE;
+        constexpr int PH = (PH0 + I) % S::NPHASE;
         const int j = j0 + I;
         const int rs = j / P;
         const int next_slot = (j + 1 == k) ? 0 : j + 1;
@@ -480,14 +497,14 @@ __device__ __forceinline__ void cont_head_group(int j0, int k, int nb, int cyc,
         }
         cont_step<S, P, PH, MASK, TRANS ? QS : -1>(A, B, An, Bn, cA, cB, chain, lane, j, rs,
                                                    next_slot, wslot, wlast, re_store, re_load, c);
-        cont_head_group<S, P, MASK, TRANS, I + 1, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB, chain,
-                                                     re, re_out, lane, c);
+        cont_head_group<S, P, PH0, MASK, TRANS, I + 1, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
+                                                          chain, re, re_out, lane, c);
     }
 }
 
 // Body of a cycle, steps j = j0 .. j0+U-1 with 64P <= j < k: no slot changes
 // band and every slot is active.
-template <class S, int P, int I, int U>
+template <class S, int P, int PH0, int I, int U>
 __device__ __forceinline__ void cont_body_group(int j0, int k, typename S::Pt (&A)[P],
                                                 typename S::Pt (&B)[P], typename S::Pt (&An)[P],
                                                 typename S::Pt (&Bn)[P], typename S::Pt& cA,
@@ -498,36 +515,34 @@ __device__ __forceinline__ void cont_body_group(int j0, int k, typename S::Pt (&
         constexpr int NB = 64 * P;
         const int j = j0 + I;
         const int next_slot = (j + 1 == k) ? 0 : j + 1;
-        cont_step<S, P, I % S::NPHASE, 0, -1>(A, B, An, Bn, cA, cB, chain, lane, j, 0, next_slot,
-                                              j - (NB - 1), true, nullptr, nullptr, c);
-        cont_body_group<S, P, I + 1, U>(j0, k, A, B, An, Bn, cA, cB, chain, lane, c);
+        cont_step<S, P, (PH0 + I) % S::NPHASE, 0, -1>(A, B, An, Bn, cA, cB, chain, lane, j, 0,
+                                                      next_slot, j - (NB - 1), true, nullptr,
+                                                      nullptr, c);
+        cont_body_group<S, P, PH0, I + 1, U>(j0, k, A, B, An, Bn, cA, cB, chain, lane, c);
     }
 }
 
-template <class S, int P>
-__global__ __launch_bounds__(64) void swept_diamond_cont_kernel(StageArgs<S> g)
+// One full diamond region (k x k pairs, every level below the target) on
+// the continuous-band schedule.  re: the left V edge (pair d at step -1),
+// read and then overwritten in place by re_out when they are the same
+// buffer; le_in: the right V edge (pair -1 at step m); le_out: the new left
+// edge; chain: 2k points of LDS.  PH0 = b mod NPHASE.
+template <class S, int P, int PH0>
+__device__ __forceinline__ void cont_region(const typename S::Pt* re, typename S::Pt* re_out,
+                                            const typename S::Pt* le_in, typename S::Pt* le_out,
+                                            typename S::Pt* chain, int k,
+                                            const typename S::Consts& cst)
 {
     using Pt = typename S::Pt;
     constexpr int NB = 64 * P;
     constexpr int G = P > S::NPHASE ? P : S::NPHASE;  // head group: QS and phase static
     constexpr int U = 4;                               // body group; k - NB is a multiple of 4
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    Pt* chain = reinterpret_cast<Pt*>(smem_raw);
-
     const int lane = threadIdx.x;
-    const int t = blockIdx.x;
-    const int k = g.k;
     const int nb = k / NB;
-    {
-        const int tn = (t + 1 == g.tiles) ? 0 : t + 1;
-        const Pt* src = g.le_in + (size_t)tn * k * 2;
-        for (int i = lane; i < 2 * k; i += 64)
-            chain[i] = src[i];
-    }
+    for (int i = lane; i < 2 * k; i += 64)
+        chain[i] = le_in[i];
     __syncthreads();
 
-    const Pt* re = g.re + (size_t)t * k * 2;
-    Pt* re_out = g.re_out + (size_t)t * k * 2;
     Pt A[P], B[P], An[P], Bn[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) {
@@ -547,20 +562,20 @@ __global__ __launch_bounds__(64) void swept_diamond_cont_kernel(StageArgs<S> g)
     for (int cyc = 0;; ++cyc) {
         if (cyc == 0) {
             for (int j0 = 0; j0 < NB; j0 += G)
-                cont_head_group<S, P, 1, false, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
-                                                      chain, re, re_out, lane, g.c);
+                cont_head_group<S, P, PH0, 1, false, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
+                                                           chain, re, re_out, lane, cst);
         } else if (cyc == nb) {
             for (int j0 = 0; j0 < NB; j0 += G)
-                cont_head_group<S, P, 2, false, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
-                                                      chain, re, re_out, lane, g.c);
+                cont_head_group<S, P, PH0, 2, false, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
+                                                           chain, re, re_out, lane, cst);
             break;
         } else {
             for (int j0 = 0; j0 < NB; j0 += G)
-                cont_head_group<S, P, 0, true, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
-                                                     chain, re, re_out, lane, g.c);
+                cont_head_group<S, P, PH0, 0, true, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
+                                                          chain, re, re_out, lane, cst);
         }
         for (int j0 = NB; j0 < k; j0 += U)
-            cont_body_group<S, P, 0, U>(j0, k, A, B, An, Bn, cA, cB, chain, lane, g.c);
+            cont_body_group<S, P, PH0, 0, U>(j0, k, A, B, An, Bn, cA, cB, chain, lane, cst);
     }
 
 #pragma unroll
@@ -570,9 +585,21 @@ __global__ __launch_bounds__(64) void swept_diamond_cont_kernel(StageArgs<S> g)
         re_out[2 * ((nb - 1) * NB + e) + 1] = A[q];
     }
     __syncthreads();
-    Pt* dst = g.le_out + (size_t)t * k * 2;
     for (int i = lane; i < 2 * k; i += 64)
-        dst[i] = chain[i];
+        le_out[i] = chain[i];
+}
+
+template <class S, int P>
+__global__ __launch_bounds__(64) void swept_diamond_cont_kernel(StageArgs<S> g)
+{
+    using Pt = typename S::Pt;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int t = blockIdx.x;
+    const int k = g.k;
+    const int tn = (t + 1 == g.tiles) ? 0 : t + 1;
+    cont_region<S, P, 0>(g.re + (size_t)t * k * 2, g.re_out + (size_t)t * k * 2,
+                         g.le_in + (size_t)tn * k * 2, g.le_out + (size_t)t * k * 2,
+                         reinterpret_cast<Pt*>(smem_raw), k, g.c);
 }
 
 // ------------------------------------------------------------ swept adjoint

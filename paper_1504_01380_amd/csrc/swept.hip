@@ -505,11 +505,13 @@ int run_adjoint(const void* u0v, void* gradv, int64_t nx, int64_t nsteps, const 
 
 // -------------------------------------------------------------------- batch
 
-// Per-instance tiling for the batch: T = ceil(h/k) tiles of half-widths
-// k_t in {base, base+1} <= k summing to the half ring length h (so the
-// deepest tile, which sets every workgroup's LDS, never exceeds the target); odd rings run on their two-fold cover
-// (the same bits: the scheme is translation-equivariant, so a field repeated
-// twice stays repeated).
+// Per-instance tiling for the batch: T = ceil(h/k) tiles, the first T-1 of
+// half-width k and the last of the remainder r = h - (T-1)k in [1, k], h the
+// half ring length (no tile exceeds the target k, which sets every
+// workgroup's LDS, and every region between two full tiles is a k x k square
+// that the continuous-band schedule can take).  Odd rings run on their
+// two-fold cover (the same bits: the scheme is translation-equivariant, so a
+// field repeated twice stays repeated).
 struct BatchPlanInst {
     int64_t n_user, n_ring, L, x_off, e_off, f_off, stages;
     int tiles, kmax, stencil;
@@ -583,15 +585,18 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
         const int64_t k = batch_depth(ids[j], p.n_ring, want);
         const int64_t half = p.n_ring / 2;
         const int64_t T = std::max<int64_t>(1, (half + k - 1) / k);   // half-widths <= k
-        const int64_t base = half / T, rem = half % T;
+        const int64_t kt = T > 1 ? k : half, rem = half - (T - 1) * kt;
         p.tiles = (int)T;
-        p.kmax = (int)(base + (rem ? 1 : 0));
+        p.kmax = (int)kt;
         p.x_off = (int64_t)X.size();
         X.push_back(0);
         for (int64_t t = 0; t < T; ++t)
-            X.push_back(X.back() + 2 * (base + (t < rem ? 1 : 0)));
-        // stage s >= 1 of tile t starts at level (X_{t+s} - X_{t+1})/2 >= (s-1)*base
-        p.stages = p.L == 0 ? 0 : 2 + (p.L + base - 1) / base;
+            X.push_back(X.back() + 2 * (t + 1 < T ? kt : rem));
+        // stage s >= 1 of tile t starts at level b = (X_{t+s} - X_{t+1})/2, the
+        // sum of s-1 consecutive half-widths, which hold the short tile at
+        // most ceil((s-1)/T) times: b >= (s-1)h/T - (kt - rem).  A tile's
+        // regions end once b >= L, so s <= 1 + (L + kt - rem)T/h.
+        p.stages = p.L == 0 ? 0 : 2 + (p.L + kt - rem) * T / half;
         if (p.stencil == SWEPT_KS_F64) {
             p.e_off = e_ks;
             e_ks += p.n_ring;

@@ -205,13 +205,30 @@ def levels_complete(visits, n, L, k):
     return True, None
 
 
-def simulate_tiles(u0, nsteps, ks_list, P, stencil, lanes=64, track=False):
+class _Offset:
+    """A window of a flat list starting at `off` (a tile's slice of the edge
+    buffer)."""
+
+    def __init__(self, data, off):
+        self.data, self.off = data, off
+
+    def __getitem__(self, i):
+        return self.data[self.off + i]
+
+    def __setitem__(self, i, v):
+        self.data[self.off + i] = v
+
+
+def simulate_tiles(u0, nsteps, ks_list, P, stencil, lanes=64, track=False, cont=False):
     """The swept schedule on tiles of unequal even widths 2*k_t (sum = N).
     Workgroup t keeps k_t pairs; at stage s its region is the rectangle of
     k_t pairs by k_{t+s} steps centred at J = (X_{t+s} + X_{t+1}) / 2 with
     base level b = (X_{t+s} - X_{t+1}) / 2 (X_t = 2*sum_{t'<t} k_t', taken
     periodically with period N).  Stage 0 is the triangle of each tile.
-    Right edges live at offset X_t, left edges at offset X_{(t+s) mod T}."""
+    Right edges live at offset X_t, left edges at offset X_{(t+s) mod T}.
+    With cont, a square k x k region strictly below level L whose k is a
+    multiple of lanes*P runs on the continuous-band schedule (as in
+    swept_batch_kernel), its cycles starting at phase b mod nph."""
     step, nph, from_field, to_field = stencil
     n = len(u0)
     T = len(ks_list)
@@ -252,6 +269,11 @@ def simulate_tiles(u0, nsteps, ks_list, P, stencil, lanes=64, track=False):
             le_off_in = X[(t + s) % T]   # written by workgroup t+1 at stage s-1
             chain = [None] * (2 * ks) if tri else list(le_in[le_off_in:le_off_in + 2 * ks])
             top = L - b
+            if cont and not tri and kp == ks and kp % band == 0 and b + 2 * kp - 1 < L:
+                _cont_stage(0, J, b, kp, P, lanes, [_Offset(RE, re_off)], chain, step, nph, n,
+                            visits)
+                le_out[le_off_out:le_off_out + 2 * ks] = chain
+                continue
             for base in range(0, kp, band):
                 nvalid = min(band, kp - base)
                 tau_first = (ks - base) if tri else 0

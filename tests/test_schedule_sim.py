@@ -94,6 +94,35 @@ def test_continuous_schedule(oracle_mod, lanes, P, k, nsteps, stencil):
     assert np.array_equal(np.array(got), want)
 
 
+@pytest.mark.parametrize("ks_list,lanes,P,nsteps,stencil", [
+    ([4, 4, 4, 2], 2, 2, 30, "heat"),    # the batch split: full tiles and a remainder
+    ([8, 8, 3], 2, 1, 41, "heat"),       # two bands per full square
+    ([4, 4, 4, 4, 1], 1, 4, 27, "heat"),
+    ([8, 8, 8, 5], 4, 1, 19, "ks"),      # b mod 4 = 1 once the short tile is below
+                                         # (KS: 4 | k and 4 | lanes*P, as in the kernel)
+    ([8, 8, 6], 1, 4, 23, "ks"),         # b mod 4 = 2
+    ([8, 8, 8, 8, 7], 2, 2, 17, "ks"),   # b mod 4 = 3
+    ([8, 8], 2, 2, 15, "ks"),            # every region a full square
+])
+def test_batch_continuous_schedule(oracle_mod, ks_list, lanes, P, nsteps, stencil):
+    """The batch schedule with its square regions on the continuous-band
+    schedule (the others banded): exactly once, the oracle's bits, for every
+    phase of the regions' base level."""
+    n = 2 * sum(ks_list)
+    if stencil == "heat":
+        u0 = workloads.white_noise(n, seed=n + nsteps)
+        st, L, want = swept_sim.heat_step(0.3), nsteps, oracle_mod.heat(u0, nsteps, 0.3)
+    else:
+        u0 = workloads.smoothed_noise(n, seed=n + nsteps)
+        st, L = swept_sim.ks_step(0.005, 0.5), 4 * nsteps
+        want = oracle_mod.ks(u0, nsteps, 0.005, 0.5)
+    got, visits = swept_sim.simulate_tiles(list(u0), nsteps, ks_list, P, st, lanes=lanes,
+                                           track=True, cont=True)
+    ok, why = swept_sim.levels_complete(visits, n, L, max(ks_list))
+    assert ok, why
+    assert np.array_equal(np.array(got), want)
+
+
 @pytest.mark.parametrize("nsteps", range(1, 26))
 def test_continuous_schedule_every_cap(oracle_mod, nsteps):
     """The continuous schedule at every target level modulo k (k = 4): a
@@ -134,10 +163,11 @@ def test_adjoint_schedule(oracle_mod, stencil, n, k, nsteps, n0, cot):
 
 def _split(half, k):
     """The batch plan's tiling of a ring of 2*half points: T = ceil(half/k)
-    tiles, half-widths base or base+1 <= k (the first half % T get base+1)."""
+    tiles, T-1 of half-width k and the last of the remainder."""
     T = max(1, -(-half // k))
-    base, rem = divmod(half, T)
-    return [base + (1 if t < rem else 0) for t in range(T)]
+    if T == 1:
+        return [half]
+    return [k] * (T - 1) + [half - (T - 1) * k]
 
 
 @pytest.mark.parametrize("ks_list,nsteps,stencil", [
@@ -145,7 +175,7 @@ def _split(half, k):
     ([3, 7, 2, 5, 6], 40, "heat"),    # arbitrary widths
     ([6], 30, "heat"),                # one tile
     ([1, 1, 2], 9, "heat"),           # k = 1 tiles
-    (_split(50, 8), 61, "heat"),      # the plan's split: 6 tiles of 8 or 9
+    (_split(50, 8), 61, "heat"),      # the plan's split: 6 tiles of 8 and one of 2
     ([4, 5, 4], 7, "ks"),
     (_split(21, 4), 6, "ks"),
 ])
