@@ -237,7 +237,7 @@ int swept_autotune(int64_t nx, int64_t nsteps, int32_t stencil_id, const double 
 /*
  * Autotuner for swept_advance_batch: for each binary64 stencil present, times
  * the batch's own shapes (zero fields, each instance's steps cut to at most
- * 3072 sub-timesteps) at depths k = 128, 192, 256, 384 and keeps the fastest
+ * 3072 sub-timesteps) at depths k = 128, 256, 384, 512 and keeps the fastest
  * for later batches.  depth_out (host, 3 entries indexed by stencil id)
  * receives the chosen depth, 0 for a stencil not in the batch.  Allocates
  * and frees its own probe fields; synchronizes the stream.

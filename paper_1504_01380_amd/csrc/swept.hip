@@ -1310,7 +1310,9 @@ int autotune_batch(const int64_t* nx, const int64_t* nsteps, const int32_t* ids,
         }
         double best_t = 1e30;
         int64_t best = kBatchWantDefault;
-        for (int64_t want : {128, 192, 256, 384}) {
+        // multiples of the band size 128 (two pairs per lane), so that the
+        // square regions can take the continuous-band schedule
+        for (int64_t want : {128, 256, 384, 512}) {
             g_batch_want[id] = want;
             double t;
             rc = time_best([&] {

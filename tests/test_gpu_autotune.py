@@ -64,7 +64,7 @@ def test_autotune_batch(sw, oracle_mod):
     depth = sw.autotune_batch(sizes, steps, kinds, pars)
     print(depth, flush=True)
     assert set(depth) == set(kinds)
-    assert all(k in (128, 192, 256, 384) for k in depth.values())
+    assert all(k in (128, 256, 384, 512) for k in depth.values())
     us = [torch.from_numpy(i.u0).cuda() for i in insts]
     sw.advance_batch(us, steps, kinds, pars)
     torch.cuda.synchronize()
