@@ -122,10 +122,16 @@ def cpu_baseline(u0_np, nsteps_full, seconds):
     t0 = time.perf_counter()
     oracle.heat(u0_np, 20, 0.25, threads=threads)
     per_step = max((time.perf_counter() - t0) / 20, 1e-6)
-    k = int(max(2, min(nsteps_full, seconds / per_step)))
-    t0 = time.perf_counter()
-    oracle.heat(u0_np, k, 0.25, threads=threads)
-    dt = time.perf_counter() - t0
+    # step on from the field reached, in chunks sized by the rate so far,
+    # until about `seconds` of work (or all steps) are done
+    u, k, dt = u0_np, 0, 0.0
+    while k < nsteps_full and dt < 0.9 * seconds:
+        chunk = int(max(2, min(nsteps_full - k, (seconds - dt) / per_step)))
+        t0 = time.perf_counter()
+        u = oracle.heat(u, chunk, 0.25, threads=threads)
+        dt += time.perf_counter() - t0
+        k += chunk
+        per_step = dt / k
     return {"value": n * k / dt, "unit": "point-updates/s", "cores": threads, "kind": "oracle",
             "sample": "heat f64 N=%d, first %d of %d steps, all points, OpenMP %d threads, "
                       "%.1f s" % (n, k, nsteps_full, threads, dt)}
