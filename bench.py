@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: a plain copy of u (calibration), then the "
                          "timed swept runs only")
+    ap.add_argument("--profile-mix", action="store_true",
+                    help="short run for rocprofv3 instruction counters: one swept run each of "
+                         "heat (2^24, 2,000 steps, W=1024 P=4), KS (2^20, 1,000 steps, W=512 "
+                         "P=2) and Euler (2^20 cells, 300 steps, W=256 P=1)")
     return ap.parse_args()
 
 
@@ -315,6 +319,22 @@ def ks_adjoint_workload(sw, torch, workloads, directions=16, eps=1e-6):
             "fd_within_1e-6": sum(e <= 1e-6 for e in errs)}
 
 
+def profile_mix(sw, torch, workloads):
+    """One swept run of each single-field stencil in its tuned launch shape,
+    for counter collection (nothing is timed or printed but progress)."""
+    we, wk = workloads.WORKLOADS["euler"], workloads.WORKLOADS["ks"]
+    for name, st, nsteps, par, W, P in (
+            ("heat_large", "heat", 2000, [0.25], 1024, 4),
+            ("ks", "ks", 1000, [wk["dt"], wk["dx"]], 512, 2),
+            ("euler", "euler", 300, [we["cfl"] / we["n"], 1.0 / we["n"], we["gamma"]], 256, 1)):
+        sw.set_tuning(W, P, sw.MODE_AUTO)
+        u = torch.from_numpy(workloads.initial(name)).cuda()
+        sw.advance(u, nsteps, st, par)
+        torch.cuda.synchronize()
+        progress("%s done" % name)
+    sw.set_tuning(0, 0, sw.MODE_AUTO)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -329,6 +349,9 @@ def main():
     sw.init(0)
     sw.set_tuning(0, 0, sw.MODE_AUTO)
     sw.clear_tuning()
+    if args.profile_mix:
+        profile_mix(sw, torch, workloads)
+        return
     n, nsteps = args.n, args.nsteps
     u0_np = workloads.white_noise(n, seed=workloads.WORKLOADS["heat_large"]["seed"])
     u0 = torch.from_numpy(u0_np).cuda()
