@@ -296,96 +296,6 @@ __global__ __launch_bounds__(64) void swept_stage_kernel(StageArgs<S> g)
                         reinterpret_cast<Pt*>(smem_raw), g.n, g.L, g.b, J, k, k, g.tri != 0, g.c);
 }
 
-// ------------------------------------------------------------------ batch
-// Many independent periodic instances, each tiled by even widths 2k_t that
-// need not be equal (k_t in {k, k+1} tiles any even length).  Workgroup t of
-// an instance keeps k_t pairs; at stage s its region is k_t pairs by
-// k_{t+s} steps, centred at J = (X_{t+s} + X_{t+1})/2 with base level
-// b = (X_{t+s} - X_{t+1})/2, where X_t = 2 sum_{t'<t} k_t' is extended
-// periodically (X_{t+T} = X_t + n).  Stage 0 is each tile's triangle; every
-// later region lies above level 0.  Right edges of tile t live at offset
-// X_t of the instance's edge buffer, left edges at offset X_{(t+s) mod T}.
-
-template <class S>
-struct BatchInst {
-    typename S::T* u;    // the instance's field (n points; the two-fold cover for odd rings)
-    int64_t n, L;        // ring length, target level
-    int64_t x_off;       // offset of X_0..X_T in the tile-boundary array
-    int64_t e_off;       // offset of the instance's edges in the edge buffers (n points)
-    int tiles;
-    int pad;
-    typename S::Consts c;
-};
-
-struct BatchTask {
-    int inst, tile;
-};
-
-template <class S>
-struct BatchArgs {
-    const BatchInst<S>* inst;
-    const BatchTask* tasks;     // this stage's tasks are tasks[0 .. gridDim.x)
-    const int64_t* X;           // tile boundaries, per instance X_0 = 0 .. X_T = n
-    typename S::Pt* re;         // right edges, all instances
-    typename S::Pt* le[2];      // left edges, by stage parity
-    int stage;
-};
-
-template <class S, int P>
-__global__ __launch_bounds__(64) void swept_batch_kernel(BatchArgs<S> g)
-{
-    using Pt = typename S::Pt;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const BatchTask task = g.tasks[blockIdx.x];
-    const BatchInst<S> I = g.inst[task.inst];
-    const int s = g.stage;
-    const int t = task.tile;
-    const int64_t* X = g.X + I.x_off;
-    const int T = I.tiles;
-    auto Xp = [&](int64_t i) { return X[i % T] + (i / T) * I.n; };
-    const int64_t xs = Xp((int64_t)t + s), x1 = Xp((int64_t)t + 1);
-    const int64_t b = (xs - x1) / 2;
-    if (s > 0 && b >= I.L)
-        return;                  // this tile's regions are all above the target level
-    const int kp = (int)((X[t + 1] - X[t]) / 2);
-    const int i = (int)(((int64_t)t + s) % T);
-    const int ks = (int)((X[i + 1] - X[i]) / 2);
-    const int64_t J = ((xs + x1) / 2) % I.n;
-    Pt* re = g.re + I.e_off + X[t];
-    const Pt* le_in = g.le[(s + 1) & 1] + I.e_off + X[i];
-    Pt* le_out = g.le[s & 1] + I.e_off + X[i];
-    Pt* chain = reinterpret_cast<Pt*>(smem_raw);
-    if (s > 0 && kp == ks && kp % (64 * P) == 0 && b + 2 * (int64_t)kp - 1 < I.L) {
-        // a full square diamond strictly below the target level: the
-        // continuous-band schedule, whose cycles start at phase b mod NPHASE
-        if constexpr (S::NPHASE == 1) {
-            cont_region<S, P, 0>(re, re, le_in, le_out, chain, kp, I.c);
-        } else {
-            static_assert(S::NPHASE == 4, "one or four sub-timesteps per step");
-            switch ((int)(b % 4)) {
-            case 0: cont_region<S, P, 0>(re, re, le_in, le_out, chain, kp, I.c); break;
-            case 1: cont_region<S, P, 1>(re, re, le_in, le_out, chain, kp, I.c); break;
-            case 2: cont_region<S, P, 2>(re, re, le_in, le_out, chain, kp, I.c); break;
-            default: cont_region<S, P, 3>(re, re, le_in, le_out, chain, kp, I.c); break;
-            }
-        }
-        return;
-    }
-    banded_region<S, P>(I.u, re, re, le_in, le_out, chain, I.n, I.L, b, J, kp, ks, s == 0, I.c);
-}
-
-template <class S>
-__global__ __launch_bounds__(256) void batch_cover_kernel(const typename S::T* __restrict__ src,
-                                                         typename S::T* __restrict__ dst,
-                                                         int64_t n, int copies)
-{
-    // dst[i] = src[i mod n] for i < copies * n
-    const int64_t total = (int64_t)copies * n;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride)
-        dst[i] = src[i % n];
-}
-
 // ------------------------------------------------- continuous diamond stage
 // The same diamond, for stages that lie entirely below the target level and
 // whose k is a multiple of the band size 64*P.  Instead of draining and
@@ -600,6 +510,100 @@ __global__ __launch_bounds__(64) void swept_diamond_cont_kernel(StageArgs<S> g)
     cont_region<S, P, 0>(g.re + (size_t)t * k * 2, g.re_out + (size_t)t * k * 2,
                          g.le_in + (size_t)tn * k * 2, g.le_out + (size_t)t * k * 2,
                          reinterpret_cast<Pt*>(smem_raw), k, g.c);
+}
+
+// ------------------------------------------------------------------ batch
+// Many independent periodic instances, each tiled by even widths 2k_t that
+// need not be equal (full tiles of k and one shorter tile the remainder, so
+// any even length tiles).  Workgroup t of
+// an instance keeps k_t pairs; at stage s its region is k_t pairs by
+// k_{t+s} steps, centred at J = (X_{t+s} + X_{t+1})/2 with base level
+// b = (X_{t+s} - X_{t+1})/2, where X_t = 2 sum_{t'<t} k_t' is extended
+// periodically (X_{t+T} = X_t + n).  Stage 0 is each tile's triangle; every
+// later region lies above level 0.  Right edges of tile t live at offset
+// X_t of the instance's edge buffer, left edges at offset X_{(t+s) mod T}.
+// A region between two full tiles is a k x k square; below the target level
+// it runs on the continuous-band schedule (cont_region), the others on the
+// banded one.
+
+template <class S>
+struct BatchInst {
+    typename S::T* u;    // the instance's field (n points; the two-fold cover for odd rings)
+    int64_t n, L;        // ring length, target level
+    int64_t x_off;       // offset of X_0..X_T in the tile-boundary array
+    int64_t e_off;       // offset of the instance's edges in the edge buffers (n points)
+    int tiles;
+    int pad;
+    typename S::Consts c;
+};
+
+struct BatchTask {
+    int inst, tile;
+};
+
+template <class S>
+struct BatchArgs {
+    const BatchInst<S>* inst;
+    const BatchTask* tasks;     // this stage's tasks are tasks[0 .. gridDim.x)
+    const int64_t* X;           // tile boundaries, per instance X_0 = 0 .. X_T = n
+    typename S::Pt* re;         // right edges, all instances
+    typename S::Pt* le[2];      // left edges, by stage parity
+    int stage;
+};
+
+template <class S, int P>
+__global__ __launch_bounds__(64) void swept_batch_kernel(BatchArgs<S> g)
+{
+    using Pt = typename S::Pt;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const BatchTask task = g.tasks[blockIdx.x];
+    const BatchInst<S> I = g.inst[task.inst];
+    const int s = g.stage;
+    const int t = task.tile;
+    const int64_t* X = g.X + I.x_off;
+    const int T = I.tiles;
+    auto Xp = [&](int64_t i) { return X[i % T] + (i / T) * I.n; };
+    const int64_t xs = Xp((int64_t)t + s), x1 = Xp((int64_t)t + 1);
+    const int64_t b = (xs - x1) / 2;
+    if (s > 0 && b >= I.L)
+        return;                  // this tile's regions are all above the target level
+    const int kp = (int)((X[t + 1] - X[t]) / 2);
+    const int i = (int)(((int64_t)t + s) % T);
+    const int ks = (int)((X[i + 1] - X[i]) / 2);
+    const int64_t J = ((xs + x1) / 2) % I.n;
+    Pt* re = g.re + I.e_off + X[t];
+    const Pt* le_in = g.le[(s + 1) & 1] + I.e_off + X[i];
+    Pt* le_out = g.le[s & 1] + I.e_off + X[i];
+    Pt* chain = reinterpret_cast<Pt*>(smem_raw);
+    if (s > 0 && kp == ks && kp % (64 * P) == 0 && b + 2 * (int64_t)kp - 1 < I.L) {
+        // a full square diamond strictly below the target level: the
+        // continuous-band schedule, whose cycles start at phase b mod NPHASE
+        if constexpr (S::NPHASE == 1) {
+            cont_region<S, P, 0>(re, re, le_in, le_out, chain, kp, I.c);
+        } else {
+            static_assert(S::NPHASE == 4, "one or four sub-timesteps per step");
+            switch ((int)(b % 4)) {
+            case 0: cont_region<S, P, 0>(re, re, le_in, le_out, chain, kp, I.c); break;
+            case 1: cont_region<S, P, 1>(re, re, le_in, le_out, chain, kp, I.c); break;
+            case 2: cont_region<S, P, 2>(re, re, le_in, le_out, chain, kp, I.c); break;
+            default: cont_region<S, P, 3>(re, re, le_in, le_out, chain, kp, I.c); break;
+            }
+        }
+        return;
+    }
+    banded_region<S, P>(I.u, re, re, le_in, le_out, chain, I.n, I.L, b, J, kp, ks, s == 0, I.c);
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void batch_cover_kernel(const typename S::T* __restrict__ src,
+                                                         typename S::T* __restrict__ dst,
+                                                         int64_t n, int copies)
+{
+    // dst[i] = src[i mod n] for i < copies * n
+    const int64_t total = (int64_t)copies * n;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride)
+        dst[i] = src[i % n];
 }
 
 // ------------------------------------------------------------ swept adjoint
