@@ -112,8 +112,10 @@ enum {
     SWEPT_MODE_AUTO = 0,      /* swept stages when the grid can be tiled, else naive */
     SWEPT_MODE_STAGE = 1,     /* swept: one kernel launch per stage (triangle, diamonds) */
     SWEPT_MODE_NAIVE = 2,     /* one launch per time step */
-    SWEPT_MODE_STAGE_BANDED = 3 /* swept stages, every diamond on the banded kernel
-                                   (the continuous-band kernel switched off) */
+    SWEPT_MODE_STAGE_BANDED = 3, /* swept stages, every diamond on the banded kernel
+                                    (the continuous-band kernel switched off) */
+    SWEPT_MODE_STAGE_LANE = 4    /* swept stages on the lane-frame kernel (one lane per
+                                    column, W <= 64): for few, latency-bound tiles */
 };
 
 /*
@@ -139,8 +141,9 @@ int swept_set_tuning(int32_t tile_w, int32_t pairs_per_lane, int32_t mode);
 
 /*
  * Plan the swept run swept_advance would use for these arguments, without
- * running it.  out[0..5] = { tile_w, depth_k, tiles, stages, pairs_per_lane,
- * mode_used }.  Returns SWEPT_EINVAL for invalid arguments.
+ * running it.  out[0..5] = { tile_w, depth_k, tiles, stages, pairs_per_lane
+ * (0 on the lane-frame kernel), mode_used }.  Returns SWEPT_EINVAL for
+ * invalid arguments.
  */
 int swept_plan(int64_t nx, int64_t nsteps, int32_t stencil_id, int64_t *out);
 
@@ -216,7 +219,9 @@ int swept_naive_advance_batch(void *const *u, const int64_t *nx, const int64_t *
  * the LDS budget) nearest W0/8, W0/4, W0/2, W0, 2 W0 and 4 W0 (the model
  * leaves out that wider tiles hold more LDS and so share a CU with fewer
  * others) and the width the untuned plan would take, each with 1, 2 or 4
- * pairs per lane (64 x pairs <= W/2), and the naive schedule.  Each tiling
+ * pairs per lane (64 x pairs <= W/2), the two widest widths of at most 64
+ * points on the lane-frame kernel (SWEPT_MODE_STAGE_LANE), and the naive
+ * schedule.  Each tiling
  * is timed (best of three) over sixteen of its stages (at most
  * nsteps steps) on as many of its tiles as fill the GPU four times over (at
  * most nx points), the naive schedule over at most 256 steps of all nx
@@ -228,7 +233,8 @@ int swept_naive_advance_batch(void *const *u, const int64_t *nx, const int64_t *
  *
  * report (host, may be NULL) receives 8 doubles: tau [s], s1 [s], s_full [s],
  * n* = sqrt(2 tau / s1) [points], W0 [points], the chosen W (0 = naive), the
- * chosen pairs per lane, the fastest probe's rate [point-steps/s].  The call
+ * chosen pairs per lane (0 = the lane-frame kernel), the fastest probe's
+ * rate [point-steps/s].  The call
  * allocates and frees its own probe fields and synchronizes the stream.
  */
 int swept_autotune(int64_t nx, int64_t nsteps, int32_t stencil_id, const double *params,

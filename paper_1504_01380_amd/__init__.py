@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libswept.so")
 
 HEAT_F64, HEAT_F32, KS_F64, EULER_F64 = 0, 1, 2, 3
-MODE_AUTO, MODE_STAGE, MODE_NAIVE, MODE_STAGE_BANDED = 0, 1, 2, 3
+MODE_AUTO, MODE_STAGE, MODE_NAIVE, MODE_STAGE_BANDED, MODE_STAGE_LANE = 0, 1, 2, 3, 4
 
 _STATUS = {0: "SWEPT_OK", -1: "SWEPT_EINVAL", -2: "SWEPT_ENOTINIT", -3: "SWEPT_ENOMEM",
            -4: "SWEPT_EHIP", -5: "SWEPT_EUNSUPPORTED", -6: "SWEPT_ETIMEOUT"}

@@ -1041,14 +1041,19 @@ __global__ __launch_bounds__(64) void swept_adjoint_kernel(AdjArgs<S> g)
     }
 }
 
-// Forward pass of the swept adjoint: each stage's regions in the same lane
-// frame as the reverse kernel, keeping only what the next stage and the
-// reverse pass read -- the new V edges, the two outermost points on each
-// side of rows k..2k-1 (the field itself is not written).  g.u is read, for
-// the triangle, and nothing else of it is touched.  LDS holds the rows from
-// the middle level up (the upper half of the adjoint layout).
-template <class S>
-__global__ __launch_bounds__(64) void swept_checkpoint_kernel(StageArgs<S> g)
+// One stage in the lane frame of the adjoint kernels (lane = column, k <= 32,
+// neighbours by DPP): the region's levels row by row, with the same edge
+// buffers and formats as the banded and continuous kernels -- the new V
+// edges, the two outermost points on each side of rows k..2k-1.  A row is a
+// handful of VALU operations on the critical path, against about two wave
+// steps of the pair-banded schedule per level, so this is the kernel for
+// regions that are latency-bound (few tiles).  FIELD: write the points that
+// reach level L to g.u (the stage kernel of swept_advance); without it, g.u
+// is only read, by the triangle (the forward pass of the swept adjoint,
+// which keeps the edges of every stage as its checkpoint).  LDS holds the
+// rows from the middle level up (the upper half of the adjoint layout).
+template <class S, bool FIELD>
+__global__ __launch_bounds__(64) void swept_lane_kernel(StageArgs<S> g)
 {
     using Pt = typename S::Pt;
     constexpr int NPH = S::NPHASE;
@@ -1114,6 +1119,13 @@ __global__ __launch_bounds__(64) void swept_checkpoint_kernel(StageArgs<S> g)
     if (!g.tri && jtop >= k)
         levels_up<NPH>(g.b - 1, k, k, [&](int j, auto ph) { up_level(j, ph, std::true_type{}); });
     levels_up<NPH>(g.b - 1, k + 1, jtop, [&](int j, auto ph) { up_level(j, ph, std::false_type{}); });
+    if constexpr (FIELD) {
+        // the top row reached is the target level: its points are the result
+        const bool own = jtop <= k ? (dx >= -jtop && dx <= jtop - 1)
+                                   : (dx >= jtop - 2 * k && dx <= 2 * k - 1 - jtop);
+        if (g.b + jtop == g.L && jtop > j0 && own)
+            g.u[wrapn(J + dx, g.n)] = S::to_field(v);
+    }
     __syncthreads();
     Pt* re_out = g.re_out + (size_t)t * k * 2;
     Pt* le_out = g.le_out + (size_t)t * k * 2;

@@ -154,6 +154,8 @@ struct Plan {
 };
 
 constexpr size_t kMaxLds = 64 * 1024;
+// the lane-frame kernel holds a region and its V edges in one wavefront
+constexpr int64_t kLaneMaxK = 32;
 
 // Measured on MI355X (20,000-step heat at N = 2^24, binary64 and binary32;
 // KS at N = 2^20; heat at N = 4096): W = 1024 is fastest for every stencil on
@@ -188,10 +190,22 @@ bool tile_fits(int id, int64_t nx, int64_t W)
     return W >= 2 && W % 2 == 0 && nx % W == 0 && (size_t)W * pt_bytes(id) <= kMaxLds;
 }
 
+// the lane-frame kernel: k <= 32 and the rows from the middle level up
+// (k^2 + 3k + 3 points) in LDS
+size_t lane_lds_bytes(int id, int64_t k)
+{
+    return (size_t)(k * k + 3 * k + 3) * pt_bytes(id);
+}
+
+bool lane_fits(int id, int64_t k)
+{
+    return k >= 1 && k <= kLaneMaxK && lane_lds_bytes(id, k) <= kMaxLds;
+}
+
 // Tilings chosen by swept_autotune, per stencil and size class floor(log2 nx).
 struct Tuned {
     int64_t W;
-    int P;
+    int P;   // pairs per lane; 0: the lane-frame kernel
 };
 std::map<std::pair<int, int>, Tuned> g_tuned;
 // Batch depth per stencil id chosen by swept_autotune_batch (0 = default).
@@ -218,15 +232,18 @@ int make_plan(int64_t nx, int64_t nsteps, int32_t id, Plan* p)
     }
     int64_t W = 0;
     int tunedP = 0;
+    bool lane = g_ctx.mode == SWEPT_MODE_STAGE_LANE;
     if (g_ctx.tile_w == 0 && g_ctx.ppl == 0 && g_ctx.mode == SWEPT_MODE_AUTO) {
         const auto it = g_tuned.find(tune_key(id, nx));
         if (it != g_tuned.end() && it->second.W < 0) {
             p->mode = SWEPT_MODE_NAIVE;   // the naive schedule was fastest
             return SWEPT_OK;
         }
-        if (it != g_tuned.end() && tile_fits(id, nx, it->second.W)) {
+        if (it != g_tuned.end() && tile_fits(id, nx, it->second.W) &&
+            (it->second.P > 0 || lane_fits(id, it->second.W / 2))) {
             W = it->second.W;
             tunedP = it->second.P;
+            lane = it->second.P == 0;
         }
     }
     if (W > 0) {
@@ -236,17 +253,22 @@ int make_plan(int64_t nx, int64_t nsteps, int32_t id, Plan* p)
             return fail(SWEPT_EINVAL,
                         "tile width %d must be even, divide nx = %lld and fit 64 KB of LDS",
                         g_ctx.tile_w, (long long)nx);
+        if (lane && !lane_fits(id, g_ctx.tile_w / 2))
+            return fail(SWEPT_EINVAL,
+                        "the lane-frame kernel takes tiles of at most %d points whose upper "
+                        "half fits 64 KB of LDS", (int)(2 * kLaneMaxK));
         W = g_ctx.tile_w;
     } else {
-        const int64_t cap = std::min(target_tile(id), std::max<int64_t>(2, nx / 16));
+        const int64_t cap = lane ? std::min<int64_t>(2 * kLaneMaxK, nx)
+                                 : std::min(target_tile(id), std::max<int64_t>(2, nx / 16));
         for (int64_t w = cap - (cap & 1); w >= 2; w -= 2)
-            if (tile_fits(id, nx, w)) {
+            if (tile_fits(id, nx, w) && (!lane || lane_fits(id, w / 2))) {
                 W = w;
                 break;
             }
     }
     if (W == 0) {
-        if (g_ctx.mode == SWEPT_MODE_STAGE || g_ctx.mode == SWEPT_MODE_STAGE_BANDED)
+        if (g_ctx.mode == SWEPT_MODE_STAGE || g_ctx.mode == SWEPT_MODE_STAGE_BANDED || lane)
             return fail(SWEPT_EUNSUPPORTED, "nx = %lld has no even tile width", (long long)nx);
         p->mode = SWEPT_MODE_NAIVE;
         return SWEPT_OK;
@@ -255,8 +277,9 @@ int make_plan(int64_t nx, int64_t nsteps, int32_t id, Plan* p)
     p->k = W / 2;
     p->tiles = nx / W;
     p->stages = L == 0 ? 0 : 1 + (L + p->k - 1) / p->k;
-    p->P = g_ctx.ppl > 0 ? g_ctx.ppl : (tunedP > 0 ? tunedP : auto_ppl(id, p->k));
-    p->mode = SWEPT_MODE_STAGE;
+    // pairs per lane: 0 on the lane-frame kernel (one point per lane)
+    p->P = lane ? 0 : (g_ctx.ppl > 0 ? g_ctx.ppl : (tunedP > 0 ? tunedP : auto_ppl(id, p->k)));
+    p->mode = lane ? SWEPT_MODE_STAGE_LANE : SWEPT_MODE_STAGE;
     return SWEPT_OK;
 }
 
@@ -305,6 +328,14 @@ void release_events()
     g_ctx.recorded = 0;
 }
 
+// LDS of the lane-frame kernel: the full points of the rows from the middle
+// level up (k^2 + 3k + 2, and one spare)
+template <class S>
+size_t lane_lds(int64_t k)
+{
+    return (size_t)(k * k + 3 * k + 3) * sizeof(typename S::Pt);
+}
+
 template <class S>
 int run_swept(void* u, int64_t nx, int64_t L, const typename S::Consts& c, const Plan& p)
 {
@@ -338,6 +369,15 @@ int run_swept(void* u, int64_t nx, int64_t L, const typename S::Consts& c, const
         a.J0 = (p.k + s * p.k) % nx;
         a.le_in = le[(s + 1) & 1];
         a.le_out = le[s & 1];
+        if (p.mode == SWEPT_MODE_STAGE_LANE) {
+            hipLaunchKernelGGL((swept_lane_kernel<S, true>), dim3((unsigned)p.tiles), dim3(64),
+                               lane_lds<S>(p.k), g_ctx.stream, a);
+            if (g_ctx.profiling) {
+                g_ctx.kinds[(size_t)s] = 2;
+                HIP_TRY(hipEventRecord(g_ctx.events[(size_t)s + 1], g_ctx.stream));
+            }
+            continue;
+        }
         const bool cont = use_continuous(p, s, L);
         // pairs per lane beyond the register budget of a point are not built
         constexpr int PMAX = pmax_of<S>();
@@ -391,12 +431,6 @@ size_t adjoint_lds(int64_t k)
     return (size_t)(2 * k * k + 6 * k + 3) * sizeof(typename S::Kept);
 }
 
-template <class S>
-size_t checkpoint_lds(int64_t k)
-{
-    return (size_t)(k * k + 3 * k + 3) * sizeof(typename S::Pt);
-}
-
 // Depth: the largest k <= want (32 by default: a stage costs a launch and
 // its edge traffic plus a chain of about 4k dependent levels, so deeper
 // stages are cheaper per level up to the lane frame's k <= 32) dividing nx/2,
@@ -405,7 +439,7 @@ template <class S>
 int64_t adjoint_depth(int64_t nx, int64_t want)
 {
     for (int64_t k = std::min<int64_t>(32, want > 0 ? want : 32); k >= 1; --k)
-        if (nx % (2 * k) == 0 && adjoint_lds<S>(k) <= kMaxLds && checkpoint_lds<S>(k) <= kMaxLds)
+        if (nx % (2 * k) == 0 && adjoint_lds<S>(k) <= kMaxLds && lane_lds<S>(k) <= kMaxLds)
             return k;
     return 0;
 }
@@ -457,7 +491,7 @@ int run_adjoint(const void* u0v, void* gradv, int64_t nx, int64_t nsteps, const 
     a.k = (int)k;
     a.tiles = (int)tiles;
     a.c = c;
-    const size_t lds_ck = checkpoint_lds<S>(k);
+    const size_t lds_ck = lane_lds<S>(k);
     for (int64_t s = 0; s < stages; ++s) {
         a.tri = s == 0;
         a.b = (s - 1) * k;
@@ -466,7 +500,7 @@ int run_adjoint(const void* u0v, void* gradv, int64_t nx, int64_t nsteps, const 
         a.re_out = ck_re + s * nx;
         a.le_in = s > 0 ? ck_le + (s - 1) * nx : ck_le;
         a.le_out = ck_le + s * nx;
-        hipLaunchKernelGGL((swept_checkpoint_kernel<S>), dim3(tiles), dim3(64), lds_ck,
+        hipLaunchKernelGGL((swept_lane_kernel<S, false>), dim3(tiles), dim3(64), lds_ck,
                            g_ctx.stream, a);
     }
     HIP_TRY(hipGetLastError());
@@ -1119,12 +1153,13 @@ size_t field_bytes(int id)
 
 // One swept run of `nsteps` steps on the zero field f with the given tiling;
 // returns its time and its number of stages.
+// P = 0: the lane-frame kernel
 int timed_swept(void* f, int64_t nx, int64_t nsteps, int id, const double* params, int64_t W,
                 int P, int reps, double* sec, int64_t* stages)
 {
     g_ctx.tile_w = (int)W;
     g_ctx.ppl = P;
-    g_ctx.mode = SWEPT_MODE_STAGE;
+    g_ctx.mode = P == 0 ? SWEPT_MODE_STAGE_LANE : SWEPT_MODE_STAGE;
     Plan p;
     int rc = make_plan(nx, nsteps, id, &p);
     if (rc)
@@ -1235,6 +1270,27 @@ int autotune(int64_t nx, int64_t nsteps, int id, const double* params, double* r
         return rc;
     double best_rate = (double)nx * (double)nn / t;
     Tuned best{-1, 0};
+    // the lane-frame kernel, for tilings whose regions are latency-bound:
+    // the two widest widths it takes
+    std::vector<int64_t> lane_Ws;
+    for (int64_t w = 2 * kLaneMaxK; w >= 4 && lane_Ws.size() < 2; w -= 2)
+        if (tile_fits(id, nx, w) && lane_fits(id, w / 2))
+            lane_Ws.push_back(w);
+    for (int64_t W : lane_Ws) {
+        const int64_t per_cu = std::max<int64_t>(
+            1, std::min<int64_t>(32, (160 * 1024) / (int64_t)lane_lds_bytes(id, W / 2)));
+        const int64_t npts = W * std::min(nx / W, 4 * (int64_t)cus * per_cu);
+        const int64_t Lp = std::min(nsteps * S, std::max<int64_t>(16 * (W / 2), 64));
+        const int64_t np = std::max<int64_t>(1, (Lp + S - 1) / S);
+        rc = timed_swept(f.p, npts, np, id, params, W, 0, 3, &t, nullptr);
+        if (rc)
+            return rc;
+        const double rate = (double)npts * (double)np / t;
+        if (rate > best_rate) {
+            best_rate = rate;
+            best = Tuned{W, 0};
+        }
+    }
     for (int64_t W : Ws) {
         // Once the tiles fill the chip the rate per point no longer depends
         // on their number: time four rounds of the workgroups that fit at
@@ -1376,7 +1432,7 @@ int swept_set_tuning(int32_t tile_w, int32_t pairs_per_lane, int32_t mode)
         pairs_per_lane != 8)
         return fail(SWEPT_EINVAL, "pairs per lane %d not in {0,1,2,4,8}", pairs_per_lane);
     if (mode != SWEPT_MODE_AUTO && mode != SWEPT_MODE_STAGE && mode != SWEPT_MODE_NAIVE &&
-        mode != SWEPT_MODE_STAGE_BANDED)
+        mode != SWEPT_MODE_STAGE_BANDED && mode != SWEPT_MODE_STAGE_LANE)
         return fail(SWEPT_EINVAL, "unknown mode %d", mode);
     g_ctx.tile_w = tile_w;
     g_ctx.ppl = pairs_per_lane;

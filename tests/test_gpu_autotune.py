@@ -43,6 +43,8 @@ def test_autotune_choice_is_used_and_exact(sw, oracle_mod, stencil, n, nsteps):
     else:
         assert n % rep["tile_w"] == 0
         assert (p["tile_w"], p["pairs_per_lane"]) == (rep["tile_w"], rep["pairs_per_lane"])
+        # pairs per lane 0: the lane-frame kernel was fastest
+        assert p["mode"] == (sw.MODE_STAGE_LANE if rep["pairs_per_lane"] == 0 else sw.MODE_STAGE)
     u0 = workloads.white_noise(n, seed=n) if stencil == "heat" else \
         workloads.smoothed_noise(n, seed=n)
     u = torch.from_numpy(u0).cuda()

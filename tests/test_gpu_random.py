@@ -30,11 +30,12 @@ def _steps_near(g, k, per_step, top):
     return min(top, -(-levels // per_step))
 
 
-def _cases(stencil, count, seed, ks, ps, nmax, top):
+def _cases(stencil, count, seed, ks, ps, nmax, top, modes=(1, 3, 0)):
+    # modes: stage, stage with the banded kernel only, automatic (4: the
+    # lane-frame kernel, k <= 32)
     g = np.random.default_rng(seed)
     per_step = 1 if stencil.startswith("heat") else 4
     out = []
-    modes = (1, 3, 0)   # stage, stage with the banded kernel only, automatic
     for _ in range(count):
         k = int(g.choice(ks))
         T = int(g.integers(1, max(2, nmax // (2 * k)) + 1))
@@ -74,6 +75,12 @@ HEAT = _cases("heat", 40, 2024, [1, 2, 3, 5, 8, 16, 32, 64, 96, 128, 256], [1, 2
 HEAT32 = _cases("heat32", 12, 2025, [4, 16, 64, 128, 256], [1, 2, 4, 8], 8192, 1100)
 KS = _cases("ks", 24, 2026, [1, 2, 4, 8, 12, 16, 64, 128, 256], [1, 2, 4], 4096, 300)
 EULER = _cases("euler", 12, 2027, [2, 4, 8, 16, 64, 128], [1, 2], 2048, 70)
+LANE = ([("heat",) + c for c in _cases("heat", 16, 2030, [1, 2, 3, 5, 8, 16, 31, 32], [1], 4096,
+                                        400, modes=(4,))] +
+        [("ks",) + c for c in _cases("ks", 12, 2031, [1, 2, 4, 8, 13, 16, 32], [1], 4096, 100,
+                                      modes=(4,))] +
+        [("euler",) + c for c in _cases("euler", 6, 2032, [2, 4, 8, 16, 28], [1], 2048, 40,
+                                         modes=(4,))])
 
 
 @pytest.mark.parametrize("n,W,P,mode,nsteps", HEAT, ids=_ids(HEAT))
@@ -115,6 +122,31 @@ def test_random_euler(sw, oracle_mod, n, W, P, mode, nsteps):
         par = [workloads.EULER_CFL * dx, dx, workloads.EULER_GAMMA]
         want = oracle_mod.euler(q0, nsteps, par[0], dx, par[2])
         assert _same(_run(sw, q0, nsteps, "euler", par), want)
+    finally:
+        sw.set_tuning(0, 0, sw.MODE_AUTO)
+
+
+@pytest.mark.parametrize("stencil,n,W,P,mode,nsteps", LANE,
+                         ids=["%s-n%d-W%d-P%d-m%d-s%d" % c for c in LANE])
+def test_random_lane_kernel(sw, oracle_mod, stencil, n, W, P, mode, nsteps):
+    """Every stage on the lane-frame kernel (mode 4)."""
+    sw.set_tuning(W, 0, mode)
+    try:
+        assert sw.plan(n, nsteps, stencil)["mode"] == sw.MODE_STAGE_LANE
+        if stencil == "heat":
+            u0 = workloads.white_noise(n, seed=n + W + nsteps)
+            want = oracle_mod.heat(u0, nsteps, HEAT_R)
+            par = [HEAT_R]
+        elif stencil == "ks":
+            u0 = workloads.smoothed_noise(n, seed=n + W + nsteps)
+            want = oracle_mod.ks(u0, nsteps, *KS_P)
+            par = KS_P
+        else:
+            u0 = workloads.euler_smooth(n, seed=n + nsteps)
+            dx = 1.0 / n
+            par = [workloads.EULER_CFL * dx, dx, workloads.EULER_GAMMA]
+            want = oracle_mod.euler(u0, nsteps, par[0], dx, par[2])
+        assert _same(_run(sw, u0, nsteps, stencil, par), want)
     finally:
         sw.set_tuning(0, 0, sw.MODE_AUTO)
 
