@@ -123,6 +123,30 @@ def test_batch_continuous_schedule(oracle_mod, ks_list, lanes, P, nsteps, stenci
     assert np.array_equal(np.array(got), want)
 
 
+@pytest.mark.parametrize("k,T,nsteps,stencil", [
+    (1, 5, 7, "heat"), (2, 3, 9, "heat"), (3, 2, 11, "heat"), (8, 3, 15, "heat"),
+    (8, 2, 16, "heat"), (31, 1, 61, "heat"), (32, 2, 63, "heat"), (32, 1, 100, "heat"),
+    (32, 2, 31, "heat"), (4, 3, 5, "ks"), (8, 2, 7, "ks"), (32, 2, 9, "ks"), (31, 1, 16, "ks"),
+])
+def test_lane_kernel_schedule(oracle_mod, k, T, nsteps, stencil):
+    """The lane-frame stage kernel (every stage, field writes at the target
+    level; k = 32 takes the outermost columns as DPP fallback values):
+    exactly once, the oracle's bits."""
+    from tests import lane_sim
+    n = 2 * k * T
+    if stencil == "heat":
+        u0 = workloads.white_noise(n, seed=n + nsteps)
+        st, L, want = swept_sim.heat_step(0.3), nsteps, oracle_mod.heat(u0, nsteps, 0.3)
+    else:
+        u0 = workloads.smoothed_noise(n, seed=n + nsteps)
+        st, L = swept_sim.ks_step(0.005, 0.5), 4 * nsteps
+        want = oracle_mod.ks(u0, nsteps, 0.005, 0.5)
+    got, visits = lane_sim.simulate_lane(list(u0), nsteps, k, st, track=True)
+    ok, why = swept_sim.levels_complete(visits, n, L, k)
+    assert ok, why
+    assert np.array_equal(np.array(got), want)
+
+
 @pytest.mark.parametrize("nsteps", range(1, 26))
 def test_continuous_schedule_every_cap(oracle_mod, nsteps):
     """The continuous schedule at every target level modulo k (k = 4): a
