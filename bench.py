@@ -47,8 +47,8 @@ def parse():
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the untuned plans (no autotuner in the warm-up)")
     ap.add_argument("--profile", action="store_true",
-                    help="short run for rocprofv3: a plain copy of u (calibration), then the "
-                         "timed swept runs only")
+                    help="short run for rocprofv3: a plain copy of u (calibration), the "
+                         "timed swept runs, then 50 naive steps")
     ap.add_argument("--profile-mix", action="store_true",
                     help="short run for rocprofv3 instruction counters: one swept run each of "
                          "heat (2^24, 2,000 steps, W=1024 P=4), KS (2^20, 1,000 steps, W=512 "
@@ -136,9 +136,25 @@ def cpu_baseline(u0_np, nsteps_full, seconds):
         dt += time.perf_counter() - t0
         k += chunk
         per_step = dt / k
+    # one thread, on a few steps of the same field (a fifth of the time)
+    per1 = (dt / k) * threads
+    k1 = int(max(2, min(nsteps_full, 0.2 * seconds / per1)))
+    t0 = time.perf_counter()
+    oracle.heat(u0_np, k1, 0.25, threads=1)
+    dt1 = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")),
+                         "")
+    except OSError:
+        pass
     return {"value": n * k / dt, "unit": "point-updates/s", "cores": threads, "kind": "oracle",
             "sample": "heat f64 N=%d, first %d of %d steps, all points, OpenMP %d threads, "
-                      "%.1f s" % (n, k, nsteps_full, threads, dt)}
+                      "%.1f s" % (n, k, nsteps_full, threads, dt),
+            "single_thread": {"value": n * k1 / dt1, "sample": "first %d steps, 1 thread, %.1f s"
+                              % (k1, dt1)},
+            "cpu": model, "host_cpus": os.cpu_count()}
 
 
 KS_OPS_PER_STEP = 30  # per point-step: 4 sub-timesteps (4 + 11 + 4 + 11 flops, no FMA)
@@ -374,7 +390,9 @@ def main():
     # the library's stream (torch's current stream).
     sw.set_profiling(True)
     k = plan["depth_k"]
-    full = [s for s in range(1, plan["stages"]) if (s - 1) * k + 2 * k - 1 <= nsteps]
+    # the full diamonds strictly below the target level (the continuous
+    # kernel's stages; a diamond whose apex is the target level is banded)
+    full = [s for s in range(1, plan["stages"]) if (s - 1) * k + 2 * k - 1 < nsteps]
     diamond_ms, stage_ms, kinds = [], [], set()
 
     def record():
@@ -425,6 +443,10 @@ def main():
     }
 
     if args.profile:
+        # a few naive steps, for the naive kernel's HBM counters
+        u = u0.clone()
+        sw.naive_advance(u, 50, "heat", [0.25])
+        torch.cuda.synchronize()
         args.no_naive = args.no_cpu = True
     if not args.no_naive:
         nt, _ = timed_runs(sw, torch, sw.naive_advance, u0, nsteps, [0.25], 1, 1)
