@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: a plain copy of u (calibration), the "
                          "timed swept runs, then 50 naive steps")
+    ap.add_argument("--sweep", action="store_true",
+                    help="the headline workload at every tile width W in {512, ..., 4096} and "
+                         "pairs per lane, one JSON line each (instead of the benchmark line)")
     ap.add_argument("--profile-mix", action="store_true",
                     help="short run for rocprofv3 instruction counters: one swept run each of "
                          "heat (2^24, 2,000 steps, W=1024 P=4), KS (2^20, 1,000 steps, W=512 "
@@ -351,6 +354,28 @@ def profile_mix(sw, torch, workloads):
     sw.set_tuning(0, 0, sw.MODE_AUTO)
 
 
+def tile_sweep(sw, torch, workloads, args):
+    """The headline heat workload (2^24 points, 20,000 steps, f64) on each
+    tiling W x pairs per lane, timed like the benchmark (best of two runs
+    after one warm-up): one JSON line per tiling."""
+    n, nsteps = args.n, args.nsteps
+    u0 = torch.from_numpy(workloads.white_noise(
+        n, seed=workloads.WORKLOADS["heat_large"]["seed"])).cuda()
+    for W in (512, 1024, 2048, 4096):
+        for P in (1, 2, 4, 8):
+            if 64 * P > W // 2:
+                continue
+            sw.set_tuning(W, P, sw.MODE_STAGE)
+            plan = sw.plan(n, nsteps, "heat", torch.float64)
+            times, _ = timed_runs(sw, torch, sw.advance, u0, nsteps, [0.25], 2, 1)
+            t = min(times)
+            print(json.dumps({"tile_w": W, "pairs_per_lane": P, "stages": plan["stages"],
+                              "ms": t * 1e3, "value": n * nsteps / t,
+                              "frac_alu": HEAT_OPS_PER_UPDATE * n * nsteps / t / VALU_LANE_OPS}),
+                  flush=True)
+    sw.set_tuning(0, 0, sw.MODE_AUTO)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -367,6 +392,9 @@ def main():
     sw.clear_tuning()
     if args.profile_mix:
         profile_mix(sw, torch, workloads)
+        return
+    if args.sweep:
+        tile_sweep(sw, torch, workloads, args)
         return
     n, nsteps = args.n, args.nsteps
     u0_np = workloads.white_noise(n, seed=workloads.WORKLOADS["heat_large"]["seed"])
