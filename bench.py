@@ -52,6 +52,10 @@ def parse():
     ap.add_argument("--sweep", action="store_true",
                     help="the headline workload at every tile width W in {512, ..., 4096} and "
                          "pairs per lane, one JSON line each (instead of the benchmark line)")
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="heat (10,000 steps) and KS (2,000 steps) at N = 2^12 ... 2^24 / 2^20, "
+                         "autotuned swept against naive, one JSON line each (instead of the "
+                         "benchmark line)")
     ap.add_argument("--profile-mix", action="store_true",
                     help="short run for rocprofv3 instruction counters: one swept run each of "
                          "heat (2^24, 2,000 steps, W=1024 P=4), KS (2^20, 1,000 steps, W=512 "
@@ -376,6 +380,45 @@ def tile_sweep(sw, torch, workloads, args):
     sw.set_tuning(0, 0, sw.MODE_AUTO)
 
 
+def size_sweep(sw, torch, workloads):
+    """Swept against naive as the grid grows (the paper's speedup against
+    points per node): heat f64 at N = 2^12 ... 2^24 over 10,000 steps and KS
+    at N = 2^12 ... 2^20 over 2,000 steps, each after the autotuner, median
+    of three runs.  One JSON line per size."""
+    def timed(fn, u0, nsteps, st, par):
+        u = u0.clone()
+        fn(u, nsteps, st, par)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            u.copy_(u0)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn(u, nsteps, st, par)
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        return sorted(ts)[1]
+    cases = [("heat", lg, 10_000, [0.25]) for lg in range(12, 25, 2)] + \
+            [("ks", lg, 2_000, [workloads.KS_DT, workloads.KS_DX]) for lg in range(12, 21, 2)]
+    for st, lg, nsteps, par in cases:
+        n = 1 << lg
+        u0 = torch.from_numpy(workloads.white_noise(n, seed=lg) if st == "heat" else
+                              workloads.smoothed_noise(n, seed=lg)).cuda()
+        sw.clear_tuning()
+        tuned = sw.autotune(n, nsteps, st, par)
+        plan = sw.plan(n, nsteps, st)
+        ts = timed(sw.advance, u0, nsteps, st, par)
+        tn = timed(sw.naive_advance, u0, nsteps, st, par)
+        print(json.dumps({"stencil": st, "n": n, "time_steps": nsteps, "tile_w": plan["tile_w"],
+                          "pairs_per_lane": plan["pairs_per_lane"], "mode": plan["mode"],
+                          "swept": n * nsteps / ts, "naive": n * nsteps / tn,
+                          "speedup_vs_naive": tn / ts, "naive_us_per_step": tn / nsteps * 1e6,
+                          "tune_probe_rate": tuned["probe_rate"]}), flush=True)
+    sw.clear_tuning()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -395,6 +438,9 @@ def main():
         return
     if args.sweep:
         tile_sweep(sw, torch, workloads, args)
+        return
+    if args.size_sweep:
+        size_sweep(sw, torch, workloads)
         return
     n, nsteps = args.n, args.nsteps
     u0_np = workloads.white_noise(n, seed=workloads.WORKLOADS["heat_large"]["seed"])
