@@ -10,6 +10,8 @@ in Section 2).
 from fractions import Fraction
 import math
 
+import os
+
 import numpy as np
 import pytest
 
@@ -577,9 +579,38 @@ def test_euler_smooth_convergence(oracle_mod):
 
 def test_exact_riemann_reference_values():
     """The test's exact Riemann solver reproduces the published star state of
-    Sod's problem (rho, u, p) = (1, 0, 1) | (0.125, 0, 0.1), gamma = 1.4:
-    p* = 0.30313, u* = 0.92745, rho*L = 0.42632, rho*R = 0.26557."""
+    Sod's problem (rho, u, p) = (1, 0, 1) | (0.125, 0, 0.1), gamma = 1.4
+    (tests/golden/sod_star_state.json, with its source)."""
+    import json
+    with open(os.path.join(os.path.dirname(__file__), "golden", "sod_star_state.json")) as fh:
+        ref = json.load(fh)
+    tol = ref["tolerance"]
     left, right = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
     a, b = exact_riemann(left, right, np.array([0.9, 1.0]))
-    assert abs(a[2] - 0.30313) < 1e-5 and abs(a[1] - 0.92745) < 1e-5
-    assert abs(a[0] - 0.42632) < 1e-5 and abs(b[0] - 0.26557) < 1e-5
+    assert abs(a[2] - ref["p_star"]) < tol and abs(a[1] - ref["u_star"]) < tol
+    assert abs(a[0] - ref["rho_star_left"]) < tol and abs(b[0] - ref["rho_star_right"]) < tol
+
+
+def test_oracle_regression_record():
+    """The oracle still gives the bits recorded in
+    tests/golden/oracle_regression.json (written by make_oracle_regression.py
+    from the oracle itself): a change to its arithmetic must come with a new
+    record, and with the reading of the paper that justifies it."""
+    import json
+    import importlib.util
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    spec = importlib.util.spec_from_file_location("make_oracle_regression",
+                                                  os.path.join(here, "make_oracle_regression.py"))
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    with open(os.path.join(here, "oracle_regression.json")) as fh:
+        rec = json.load(fh)
+    names = []
+    for name, fn in gen.cases():
+        names.append(name)
+        got = np.asarray(fn())
+        want = rec[name]
+        assert str(got.dtype) == want["dtype"] and list(got.shape) == want["shape"], name
+        vals = np.array([float.fromhex(h) for h in want["values"]]).astype(got.dtype)
+        assert np.array_equal(got.ravel().view(np.uint8), vals.view(np.uint8)), name
+    assert sorted(names) == sorted(rec)
