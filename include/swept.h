@@ -261,7 +261,8 @@ int swept_clear_tuning(void);
  * most recent swept_advance, the duration of each stage launch in
  * milliseconds (ms_out[i]) and which kernel ran it (kind_out[i]: 0 = banded
  * kernel -- the triangle or a stage capped at the target level, 1 =
- * continuous-band diamond kernel).  At most cap entries are written; *count
+ * continuous-band diamond kernel, 2 = lane-frame kernel).  At most cap
+ * entries are written; *count
  * receives the number of stages.  Either output array may be NULL.
  * Returns SWEPT_EINVAL if profiling is off or no swept run was recorded.
  */
