@@ -54,6 +54,8 @@ def test_tuning_validation(swept):
     assert lib.swept_set_tuning(3, 0, 0) == -1      # odd tile
     assert lib.swept_set_tuning(0, 3, 0) == -1      # bad pairs per lane
     assert lib.swept_set_tuning(0, 0, 9) == -1      # bad mode
+    assert lib.swept_set_tuning(0, 0, 5) == -1
+    assert lib.swept_set_tuning(0, 0, 4) == 0       # the lane-frame kernel
     assert lib.swept_set_tuning(0, 0, 0) == 0
     assert lib.swept_set_tuning(128, 2, 1) == 0
     assert lib.swept_set_tuning(0, 0, 0) == 0
@@ -83,6 +85,32 @@ def test_plan_geometry(swept):
     assert lib.swept_plan(2, 5, 0, out) == -1                       # nx < 3
     assert lib.swept_plan(64, -1, 0, out) == -1
     assert lib.swept_plan(64, 1, 7, out) == -1
+
+
+def test_plan_lane_frame(swept):
+    """The lane-frame schedule plans tiles of at most 64 points (k <= 32)
+    whose rows from the middle level up fit the LDS budget, and reports 0
+    pairs per lane."""
+    lib = swept.lib()
+    try:
+        lib.swept_set_tuning(0, 0, swept.MODE_STAGE_LANE)
+        p = swept.plan(4096, 100, "heat")
+        assert (p["tile_w"], p["depth_k"], p["pairs_per_lane"], p["mode"]) == \
+            (64, 32, 0, swept.MODE_STAGE_LANE)
+        assert p["stages"] == 1 + (100 + 31) // 32
+        p = swept.plan(96, 10, "ks")
+        assert p["tile_w"] == 48 and p["mode"] == swept.MODE_STAGE_LANE
+        # Euler points are 72 bytes: k = 32 would need 79 KB, so the plan
+        # falls back to the widest dividing tile that fits (k = 16 for 4096)
+        p = swept.plan(4096, 10, "euler")
+        assert p["tile_w"] == 32 and p["mode"] == swept.MODE_STAGE_LANE
+        out = (ctypes.c_int64 * 6)()
+        lib.swept_set_tuning(128, 0, swept.MODE_STAGE_LANE)
+        assert lib.swept_plan(4096, 10, 0, out) == -1          # W = 128 > 64
+        lib.swept_set_tuning(0, 0, swept.MODE_STAGE_LANE)
+        assert lib.swept_plan(1001, 10, 0, out) == -5          # odd: no even tile
+    finally:
+        lib.swept_set_tuning(0, 0, 0)
 
 
 def test_tuner_rejects_bad_requests_without_a_gpu():
