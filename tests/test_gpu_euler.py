@@ -98,3 +98,9 @@ def test_euler_workload_full_size(sw, oracle_mod):
     dt, dx, gamma = params(n)
     ref = oracle_mod.euler(q0, nsteps, dt, dx, gamma, threads=oracle_mod.max_threads())
     assert np.array_equal(got, ref)
+    # the tiling the benchmark's autotuner picks (W = 256, one pair per lane)
+    sw.set_tuning(256, 1, sw.MODE_STAGE)
+    try:
+        assert np.array_equal(run(sw, sw.advance, q0, nsteps), ref)
+    finally:
+        sw.set_tuning(0, 0, sw.MODE_AUTO)

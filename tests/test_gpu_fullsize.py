@@ -54,10 +54,12 @@ def test_heat_large_full_size(sw, oracle_mod, dtype):
     assert np.array_equal(swept.view(np.uint8), naive.view(np.uint8))
 
 
-def test_ks_full_size(sw, oracle_mod):
+@pytest.mark.parametrize("tile_w,ppl", [(0, 0), (512, 2)])   # default; the tuned bench tiling
+def test_ks_full_size(sw, oracle_mod, tile_w, ppl):
     w = workloads.WORKLOADS["ks"]
     n, nsteps, par = w["n"], w["nsteps"], [w["dt"], w["dx"]]
     u0 = workloads.initial("ks")
+    sw.set_tuning(tile_w, ppl, sw.MODE_AUTO)
     plan = sw.plan(n, nsteps, "ks")
     print("ks N=%d steps=%d plan=%s" % (n, nsteps, plan), flush=True)
     swept = gpu_run(sw, sw.advance, u0, nsteps, "ks", par)
@@ -72,6 +74,7 @@ def test_ks_full_size(sw, oracle_mod):
     idx = sample_indices(n, plan["tile_w"], 78)
     want = oracle_mod.ks_points(u0, short, *par, idx)
     assert np.array_equal(got[idx].view(np.uint8), want.view(np.uint8))
+    sw.set_tuning(0, 0, sw.MODE_AUTO)
 
 
 def test_ks_adjoint_full_grid(sw, oracle_mod):
