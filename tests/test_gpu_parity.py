@@ -91,6 +91,9 @@ def test_heat_small_workload_full(sw, oracle_mod):
     want = oracle_mod.heat(u0, w["nsteps"], w["r"])
     assert same_bits(run(sw, sw.advance, u0, w["nsteps"], "heat", [w["r"]]), want)
     assert same_bits(run(sw, sw.naive_advance, u0, w["nsteps"], "heat", [w["r"]]), want)
+    # the tiling the benchmark's autotuner picks: W = 64 on the lane-frame kernel
+    sw.set_tuning(64, 0, sw.MODE_STAGE_LANE)
+    assert same_bits(run(sw, sw.advance, u0, w["nsteps"], "heat", [w["r"]]), want)
 
 
 # ---------------------------------------------------------------- heat f32
