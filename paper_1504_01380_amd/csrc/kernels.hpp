@@ -86,6 +86,32 @@ template <class S>
 struct chain_prefetch<S, std::void_t<decltype(S::kChainPrefetch)>>
     : std::integral_constant<bool, S::kChainPrefetch> {};
 
+// A stencil may set kFaces: its flux sub-timesteps then come as face fluxes
+// (face_of, step_faces), and the continuous kernel computes each face once.
+template <class S, class = void>
+struct has_faces : std::false_type {};
+template <class S>
+struct has_faces<S, std::void_t<decltype(S::kFaces)>> : std::integral_constant<bool, S::kFaces> {};
+struct NoFace {};
+template <class S, bool = has_faces<S>::value>
+struct face_type {
+    using type = NoFace;
+};
+template <class S>
+struct face_type<S, true> {
+    using type = typename S::Face;
+};
+template <class S>
+using face_t = typename face_type<S>::type;
+template <class S, int PH>
+constexpr bool face_phase()
+{
+    if constexpr (has_faces<S>::value)
+        return S::template flux_phase<PH>;
+    else
+        return false;
+}
+
 // One wave step of a band: every active pair advances one level.  Pairs are
 // visited from the last to the first so that pair q still reads pair q-1's
 // state from the previous step.
@@ -311,6 +337,20 @@ __global__ __launch_bounds__(64) void swept_stage_kernel(StageArgs<S> g)
 // MASK: 0 = all slots active; 1 = pipeline fill (slot e active iff e <= j);
 // 2 = pipeline drain (slot e active iff e > j).  QS >= 0: slot (rs, QS)
 // changes band before it computes.
+//
+// Face sharing (stencils with kFaces, flux sub-timesteps).  Pair e's update
+// needs three faces: F[e] between its B and A, G between its A and pair
+// e-1's B, and pair e-1's F.  So F is computed for every pair first, from
+// the states before the step, and reaches pair e+1 in the same lane or, for
+// the last pair, the next lane by a DPP shift; slot 0 takes the face of
+// pair -1 from the face chain.  The face chain holds the right V edge's
+// faces at first; the last slot then leaves there the face of the chain
+// entry it wrote one step before (fslot), which slot 0 reads k - 64P steps
+// later, at the same sub-timestep.  Flux steps are the odd sub-timesteps
+// and k, 64P are even, so a chain index m is a flux one for one parity of m
+// only: entry m of the face chain sits at fch[m / 2].  A slot that changes
+// band takes the face of its new state from Fn, computed before the
+// cycle's head.
 template <class S, int P, int PH, int MASK, int QS>
 __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt (&B)[P],
                                           typename S::Pt (&An)[P], typename S::Pt (&Bn)[P],
@@ -319,52 +359,95 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
                                           int next_slot, int wslot, bool wlast,
                                           typename S::Pt* re_store,
                                           const typename S::Pt* re_load,
-                                          const typename S::Consts& c)
+                                          const typename S::Consts& c, face_t<S> (&Fn)[P],
+                                          void* fch, int fslot)
 {
     using Pt = typename S::Pt;
-    Pt inA, inB, nA, nB;
-    if constexpr (chain_prefetch<S>::value) {
-        inA = S::shr1(A[P - 1], cA);
-        inB = S::shr1(B[P - 1], cB);
-        nA = chain[2 * next_slot + 1];
-        nB = chain[2 * next_slot];
-    } else {   // slot 0 is at step j of its band: pair -1 of step j
-        inA = S::shr1(A[P - 1], chain[2 * j + 1]);
-        inB = S::shr1(B[P - 1], chain[2 * j]);
-    }
+    if constexpr (face_phase<S, PH>()) {
+        using Face = typename S::Face;
+        static_assert(!chain_prefetch<S>::value, "face sharing reads the chain at its step");
+        Face* fchain = static_cast<Face*>(fch);
+        const Pt inB = S::shr1(B[P - 1], chain[2 * j]);
+        Face F[P];
 #pragma unroll
-    for (int q = P - 1; q >= 0; --q) {
-        if (QS == q) {     // folded at compile time after unrolling
-            if (lane == rs) {  // this slot enters the next band
-                re_store[0] = B[q];
-                re_store[1] = A[q];
-                A[q] = An[q];
-                B[q] = Bn[q];
-                if (re_load) {
-                    Bn[q] = re_load[0];
-                    An[q] = re_load[1];
+        for (int q = 0; q < P; ++q)
+            F[q] = S::template face_of<PH>(B[q], A[q], c);
+        const Face H0 = S::shr1(F[P - 1], fchain[j >> 1]);
+        if (MASK != 1 && lane == 63)
+            fchain[fslot >> 1] = F[P - 1];
+#pragma unroll
+        for (int q = P - 1; q >= 0; --q) {
+            if (QS == q) {
+                if (lane == rs) {
+                    re_store[0] = B[q];
+                    re_store[1] = A[q];
+                    A[q] = An[q];
+                    B[q] = Bn[q];
+                    F[q] = Fn[q];
+                    if (re_load) {
+                        Bn[q] = re_load[0];
+                        An[q] = re_load[1];
+                    }
                 }
             }
+            const Pt cBq = (q == 0) ? inB : B[q - 1];
+            bool act = true;
+            if constexpr (MASK == 1)
+                act = lane * P + q <= j;
+            if constexpr (MASK == 2)
+                act = lane * P + q > j;
+            if (act) {
+                const Face G = S::template face_of<PH>(A[q], cBq, c);
+                const Face H = (q == 0) ? H0 : F[q - 1];
+                B[q] = S::template step_faces<PH>(A[q], F[q], G, c);
+                A[q] = S::template step_faces<PH>(cBq, G, H, c);
+            }
         }
-        const Pt rA = (q == 0) ? inA : A[q - 1];
-        const Pt cBq = (q == 0) ? inB : B[q - 1];
-        bool act = true;
-        if constexpr (MASK == 1)
-            act = lane * P + q <= j;
-        if constexpr (MASK == 2)
-            act = lane * P + q > j;
-        if (act) {
-            B[q] = S::template step<PH>(B[q], A[q], cBq, c);
-            A[q] = S::template step<PH>(A[q], cBq, rA, c);
+    } else {
+        Pt inA, inB, nA, nB;
+        if constexpr (chain_prefetch<S>::value) {
+            inA = S::shr1(A[P - 1], cA);
+            inB = S::shr1(B[P - 1], cB);
+            nA = chain[2 * next_slot + 1];
+            nB = chain[2 * next_slot];
+        } else {   // slot 0 is at step j of its band: pair -1 of step j
+            inA = S::shr1(A[P - 1], chain[2 * j + 1]);
+            inB = S::shr1(B[P - 1], chain[2 * j]);
+        }
+#pragma unroll
+        for (int q = P - 1; q >= 0; --q) {
+            if (QS == q) {     // folded at compile time after unrolling
+                if (lane == rs) {  // this slot enters the next band
+                    re_store[0] = B[q];
+                    re_store[1] = A[q];
+                    A[q] = An[q];
+                    B[q] = Bn[q];
+                    if (re_load) {
+                        Bn[q] = re_load[0];
+                        An[q] = re_load[1];
+                    }
+                }
+            }
+            const Pt rA = (q == 0) ? inA : A[q - 1];
+            const Pt cBq = (q == 0) ? inB : B[q - 1];
+            bool act = true;
+            if constexpr (MASK == 1)
+                act = lane * P + q <= j;
+            if constexpr (MASK == 2)
+                act = lane * P + q > j;
+            if (act) {
+                B[q] = S::template step<PH>(B[q], A[q], cBq, c);
+                A[q] = S::template step<PH>(A[q], cBq, rA, c);
+            }
+        }
+        if constexpr (chain_prefetch<S>::value) {
+            cA = nA;
+            cB = nB;
         }
     }
     if (wlast && lane == 63) {  // the last slot traces the band's left edge
         chain[2 * wslot] = B[P - 1];
         chain[2 * wslot + 1] = A[P - 1];
-    }
-    if constexpr (chain_prefetch<S>::value) {
-        cA = nA;
-        cB = nB;
     }
 }
 
@@ -385,7 +468,8 @@ __device__ __forceinline__ void cont_head_group(int j0, int k, int nb, int cyc,
                                                 typename S::Pt& cB, typename S::Pt* chain,
                                                 const typename S::Pt* re,
                                                 typename S::Pt* re_out, int lane,
-                                                const typename S::Consts& c)
+                                                const typename S::Consts& c,
+                                                face_t<S> (&Fn)[P], void* fch)
 {
     if constexpr (I < G) {
         constexpr int NB = 64 * P;
@@ -405,10 +489,13 @@ __device__ __forceinline__ void cont_head_group(int j0, int k, int nb, int cyc,
             if (cyc + 1 < nb)
                 re_load = re + 2 * ((cyc + 1) * NB + j);
         }
+        // the chain entry the last slot wrote one step before (j < 64P here)
+        const int fslot = j + k - NB;
         cont_step<S, P, PH, MASK, TRANS ? QS : -1>(A, B, An, Bn, cA, cB, chain, lane, j, rs,
-                                                   next_slot, wslot, wlast, re_store, re_load, c);
+                                                   next_slot, wslot, wlast, re_store, re_load, c,
+                                                   Fn, fch, fslot);
         cont_head_group<S, P, PH0, MASK, TRANS, I + 1, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
-                                                          chain, re, re_out, lane, c);
+                                                          chain, re, re_out, lane, c, Fn, fch);
     }
 }
 
@@ -419,7 +506,8 @@ __device__ __forceinline__ void cont_body_group(int j0, int k, typename S::Pt (&
                                                 typename S::Pt (&B)[P], typename S::Pt (&An)[P],
                                                 typename S::Pt (&Bn)[P], typename S::Pt& cA,
                                                 typename S::Pt& cB, typename S::Pt* chain,
-                                                int lane, const typename S::Consts& c)
+                                                int lane, const typename S::Consts& c,
+                                                face_t<S> (&Fn)[P], void* fch)
 {
     if constexpr (I < U) {
         constexpr int NB = 64 * P;
@@ -427,8 +515,9 @@ __device__ __forceinline__ void cont_body_group(int j0, int k, typename S::Pt (&
         const int next_slot = (j + 1 == k) ? 0 : j + 1;
         cont_step<S, P, (PH0 + I) % S::NPHASE, 0, -1>(A, B, An, Bn, cA, cB, chain, lane, j, 0,
                                                       next_slot, j - (NB - 1), true, nullptr,
-                                                      nullptr, c);
-        cont_body_group<S, P, PH0, I + 1, U>(j0, k, A, B, An, Bn, cA, cB, chain, lane, c);
+                                                      nullptr, c, Fn, fch, j - NB);
+        cont_body_group<S, P, PH0, I + 1, U>(j0, k, A, B, An, Bn, cA, cB, chain, lane, c, Fn,
+                                             fch);
     }
 }
 
@@ -436,7 +525,8 @@ __device__ __forceinline__ void cont_body_group(int j0, int k, typename S::Pt (&
 // the continuous-band schedule.  re: the left V edge (pair d at step -1),
 // read and then overwritten in place by re_out when they are the same
 // buffer; le_in: the right V edge (pair -1 at step m); le_out: the new left
-// edge; chain: 2k points of LDS.  PH0 = b mod NPHASE.
+// edge; chain: 2k points of LDS, followed for stencils with kFaces by the
+// face chain (k/2 faces).  PH0 = b mod NPHASE.
 template <class S, int P, int PH0>
 __device__ __forceinline__ void cont_region(const typename S::Pt* re, typename S::Pt* re_out,
                                             const typename S::Pt* le_in, typename S::Pt* le_out,
@@ -452,6 +542,20 @@ __device__ __forceinline__ void cont_region(const typename S::Pt* re, typename S
     for (int i = lane; i < 2 * k; i += 64)
         chain[i] = le_in[i];
     __syncthreads();
+    void* fch = nullptr;
+    face_t<S> Fn[P];
+    if constexpr (has_faces<S>::value) {
+        // faces of the right V edge: slot 0 meets pair -1 of step m at
+        // sub-timestep (PH0 + m) mod 4, a flux one for m = 2i + 1 - PH0 mod 2
+        using Face = typename S::Face;
+        Face* fchain = reinterpret_cast<Face*>(chain + 2 * k);
+        for (int i = lane; i < k / 2; i += 64) {
+            const int m = 2 * i + ((PH0 + 1) & 1);
+            fchain[i] = S::face_sel(chain[2 * m], chain[2 * m + 1], ((PH0 + m) & 3) == 3, cst);
+        }
+        fch = fchain;
+        __syncthreads();
+    }
 
     Pt A[P], B[P], An[P], Bn[P];
 #pragma unroll
@@ -473,19 +577,31 @@ __device__ __forceinline__ void cont_region(const typename S::Pt* re, typename S
         if (cyc == 0) {
             for (int j0 = 0; j0 < NB; j0 += G)
                 cont_head_group<S, P, PH0, 1, false, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
-                                                           chain, re, re_out, lane, cst);
+                                                           chain, re, re_out, lane, cst, Fn,
+                                                           fch);
         } else if (cyc == nb) {
             for (int j0 = 0; j0 < NB; j0 += G)
                 cont_head_group<S, P, PH0, 2, false, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
-                                                           chain, re, re_out, lane, cst);
+                                                           chain, re, re_out, lane, cst, Fn,
+                                                           fch);
             break;
         } else {
+            if constexpr (has_faces<S>::value) {
+                // slot e takes its next state at cycle step e, sub-timestep
+                // (PH0 + e) mod 4 (read only when that is a flux one)
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    const int e = lane * P + q;
+                    Fn[q] = S::face_sel(Bn[q], An[q], ((PH0 + e) & 3) == 3, cst);
+                }
+            }
             for (int j0 = 0; j0 < NB; j0 += G)
                 cont_head_group<S, P, PH0, 0, true, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
-                                                          chain, re, re_out, lane, cst);
+                                                          chain, re, re_out, lane, cst, Fn, fch);
         }
         for (int j0 = NB; j0 < k; j0 += U)
-            cont_body_group<S, P, PH0, 0, U>(j0, k, A, B, An, Bn, cA, cB, chain, lane, cst);
+            cont_body_group<S, P, PH0, 0, U>(j0, k, A, B, An, Bn, cA, cB, chain, lane, cst, Fn,
+                                             fch);
     }
 
 #pragma unroll

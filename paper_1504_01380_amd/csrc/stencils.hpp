@@ -298,12 +298,72 @@ struct EulerF64 {
         for (int c = 0; c < 3; ++c)
             F[c] = (0.5 * (fL[c] + fR[c])) - (hl * (qR[c] - qL[c]));
     }
+    // The flux sub-timesteps (1 and 3) split into face fluxes and their
+    // difference, so that a kernel can compute the face between two cells
+    // once and hand it to both (the face of cell pair (l, r) is the same
+    // value for the update of l and of r).
+    static constexpr bool kFaces = true;
+    struct Face {
+        double f[3];
+    };
+    template <int PH>
+    static constexpr bool flux_phase = PH == 1 || PH == 3;
+    // the face between cells l and r for flux sub-timestep PH
+    template <int PH>
+    __device__ __forceinline__ static Face face_of(const Pt& l, const Pt& r, const Consts& k)
+    {
+        Face F;
+        if constexpr (PH == 1)
+            face(l.q, l.s, r.q, r.s, k.gm1, F.f);
+        else
+            face(l.r, l.s, r.r, r.s, k.gm1, F.f);
+        return F;
+    }
+    // the same with the sub-timestep chosen per lane: 3 if r3, else 1
+    __device__ __forceinline__ static Face face_sel(const Pt& l, const Pt& r, bool r3,
+                                                    const Consts& k)
+    {
+        double vl[3], vr[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            vl[c] = r3 ? l.r[c] : l.q[c];
+            vr[c] = r3 ? r.r[c] : r.q[c];
+        }
+        Face F;
+        face(vl, l.s, vr, r.s, k.gm1, F.f);
+        return F;
+    }
+    __device__ __forceinline__ static Face shr1(const Face& v, const Face& old)
+    {
+        Face o;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            o.f[c] = dpp_shr1(v.f[c], old.f[c]);
+        return o;
+    }
+    // cell c after flux sub-timestep PH, from its left and right face fluxes
+    template <int PH>
+    __device__ __forceinline__ static Pt step_faces(const Pt& c, const Face& FL, const Face& FR,
+                                                    const Consts& k)
+    {
+        Pt o = c;
+        const double coef = PH == 1 ? k.ch : k.cf;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double v = c.q[j] - (coef * (FR.f[j] - FL.f[j]));
+            if constexpr (PH == 1)
+                o.r[j] = v;
+            else
+                o.q[j] = o.r[j] = v;
+        }
+        return o;
+    }
     template <int PH>
     __device__ __forceinline__ static Pt step(const Pt& l, const Pt& c, const Pt& r,
                                               const Consts& k)
     {
-        Pt o = c;
         if constexpr (PH == 0 || PH == 2) {   // limited slopes of q (sub0) or r (sub2)
+            Pt o = c;
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const double vl = PH == 0 ? l.q[j] : l.r[j];
@@ -311,26 +371,10 @@ struct EulerF64 {
                 const double vr = PH == 0 ? r.q[j] : r.r[j];
                 o.s[j] = minmod(vc - vl, vr - vc);
             }
+            return o;
         } else {                              // flux differences of (q, s) or (r, s)
-            double FL[3], FR[3];
-            if constexpr (PH == 1) {
-                face(l.q, l.s, c.q, c.s, k.gm1, FL);
-                face(c.q, c.s, r.q, r.s, k.gm1, FR);
-            } else {
-                face(l.r, l.s, c.r, c.s, k.gm1, FL);
-                face(c.r, c.s, r.r, r.s, k.gm1, FR);
-            }
-            const double coef = PH == 1 ? k.ch : k.cf;
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const double v = c.q[j] - (coef * (FR[j] - FL[j]));
-                if constexpr (PH == 1)
-                    o.r[j] = v;
-                else
-                    o.q[j] = o.r[j] = v;
-            }
+            return step_faces<PH>(c, face_of<PH>(l, c, k), face_of<PH>(c, r, k), k);
         }
-        return o;
     }
 };
 

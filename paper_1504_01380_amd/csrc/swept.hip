@@ -185,9 +185,29 @@ int auto_ppl(int id, int64_t k)
     return std::min(pmax(id) == 2 ? 1 : 4, k >= 512 ? 4 : (k >= 128 ? 2 : 1));
 }
 
+// LDS of the stage kernels: the 2k-point edge chain and, on the continuous
+// kernel of a stencil that shares face fluxes (Euler), the face chain (k/2
+// faces).  LDS sets how many workgroups share a CU: Euler at W = 256 takes
+// 19,968 bytes, eight per CU.
+size_t stage_lds_bytes(int id, int64_t W)
+{
+    const size_t face = id == SWEPT_EULER_F64 ? sizeof(EulerF64::Face) : 0;
+    return (size_t)W * pt_bytes(id) + (size_t)(W / 4) * face;
+}
+
+template <class S>
+size_t stage_lds(int64_t W, bool cont)
+{
+    size_t bytes = (size_t)W * sizeof(typename S::Pt);
+    if constexpr (has_faces<S>::value)
+        if (cont)
+            bytes += (size_t)(W / 4) * sizeof(typename S::Face);
+    return bytes;
+}
+
 bool tile_fits(int id, int64_t nx, int64_t W)
 {
-    return W >= 2 && W % 2 == 0 && nx % W == 0 && (size_t)W * pt_bytes(id) <= kMaxLds;
+    return W >= 2 && W % 2 == 0 && nx % W == 0 && stage_lds_bytes(id, W) <= kMaxLds;
 }
 
 // the lane-frame kernel: k <= 32 and the rows from the middle level up
@@ -346,7 +366,7 @@ int run_swept(void* u, int64_t nx, int64_t L, const typename S::Consts& c, const
         return rc;
     Pt* re = static_cast<Pt*>(g_ctx.scratch);
     Pt* le[2] = {re + nx, re + 2 * nx};
-    const size_t lds = (size_t)p.W * sizeof(Pt);
+    const size_t lds_band = stage_lds<S>(p.W, false), lds_cont = stage_lds<S>(p.W, true);
 
     StageArgs<S> a{};
     a.u = static_cast<typename S::T*>(u);
@@ -379,6 +399,7 @@ int run_swept(void* u, int64_t nx, int64_t L, const typename S::Consts& c, const
             continue;
         }
         const bool cont = use_continuous(p, s, L);
+        const size_t lds = cont ? lds_cont : lds_band;
         // pairs per lane beyond the register budget of a point are not built
         constexpr int PMAX = pmax_of<S>();
         switch (p.P) {
@@ -1297,7 +1318,8 @@ int autotune(int64_t nx, int64_t nsteps, int id, const double* params, double* r
         // once (64-lane workgroups, at most 32 per CU, LDS of W points
         // each), over sixteen stages.
         const int64_t per_cu =
-            std::max<int64_t>(1, std::min<int64_t>(32, (160 * 1024) / ((int64_t)W * pt_bytes(id))));
+            std::max<int64_t>(1, std::min<int64_t>(32, (int64_t)((160 * 1024) /
+                                                                 stage_lds_bytes(id, W))));
         const int64_t npts = W * std::min(nx / W, 4 * (int64_t)cus * per_cu);
         const int64_t Lp = std::min(nsteps * S, std::max<int64_t>(16 * (W / 2), 64));
         const int64_t np = std::max<int64_t>(1, (Lp + S - 1) / S);

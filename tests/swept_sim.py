@@ -97,6 +97,114 @@ def _cont_stage(t, J, b, k, P, lanes, RE, chain, step, nph, n, visits):
         RE[t][2 * ((nb - 1) * NB + e) + 1] = A[e]
 
 
+def cont_faces_symbolic(k, P, b, lanes=64):
+    """The face-sharing bookkeeping of the continuous kernel for a stencil
+    whose flux sub-timesteps (1 and 3 of 4) split into face fluxes, on
+    symbolic values: a point is (x, level) and a face is ('F', x, level,
+    phase), the face between x and x+1.  Every update asserts that it gets
+    exactly the neighbours and the two faces it needs; returns the final
+    right edge and the chain (the new left edge) for a check of the
+    geometry.  Mirrors the kernel: F[e] = face of pair e (B, A) before the
+    step; pair e's right face is F[e-1], slot 0's comes from the face chain
+    (the right V edge's faces, then those the last slot leaves one step
+    after each chain entry), entry m at index m // 2 (the flux entries are
+    those of one parity of m); a slot that changes band takes the face of
+    its new state computed before the cycle's head."""
+    NB = lanes * P
+    assert k % NB == 0 and NB % 4 == 0   # as 64P in the kernel
+    nb = k // NB
+
+    def step(ph, l, c, r):
+        assert l == (c[0] - 1, c[1]) and r == (c[0] + 1, c[1]) and ph == c[1] % 4, (l, c, r, ph)
+        return (c[0], c[1] + 1)
+
+    def face(ph, l, r):
+        assert r == (l[0] + 1, l[1]) and ph == l[1] % 4, (l, r, ph)
+        return ('F', l[0], l[1], ph)
+
+    def step_f(ph, c, FL, FR):
+        assert FL == ('F', c[0] - 1, c[1], ph) and FR == ('F', c[0], c[1], ph), (c, FL, FR, ph)
+        return (c[0], c[1] + 1)
+
+    J = 0
+    # left V edge: pair d at step -1; right V edge (chain): pair -1 at step m
+    RE = []
+    for d in range(k):
+        RE += [(J - 2 - d, b + d), (J - 1 - d, b + d)]
+    chain = []
+    for m in range(k):
+        chain += [(J + m, b + m), (J + m + 1, b + m)]
+    flux = (1, 3)
+    fchain = [None] * (k // 2)
+    for i in range(k // 2):
+        m = 2 * i + (b + 1) % 2
+        assert (b + m) % 4 in flux
+        fchain[i] = face((b + m) % 4, chain[2 * m], chain[2 * m + 1])
+    fnext = [None] * NB
+    A = [RE[2 * e + 1] for e in range(NB)]
+    B = [RE[2 * e] for e in range(NB)]
+    An = [RE[2 * (NB + e) + 1] if nb > 1 else None for e in range(NB)]
+    Bn = [RE[2 * (NB + e)] if nb > 1 else None for e in range(NB)]
+    out = list(RE)
+    for cyc in range(nb + 1):
+        if 0 < cyc < nb:   # faces of the states the slots take at this cycle's head
+            for e in range(NB):
+                ph = (b + cyc * k + e) % 4
+                fnext[e] = face(ph, Bn[e], An[e]) if ph in flux else None
+        for j in (range(NB) if cyc == nb else range(k)):
+            mask = 1 if (cyc == 0 and j < NB) else (2 if cyc == nb else 0)
+            trans = 0 < cyc < nb and j < NB
+            ph = (b + cyc * k + j) % 4
+            inA = [chain[2 * j + 1]] + [A[(r - 1) * P + P - 1] for r in range(1, lanes)]
+            inB = [chain[2 * j]] + [B[(r - 1) * P + P - 1] for r in range(1, lanes)]
+            fl = ph in flux
+            if fl:
+                def own_face(e):
+                    try:
+                        return face(ph, B[e], A[e])
+                    except AssertionError:
+                        return None   # a slot outside its band: never read
+                F = [own_face(e) for e in range(NB)]
+                H0 = [fchain[j >> 1]] + [F[(r - 1) * P + P - 1] for r in range(1, lanes)]
+                if mask != 1:
+                    fs = j + k - NB if j < NB else j - NB
+                    assert fs % 2 == j % 2
+                    fchain[fs >> 1] = F[NB - 1]
+            for r in range(lanes):
+                for q in range(P - 1, -1, -1):
+                    e = r * P + q
+                    if trans and e == j:
+                        out[2 * ((cyc - 1) * NB + j)] = B[e]
+                        out[2 * ((cyc - 1) * NB + j) + 1] = A[e]
+                        A[e], B[e] = An[e], Bn[e]
+                        if cyc + 1 < nb:
+                            Bn[e] = RE[2 * ((cyc + 1) * NB + j)]
+                            An[e] = RE[2 * ((cyc + 1) * NB + j) + 1]
+                        if fl:
+                            F[e] = fnext[e]
+                    act = (e <= j) if mask == 1 else ((e > j) if mask == 2 else True)
+                    if not act:
+                        continue
+                    rA = inA[r] if q == 0 else A[e - 1]
+                    cBv = inB[r] if q == 0 else B[e - 1]
+                    if fl:
+                        G = face(ph, A[e], cBv)
+                        H = H0[r] if q == 0 else F[e - 1]
+                        B[e] = step_f(ph, A[e], F[e], G)
+                        A[e] = step_f(ph, cBv, G, H)
+                    else:
+                        B[e] = step(ph, B[e], A[e], cBv)
+                        A[e] = step(ph, A[e], cBv, rA)
+            wlast = (j == NB - 1) if mask == 1 else ((j < NB - 1) if mask == 2 else True)
+            if wlast:
+                ws = (j + k - (NB - 1)) % k
+                chain[2 * ws], chain[2 * ws + 1] = B[NB - 1], A[NB - 1]
+    for e in range(NB):
+        out[2 * ((nb - 1) * NB + e)] = B[e]
+        out[2 * ((nb - 1) * NB + e) + 1] = A[e]
+    return out, chain
+
+
 def simulate(u0, nsteps, k, P, stencil, lanes=64, track=False, cont=False):
     """Run the swept schedule on a Python list; returns (u, visits) where
     visits maps (x, level) -> number of times it was computed (if track)."""

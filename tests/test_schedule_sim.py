@@ -230,3 +230,19 @@ def test_odd_ring_on_two_fold_cover(oracle_mod, n, k, nsteps):
     want = oracle_mod.heat(u0, nsteps, 0.25)
     assert np.array_equal(np.array(got[:n]), want)
     assert np.array_equal(np.array(got[n:]), want)
+
+
+@pytest.mark.parametrize("k,P,lanes", [(8, 1, 4), (16, 2, 2), (16, 1, 4), (24, 2, 2), (32, 4, 2),
+                                       (64, 1, 64), (128, 1, 64), (256, 2, 64), (128, 2, 64)])
+@pytest.mark.parametrize("b", [0, 1, 2, 3])
+def test_continuous_face_sharing(k, P, lanes, b):
+    """The continuous kernel's face sharing (Euler): each pair's update gets
+    exactly the neighbours and faces it needs, and the stage leaves the
+    right and left edges of the diamond."""
+    out, chain = swept_sim.cont_faces_symbolic(k, P, b, lanes)
+    for d in range(k):   # final states: pair d at step k-1
+        assert out[2 * d] == (k - 1 - d - 1, b + k - 1 + d + 1)
+        assert out[2 * d + 1] == (k - 1 - d, b + k - 1 + d + 1)
+    for m in range(k):   # last pair (k-1) at step m
+        assert chain[2 * m] == (m - (k - 1) - 1, b + m + k)
+        assert chain[2 * m + 1] == (m - (k - 1), b + m + k)
