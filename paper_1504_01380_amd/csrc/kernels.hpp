@@ -1168,6 +1168,26 @@ __global__ __launch_bounds__(64) void swept_adjoint_kernel(AdjArgs<S> g)
 // is only read, by the triangle (the forward pass of the swept adjoint,
 // which keeps the edges of every stage as its checkpoint).  LDS holds the
 // rows from the middle level up (the upper half of the adjoint layout).
+// One row of the lane frame: every column advances one level from its
+// neighbours in the lanes beside it.  A stencil with face fluxes computes,
+// in a flux sub-timestep, the face to its right once and takes the face to
+// its left from the lane before (lane 0's is never read: it lies outside
+// the region on every row that comes here).
+template <class S, int PH>
+__device__ __forceinline__ typename S::Pt lane_row(const typename S::Pt& v,
+                                                   const typename S::Consts& c)
+{
+    using Pt = typename S::Pt;
+    if constexpr (face_phase<S, PH>()) {
+        const Pt r = dpp_record<kWaveShl1>(v);
+        const typename S::Face F = S::template face_of<PH>(v, r, c);
+        return S::template step_faces<PH>(v, dpp_record<kWaveShr1>(F), F, c);
+    } else {
+        const Pt l = dpp_record<kWaveShr1>(v), r = dpp_record<kWaveShl1>(v);
+        return S::template step<PH>(l, v, r, c);
+    }
+}
+
 template <class S, bool FIELD>
 __global__ __launch_bounds__(64) void swept_lane_kernel(StageArgs<S> g)
 {
@@ -1214,20 +1234,17 @@ __global__ __launch_bounds__(64) void swept_lane_kernel(StageArgs<S> g)
     }
     levels_up<NPH>(g.b - 1, j0 + 1, min(k - 1, jtop), [&](int j, auto ph) {
         constexpr int PH = decltype(ph)::value;
-        const Pt l = dpp_record<kWaveShr1>(v), r = dpp_record<kWaveShl1>(v);
-        v = pick(iA == j, eA, pick(iB == j, eB, S::template step<PH>(l, v, r, g.c)));
+        v = pick(iA == j, eA, pick(iB == j, eB, lane_row<S, PH>(v, g.c)));
     });
     auto up_level = [&](int j, auto ph, auto outer) {
         constexpr int PH = decltype(ph)::value;
-        Pt l, r;
-        if constexpr (decltype(outer)::value) {
-            l = dpp_record_keep<kWaveShr1>(v, oL);
-            r = dpp_record_keep<kWaveShl1>(v, oR);
+        if constexpr (decltype(outer)::value) {   // k = 32: the outermost columns' neighbours
+            const Pt l = dpp_record_keep<kWaveShr1>(v, oL);
+            const Pt r = dpp_record_keep<kWaveShl1>(v, oR);
+            v = S::template step<PH>(l, v, r, g.c);
         } else {
-            l = dpp_record<kWaveShr1>(v);
-            r = dpp_record<kWaveShl1>(v);
+            v = lane_row<S, PH>(v, g.c);
         }
-        v = S::template step<PH>(l, v, r, g.c);
         const bool own = (unsigned)(dx - (j - 2 * k)) <= (unsigned)(4 * k - 1 - 2 * j);
         const unsigned at = (unsigned)(ly.template base_h<true>(j) + dx - low) * PB;
         *reinterpret_cast<Pt*>(Fb + (own ? at : dump_b)) = v;
