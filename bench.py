@@ -177,12 +177,14 @@ def other_workloads(sw, torch, workloads, tune=True):
     sub-timesteps per step), each after the autotuner has chosen its
     tiling."""
     out = {}
-    we = workloads.WORKLOADS["euler"]
+    we, wes = workloads.WORKLOADS["euler"], workloads.WORKLOADS["euler_small"]
     cases = [("heat_small", "heat", workloads.WORKLOADS["heat_small"], [0.25],
               HEAT_OPS_PER_UPDATE, 16),
              ("ks", "ks", workloads.WORKLOADS["ks"],
               [workloads.KS_DT, workloads.KS_DX], KS_OPS_PER_STEP, 16),
              ("euler", "euler", we, [we["cfl"] / we["n"], 1.0 / we["n"], we["gamma"]],
+              EULER_OPS_PER_STEP, 48),
+             ("euler_small", "euler", wes, [wes["cfl"] / wes["n"], 1.0 / wes["n"], wes["gamma"]],
               EULER_OPS_PER_STEP, 48)]
     for name, st, w, par, ops, naive_bytes in cases:
         u0 = torch.from_numpy(workloads.initial(name)).cuda()

@@ -104,3 +104,22 @@ def test_euler_workload_full_size(sw, oracle_mod):
         assert np.array_equal(run(sw, sw.advance, q0, nsteps), ref)
     finally:
         sw.set_tuning(0, 0, sw.MODE_AUTO)
+
+
+def test_euler_small_workload_full_size(sw, oracle_mod):
+    """The small Euler workload (periodic Sod, 4096 cells, 10,000 steps)
+    against the full oracle run, in the automatic configuration and on the
+    lane-frame kernel at the tilings the autotuner weighs for it (W = 32 and
+    16: each face flux computed once and handed to the next lane)."""
+    w = workloads.WORKLOADS["euler_small"]
+    n, nsteps = w["n"], w["nsteps"]
+    q0 = workloads.initial("euler_small")
+    dt, dx, gamma = params(n)
+    ref = oracle_mod.euler(q0, nsteps, dt, dx, gamma, threads=oracle_mod.max_threads())
+    assert np.array_equal(run(sw, sw.advance, q0, nsteps), ref)
+    try:
+        for W in (32, 16):
+            sw.set_tuning(W, 0, sw.MODE_STAGE_LANE)
+            assert np.array_equal(run(sw, sw.advance, q0, nsteps), ref), W
+    finally:
+        sw.set_tuning(0, 0, sw.MODE_AUTO)

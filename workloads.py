@@ -28,6 +28,8 @@ Workloads (sizes and distributions of the five benchmark configurations):
   rho = 0.125, u = 0, p = 0.1 on the left half, rho = 1, u = 0, p = 1 on the
   right half (no randomness).  Parity tests also use ``euler_smooth``: seeded
   random Fourier modes in rho, u, p around (1, 0, 1).
+* ``euler_small``  the same problem on N=4096 cells, 10,000 steps (a grid
+  small enough that each stage is latency-bound).
 """
 from __future__ import annotations
 
@@ -141,6 +143,8 @@ WORKLOADS = {
     "ks_adjoint": dict(stencil="ks", n=1 << 16, nsteps=20_000, dt=KS_DT, dx=KS_DX, seed=1004),
     "euler": dict(stencil="euler", n=1 << 20, nsteps=10_000, gamma=EULER_GAMMA, cfl=EULER_CFL,
                   seed=1005),
+    "euler_small": dict(stencil="euler", n=4096, nsteps=10_000, gamma=EULER_GAMMA,
+                        cfl=EULER_CFL, seed=1006),
 }
 
 
@@ -154,6 +158,6 @@ def initial(name: str, dtype=np.float64, n: int | None = None) -> np.ndarray:
         return white_noise(size, w["seed"], dtype)
     if name in ("ks", "ks_adjoint"):
         return smoothed_noise(size, w["seed"]).astype(dtype)
-    if name == "euler":
+    if name in ("euler", "euler_small"):
         return euler_mirrored_sod(size)
     raise KeyError(name)
