@@ -63,7 +63,11 @@ def lib() -> ctypes.CDLL:
         L.oracle_heat_f64_adjoint.argtypes = [vp, i64, i64, dbl, i64, dbl, vp, vp, i32]
         L.oracle_ks_f64_adjoint.argtypes = [vp, i64, i64, dbl, dbl, i64, dbl, vp, vp, i32]
         L.oracle_euler_f64.argtypes = [vp, i64, i64, dbl, dbl, dbl, i32]
+        L.oracle_heat_fma_f64.argtypes = [vp, i64, i64, dbl, i32]
+        L.oracle_heat_fma_f32.argtypes = [vp, i64, i64, flt, i32]
+        L.oracle_ks_fma_f64.argtypes = [vp, i64, i64, dbl, dbl, i32]
         for name in ("oracle_heat_f64", "oracle_heat_f32", "oracle_ks_f64",
+                     "oracle_heat_fma_f64", "oracle_heat_fma_f32", "oracle_ks_fma_f64",
                      "oracle_heat_f64_points", "oracle_heat_f32_points",
                      "oracle_ks_f64_points", "oracle_max_threads", "oracle_heat_f64_adjoint",
                      "oracle_ks_f64_adjoint", "oracle_euler_f64"):
@@ -103,6 +107,31 @@ def ks(u0: np.ndarray, nsteps: int, dt: float, dx: float, threads: int = 0) -> n
     u = np.array(u0, dtype=np.float64, copy=True, order="C")
     _check(lib().oracle_ks_f64(u.ctypes.data, u.size, int(nsteps), float(dt), float(dx),
                                int(threads)), "oracle_ks_f64")
+    return u
+
+
+def heat_fma(u0: np.ndarray, nsteps: int, r: float, threads: int = 0) -> np.ndarray:
+    """The heat scheme with its multiply-adds fused (Section 4's 3-FLOP
+    form): u' = fma(r, fma(-2, u, u[i-1] + u[i+1]), u).  float64 or float32."""
+    u = np.array(u0, copy=True, order="C")
+    if u.dtype == np.float64:
+        _check(lib().oracle_heat_fma_f64(u.ctypes.data, u.size, int(nsteps), float(r),
+                                         int(threads)), "oracle_heat_fma_f64")
+    elif u.dtype == np.float32:
+        _check(lib().oracle_heat_fma_f32(u.ctypes.data, u.size, int(nsteps),
+                                         float(np.float32(r)), int(threads)), "oracle_heat_fma_f32")
+    else:
+        raise TypeError("heat oracle takes float64 or float32")
+    return u
+
+
+def ks_fma(u0: np.ndarray, nsteps: int, dt: float, dx: float, threads: int = 0) -> np.ndarray:
+    """The KS scheme with its multiply-adds fused: D2(a) = fma(-2, a,
+    a[i-1] + a[i+1]) c2, F(a,b) = -(fma(a, D1 a, b) + D2 b), v = fma(h, F, u),
+    u' = fma(dt, F, u).  float64."""
+    u = np.array(u0, dtype=np.float64, copy=True, order="C")
+    _check(lib().oracle_ks_fma_f64(u.ctypes.data, u.size, int(nsteps), float(dt), float(dx),
+                                   int(threads)), "oracle_ks_fma_f64")
     return u
 
 

@@ -257,6 +257,138 @@ int oracle_ks_f64(double *u, int64_t n, int64_t nsteps, double dt, double dx,
     return ORACLE_OK;
 }
 
+/* ------------------------------------------------- contraction-on forms */
+/*
+ * The same schemes with each multiply-add fused, as the paper's Section 4
+ * counts the heat sub-timestep ("3 FLOPs": an add and two multiply-adds).
+ * fma() is the correctly rounded a*b + c of C99, so these definitions fix
+ * every bit too:
+ *   heat:  u'[i] = fma(r, fma(-2, u[i], u[i-1] + u[i+1]), u[i])
+ *   KS:    D2(a)[i]  = fma(-2, a[i], a[i-1] + a[i+1]) * c2
+ *          F(a,b)[i] = -(fma(a[i], D1(a)[i], b[i]) + D2(b)[i])
+ *          v = fma(h, F(u,w), u),  u' = fma(dt, F(v,z), u)
+ */
+static void heat_fma_step_f64(const double *a, double *b, int64_t n, double r)
+{
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < n; ++i) {
+        double lap = fma(-2.0, a[i], a[wrap(i - 1, n)] + a[wrap(i + 1, n)]);
+        b[i] = fma(r, lap, a[i]);
+    }
+}
+
+static void heat_fma_step_f32(const float *a, float *b, int64_t n, float r)
+{
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < n; ++i) {
+        float lap = fmaf(-2.0f, a[i], a[wrap(i - 1, n)] + a[wrap(i + 1, n)]);
+        b[i] = fmaf(r, lap, a[i]);
+    }
+}
+
+int oracle_heat_fma_f64(double *u, int64_t n, int64_t nsteps, double r, int nthreads)
+{
+    double *a, *b, *t;
+    int64_t s;
+    if (!u || n < 3 || nsteps < 0)
+        return ORACLE_EINVAL;
+    set_threads(nthreads);
+    b = (double *)malloc((size_t)n * sizeof(double));
+    if (!b)
+        return ORACLE_ENOMEM;
+    a = u;
+    for (s = 0; s < nsteps; ++s) {
+        heat_fma_step_f64(a, b, n, r);
+        t = a; a = b; b = t;
+    }
+    if (a != u) {
+        memcpy(u, a, (size_t)n * sizeof(double));
+        free(a);
+    } else {
+        free(b);
+    }
+    return ORACLE_OK;
+}
+
+int oracle_heat_fma_f32(float *u, int64_t n, int64_t nsteps, float r, int nthreads)
+{
+    float *a, *b, *t;
+    int64_t s;
+    if (!u || n < 3 || nsteps < 0)
+        return ORACLE_EINVAL;
+    set_threads(nthreads);
+    b = (float *)malloc((size_t)n * sizeof(float));
+    if (!b)
+        return ORACLE_ENOMEM;
+    a = u;
+    for (s = 0; s < nsteps; ++s) {
+        heat_fma_step_f32(a, b, n, r);
+        t = a; a = b; b = t;
+    }
+    if (a != u) {
+        memcpy(u, a, (size_t)n * sizeof(float));
+        free(a);
+    } else {
+        free(b);
+    }
+    return ORACLE_OK;
+}
+
+static double ks_fma_d2(double l, double m, double r, const ks_consts *k)
+{
+    return fma(-2.0, m, l + r) * k->c2;
+}
+
+static double ks_fma_rhs(double al, double am, double ar,
+                         double bl, double bm, double br, const ks_consts *k)
+{
+    double d1a = (ar - al) * k->c1;
+    return -(fma(am, d1a, bm) + ks_fma_d2(bl, bm, br, k));
+}
+
+int oracle_ks_fma_f64(double *u, int64_t n, int64_t nsteps, double dt, double dx,
+                      int nthreads)
+{
+    ks_consts k;
+    double *un, *w, *v, *z;
+    int64_t s, i;
+    if (!u || n < 3 || nsteps < 0 || !(dx > 0.0))
+        return ORACLE_EINVAL;
+    set_threads(nthreads);
+    k = ks_make(dt, dx);
+    un = (double *)malloc((size_t)n * sizeof(double));
+    w = (double *)malloc((size_t)n * sizeof(double));
+    v = (double *)malloc((size_t)n * sizeof(double));
+    z = (double *)malloc((size_t)n * sizeof(double));
+    if (!un || !w || !v || !z) {
+        free(un); free(w); free(v); free(z);
+        return ORACLE_ENOMEM;
+    }
+    for (s = 0; s < nsteps; ++s) {
+#pragma omp parallel for schedule(static)
+        for (i = 0; i < n; ++i)
+            w[i] = ks_fma_d2(u[wrap(i - 1, n)], u[i], u[wrap(i + 1, n)], &k);
+#pragma omp parallel for schedule(static)
+        for (i = 0; i < n; ++i) {
+            int64_t l = wrap(i - 1, n), r = wrap(i + 1, n);
+            v[i] = fma(k.h, ks_fma_rhs(u[l], u[i], u[r], w[l], w[i], w[r], &k), u[i]);
+        }
+#pragma omp parallel for schedule(static)
+        for (i = 0; i < n; ++i)
+            z[i] = ks_fma_d2(v[wrap(i - 1, n)], v[i], v[wrap(i + 1, n)], &k);
+#pragma omp parallel for schedule(static)
+        for (i = 0; i < n; ++i) {
+            int64_t l = wrap(i - 1, n), r = wrap(i + 1, n);
+            un[i] = fma(k.dt, ks_fma_rhs(v[l], v[i], v[r], z[l], z[i], z[r], &k), u[i]);
+        }
+        memcpy(u, un, (size_t)n * sizeof(double));
+    }
+    free(un); free(w); free(v); free(z);
+    return ORACLE_OK;
+}
+
 /* ------------------------------------------------ single outputs by cone */
 /*
  * The value of point i after L sub-timesteps depends only on the inputs

@@ -26,3 +26,13 @@ def oracle_mod():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+def same_bits(a, b) -> bool:
+    """True when a and b hold the same bytes (same dtype and shape): the
+    bit-exact bar, which tells -0.0 from +0.0 and compares NaN payloads."""
+    import numpy as np
+    a = np.ascontiguousarray(a)
+    b = np.ascontiguousarray(b)
+    return a.dtype == b.dtype and a.shape == b.shape and \
+        np.array_equal(a.view(np.uint8), b.view(np.uint8))

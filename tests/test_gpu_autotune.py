@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import workloads
-from tests.conftest import gpu_available
+from tests.conftest import gpu_available, same_bits
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
@@ -51,7 +51,7 @@ def test_autotune_choice_is_used_and_exact(sw, oracle_mod, stencil, n, nsteps):
     sw.advance(u, nsteps, stencil, par)
     want = oracle_mod.heat(u0, nsteps, 0.25) if stencil == "heat" else \
         oracle_mod.ks(u0, nsteps, *KS_P)
-    assert np.array_equal(u.cpu().numpy(), want)
+    assert same_bits(u.cpu().numpy(), want)
     sw.clear_tuning()
     assert sw.plan(n, nsteps, stencil, torch.float64)["mode"] == sw.MODE_STAGE
 
@@ -73,4 +73,4 @@ def test_autotune_batch(sw, oracle_mod):
     for i, u in zip(insts, us):
         want = oracle_mod.heat(i.u0, i.nsteps, 0.25) if i.stencil == "heat" else \
             oracle_mod.ks(i.u0, i.nsteps, *KS_P)
-        assert np.array_equal(u.cpu().numpy(), want)
+        assert same_bits(u.cpu().numpy(), want)

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import workloads
-from tests.conftest import gpu_available
+from tests.conftest import gpu_available, same_bits
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
@@ -95,7 +95,7 @@ def test_naive_batch_bitwise(sw, oracle_mod):
     torch.cuda.synchronize()
     for (st, ns, u0), u in zip(insts, us):
         want = oracle_run(oracle_mod, st, u0, ns)
-        assert np.array_equal(u.cpu().numpy(), want), (st, u0.size, ns)
+        assert same_bits(u.cpu().numpy(), want), (st, u0.size, ns)
 
 
 def test_full_ensemble(sw, oracle_mod):
@@ -130,4 +130,4 @@ def test_full_ensemble(sw, oracle_mod):
         want = (oracle_mod.heat(i.u0, i.nsteps, 0.25, threads=threads) if i.stencil == "heat"
                 else oracle_mod.ks(i.u0, i.nsteps, *KS_P, threads=threads))
         print(key, i.n, i.nsteps, flush=True)
-        assert np.array_equal(us[q].cpu().numpy(), want)
+        assert same_bits(us[q].cpu().numpy(), want)

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import workloads
-from tests.conftest import gpu_available
+from tests.conftest import gpu_available, same_bits
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
@@ -60,8 +60,8 @@ def test_euler_swept_bitwise(sw, oracle_mod, n, W, P, nsteps, ic, mode):
 def test_euler_naive_bitwise(sw, oracle_mod, n, nsteps):
     q0 = workloads.euler_smooth(n, seed=n)
     w = want(oracle_mod, q0, nsteps)
-    assert np.array_equal(run(sw, sw.naive_advance, q0, nsteps), w)
-    assert np.array_equal(run(sw, sw.naive_substep_advance, q0, nsteps), w)
+    assert same_bits(run(sw, sw.naive_advance, q0, nsteps), w)
+    assert same_bits(run(sw, sw.naive_substep_advance, q0, nsteps), w)
 
 
 def test_euler_auto_plan_and_odd_grid(sw, oracle_mod):
@@ -69,7 +69,7 @@ def test_euler_auto_plan_and_odd_grid(sw, oracle_mod):
     p = sw.plan(1 << 20, 100, "euler", torch.float64)
     assert p["mode"] == sw.MODE_STAGE and p["tile_w"] * 72 <= 64 * 1024
     q0 = workloads.euler_mirrored_sod(1001)            # odd: the naive schedule
-    assert np.array_equal(run(sw, sw.advance, q0, 60), want(oracle_mod, q0, 60))
+    assert same_bits(run(sw, sw.advance, q0, 60), want(oracle_mod, q0, 60))
 
 
 def test_euler_rejects_bad_shapes_and_params(sw):
@@ -97,11 +97,11 @@ def test_euler_workload_full_size(sw, oracle_mod):
     got = run(sw, sw.advance, q0, nsteps)
     dt, dx, gamma = params(n)
     ref = oracle_mod.euler(q0, nsteps, dt, dx, gamma, threads=oracle_mod.max_threads())
-    assert np.array_equal(got, ref)
+    assert same_bits(got, ref)
     # the tiling the benchmark's autotuner picks (W = 256, one pair per lane)
     sw.set_tuning(256, 1, sw.MODE_STAGE)
     try:
-        assert np.array_equal(run(sw, sw.advance, q0, nsteps), ref)
+        assert same_bits(run(sw, sw.advance, q0, nsteps), ref)
     finally:
         sw.set_tuning(0, 0, sw.MODE_AUTO)
 
@@ -116,10 +116,10 @@ def test_euler_small_workload_full_size(sw, oracle_mod):
     q0 = workloads.initial("euler_small")
     dt, dx, gamma = params(n)
     ref = oracle_mod.euler(q0, nsteps, dt, dx, gamma, threads=oracle_mod.max_threads())
-    assert np.array_equal(run(sw, sw.advance, q0, nsteps), ref)
+    assert same_bits(run(sw, sw.advance, q0, nsteps), ref)
     try:
         for W in (32, 16):
             sw.set_tuning(W, 0, sw.MODE_STAGE_LANE)
-            assert np.array_equal(run(sw, sw.advance, q0, nsteps), ref), W
+            assert same_bits(run(sw, sw.advance, q0, nsteps), ref), W
     finally:
         sw.set_tuning(0, 0, sw.MODE_AUTO)

@@ -577,6 +577,116 @@ def test_euler_smooth_convergence(oracle_mod):
     assert errs[0] / errs[1] > 2.8 and errs[1] / errs[2] > 2.8
 
 
+def roe_average(qL, qR, gamma=GAMMA):
+    """Roe's averaged velocity and total enthalpy of two states (paper,
+    Section 7 names the Roe matrix): the square-root-of-density weighted
+    means, written from their definition and pinned below by the property
+    that defines them, not by the oracle."""
+    rl, rr = qL[0], qR[0]
+    ul, ur = qL[1] / rl, qR[1] / rr
+    pl = (gamma - 1) * (qL[2] - 0.5 * rl * ul * ul)
+    pr = (gamma - 1) * (qR[2] - 0.5 * rr * ur * ur)
+    hl, hr = (qL[2] + pl) / rl, (qR[2] + pr) / rr
+    a, b = math.sqrt(rl), math.sqrt(rr)
+    return (a * ul + b * ur) / (a + b), (a * hl + b * hr) / (a + b)
+
+
+def euler_jacobian(u, H, gamma=GAMMA):
+    """The flux Jacobian df/dq of the 1D Euler equations written in the
+    velocity u and total enthalpy H."""
+    g = gamma
+    return np.array([[0.0, 1.0, 0.0],
+                     [0.5 * (g - 3) * u * u, (3 - g) * u, g - 1],
+                     [u * (0.5 * (g - 1) * u * u - H), H - (g - 1) * u * u, g * u]])
+
+
+def euler_flux(q, gamma=GAMMA):
+    rho, m, E = q
+    u = m / rho
+    p = (gamma - 1) * (E - 0.5 * m * u)
+    return np.array([m, m * u + p, (E + p) * u])
+
+
+def _roe_property_residual(avg):
+    rng = np.random.default_rng(71)
+    worst = 0.0
+    for _ in range(200):
+        qL = euler_state(rng.uniform(0.1, 2.0), rng.uniform(-1.5, 1.5), rng.uniform(0.1, 3.0))
+        qR = euler_state(rng.uniform(0.1, 2.0), rng.uniform(-1.5, 1.5), rng.uniform(0.1, 3.0))
+        u, H = avg(qL, qR)
+        lhs = euler_jacobian(u, H) @ (qR - qL)
+        rhs = euler_flux(qR) - euler_flux(qL)
+        worst = max(worst, float(np.abs(lhs - rhs).max() / np.abs(rhs).max()))
+    return worst
+
+
+def test_roe_average_satisfies_the_roe_property():
+    """A(u~, H~)(qR - qL) = f(qR) - f(qL) is the property that defines Roe's
+    average; the test's roe_average meets it on random state pairs, and the
+    plausible slips (weights swapped between the sides, plain arithmetic
+    means) do not, so the property pins the weighting."""
+    assert _roe_property_residual(roe_average) < 1e-12
+
+    def enthalpy(q):
+        u = q[1] / q[0]
+        p = (GAMMA - 1) * (q[2] - 0.5 * q[0] * u * u)
+        return (q[2] + p) / q[0]
+
+    def swapped(qL, qR):
+        a, b = math.sqrt(qL[0]), math.sqrt(qR[0])
+        return (b * qL[1] / qL[0] + a * qR[1] / qR[0]) / (a + b), \
+            (b * enthalpy(qL) + a * enthalpy(qR)) / (a + b)
+
+    def arithmetic(qL, qR):
+        return 0.5 * (qL[1] / qL[0] + qR[1] / qR[0]), 0.5 * (enthalpy(qL) + enthalpy(qR))
+
+    assert _roe_property_residual(swapped) > 1e-2
+    assert _roe_property_residual(arithmetic) > 1e-2
+
+
+def _oracle_face_speed(oracle_mod, left, right, n=16):
+    """The dissipation speed the oracle uses at the face between two flat
+    states.  Cells 0..n/2-1 hold `left`, the rest `right`; all minmod slopes
+    vanish, so at face n/2 - 1/2 the first flux sub-timestep sees exactly
+    qL = left, qR = right, and the face i - 1/2 of cell i = n/2 - 1 carries the
+    plain flux f(left).  One step with dt = 1e-7 dx changes the density of that
+    cell by -(dt/dx)(F - f(left)) up to O(dt^2): solve for the speed in
+    F = (f(qL) + f(qR))/2 - (speed/2)(qR - qL)."""
+    q0 = np.concatenate([np.tile(euler_state(*left), (n // 2, 1)),
+                         np.tile(euler_state(*right), (n // 2, 1))])
+    dx = 1.0 / n
+    dt = 1e-7 * dx
+    q = oracle_mod.euler(q0, 1, dt, dx, GAMMA)
+    i = n // 2 - 1
+    F_rho = q0[i, 1] - (q[i, 0] - q0[i, 0]) * dx / dt      # f(left)[rho] = m_left
+    qL, qR = q0[i], q0[i + 1]
+    return (0.5 * (qL[1] + qR[1]) - F_rho) / (0.5 * (qR[0] - qL[0]))
+
+
+def test_euler_oracle_roe_speed_at_a_stationary_contact(oracle_mod):
+    """At a contact at rest (u = 0, uniform p, rho = 1 | 0.25) the physical
+    fluxes agree, so the density change of one step is the dissipation term
+    alone: it recovers the oracle's speed |u~| + c~, which must be Roe's.
+    (Weights swapped between the sides give a speed 22% off, arithmetic
+    means 12% off.)"""
+    left, right = (1.0, 0.0, 1.0), (0.25, 0.0, 1.0)
+    got = _oracle_face_speed(oracle_mod, left, right)
+    u, H = roe_average(euler_state(*left), euler_state(*right))
+    want = abs(u) + math.sqrt((GAMMA - 1) * (H - 0.5 * u * u))
+    assert abs(got - want) <= 1e-6 * want, (got, want)
+
+
+def test_euler_oracle_roe_speed_at_a_general_jump(oracle_mod):
+    """The same for two flat states that differ in density, velocity and
+    pressure, so that the velocity's weighting matters too."""
+    for left, right in (((1.0, 0.3, 1.0), (0.3, -0.4, 0.6)),
+                        ((0.2, -0.7, 0.3), (1.4, 0.5, 2.0))):
+        got = _oracle_face_speed(oracle_mod, left, right)
+        u, H = roe_average(euler_state(*left), euler_state(*right))
+        want = abs(u) + math.sqrt((GAMMA - 1) * (H - 0.5 * u * u))
+        assert abs(got - want) <= 1e-6 * want, (left, right, got, want)
+
+
 def test_exact_riemann_reference_values():
     """The test's exact Riemann solver reproduces the published star state of
     Sod's problem (rho, u, p) = (1, 0, 1) | (0.125, 0, 0.1), gamma = 1.4

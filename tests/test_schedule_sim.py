@@ -10,6 +10,7 @@ import pytest
 
 import workloads
 from tests import swept_sim
+from tests.conftest import same_bits
 
 
 @pytest.mark.parametrize("n,k,P,nsteps", [
@@ -24,7 +25,7 @@ def test_heat_exactly_once_and_bitwise(oracle_mod, n, k, P, nsteps):
     ok, why = swept_sim.levels_complete(visits, n, nsteps, k)
     assert ok, why
     want = oracle_mod.heat(u0, nsteps, 0.25)
-    assert np.array_equal(np.array(got), want)
+    assert same_bits(np.array(got), want)
 
 
 @pytest.mark.parametrize("lanes,P,k,nsteps", [
@@ -40,7 +41,7 @@ def test_heat_multiband(oracle_mod, lanes, P, k, nsteps):
                                      lanes=lanes, track=True)
     ok, why = swept_sim.levels_complete(visits, n, nsteps, k)
     assert ok, why
-    assert np.array_equal(np.array(got), oracle_mod.heat(u0, nsteps, 0.3))
+    assert same_bits(np.array(got), oracle_mod.heat(u0, nsteps, 0.3))
 
 
 @pytest.mark.parametrize("lanes,P,k,nsteps", [(64, 1, 8, 9), (4, 2, 12, 11), (64, 2, 6, 5)])
@@ -51,7 +52,7 @@ def test_ks_bitwise(oracle_mod, lanes, P, k, nsteps):
                                      lanes=lanes, track=True)
     ok, why = swept_sim.levels_complete(visits, n, 4 * nsteps, k)
     assert ok, why
-    assert np.array_equal(np.array(got), oracle_mod.ks(u0, nsteps, 0.005, 0.5))
+    assert same_bits(np.array(got), oracle_mod.ks(u0, nsteps, 0.005, 0.5))
 
 
 def test_dropped_update_is_caught(oracle_mod):
@@ -66,7 +67,7 @@ def test_dropped_update_is_caught(oracle_mod):
         return c if calls["n"] == 37 else step(ph, l, c, r)
 
     got, _ = swept_sim.simulate(list(u0), nsteps, k, 1, (skipping, nph, ff, tf), track=True)
-    assert not np.array_equal(np.array(got), oracle_mod.heat(u0, nsteps, 0.25))
+    assert not same_bits(np.array(got), oracle_mod.heat(u0, nsteps, 0.25))
 
 
 @pytest.mark.parametrize("lanes,P,k,nsteps,stencil", [
@@ -91,7 +92,7 @@ def test_continuous_schedule(oracle_mod, lanes, P, k, nsteps, stencil):
                                      cont=True)
     ok, why = swept_sim.levels_complete(visits, n, L, k)
     assert ok, why
-    assert np.array_equal(np.array(got), want)
+    assert same_bits(np.array(got), want)
 
 
 @pytest.mark.parametrize("ks_list,lanes,P,nsteps,stencil", [
@@ -120,7 +121,7 @@ def test_batch_continuous_schedule(oracle_mod, ks_list, lanes, P, nsteps, stenci
                                            track=True, cont=True)
     ok, why = swept_sim.levels_complete(visits, n, L, max(ks_list))
     assert ok, why
-    assert np.array_equal(np.array(got), want)
+    assert same_bits(np.array(got), want)
 
 
 @pytest.mark.parametrize("k,T,nsteps,stencil", [
@@ -144,7 +145,7 @@ def test_lane_kernel_schedule(oracle_mod, k, T, nsteps, stencil):
     got, visits = lane_sim.simulate_lane(list(u0), nsteps, k, st, track=True)
     ok, why = swept_sim.levels_complete(visits, n, L, k)
     assert ok, why
-    assert np.array_equal(np.array(got), want)
+    assert same_bits(np.array(got), want)
 
 
 @pytest.mark.parametrize("nsteps", range(1, 26))
@@ -159,7 +160,7 @@ def test_continuous_schedule_every_cap(oracle_mod, nsteps):
                                      track=True, cont=True)
     ok, why = swept_sim.levels_complete(visits, n, nsteps, k)
     assert ok, why
-    assert np.array_equal(np.array(got), oracle_mod.heat(u0, nsteps, 0.3))
+    assert same_bits(np.array(got), oracle_mod.heat(u0, nsteps, 0.3))
 
 
 @pytest.mark.parametrize("stencil,n,k,nsteps,n0,cot", [
@@ -182,7 +183,7 @@ def test_adjoint_schedule(oracle_mod, stencil, n, k, nsteps, n0, cot):
         loc = swept_adj_sim.ks_local(0.005, 0.5)
         want = oracle_mod.ks_adjoint(u0, nsteps, 0.005, 0.5, n0, w, c)
     got = swept_adj_sim.adjoint(list(u0), nsteps, k, loc, n0, w, None if c is None else list(c))
-    assert np.array_equal(np.array(got), want)
+    assert same_bits(np.array(got), want)
 
 
 def _split(half, k):
@@ -216,7 +217,7 @@ def test_unequal_tiles(oracle_mod, ks_list, nsteps, stencil):
     got, visits = swept_sim.simulate_tiles(list(u0), nsteps, ks_list, 1, st, lanes=2, track=True)
     ok, why = swept_sim.levels_complete(visits, n, L, 0)
     assert ok, why
-    assert np.array_equal(np.array(got), want)
+    assert same_bits(np.array(got), want)
 
 
 @pytest.mark.parametrize("n,k,nsteps", [(17, 4, 30), (9, 2, 11), (3, 8, 5), (101, 16, 70)])
@@ -228,8 +229,8 @@ def test_odd_ring_on_two_fold_cover(oracle_mod, n, k, nsteps):
     got, _ = swept_sim.simulate_tiles(cover, nsteps, _split(n, k), 1, swept_sim.heat_step(0.25),
                                       lanes=4)
     want = oracle_mod.heat(u0, nsteps, 0.25)
-    assert np.array_equal(np.array(got[:n]), want)
-    assert np.array_equal(np.array(got[n:]), want)
+    assert same_bits(np.array(got[:n]), want)
+    assert same_bits(np.array(got[n:]), want)
 
 
 @pytest.mark.parametrize("k,P,lanes", [(8, 1, 4), (16, 2, 2), (16, 1, 4), (24, 2, 2), (32, 4, 2),
