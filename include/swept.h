@@ -99,12 +99,30 @@ typedef enum {
  *   three binary64 values (rho, rho*u, E), interleaved: u points to 3*nx
  *   doubles.  params = { dt, dx, gamma } (nparams >= 3, dx > 0, gamma > 1).
  *   Not available in swept_advance_batch or swept_adjoint.
+ *
+ * SWEPT_HEAT_F64_FMA / SWEPT_HEAT_F32_FMA / SWEPT_KS_F64_FMA: the same
+ *   schemes and parameters with their multiply-adds fused (the contraction-on
+ *   build of the schemes; the paper's Section 4 counts the heat sub-timestep
+ *   as 3 FLOPs, which is this form):
+ *     heat  u' = fma(r, fma(-2, u, u[i-1] + u[i+1]), u)
+ *     KS    D2(a) = fma(-2, a, a[i-1] + a[i+1]) * c2,
+ *           F(a,b) = -(fma(a, D1(a), b) + D2(b)),
+ *           v = fma(h, F(u,w), u),  u' = fma(dt, F(v,z), u)
+ *   A fused multiply-add rounds once where the canonical form rounds twice,
+ *   so these results agree with the canonical ones to within rounding, not
+ *   bit for bit.
+ *   swept_advance and swept_naive_advance give the same bits as each other
+ *   for these ids.  Not available in swept_advance_batch, swept_adjoint or
+ *   swept_naive_substep_advance.
  */
 enum {
     SWEPT_HEAT_F64 = 0,
     SWEPT_HEAT_F32 = 1,
     SWEPT_KS_F64 = 2,
-    SWEPT_EULER_F64 = 3
+    SWEPT_EULER_F64 = 3,
+    SWEPT_HEAT_F64_FMA = 4,
+    SWEPT_HEAT_F32_FMA = 5,
+    SWEPT_KS_F64_FMA = 6
 };
 
 /* Schedules for swept_set_tuning. */

@@ -21,6 +21,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libswept.so")
 
 HEAT_F64, HEAT_F32, KS_F64, EULER_F64 = 0, 1, 2, 3
+# the same schemes with their multiply-adds fused (results equal the above to rounding)
+HEAT_F64_FMA, HEAT_F32_FMA, KS_F64_FMA = 4, 5, 6
 MODE_AUTO, MODE_STAGE, MODE_NAIVE, MODE_STAGE_BANDED, MODE_STAGE_LANE = 0, 1, 2, 3, 4
 
 _STATUS = {0: "SWEPT_OK", -1: "SWEPT_EINVAL", -2: "SWEPT_ENOTINIT", -3: "SWEPT_ENOMEM",
@@ -96,25 +98,30 @@ def _check(rc: int, what: str) -> None:
 
 
 def stencil_id(stencil, dtype: torch.dtype | None = None) -> int:
-    """'heat' (float64 or float32 by dtype), 'ks', 'euler', or an integer id."""
+    """'heat' (float64 or float32 by dtype), 'ks', 'euler', their
+    contraction-on forms 'heat_fma' and 'ks_fma', or an integer id."""
     if isinstance(stencil, int):
         return stencil
     s = stencil.lower()
     if s == "heat":
         return HEAT_F32 if dtype == torch.float32 else HEAT_F64
+    if s == "heat_fma":
+        return HEAT_F32_FMA if dtype == torch.float32 else HEAT_F64_FMA
     if s == "ks":
         return KS_F64
+    if s == "ks_fma":
+        return KS_F64_FMA
     if s == "euler":
         return EULER_F64
     raise ValueError("unknown stencil %r" % (stencil,))
 
 
 def dtype_of(sid: int) -> torch.dtype:
-    return torch.float32 if sid == HEAT_F32 else torch.float64
+    return torch.float32 if sid in (HEAT_F32, HEAT_F32_FMA) else torch.float64
 
 
 def substeps(sid: int) -> int:
-    return 4 if sid in (KS_F64, EULER_F64) else 1
+    return 4 if sid in (KS_F64, EULER_F64, KS_F64_FMA) else 1
 
 
 def init(device: int = 0) -> None:
@@ -343,9 +350,15 @@ class SweptAdvance(torch.autograd.Function):
         return g, None, None, None
 
 
+def _check_window(nsteps: int, window: int) -> None:
+    if not 1 <= int(window) <= int(nsteps):
+        raise ValueError("window = %r must satisfy 1 <= window <= nsteps = %r" % (window, nsteps))
+
+
 def window_mean_square_value(u0: torch.Tensor, nsteps: int, stencil, params, window: int):
     """J = mean of u^2 over all points and the last `window` time steps
     (steps nsteps-window+1 .. nsteps), computed by stepping the field."""
+    _check_window(nsteps, window)
     u = u0.detach().clone()
     first = nsteps - window + 1
     if first > 1:
@@ -363,6 +376,7 @@ class WindowMeanSquare(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, u0, nsteps, stencil, params, window):
+        _check_window(nsteps, window)
         ctx.save_for_backward(u0.detach())
         ctx.args = (nsteps, stencil, tuple(params), window)
         return window_mean_square_value(u0, nsteps, stencil, params, window)

@@ -15,7 +15,8 @@
 //
 // Arithmetic is written in the exact association the scheme defines and the
 // library is compiled with -ffp-contract=off: no multiply-add is fused, so
-// every path that evaluates these functions produces the same bits.
+// every path that evaluates these functions produces the same bits.  The
+// contraction-on variants (HeatFma, KSFmaF64) fuse theirs explicitly.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -205,6 +206,58 @@ struct KSF64 {
         return Ad{a.u + two_w * u, a.x, a.y};
     }
     __device__ __forceinline__ static double grad(const Ad& a) { return a.u; }
+};
+
+// ------------------------------------------------ contraction-on variants
+// The same schemes with the multiply-adds fused, the form in which the
+// paper's Section 4 counts the heat sub-timestep as 3 FLOPs.  Each fused
+// multiply-add rounds once instead of twice, so these results differ from
+// the canonical (unfused) ones by rounding only; they are a separate
+// stencil id, never mixed with the bit-exact ones.
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// heat: s = u[i-1] + u[i+1];  lap = fma(-2, u, s);  u' = fma(r, lap, u)
+template <class TT>
+struct HeatFma : Heat<TT> {
+    using Base = Heat<TT>;
+    using typename Base::Pt;
+    using typename Base::Consts;
+    template <int PH>
+    __device__ __forceinline__ static Pt step(const Pt& l, const Pt& c, const Pt& r,
+                                              const Consts& k)
+    {
+        const TT lap = fmad(TT(-2), c.u, l.u + r.u);
+        return Pt{fmad(k.r, lap, c.u)};
+    }
+};
+
+using HeatFmaF64 = HeatFma<double>;
+using HeatFmaF32 = HeatFma<float>;
+
+// KS: D2(a) = fma(-2, a, a[i-1] + a[i+1]) * c2,
+//     F(a,b) = -(fma(a, D1(a), b) + D2(b)),  v = fma(h, F, u),  u' = fma(dt, F, u)
+struct KSFmaF64 : KSF64 {
+    __device__ __forceinline__ static double rhs(const Pt& l, const Pt& c, const Pt& r,
+                                                 const Consts& k)
+    {
+        const double d1a = (r.a - l.a) * k.c1;
+        const double d2b = fmad(-2.0, c.b, l.b + r.b) * k.c2;
+        return -(fmad(c.a, d1a, c.b) + d2b);
+    }
+    template <int PH>
+    __device__ __forceinline__ static Pt step(const Pt& l, const Pt& c, const Pt& r,
+                                              const Consts& k)
+    {
+        if constexpr (PH == 0 || PH == 2) {
+            return Pt{c.u, c.a, fmad(-2.0, c.a, l.a + r.a) * k.c2};
+        } else if constexpr (PH == 1) {
+            return Pt{c.u, fmad(k.h, rhs(l, c, r, k), c.u), c.b};
+        } else {
+            const double un = fmad(k.dt, rhs(l, c, r, k), c.u);
+            return Pt{un, un, c.b};
+        }
+    }
 };
 
 // ---------------------------------------------------------------- Euler

@@ -88,11 +88,29 @@ int ensure_scratch(size_t bytes)
 
 // ------------------------------------------------------------------ stencils
 
-int substeps_of(int id) { return (id == SWEPT_KS_F64 || id == SWEPT_EULER_F64) ? 4 : 1; }
+// the canonical stencil an id shares its point layout and sizes with (the
+// contraction-on ids differ from theirs only in rounding)
+int base_id(int id)
+{
+    switch (id) {
+    case SWEPT_HEAT_F64_FMA: return SWEPT_HEAT_F64;
+    case SWEPT_HEAT_F32_FMA: return SWEPT_HEAT_F32;
+    case SWEPT_KS_F64_FMA: return SWEPT_KS_F64;
+    default: return id;
+    }
+}
+
+bool known_id(int id) { return id >= SWEPT_HEAT_F64 && id <= SWEPT_KS_F64_FMA; }
+
+int substeps_of(int id)
+{
+    const int b = base_id(id);
+    return (b == SWEPT_KS_F64 || b == SWEPT_EULER_F64) ? 4 : 1;
+}
 
 size_t pt_bytes(int id)
 {
-    switch (id) {
+    switch (base_id(id)) {
     case SWEPT_HEAT_F64: return sizeof(HeatF64::Pt);
     case SWEPT_HEAT_F32: return sizeof(HeatF32::Pt);
     case SWEPT_EULER_F64: return sizeof(EulerF64::Pt);
@@ -108,16 +126,16 @@ int check_problem(int64_t nx, int64_t nsteps, int32_t id, const double* params, 
         return fail(SWEPT_EINVAL, "nx = %lld: need at least 3 points", (long long)nx);
     if (nsteps < 0)
         return fail(SWEPT_EINVAL, "nsteps = %lld is negative", (long long)nsteps);
-    if (id != SWEPT_HEAT_F64 && id != SWEPT_HEAT_F32 && id != SWEPT_KS_F64 &&
-        id != SWEPT_EULER_F64)
+    if (!known_id(id))
         return fail(SWEPT_EINVAL, "unknown stencil id %d", id);
-    const int need = id == SWEPT_EULER_F64 ? 3 : (id == SWEPT_KS_F64 ? 2 : 1);
+    const int bid = base_id(id);
+    const int need = bid == SWEPT_EULER_F64 ? 3 : (bid == SWEPT_KS_F64 ? 2 : 1);
     if (!params || nparams < need)
         return fail(SWEPT_EINVAL, "stencil %d needs %d parameter(s)", id, need);
     for (int i = 0; i < need; ++i)
         if (!std::isfinite(params[i]))
             return fail(SWEPT_EINVAL, "parameter %d is not finite", i);
-    if ((id == SWEPT_KS_F64 || id == SWEPT_EULER_F64) && !(params[1] > 0.0))
+    if ((bid == SWEPT_KS_F64 || bid == SWEPT_EULER_F64) && !(params[1] > 0.0))
         return fail(SWEPT_EINVAL, "stencil %d needs dx > 0", id);
     if (id == SWEPT_EULER_F64 && !(params[2] > 1.0))
         return fail(SWEPT_EINVAL, "Euler needs gamma > 1");
@@ -173,7 +191,7 @@ constexpr int pmax_of()
 
 int pmax(int id)
 {
-    switch (id) {
+    switch (base_id(id)) {
     case SWEPT_KS_F64: return pmax_of<KSF64>();
     case SWEPT_EULER_F64: return pmax_of<EulerF64>();
     default: return 8;
@@ -191,7 +209,7 @@ int auto_ppl(int id, int64_t k)
 // 19,968 bytes, eight per CU.
 size_t stage_lds_bytes(int id, int64_t W)
 {
-    const size_t face = id == SWEPT_EULER_F64 ? sizeof(EulerF64::Face) : 0;
+    const size_t face = base_id(id) == SWEPT_EULER_F64 ? sizeof(EulerF64::Face) : 0;
     return (size_t)W * pt_bytes(id) + (size_t)(W / 4) * face;
 }
 
@@ -893,6 +911,14 @@ int naive_dispatch(void* u, int64_t nx, int64_t nsteps, int32_t id, const double
     switch (id) {
     case SWEPT_HEAT_F64: return run_naive_single<HeatF64>(u, nx, nsteps, heat64_consts(params));
     case SWEPT_HEAT_F32: return run_naive_single<HeatF32>(u, nx, nsteps, heat32_consts(params));
+    case SWEPT_HEAT_F64_FMA:
+        return run_naive_single<HeatFmaF64>(u, nx, nsteps, heat64_consts(params));
+    case SWEPT_HEAT_F32_FMA:
+        return run_naive_single<HeatFmaF32>(u, nx, nsteps, heat32_consts(params));
+    case SWEPT_KS_F64_FMA:
+        return nx >= 1024 * 512
+                   ? run_naive_fused<KSFmaF64, 1024, 512>(u, nx, nsteps, ks_consts(params))
+                   : run_naive_fused<KSFmaF64, 256, 256>(u, nx, nsteps, ks_consts(params));
     // large blocks where the grid still has at least 512 of them (two per CU)
     case SWEPT_EULER_F64:
         return nx >= 256 * 512
@@ -1061,6 +1087,9 @@ int advance_dispatch(void* u, int64_t nx, int64_t nsteps, int32_t id, const doub
     case SWEPT_HEAT_F64: return run_swept<HeatF64>(u, nx, L, heat64_consts(params), p);
     case SWEPT_HEAT_F32: return run_swept<HeatF32>(u, nx, L, heat32_consts(params), p);
     case SWEPT_EULER_F64: return run_swept<EulerF64>(u, nx, L, euler_consts(params), p);
+    case SWEPT_HEAT_F64_FMA: return run_swept<HeatFmaF64>(u, nx, L, heat64_consts(params), p);
+    case SWEPT_HEAT_F32_FMA: return run_swept<HeatFmaF32>(u, nx, L, heat32_consts(params), p);
+    case SWEPT_KS_F64_FMA: return run_swept<KSFmaF64>(u, nx, L, ks_consts(params), p);
     default: return run_swept<KSF64>(u, nx, L, ks_consts(params), p);
     }
 }
@@ -1165,7 +1194,7 @@ int time_best(F&& fn, int reps, double* sec)
 
 size_t field_bytes(int id)
 {
-    switch (id) {
+    switch (base_id(id)) {
     case SWEPT_HEAT_F32: return sizeof(float);
     case SWEPT_EULER_F64: return sizeof(Cons);
     default: return sizeof(double);
@@ -1464,9 +1493,7 @@ int swept_set_tuning(int32_t tile_w, int32_t pairs_per_lane, int32_t mode)
 
 int swept_plan(int64_t nx, int64_t nsteps, int32_t stencil_id, int64_t* out)
 {
-    if (!out || nx < 3 || nsteps < 0 ||
-        (stencil_id != SWEPT_HEAT_F64 && stencil_id != SWEPT_HEAT_F32 &&
-         stencil_id != SWEPT_KS_F64 && stencil_id != SWEPT_EULER_F64))
+    if (!out || nx < 3 || nsteps < 0 || !known_id(stencil_id))
         return fail(SWEPT_EINVAL, "invalid plan request");
     Plan p;
     int rc = make_plan(nx, nsteps, stencil_id, &p);
