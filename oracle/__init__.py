@@ -63,11 +63,13 @@ def lib() -> ctypes.CDLL:
         L.oracle_heat_f64_adjoint.argtypes = [vp, i64, i64, dbl, i64, dbl, vp, vp, i32]
         L.oracle_ks_f64_adjoint.argtypes = [vp, i64, i64, dbl, dbl, i64, dbl, vp, vp, i32]
         L.oracle_euler_f64.argtypes = [vp, i64, i64, dbl, dbl, dbl, i32]
+        L.oracle_ks_f64_tlm.argtypes = [vp, i64, i64, dbl, dbl, i64, dbl, vp, vp, i64, vp, i32]
         L.oracle_heat_fma_f64.argtypes = [vp, i64, i64, dbl, i32]
         L.oracle_heat_fma_f32.argtypes = [vp, i64, i64, flt, i32]
         L.oracle_ks_fma_f64.argtypes = [vp, i64, i64, dbl, dbl, i32]
         for name in ("oracle_heat_f64", "oracle_heat_f32", "oracle_ks_f64",
                      "oracle_heat_fma_f64", "oracle_heat_fma_f32", "oracle_ks_fma_f64",
+                     "oracle_ks_f64_tlm",
                      "oracle_heat_f64_points", "oracle_heat_f32_points",
                      "oracle_ks_f64_points", "oracle_max_threads", "oracle_heat_f64_adjoint",
                      "oracle_ks_f64_adjoint", "oracle_euler_f64"):
@@ -202,6 +204,22 @@ def ks_adjoint(u0, nsteps, dt, dx, n0, wgt, cot_final=None, threads=0):
                                        int(n0), float(wgt), None if cot is None else cot.ctypes.data,
                                        grad.ctypes.data, int(threads)), "oracle_ks_f64_adjoint")
     return grad
+
+
+def ks_tlm(u0, nsteps, dt, dx, n0, wgt, dirs, cot_final=None, threads=0):
+    """<dJ/du0, v> for each row v of dirs (same objective as ks_adjoint), by
+    forward-mode stepping of the KS scheme with its tangent-linear model."""
+    u0 = np.ascontiguousarray(u0, dtype=np.float64)
+    dirs = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
+    if dirs.shape[1] != u0.size:
+        raise ValueError("directions must have the field's length")
+    cot = None if cot_final is None else np.ascontiguousarray(cot_final, dtype=np.float64)
+    out = np.empty(dirs.shape[0])
+    _check(lib().oracle_ks_f64_tlm(u0.ctypes.data, u0.size, int(nsteps), float(dt), float(dx),
+                                   int(n0), float(wgt), None if cot is None else cot.ctypes.data,
+                                   dirs.ctypes.data, dirs.shape[0], out.ctypes.data,
+                                   int(threads)), "oracle_ks_f64_tlm")
+    return out
 
 
 def window_objective(u_steps, wgt):

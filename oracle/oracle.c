@@ -719,6 +719,160 @@ int oracle_ks_f64_adjoint(const double *u0, int64_t n, int64_t nsteps, double dt
     return ORACLE_OK;
 }
 
+/* ------------------------------------------------- KS tangent-linear model */
+/*
+ * Forward-mode derivative of the same objective as the adjoints above along
+ * given directions: each sub-timestep of the KS scheme and its derivative
+ * (the tangent-linear model, no truncation error) are stepped together,
+ *   dw = D2(du)
+ *   dF(a,b; da,db) = -(((da*D1(a) + a*D1(da)) + db) + D2(db))
+ *   dv = du + h*dF(u,w; du,dw),   dz = D2(dv),   du' = du + dt*dF(v,z; dv,dz)
+ * with D1, D2 as in the forward scheme, and
+ *   dJ[q] = sum_{j=n0}^{nsteps} 2*wgt*<u^j, du^j> + <cot_final, du^nsteps>.
+ * The forward values are computed exactly as oracle_ks_f64 computes them.
+ * dirs holds ndirs directions of n points each (row q = direction q).  The
+ * dot products are summed serially with a compensated (Neumaier) sum, so the
+ * result does not depend on the thread count.
+ */
+typedef struct {
+    double s, c;
+} nsum;
+
+static void nsum_add(nsum *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x))
+        a->c += (a->s - t) + x;
+    else
+        a->c += (x - t) + a->s;
+    a->s = t;
+}
+
+static double nsum_val(const nsum *a) { return a->s + a->c; }
+
+/* acc[q] += scale * <x, d[., q]> for every direction q */
+static void tlm_dot(nsum *acc, const double *x, const double *d, int64_t n, int64_t nd,
+                    double scale)
+{
+    int64_t q, i;
+    for (q = 0; q < nd; ++q) {
+        nsum s = {0.0, 0.0};
+        for (i = 0; i < n; ++i)
+            nsum_add(&s, x[i] * d[i * nd + q]);
+        nsum_add(&acc[q], scale * nsum_val(&s));
+    }
+}
+
+/* dF(a,b; da,db) at every point and direction (linear in b, so b is not read) */
+static void tlm_rhs(const double *a, const double *da, const double *db,
+                    int64_t n, int64_t nd, const ks_consts *k, double *out)
+{
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < n; ++i) {
+        const int64_t l = wrap(i - 1, n), r = wrap(i + 1, n);
+        const double d1a = (a[r] - a[l]) * k->c1;
+        int64_t q;
+        for (q = 0; q < nd; ++q) {
+            const double d1da = (da[r * nd + q] - da[l * nd + q]) * k->c1;
+            const double d2db = ((db[l * nd + q] + db[r * nd + q]) - 2.0 * db[i * nd + q]) * k->c2;
+            out[i * nd + q] = -((((da[i * nd + q] * d1a) + (a[i] * d1da)) + db[i * nd + q]) + d2db);
+        }
+    }
+}
+
+static void tlm_d2(const double *a, int64_t n, int64_t nd, const ks_consts *k, double *out)
+{
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < n; ++i) {
+        const int64_t l = wrap(i - 1, n), r = wrap(i + 1, n);
+        int64_t q;
+        for (q = 0; q < nd; ++q)
+            out[i * nd + q] = ((a[l * nd + q] + a[r * nd + q]) - 2.0 * a[i * nd + q]) * k->c2;
+    }
+}
+
+int oracle_ks_f64_tlm(const double *u0, int64_t n, int64_t nsteps, double dt, double dx,
+                      int64_t n0, double wgt, const double *cot_final, const double *dirs,
+                      int64_t ndirs, double *dJ, int nthreads)
+{
+    ks_consts k;
+    double *u, *w, *v, *z, *un, *du, *dw, *dv, *dz, *df;
+    nsum *acc;
+    const double two_w = 2.0 * wgt;
+    int64_t s, i, q;
+    const int64_t nd = ndirs;
+    if (!u0 || !dirs || !dJ || n < 3 || nsteps < 0 || ndirs < 1 || !(dx > 0.0))
+        return ORACLE_EINVAL;
+    set_threads(nthreads);
+    k = ks_make(dt, dx);
+    u = (double *)malloc((size_t)n * sizeof(double));
+    w = (double *)malloc((size_t)n * sizeof(double));
+    v = (double *)malloc((size_t)n * sizeof(double));
+    z = (double *)malloc((size_t)n * sizeof(double));
+    un = (double *)malloc((size_t)n * sizeof(double));
+    du = (double *)malloc((size_t)(n * nd) * sizeof(double));
+    dw = (double *)malloc((size_t)(n * nd) * sizeof(double));
+    dv = (double *)malloc((size_t)(n * nd) * sizeof(double));
+    dz = (double *)malloc((size_t)(n * nd) * sizeof(double));
+    df = (double *)malloc((size_t)(n * nd) * sizeof(double));
+    acc = (nsum *)calloc((size_t)nd, sizeof(nsum));
+    if (!u || !w || !v || !z || !un || !du || !dw || !dv || !dz || !df || !acc) {
+        free(u); free(w); free(v); free(z); free(un);
+        free(du); free(dw); free(dv); free(dz); free(df); free(acc);
+        return ORACLE_ENOMEM;
+    }
+    memcpy(u, u0, (size_t)n * sizeof(double));
+    for (i = 0; i < n; ++i)
+        for (q = 0; q < nd; ++q)
+            du[i * nd + q] = dirs[q * n + i];
+    if (n0 <= 0)
+        tlm_dot(acc, u, du, n, nd, two_w);
+    for (s = 1; s <= nsteps; ++s) {
+        /* sub0: w = D2(u), dw = D2(du) */
+#pragma omp parallel for schedule(static)
+        for (i = 0; i < n; ++i)
+            w[i] = ks_d2(u[wrap(i - 1, n)], u[i], u[wrap(i + 1, n)], &k);
+        tlm_d2(du, n, nd, &k, dw);
+        /* sub1: v = u + h*F(u,w), dv = du + h*dF */
+#pragma omp parallel for schedule(static)
+        for (i = 0; i < n; ++i) {
+            int64_t l = wrap(i - 1, n), r = wrap(i + 1, n);
+            v[i] = u[i] + k.h * ks_rhs(u[l], u[i], u[r], w[l], w[i], w[r], &k);
+        }
+        tlm_rhs(u, du, dw, n, nd, &k, df);
+#pragma omp parallel for schedule(static)
+        for (i = 0; i < n * nd; ++i)
+            dv[i] = du[i] + k.h * df[i];
+        /* sub2: z = D2(v), dz = D2(dv) */
+#pragma omp parallel for schedule(static)
+        for (i = 0; i < n; ++i)
+            z[i] = ks_d2(v[wrap(i - 1, n)], v[i], v[wrap(i + 1, n)], &k);
+        tlm_d2(dv, n, nd, &k, dz);
+        /* sub3: u' = u + dt*F(v,z), du' = du + dt*dF */
+#pragma omp parallel for schedule(static)
+        for (i = 0; i < n; ++i) {
+            int64_t l = wrap(i - 1, n), r = wrap(i + 1, n);
+            un[i] = u[i] + k.dt * ks_rhs(v[l], v[i], v[r], z[l], z[i], z[r], &k);
+        }
+        tlm_rhs(v, dv, dz, n, nd, &k, df);
+#pragma omp parallel for schedule(static)
+        for (i = 0; i < n * nd; ++i)
+            du[i] = du[i] + k.dt * df[i];
+        memcpy(u, un, (size_t)n * sizeof(double));
+        if (s >= n0)
+            tlm_dot(acc, u, du, n, nd, two_w);
+    }
+    if (cot_final)
+        tlm_dot(acc, cot_final, du, n, nd, 1.0);
+    for (q = 0; q < nd; ++q)
+        dJ[q] = nsum_val(&acc[q]);
+    free(u); free(w); free(v); free(z); free(un);
+    free(du); free(dw); free(dv); free(dz); free(df); free(acc);
+    return ORACLE_OK;
+}
+
 /* ------------------------------------------------------------------ Euler */
 
 typedef struct {

@@ -414,6 +414,51 @@ def test_ks_adjoint_matches_forward_mode(oracle_mod, n, nsteps, n0, with_cot):
         assert abs(np.dot(g, v) - dJ) <= 1e-11 * (abs(dJ) + np.abs(g).sum() * np.abs(v).max())
 
 
+@pytest.mark.parametrize("n,nsteps,n0,with_cot", [(16, 5, 2, True), (40, 30, 20, False),
+                                                  (9, 12, 0, True)])
+def test_ks_tlm_matches_dual_numbers(oracle_mod, n, nsteps, n0, with_cot):
+    """The oracle's tangent-linear model along several directions at once
+    against the test's own forward-mode (dual-number) stepping."""
+    g = workloads.rng(200 + n)
+    u0 = 3 * workloads.smoothed_noise(n, seed=n)
+    dirs = g.standard_normal((5, n))
+    cot = g.standard_normal(n) if with_cot else None
+    wgt = 0.37
+    got = oracle_mod.ks_tlm(u0, nsteps, 0.005, 0.5, n0, wgt, dirs, cot, threads=1)
+    for q in range(dirs.shape[0]):
+        _, dJ = _ks_jvp(u0, dirs[q], nsteps, 0.005, 0.5, n0, wgt, cot)
+        assert abs(got[q] - dJ) <= 1e-12 * max(abs(dJ), 1e-300) + 1e-15, (q, got[q], dJ)
+
+
+def test_ks_tlm_against_finite_differences_and_the_adjoint(oracle_mod):
+    """Along random directions the tangent-linear derivative equals a
+    Richardson-extrapolated central difference of the (pinned) forward
+    oracle, and the (pinned) adjoint's <g, v>."""
+    n, nsteps, n0 = 64, 200, 150
+    u0 = 3 * workloads.smoothed_noise(n, seed=9)
+    dirs = workloads.rng(9).standard_normal((3, n))
+    wgt = 1.0 / ((nsteps - n0 + 1) * n)
+    got = oracle_mod.ks_tlm(u0, nsteps, 0.005, 0.5, n0, wgt, dirs, threads=1)
+
+    def J(u):
+        out = 0.0
+        u = oracle_mod.ks(u, n0 - 1, 0.005, 0.5, threads=1)
+        for _ in range(n0, nsteps + 1):
+            u = oracle_mod.ks(u, 1, 0.005, 0.5, threads=1)
+            out += wgt * math.fsum(u * u)
+        return out
+
+    g = oracle_mod.ks_adjoint(u0, nsteps, 0.005, 0.5, n0, wgt, threads=1)
+    for q in range(3):
+        v = dirs[q]
+        e = 1e-4
+        d1 = (J(u0 + e * v) - J(u0 - e * v)) / (2 * e)
+        d2 = (J(u0 + 0.5 * e * v) - J(u0 - 0.5 * e * v)) / e
+        fd = (4 * d2 - d1) / 3
+        assert abs(got[q] - fd) <= 1e-8 * abs(got[q]), (q, got[q], fd)
+        assert abs(got[q] - float(np.dot(g, v))) <= 1e-12 * np.abs(g).sum() * np.abs(v).max()
+
+
 # ------------------------------------------------------------------- Euler
 GAMMA = 1.4
 

@@ -148,6 +148,20 @@ WORKLOADS = {
 }
 
 
+KS_ADJOINT_WINDOW = 2000   # J = mean of u^2 over the final 2,000 steps
+
+
+def adjoint_directions(n: int, count: int = 16, seed: int = 1104) -> np.ndarray:
+    """Seeded unit directions for checks of a gradient: row q is z / |z|_2
+    with z ~ N(0, I) (the q-th draw of n normals)."""
+    g = rng(seed)
+    out = np.empty((count, n))
+    for q in range(count):
+        z = g.standard_normal(n)
+        out[q] = z / np.linalg.norm(z)
+    return out
+
+
 def initial(name: str, dtype=np.float64, n: int | None = None) -> np.ndarray:
     """Initial field of a named workload (optionally at another size n)."""
     w = WORKLOADS[name]
