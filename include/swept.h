@@ -175,6 +175,26 @@ int swept_advance(void *u, int64_t nx, int64_t nsteps, int32_t stencil_id,
                   const double *params, int32_t nparams);
 
 /*
+ * For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the same
+ * as swept_advance (same arguments, plan, kernels and bits), with the scratch
+ * in a fixed array of SWEPT_NOALLOC_SCRATCH_BYTES that the library holds on
+ * each GPU it runs on (from swept_init until the process ends) instead of
+ * memory it allocates.  The call allocates nothing.  It needs
+ * 3 * nx * (point size) bytes on the swept path (point size: 8 for heat f64,
+ * 4 for heat f32, 24 for KS, 72 for Euler; heat f64 up to 5,592,405 points,
+ * KS up to 1,864,135) and nx field elements on the naive path (odd nx, or a
+ * naive tuning); larger requests fail with SWEPT_EINVAL before any work is
+ * enqueued.  Every call on a GPU shares that GPU's array, which keeps the
+ * last call's contents: calls that overlap on one GPU (two streams, or two
+ * threads) race and must be serialised by the caller.  Stage profiling is
+ * ignored during the call.
+ */
+#define SWEPT_NOALLOC_SCRATCH_BYTES (128u << 20)
+int swept_advance_noalloc(void *u, int64_t nx, int64_t nsteps, int32_t stencil_id,
+                          const double *params, int32_t nparams);
+
+/*
  * Advance u by nsteps time steps with one kernel launch per time step
  * (KS: the four sub-timesteps of a step fused in one launch, the halo of
  * each block recomputed).  Same arguments and results as swept_advance.

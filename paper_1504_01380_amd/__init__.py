@@ -23,13 +23,15 @@ LIB_PATH = os.path.join(_HERE, "libswept.so")
 HEAT_F64, HEAT_F32, KS_F64, EULER_F64 = 0, 1, 2, 3
 # the same schemes with their multiply-adds fused (results equal the above to rounding)
 HEAT_F64_FMA, HEAT_F32_FMA, KS_F64_FMA = 4, 5, 6
+NOALLOC_SCRATCH_BYTES = 128 << 20   # SWEPT_NOALLOC_SCRATCH_BYTES
 MODE_AUTO, MODE_STAGE, MODE_NAIVE, MODE_STAGE_BANDED, MODE_STAGE_LANE = 0, 1, 2, 3, 4
 
 _STATUS = {0: "SWEPT_OK", -1: "SWEPT_EINVAL", -2: "SWEPT_ENOTINIT", -3: "SWEPT_ENOMEM",
            -4: "SWEPT_EHIP", -5: "SWEPT_EUNSUPPORTED", -6: "SWEPT_ETIMEOUT"}
 
 EXPORTS = ("swept_init", "swept_set_stream", "swept_set_tuning", "swept_plan",
-           "swept_advance", "swept_naive_advance", "swept_naive_substep_advance",
+           "swept_advance", "swept_advance_noalloc", "swept_naive_advance",
+           "swept_naive_substep_advance",
            "swept_set_profiling", "swept_stage_times", "swept_adjoint", "swept_naive_adjoint",
            "swept_advance_batch",
            "swept_naive_advance_batch", "swept_autotune", "swept_autotune_batch",
@@ -55,7 +57,8 @@ def _load() -> ctypes.CDLL:
     L.swept_set_stream.argtypes = [vp]
     L.swept_set_tuning.argtypes = [i32, i32, i32]
     L.swept_plan.argtypes = [i64, i64, i32, ctypes.POINTER(i64)]
-    for f in (L.swept_advance, L.swept_naive_advance, L.swept_naive_substep_advance):
+    for f in (L.swept_advance, L.swept_advance_noalloc, L.swept_naive_advance,
+              L.swept_naive_substep_advance):
         f.argtypes = [vp, i64, i64, i32, dp, i32]
     L.swept_adjoint.argtypes = [vp, vp, i64, i64, i32, dp, i32, i64, ctypes.c_double, vp]
     L.swept_naive_adjoint.argtypes = L.swept_adjoint.argtypes
@@ -172,6 +175,18 @@ def advance(u: torch.Tensor, nsteps: int, stencil, params: Sequence[float]) -> t
     p, npar = _params(params)
     _check(_lib.swept_advance(ctypes.c_void_p(u.data_ptr()), nx, int(nsteps), sid, p, npar),
            "swept_advance")
+    return u
+
+
+def advance_noalloc(u: torch.Tensor, nsteps: int, stencil, params: Sequence[float]) -> torch.Tensor:
+    """advance() with the library's fixed scratch array: the call allocates no
+    device memory (for graph capture and serving loops); sizes beyond
+    NOALLOC_SCRATCH_BYTES of scratch raise SweptError."""
+    sid = stencil_id(stencil, u.dtype)
+    nx = _prepare(u, sid)
+    p, npar = _params(params)
+    _check(_lib.swept_advance_noalloc(ctypes.c_void_p(u.data_ptr()), nx, int(nsteps), sid, p,
+                                      npar), "swept_advance_noalloc")
     return u
 
 

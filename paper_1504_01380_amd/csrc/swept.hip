@@ -18,6 +18,12 @@
 #include "swept.h"
 #include "kernels.hpp"
 
+// Scratch of swept_advance_noalloc: a fixed array that every GPU the library
+// runs on holds until the process ends.  Host code never uses its name as an
+// address (in host code the name is only a stand-in); it uses the per-device
+// address from hipGetSymbolAddress, taken in swept_init.
+static __device__ __align__(256) unsigned char scratch[SWEPT_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 using namespace swept;
@@ -39,6 +45,12 @@ struct Context {
 
 Context g_ctx;
 thread_local std::string g_err;
+
+// Device address of `scratch` on each device swept_init has selected.
+std::map<int, void*> g_noalloc_ptr;
+// While swept_advance_noalloc runs: the fixed array stands in for the
+// library's growing scratch (nullptr otherwise).
+void* g_fixed = nullptr;
 
 int fail(int code, const char* fmt, ...)
 {
@@ -66,6 +78,14 @@ void batch_release();
 
 int ensure_scratch(size_t bytes)
 {
+    if (g_fixed) {
+        if (bytes > (size_t)SWEPT_NOALLOC_SCRATCH_BYTES)
+            return fail(SWEPT_EINVAL,
+                        "swept_advance_noalloc: this call needs %zu bytes of scratch, the fixed "
+                        "array holds %zu (SWEPT_NOALLOC_SCRATCH_BYTES)",
+                        bytes, (size_t)SWEPT_NOALLOC_SCRATCH_BYTES);
+        return SWEPT_OK;
+    }
     if (bytes <= g_ctx.scratch_bytes)
         return SWEPT_OK;
     if (g_ctx.scratch) {
@@ -85,6 +105,10 @@ int ensure_scratch(size_t bytes)
     g_ctx.scratch_bytes = bytes;
     return SWEPT_OK;
 }
+
+// The scratch the current call works in: the fixed array during
+// swept_advance_noalloc, else the library's allocation.
+void* scratch_base() { return g_fixed ? g_fixed : g_ctx.scratch; }
 
 // ------------------------------------------------------------------ stencils
 
@@ -382,7 +406,7 @@ int run_swept(void* u, int64_t nx, int64_t L, const typename S::Consts& c, const
     int rc = ensure_scratch(3 * edge);
     if (rc)
         return rc;
-    Pt* re = static_cast<Pt*>(g_ctx.scratch);
+    Pt* re = static_cast<Pt*>(scratch_base());
     Pt* le[2] = {re + nx, re + 2 * nx};
     const size_t lds_band = stage_lds<S>(p.W, false), lds_cont = stage_lds<S>(p.W, true);
 
@@ -834,7 +858,7 @@ int run_naive_single(void* u, int64_t nx, int64_t nsteps, const typename S::Cons
     if (rc)
         return rc;
     T* a = static_cast<T*>(u);
-    T* b = static_cast<T*>(g_ctx.scratch);
+    T* b = static_cast<T*>(scratch_base());
     // 16 bytes of points per thread where the length and the field allow
     constexpr int V = 16 / sizeof(T);
     const bool vec = nx % V == 0 && reinterpret_cast<uintptr_t>(u) % 16 == 0;
@@ -863,7 +887,7 @@ int run_naive_fused(void* u, int64_t nx, int64_t nsteps, const typename S::Const
     if (rc)
         return rc;
     T* a = static_cast<T*>(u);
-    T* b = static_cast<T*>(g_ctx.scratch);
+    T* b = static_cast<T*>(scratch_base());
     const unsigned grid = (unsigned)((nx + NB - 1) / NB);
     for (int64_t s = 0; s < nsteps; ++s) {
         hipLaunchKernelGGL((naive_fused_kernel<S, NB, NT>), dim3(grid), dim3(NT), 0, g_ctx.stream,
@@ -885,7 +909,7 @@ int run_naive_substep(void* u, int64_t nx, int64_t nsteps, const typename S::Con
     int rc = ensure_scratch(2 * (size_t)nx * sizeof(Pt));
     if (rc)
         return rc;
-    Pt* a = static_cast<Pt*>(g_ctx.scratch);
+    Pt* a = static_cast<Pt*>(scratch_base());
     Pt* b = a + nx;
     const unsigned grid = grid_for(nx, 256);
     T* uf = static_cast<T*>(u);
@@ -1460,6 +1484,13 @@ int swept_init(int device)
     if (g_ctx.ready && g_ctx.device != device)
         swept_finalize();
     HIP_TRY(hipSetDevice(device));
+    if (g_noalloc_ptr.find(device) == g_noalloc_ptr.end()) {
+        // the fixed scratch array's address on this device (each GPU holds
+        // its own copy); host code uses only this address
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_noalloc_ptr[device] = p;
+    }
     g_ctx.ready = true;
     g_ctx.device = device;
     g_ctx.stream = nullptr;
@@ -1514,6 +1545,33 @@ int swept_advance(void* u, int64_t nx, int64_t nsteps, int32_t stencil_id, const
     int rc = check_common(u, nx, nsteps, stencil_id, params, nparams);
     if (rc)
         return rc;
+    return advance_dispatch(u, nx, nsteps, stencil_id, params);
+}
+
+int swept_advance_noalloc(void* u, int64_t nx, int64_t nsteps, int32_t stencil_id,
+                          const double* params, int32_t nparams)
+{
+    int rc = check_common(u, nx, nsteps, stencil_id, params, nparams);
+    if (rc)
+        return rc;
+    const auto it = g_noalloc_ptr.find(g_ctx.device);
+    if (it == g_noalloc_ptr.end() || !it->second)
+        return fail(SWEPT_ENOTINIT, "no fixed scratch address for device %d", g_ctx.device);
+    // the fixed array replaces the growing scratch for this call; stage
+    // profiling (which creates events) is off during it
+    struct Fixed {
+        bool prof = g_ctx.profiling;
+        explicit Fixed(void* p)
+        {
+            g_fixed = p;
+            g_ctx.profiling = false;
+        }
+        ~Fixed()
+        {
+            g_fixed = nullptr;
+            g_ctx.profiling = prof;
+        }
+    } fixed(it->second);
     return advance_dispatch(u, nx, nsteps, stencil_id, params);
 }
 
