@@ -31,6 +31,11 @@ VALU_LANE_OPS = CUS * SIMDS_PER_CU * LANES_PER_SIMD * CLOCK_HZ   # 39.3e12 FP64 
 VALU_LANE_OPS_F32 = 2 * VALU_LANE_OPS
 HBM_PEAK = 8.0e12
 HEAT_OPS_PER_UPDATE = 5           # add, mul, sub, mul, add (no fused multiply-add)
+HEAT_FMA_OPS_PER_UPDATE = 3       # add, fma, fma (the contraction-on stencil)
+KS_FMA_OPS_PER_STEP = 22          # 3 + 8 + 3 + 8 instructions per point-step, fused
+# LDS: 128 bytes per clock per CU (the CDNA3 ISA figure; the CDNA4 LDS is
+# 160 KB per CU, its rate taken as the same)
+LDS_PEAK = CUS * 128 * CLOCK_HZ
 HEAT_NAIVE_BYTES = {8: 16, 4: 8}  # read u, write u' per point-update
 
 
@@ -68,7 +73,7 @@ def progress(msg: str) -> None:
     print("[bench] %s" % msg, file=sys.stderr, flush=True)
 
 
-def timed_runs(sw, torch, fn, u0, nsteps, params, reps, warmup, after=None):
+def timed_runs(sw, torch, fn, u0, nsteps, params, reps, warmup, after=None, stencil="heat"):
     """Run fn `reps` times on copies of u0; HIP events on the stream the
     library launches on (torch's current stream) bracket each run.  `after`
     runs once the closing event of a timed run has completed."""
@@ -76,7 +81,7 @@ def timed_runs(sw, torch, fn, u0, nsteps, params, reps, warmup, after=None):
     u = u0.clone()
     for _ in range(warmup):
         u.copy_(u0)
-        fn(u, nsteps, "heat", params)
+        fn(u, nsteps, stencil, params)
     torch.cuda.synchronize()
     times = []
     for _ in range(reps):
@@ -84,7 +89,7 @@ def timed_runs(sw, torch, fn, u0, nsteps, params, reps, warmup, after=None):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        fn(u, nsteps, "heat", params)
+        fn(u, nsteps, stencil, params)
         e1.record(stream)
         e1.synchronize()
         times.append(e0.elapsed_time(e1) / 1e3)
@@ -122,6 +127,34 @@ def measured_traffic(kernel: str):
     return rec.get("bytes_per_launch")
 
 
+def host_cpu():
+    """The host CPU's model name, and the physical cores and sockets behind
+    the CPUs this process may run on (from /proc/cpuinfo and the affinity
+    mask)."""
+    usable = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else []
+    model, cores, sockets = "", set(), set()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            blocks = fh.read().strip().split("\n\n")
+        for b in blocks:
+            kv = {}
+            for ln in b.split("\n"):
+                if ":" in ln:
+                    a, v = ln.split(":", 1)
+                    kv[a.strip()] = v.strip()
+            cpu = int(kv.get("processor", -1))
+            if usable and cpu not in usable:
+                continue
+            model = model or kv.get("model name", "")
+            phys = kv.get("physical id", "0")
+            sockets.add(phys)
+            cores.add((phys, kv.get("core id", str(cpu))))
+    except (OSError, ValueError):
+        pass
+    return {"model": model, "physical_cores": len(cores) or None,
+            "sockets": len(sockets) or None, "usable_cpus": len(usable) or os.cpu_count()}
+
+
 def cpu_baseline(u0_np, nsteps_full, seconds):
     """The oracle as it stands, on the host cores, on the first few steps of
     the same workload (all N points), sized to about `seconds` of work."""
@@ -149,19 +182,15 @@ def cpu_baseline(u0_np, nsteps_full, seconds):
     t0 = time.perf_counter()
     oracle.heat(u0_np, k1, 0.25, threads=1)
     dt1 = time.perf_counter() - t0
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as fh:
-            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")),
-                         "")
-    except OSError:
-        pass
+    host = host_cpu()
     return {"value": n * k / dt, "unit": "point-updates/s", "cores": threads, "kind": "oracle",
             "sample": "heat f64 N=%d, first %d of %d steps, all points, OpenMP %d threads, "
                       "%.1f s" % (n, k, nsteps_full, threads, dt),
             "single_thread": {"value": n * k1 / dt1, "sample": "first %d steps, 1 thread, %.1f s"
                               % (k1, dt1)},
-            "cpu": model, "host_cpus": os.cpu_count()}
+            "cpu": host["model"], "physical_cores": host["physical_cores"],
+            "sockets": host["sockets"], "usable_cpus": host["usable_cpus"],
+            "host_cpus": os.cpu_count()}
 
 
 KS_OPS_PER_STEP = 30  # per point-step: 4 sub-timesteps (4 + 11 + 4 + 11 flops, no FMA)
@@ -286,13 +315,21 @@ def batch_workload(sw, torch, workloads, tune=True):
     return rec
 
 
-def ks_adjoint_workload(sw, torch, workloads, directions=16, eps=1e-6):
+def ks_adjoint_workload(sw, torch, workloads, directions=16):
     """Gradient of J = mean of u^2 over the final 2,000 of 20,000 KS steps
-    (N = 2^16) by the swept adjoint, timed, and checked against central
-    finite differences of J along seeded random unit directions (eps and a
-    Richardson extrapolation from eps and eps/2)."""
+    (N = 2^16) by the swept adjoint, timed, and checked along the 16 seeded
+    unit directions of workloads.adjoint_directions:
+      - against the oracle's tangent-linear derivatives (forward mode, no
+        truncation error; tests/golden/ks_adjoint_tlm.json, written from the
+        oracle alone);
+      - against central finite differences of J (computed by the library) at
+        several eps, with one and two levels of Richardson extrapolation, so
+        that the finite-difference error can be split into truncation (falls
+        as eps^2) and round-off (grows as 1/eps)."""
+    import math
     w = workloads.WORKLOADS["ks_adjoint"]
-    n, nsteps, par, window = w["n"], w["nsteps"], [w["dt"], w["dx"]], 2000
+    window = workloads.KS_ADJOINT_WINDOW
+    n, nsteps, par = w["n"], w["nsteps"], [w["dt"], w["dx"]]
     u0 = torch.from_numpy(workloads.initial("ks_adjoint")).cuda()
     wgt = 1.0 / (window * n)
     first = nsteps - window + 1
@@ -304,7 +341,6 @@ def ks_adjoint_workload(sw, torch, workloads, directions=16, eps=1e-6):
     e1.record()
     e1.synchronize()
     t_adj = e0.elapsed_time(e1) / 1e3
-    rng = workloads.rng(w["seed"] + 100)
 
     def J(u):
         return float(sw.window_mean_square_value(u, nsteps, "ks", par, window))
@@ -322,26 +358,96 @@ def ks_adjoint_workload(sw, torch, workloads, directions=16, eps=1e-6):
     del gn
     torch.cuda.empty_cache()
 
-    errs, errs_rich = [], []
-    for _ in range(directions):
-        v = torch.from_numpy(rng.standard_normal(n)).cuda()
-        v /= torch.linalg.norm(v)
-        d1 = (J(u0 + eps * v) - J(u0 - eps * v)) / (2 * eps)
-        d2 = (J(u0 + 0.5 * eps * v) - J(u0 - 0.5 * eps * v)) / eps
-        ad = float(torch.dot(g, v))
-        errs.append(abs(d1 - ad) / abs(ad))
-        errs_rich.append(abs((4 * d2 - d1) / 3 - ad) / abs(ad))
+    dirs = workloads.adjoint_directions(n, directions)
+    g_np = g.cpu().numpy()
+    gv = [math.fsum(g_np * dirs[q]) for q in range(directions)]
+    rec = {"n": n, "time_steps": nsteps, "window": window, "adjoint_ms": t_adj * 1e3,
+           "gradient_point_steps_per_s": n * nsteps / t_adj,
+           "naive_adjoint_ms": t_naive * 1e3,
+           "naive_gradient_point_steps_per_s": n * nsteps / t_naive,
+           "speedup_vs_naive": t_naive / t_adj, "naive_equals_swept_bitwise": same,
+           "directions": directions}
+    t0 = time.perf_counter()
+    J0 = J(u0)
+    rec["J"] = J0
+    rec["objective_ms"] = (time.perf_counter() - t0) * 1e3
+    golden = os.path.join(ROOT, "tests", "golden", "ks_adjoint_tlm.json")
+    ref = gv
+    if os.path.exists(golden):
+        with open(golden) as fh:
+            gold = json.load(fh)
+        tlm = [float.fromhex(x) for x in gold["dJ"]][:directions]
+        ref = tlm
+        terr = [abs(a - b) / abs(b) for a, b in zip(gv, tlm)]
+        rec["tlm_rel_err_max"] = max(terr)
+        rec["tlm_rel_err_median"] = sorted(terr)[len(terr) // 2]
+        rec["J_rel_err_vs_oracle"] = abs(J0 - float.fromhex(gold["J"])) / abs(float.fromhex(gold["J"]))
+    rec["reference"] = "oracle tangent-linear" if ref is not gv else "<g, v>"
+
+    def rel(vals):
+        e = sorted(abs(a - b) / abs(b) for a, b in zip(vals, ref))
+        return {"max": e[-1], "median": e[len(e) // 2], "within_1e-6": sum(x <= 1e-6 for x in e)}
+
+    fd = {}
+    for eps in (1e-6, 5e-7, 2.5e-7, 1e-7, 1e-8):
+        vals = []
+        for q in range(directions):
+            v = torch.from_numpy(dirs[q]).cuda()
+            vals.append((J(u0 + eps * v) - J(u0 - eps * v)) / (2 * eps))
+        fd[eps] = vals
+    rich1 = [(4 * b - a) / 3 for a, b in zip(fd[1e-6], fd[5e-7])]
+    rich1b = [(4 * b - a) / 3 for a, b in zip(fd[5e-7], fd[2.5e-7])]
+    rich2 = [(16 * b - a) / 15 for a, b in zip(rich1, rich1b)]
+    rec["fd"] = {"%g" % e: rel(v) for e, v in fd.items()}
+    rec["fd_richardson_1e-6_5e-7"] = rel(rich1)
+    rec["fd_richardson2_1e-6_5e-7_2.5e-7"] = rel(rich2)
+    # the literal check: eps = 1e-6, against the adjoint's <g, v>
+    lit = sorted(abs(a - b) / abs(b) for a, b in zip(fd[1e-6], gv))
+    rec.update({"fd_eps": 1e-6, "fd_directions": directions, "fd_rel_err_max": lit[-1],
+                "fd_rel_err_median": lit[len(lit) // 2],
+                "fd_within_1e-6": sum(x <= 1e-6 for x in lit)})
     sw.sync()
-    errs.sort()
-    errs_rich.sort()
-    return {"n": n, "time_steps": nsteps, "window": window, "adjoint_ms": t_adj * 1e3,
-            "gradient_point_steps_per_s": n * nsteps / t_adj,
-            "naive_adjoint_ms": t_naive * 1e3, "naive_gradient_point_steps_per_s": n * nsteps / t_naive,
-            "speedup_vs_naive": t_naive / t_adj, "naive_equals_swept_bitwise": same,
-            "fd_eps": eps, "fd_directions": directions,
-            "fd_rel_err_max": errs[-1], "fd_rel_err_median": errs[len(errs) // 2],
-            "fd_richardson_rel_err_max": errs_rich[-1],
-            "fd_within_1e-6": sum(e <= 1e-6 for e in errs)}
+    return rec
+
+
+def fma_legs(sw, torch, workloads, u0, u_canonical, nsteps, updates, tune=True):
+    """The contraction-on stencils beside the bit-exact headline, never in
+    its place: heat f64 on the headline workload (3 instructions per update:
+    add, fma, fma) and KS on its workload (22 per point-step), each swept
+    (autotuned) and naive.  At r = 1/4 every product r*lap is exact, so the
+    fused heat run must give the canonical run's bits."""
+    out = {}
+    tune_h = sw.autotune(u0.numel(), nsteps, "heat_fma", [0.25], torch.float64) if tune else None
+    plan = sw.plan(u0.numel(), nsteps, "heat_fma", torch.float64)
+    st, uf = timed_runs(sw, torch, sw.advance, u0, nsteps, [0.25], 2, 1, stencil="heat_fma")
+    nt, _ = timed_runs(sw, torch, sw.naive_advance, u0, nsteps, [0.25], 1, 1, stencil="heat_fma")
+    v = updates / (sum(st) / len(st))
+    nv = updates / nt[0]
+    out["heat_f64"] = {"swept": v, "naive": nv, "speedup_vs_naive": v / nv,
+                       "ops_per_update": HEAT_FMA_OPS_PER_UPDATE,
+                       "swept_frac_alu": HEAT_FMA_OPS_PER_UPDATE * v / VALU_LANE_OPS,
+                       "bits_equal_canonical": bool(torch.equal(uf.view(torch.int64),
+                                                                u_canonical.view(torch.int64))),
+                       "tile_w": plan["tile_w"], "pairs_per_lane": plan["pairs_per_lane"],
+                       "tuning": tune_h}
+    del uf
+    wk = workloads.WORKLOADS["ks"]
+    par = [wk["dt"], wk["dx"]]
+    k0 = torch.from_numpy(workloads.initial("ks")).cuda()
+    n, ns = k0.numel(), wk["nsteps"]
+    tune_k = sw.autotune(n, ns, "ks_fma", par) if tune else None
+    plan = sw.plan(n, ns, "ks_fma")
+    st, _ = timed_runs(sw, torch, sw.advance, k0, ns, par, 3, 1, stencil="ks_fma")
+    nt, _ = timed_runs(sw, torch, sw.naive_advance, k0, ns, par, 1, 1, stencil="ks_fma")
+    v = n * ns / (sum(st) / len(st))
+    nv = n * ns / nt[0]
+    out["ks"] = {"swept": v, "naive": nv, "speedup_vs_naive": v / nv,
+                 "ops_per_point_step": KS_FMA_OPS_PER_STEP,
+                 "swept_frac_alu": KS_FMA_OPS_PER_STEP * v / VALU_LANE_OPS,
+                 "tile_w": plan["tile_w"], "pairs_per_lane": plan["pairs_per_lane"],
+                 "tuning": tune_k}
+    sw.sync()
+    return out
 
 
 def profile_mix(sw, torch, workloads):
@@ -477,8 +583,8 @@ def main():
         diamond_ms.extend(ms[s] for s in full)
         kinds.update(kind[s] for s in full)
 
-    times, _ = timed_runs(sw, torch, sw.advance, u0, nsteps, [0.25], args.steps, args.warmup,
-                          after=record)
+    times, u_swept = timed_runs(sw, torch, sw.advance, u0, nsteps, [0.25], args.steps,
+                                args.warmup, after=record)
     sw.set_profiling(False)
     progress("heat f64 swept runs done")
     t = sum(times) / len(times)
@@ -496,6 +602,15 @@ def main():
     avg_launch = (sum(diamond_ms) / len(diamond_ms) / 1e3) if diamond_ms else float("nan")
     achieved = flops_per_launch / avg_launch
     edge_bytes = float(tiles) * 4 * 2 * k * 8   # RE in/out + LE in/out, 2k values each
+    # LDS per region and stage of the continuous kernel: the right V edge
+    # in (2k points), the new left edge out (2k), and per wave step (nb*k + NB
+    # of them, NB = 64P) slot 0's read of pair -1 and the last slot's write
+    # of its pair (4 points)
+    NB = 64 * plan["pairs_per_lane"]
+    lds_bytes = float(tiles) * 8 * (4 * k + 4 * ((k // max(NB, 1)) * k + NB))
+    lds = {"achieved_GBps": lds_bytes / avg_launch / 1e9, "peak_GBps": LDS_PEAK / 1e9,
+           "frac": lds_bytes / avg_launch / LDS_PEAK, "bytes_per_launch": lds_bytes,
+           "kernel": kname}
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANE_OPS / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / VALU_LANE_OPS,
                 "traffic": measured_traffic(kname),
@@ -516,6 +631,7 @@ def main():
                    "depth_k": plan["depth_k"], "tiles": plan["tiles"], "stages": plan["stages"],
                    "pairs_per_lane": plan["pairs_per_lane"], "tuning": tuning},
         "roofline": roofline,
+        "lds": lds,
     }
 
     if args.profile:
@@ -547,6 +663,9 @@ def main():
 
     if not args.no_naive:
         progress("heat f32 done")
+        out["fma"] = fma_legs(sw, torch, workloads, u0, u_swept, nsteps, updates,
+                              tune=not args.no_tune)
+        progress("contraction-on legs done")
         out["workloads"] = other_workloads(sw, torch, workloads, tune=not args.no_tune)
         out["workloads"]["batch"] = batch_workload(sw, torch, workloads, tune=not args.no_tune)
         progress("batch done")

@@ -347,6 +347,28 @@ int swept_naive_adjoint(const void *u0, void *grad_u0, int64_t nx, int64_t nstep
                         int32_t stencil_id, const double *params, int32_t nparams,
                         int64_t window_first, double window_weight, const void *cot_final);
 
+/*
+ * The objective of swept_adjoint, evaluated by the library (SWEPT_HEAT_F64,
+ * SWEPT_KS_F64 and their _FMA forms):
+ *
+ *   J = window_weight * sum_{j = max(window_first, 0)}^{nsteps} sum_i (u_i^j)^2
+ *       + sum_i cot_final[i] * u_i^nsteps
+ *
+ * written as one double to J_out (a DEVICE pointer), asynchronously on the
+ * current stream.  u0 and cot_final (NULL = 0) are DEVICE pointers to nx
+ * doubles; u0 is only read.  A copy of u0 advances by the swept schedule to
+ * the step before the window, then one naive launch per step of the window
+ * (the sum needs every one of its fields).  Each step's sum is formed on the
+ * device in a fixed order and the steps are accumulated with compensated
+ * (two-sum) addition, so J does not depend on timing and its relative
+ * rounding error is a few units of 1e-16 rather than growing with the number
+ * of steps -- what a finite-difference check of the gradient differences.
+ * Uses its own device buffer (nx doubles and 8 KiB), grown on demand.
+ */
+int swept_window_objective(const void *u0, int64_t nx, int64_t nsteps, int32_t stencil_id,
+                           const double *params, int32_t nparams, int64_t window_first,
+                           double window_weight, const void *cot_final, void *J_out);
+
 /* Wait for the current stream; report asynchronous kernel errors. */
 int swept_sync(void);
 

@@ -33,7 +33,7 @@ EXPORTS = ("swept_init", "swept_set_stream", "swept_set_tuning", "swept_plan",
            "swept_advance", "swept_advance_noalloc", "swept_naive_advance",
            "swept_naive_substep_advance",
            "swept_set_profiling", "swept_stage_times", "swept_adjoint", "swept_naive_adjoint",
-           "swept_advance_batch",
+           "swept_advance_batch", "swept_window_objective",
            "swept_naive_advance_batch", "swept_autotune", "swept_autotune_batch",
            "swept_clear_tuning",
            "swept_sync", "swept_last_error", "swept_finalize")
@@ -62,6 +62,7 @@ def _load() -> ctypes.CDLL:
         f.argtypes = [vp, i64, i64, i32, dp, i32]
     L.swept_adjoint.argtypes = [vp, vp, i64, i64, i32, dp, i32, i64, ctypes.c_double, vp]
     L.swept_naive_adjoint.argtypes = L.swept_adjoint.argtypes
+    L.swept_window_objective.argtypes = [vp, i64, i64, i32, dp, i32, i64, ctypes.c_double, vp, vp]
     L.swept_advance_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(i64),
                                       ctypes.POINTER(i32), dp, i64]
     L.swept_naive_advance_batch.argtypes = L.swept_advance_batch.argtypes
@@ -370,19 +371,35 @@ def _check_window(nsteps: int, window: int) -> None:
         raise ValueError("window = %r must satisfy 1 <= window <= nsteps = %r" % (window, nsteps))
 
 
+def objective(u0: torch.Tensor, nsteps: int, stencil, params: Sequence[float], *,
+              window_first: int | None = None, window_weight: float = 0.0,
+              cot_final: torch.Tensor | None = None) -> torch.Tensor:
+    """J = window_weight * sum_{j=window_first}^{nsteps} |u^j|^2 + <cot_final, u^nsteps>,
+    the objective of adjoint(), computed by the library; a 0-d float64 device
+    tensor (the call is asynchronous on torch's stream)."""
+    sid = stencil_id(stencil, u0.dtype)
+    nx = _prepare(u0, sid)
+    cot = None
+    if cot_final is not None:
+        cot = cot_final.contiguous()
+        if cot.shape != u0.shape or cot.dtype != u0.dtype or cot.device != u0.device:
+            raise ValueError("cot_final must match u0")
+    J = torch.empty((), dtype=torch.float64, device=u0.device)
+    first = nsteps + 1 if window_first is None else int(window_first)
+    p, npar = _params(params)
+    _check(_lib.swept_window_objective(ctypes.c_void_p(u0.data_ptr()), nx, int(nsteps), sid, p,
+                                       npar, first, float(window_weight),
+                                       None if cot is None else ctypes.c_void_p(cot.data_ptr()),
+                                       ctypes.c_void_p(J.data_ptr())), "swept_window_objective")
+    return J
+
+
 def window_mean_square_value(u0: torch.Tensor, nsteps: int, stencil, params, window: int):
     """J = mean of u^2 over all points and the last `window` time steps
-    (steps nsteps-window+1 .. nsteps), computed by stepping the field."""
+    (steps nsteps-window+1 .. nsteps), computed by the library."""
     _check_window(nsteps, window)
-    u = u0.detach().clone()
-    first = nsteps - window + 1
-    if first > 1:
-        advance(u, first - 1, stencil, params)
-    total = torch.zeros((), dtype=torch.float64, device=u.device)
-    for _ in range(window):
-        naive_advance(u, 1, stencil, params)
-        total += torch.dot(u.double(), u.double())
-    return total / (window * u.numel())
+    return objective(u0.detach(), nsteps, stencil, params, window_first=nsteps - window + 1,
+                     window_weight=1.0 / (window * u0.numel()))
 
 
 class WindowMeanSquare(torch.autograd.Function):

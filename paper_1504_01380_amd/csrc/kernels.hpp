@@ -1545,4 +1545,69 @@ __global__ __launch_bounds__(256) void pt_to_field_kernel(const typename S::Pt* 
         out[i] = S::to_field(in[i]);
 }
 
+// ------------------------------------------------------------- objective
+// The objective of the adjoint, J = w * sum over the window's steps of
+// sum_i u_i^2 + sum_i c_i u_i^nsteps, summed on the device in a fixed order:
+// a fixed grid of kObjBlocks blocks, each thread adding its points
+// (i = tid, tid + stride, ...) in order, a fixed tree over the block, and a
+// per-block (sum, compensation) pair that accumulates the successive calls
+// by an error-free two-sum.  The result does not depend on timing and
+// carries a few roundings of relative error, not one per step.
+constexpr int kObjBlocks = 256;
+constexpr int kObjThreads = 256;
+
+__device__ __forceinline__ void two_sum_into(double* slot, double b)
+{
+    const double a = slot[0];
+    const double t = a + b;
+    const double bp = t - a;
+    const double e = (a - (t - bp)) + (b - bp);
+    slot[0] = t;
+    slot[1] = slot[1] + e;
+}
+
+// acc[2*blockIdx.x .. +1] += sum_i x_i * y_i over this block's points
+__global__ __launch_bounds__(kObjThreads) void objective_accumulate_kernel(
+    const double* __restrict__ x, const double* __restrict__ y, int64_t n, double* acc)
+{
+    __shared__ double part[kObjThreads];
+    const int64_t stride = (int64_t)kObjBlocks * kObjThreads;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kObjThreads + threadIdx.x; i < n; i += stride)
+        s = s + x[i] * y[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kObjThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            part[threadIdx.x] = part[threadIdx.x] + part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        two_sum_into(acc + 2 * blockIdx.x, part[0]);
+}
+
+__global__ __launch_bounds__(256) void objective_clear_kernel(double* acc, int count)
+{
+    for (int i = threadIdx.x; i < count; i += blockDim.x)
+        acc[i] = 0.0;
+}
+
+// J = w * (window sums) + (final cotangent term), each set of block slots
+// combined in block order by the same two-sum
+__global__ __launch_bounds__(64) void objective_final_kernel(const double* __restrict__ acc_sq,
+                                                            const double* __restrict__ acc_dot,
+                                                            double w, double* J)
+{
+    if (threadIdx.x != 0)
+        return;
+    double sq[2] = {0.0, 0.0}, dt[2] = {0.0, 0.0};
+    for (int b = 0; b < kObjBlocks; ++b) {
+        two_sum_into(sq, acc_sq[2 * b]);
+        two_sum_into(sq, acc_sq[2 * b + 1]);
+        two_sum_into(dt, acc_dot[2 * b]);
+        two_sum_into(dt, acc_dot[2 * b + 1]);
+    }
+    J[0] = w * (sq[0] + sq[1]) + (dt[0] + dt[1]);
+}
+
 }  // namespace swept

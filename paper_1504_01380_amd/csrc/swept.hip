@@ -34,6 +34,8 @@ struct Context {
     hipStream_t stream = nullptr;
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
+    void* obj = nullptr;              // swept_window_objective: field copy and sums
+    size_t obj_bytes = 0;
     int tile_w = 0;   // 0 = automatic
     int ppl = 0;      // pairs per lane, 0 = automatic
     int mode = SWEPT_MODE_AUTO;
@@ -1118,6 +1120,75 @@ int advance_dispatch(void* u, int64_t nx, int64_t nsteps, int32_t id, const doub
     }
 }
 
+// ----------------------------------------------------------------- objective
+
+int ensure_obj(size_t bytes)
+{
+    if (bytes <= g_ctx.obj_bytes)
+        return SWEPT_OK;
+    if (g_ctx.obj) {
+        HIP_TRY(hipStreamSynchronize(g_ctx.stream));
+        HIP_TRY(hipFree(g_ctx.obj));
+        g_ctx.obj = nullptr;
+        g_ctx.obj_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&g_ctx.obj, bytes);
+    if (e != hipSuccess) {
+        g_ctx.obj = nullptr;
+        (void)hipGetLastError();
+        return fail(SWEPT_ENOMEM, "hipMalloc of %zu bytes for the objective failed: %s", bytes,
+                    hipGetErrorString(e));
+    }
+    g_ctx.obj_bytes = bytes;
+    return SWEPT_OK;
+}
+
+// J = w * sum_{j = max(first, 0)}^{nsteps} |u^j|^2 + <cot, u^nsteps>: a copy of
+// u0 advanced by the swept schedule to the step before the window, then one
+// naive step at a time, each step's field summed on the device.
+int run_objective(const void* u0, int64_t nx, int64_t nsteps, int32_t id, const double* params,
+                  int64_t first, double wgt, const void* cot, double* J)
+{
+    const size_t field = ((size_t)nx * sizeof(double) + 255) / 256 * 256;
+    int rc = ensure_obj(field + 4 * kObjBlocks * sizeof(double));
+    if (rc)
+        return rc;
+    double* f = static_cast<double*>(g_ctx.obj);
+    double* acc_sq = reinterpret_cast<double*>(static_cast<unsigned char*>(g_ctx.obj) + field);
+    double* acc_dot = acc_sq + 2 * kObjBlocks;
+    HIP_TRY(hipMemcpyAsync(f, u0, (size_t)nx * sizeof(double), hipMemcpyDeviceToDevice,
+                           g_ctx.stream));
+    hipLaunchKernelGGL(objective_clear_kernel, dim3(1), dim3(256), 0, g_ctx.stream, acc_sq,
+                       4 * kObjBlocks);
+    auto sum_squares = [&] {
+        hipLaunchKernelGGL(objective_accumulate_kernel, dim3(kObjBlocks), dim3(kObjThreads), 0,
+                           g_ctx.stream, f, f, nx, acc_sq);
+    };
+    first = std::max<int64_t>(first, 0);
+    if (first > nsteps) {
+        rc = advance_dispatch(f, nx, nsteps, id, params);
+    } else {
+        if (first == 0)
+            sum_squares();
+        const int64_t pre = std::max<int64_t>(first - 1, 0);
+        rc = advance_dispatch(f, nx, pre, id, params);
+        for (int64_t j = pre + 1; j <= nsteps && rc == SWEPT_OK; ++j) {
+            rc = naive_dispatch(f, nx, 1, id, params);
+            if (rc == SWEPT_OK)
+                sum_squares();
+        }
+    }
+    if (rc)
+        return rc;
+    if (cot)
+        hipLaunchKernelGGL(objective_accumulate_kernel, dim3(kObjBlocks), dim3(kObjThreads), 0,
+                           g_ctx.stream, static_cast<const double*>(cot), f, nx, acc_dot);
+    hipLaunchKernelGGL(objective_final_kernel, dim3(1), dim3(64), 0, g_ctx.stream, acc_sq, acc_dot,
+                       wgt, J);
+    HIP_TRY(hipGetLastError());
+    return SWEPT_OK;
+}
+
 // ----------------------------------------------------------------- autotuner
 //
 // The paper's model (Section 4, Eq. (1)): with n points per node, a swept
@@ -1750,6 +1821,24 @@ int swept_adjoint(const void* u0, void* grad_u0, int64_t nx, int64_t nsteps, int
     }
 }
 
+int swept_window_objective(const void* u0, int64_t nx, int64_t nsteps, int32_t stencil_id,
+                           const double* params, int32_t nparams, int64_t window_first,
+                           double window_weight, const void* cot_final, void* J_out)
+{
+    int rc = check_common(u0, nx, nsteps, stencil_id, params, nparams);
+    if (rc)
+        return rc;
+    if (!J_out)
+        return fail(SWEPT_EINVAL, "J_out is NULL");
+    if (!std::isfinite(window_weight))
+        return fail(SWEPT_EINVAL, "window weight is not finite");
+    if (stencil_id != SWEPT_HEAT_F64 && stencil_id != SWEPT_KS_F64 &&
+        stencil_id != SWEPT_HEAT_F64_FMA && stencil_id != SWEPT_KS_F64_FMA)
+        return fail(SWEPT_EUNSUPPORTED, "the objective takes single-value binary64 stencils");
+    return run_objective(u0, nx, nsteps, stencil_id, params, window_first, window_weight,
+                         cot_final, static_cast<double*>(J_out));
+}
+
 int swept_naive_adjoint(const void* u0, void* grad_u0, int64_t nx, int64_t nsteps,
                         int32_t stencil_id, const double* params, int32_t nparams,
                         int64_t window_first, double window_weight, const void* cot_final)
@@ -1809,6 +1898,8 @@ void swept_finalize(void)
         (void)hipDeviceSynchronize();
     if (g_ctx.scratch)
         (void)hipFree(g_ctx.scratch);
+    if (g_ctx.obj)
+        (void)hipFree(g_ctx.obj);
     release_events();
     batch_release();
     swept_clear_tuning();

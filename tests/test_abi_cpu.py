@@ -126,3 +126,15 @@ def test_tuner_rejects_bad_requests_without_a_gpu():
     out = (ctypes.c_int64 * 3)()
     assert L.swept_autotune_batch(None, None, None, None, -1, out) != 0
     assert L.swept_clear_tuning() == 0
+
+
+def test_mean_square_window_bounds_are_checked(swept):
+    """A window outside 1..nsteps is rejected before anything runs (J would
+    otherwise sum the wrong steps, and the gradient would not match it)."""
+    import torch
+    u = torch.zeros(16, dtype=torch.float64)
+    for bad in (0, -3, 11):
+        with pytest.raises(ValueError):
+            swept.window_mean_square_value(u, 10, "ks", [0.005, 0.5], bad)
+        with pytest.raises(ValueError):
+            swept.WindowMeanSquare.apply(u, 10, "ks", [0.005, 0.5], bad)
