@@ -389,7 +389,7 @@ def ks_adjoint_workload(sw, torch, workloads, directions=16):
         return {"max": e[-1], "median": e[len(e) // 2], "within_1e-6": sum(x <= 1e-6 for x in e)}
 
     fd = {}
-    for eps in (1e-6, 5e-7, 2.5e-7, 1e-7, 1e-8):
+    for eps in (1e-6, 5e-7, 2.5e-7, 1.25e-7, 1e-7, 1e-8):
         vals = []
         for q in range(directions):
             v = torch.from_numpy(dirs[q]).cuda()
@@ -397,10 +397,14 @@ def ks_adjoint_workload(sw, torch, workloads, directions=16):
         fd[eps] = vals
     rich1 = [(4 * b - a) / 3 for a, b in zip(fd[1e-6], fd[5e-7])]
     rich1b = [(4 * b - a) / 3 for a, b in zip(fd[5e-7], fd[2.5e-7])]
+    rich1c = [(4 * b - a) / 3 for a, b in zip(fd[2.5e-7], fd[1.25e-7])]
     rich2 = [(16 * b - a) / 15 for a, b in zip(rich1, rich1b)]
+    rich2b = [(16 * b - a) / 15 for a, b in zip(rich1b, rich1c)]
+    rich3 = [(64 * b - a) / 63 for a, b in zip(rich2, rich2b)]
     rec["fd"] = {"%g" % e: rel(v) for e, v in fd.items()}
     rec["fd_richardson_1e-6_5e-7"] = rel(rich1)
     rec["fd_richardson2_1e-6_5e-7_2.5e-7"] = rel(rich2)
+    rec["fd_richardson3_1e-6_to_1.25e-7"] = rel(rich3)
     # the literal check: eps = 1e-6, against the adjoint's <g, v>
     lit = sorted(abs(a - b) / abs(b) for a, b in zip(fd[1e-6], gv))
     rec.update({"fd_eps": 1e-6, "fd_directions": directions, "fd_rel_err_max": lit[-1],
