@@ -132,8 +132,11 @@ enum {
     SWEPT_MODE_NAIVE = 2,     /* one launch per time step */
     SWEPT_MODE_STAGE_BANDED = 3, /* swept stages, every diamond on the banded kernel
                                     (the continuous-band kernel switched off) */
-    SWEPT_MODE_STAGE_LANE = 4    /* swept stages on the lane-frame kernel (one lane per
+    SWEPT_MODE_STAGE_LANE = 4,   /* swept stages on the lane-frame kernel (one lane per
                                     column, W <= 64): for few, latency-bound tiles */
+    SWEPT_MODE_STAGE_RAGGED = 5  /* swept stages on unequal tiles: T-1 tiles of 2k points
+                                    and one of the remainder (odd nx on its two-fold
+                                    cover); k = tile_w/2, or the target depth if 0 */
 };
 
 /*
@@ -160,16 +163,23 @@ int swept_set_tuning(int32_t tile_w, int32_t pairs_per_lane, int32_t mode);
 /*
  * Plan the swept run swept_advance would use for these arguments, without
  * running it.  out[0..5] = { tile_w, depth_k, tiles, stages, pairs_per_lane
- * (0 on the lane-frame kernel), mode_used }.  Returns SWEPT_EINVAL for
+ * (0 on the lane-frame kernel), mode_used }.  For SWEPT_MODE_STAGE_RAGGED
+ * tile_w = 2k is the width of the full tiles and tiles counts the tiles of
+ * the ring (the two-fold cover for odd nx).  Returns SWEPT_EINVAL for
  * invalid arguments.
  */
 int swept_plan(int64_t nx, int64_t nsteps, int32_t stencil_id, int64_t *out);
 
 /*
  * Advance u (device, nx points of the stencil's type, periodic) by nsteps
- * time steps with the swept rule.  nsteps == 0 is a no-op.  If the grid
- * cannot be tiled (no even tile width divides nx) the automatic mode uses the
- * naive schedule, which gives the same bits.
+ * time steps with the swept rule.  nsteps == 0 is a no-op.  The automatic
+ * plan tiles every grid: with equal tiles of the largest even width W that
+ * divides nx, up to min(1024, nx/16) points, when W is at least half that
+ * target; otherwise (odd nx, or an even nx without such a divisor) with
+ * SWEPT_MODE_STAGE_RAGGED's unequal tiles at the target depth, odd nx on its
+ * two-fold cover.  Grids whose target depth is below 4 points (nx < 128)
+ * without a good equal tiling use the naive schedule.  Every plan gives the
+ * same bits.
  */
 int swept_advance(void *u, int64_t nx, int64_t nsteps, int32_t stencil_id,
                   const double *params, int32_t nparams);
@@ -181,11 +191,12 @@ int swept_advance(void *u, int64_t nx, int64_t nsteps, int32_t stencil_id,
  * in a fixed array of SWEPT_NOALLOC_SCRATCH_BYTES that the library holds on
  * each GPU it runs on (from swept_init until the process ends) instead of
  * memory it allocates.  The call allocates nothing.  It needs
- * 3 * nx * (point size) bytes on the swept path (point size: 8 for heat f64,
- * 4 for heat f32, 24 for KS, 72 for Euler; heat f64 up to 5,592,405 points,
- * KS up to 1,864,135) and nx field elements on the naive path (odd nx, or a
- * naive tuning); larger requests fail with SWEPT_EINVAL before any work is
- * enqueued.  Every call on a GPU shares that GPU's array, which keeps the
+ * 3 * nx * (point size) bytes on the swept path with equal tiles (point
+ * size: 8 for heat f64, 4 for heat f32, 24 for KS, 72 for Euler; heat f64 up
+ * to 5,592,405 points, KS up to 1,864,135), 6 * nx * (point size) + 2 * nx
+ * field elements on the unequal tiling of an odd nx, and nx field elements
+ * on the naive path; larger requests fail with SWEPT_EINVAL before any work
+ * is enqueued.  Every call on a GPU shares that GPU's array, which keeps the
  * last call's contents: calls that overlap on one GPU (two streams, or two
  * threads) race and must be serialised by the caller.  Stage profiling is
  * ignored during the call.
@@ -299,7 +310,8 @@ int swept_clear_tuning(void);
  * most recent swept_advance, the duration of each stage launch in
  * milliseconds (ms_out[i]) and which kernel ran it (kind_out[i]: 0 = banded
  * kernel -- the triangle or a stage capped at the target level, 1 =
- * continuous-band diamond kernel, 2 = lane-frame kernel).  At most cap
+ * continuous-band diamond kernel, 2 = lane-frame kernel, 3 = the unequal
+ * tiling's kernel, which runs every stage of SWEPT_MODE_STAGE_RAGGED).  At most cap
  * entries are written; *count
  * receives the number of stages.  Either output array may be NULL.
  * Returns SWEPT_EINVAL if profiling is off or no swept run was recorded.

@@ -24,7 +24,8 @@ HEAT_F64, HEAT_F32, KS_F64, EULER_F64 = 0, 1, 2, 3
 # the same schemes with their multiply-adds fused (results equal the above to rounding)
 HEAT_F64_FMA, HEAT_F32_FMA, KS_F64_FMA = 4, 5, 6
 NOALLOC_SCRATCH_BYTES = 128 << 20   # SWEPT_NOALLOC_SCRATCH_BYTES
-MODE_AUTO, MODE_STAGE, MODE_NAIVE, MODE_STAGE_BANDED, MODE_STAGE_LANE = 0, 1, 2, 3, 4
+MODE_AUTO, MODE_STAGE, MODE_NAIVE, MODE_STAGE_BANDED, MODE_STAGE_LANE, MODE_STAGE_RAGGED = \
+    0, 1, 2, 3, 4, 5
 
 _STATUS = {0: "SWEPT_OK", -1: "SWEPT_EINVAL", -2: "SWEPT_ENOTINIT", -3: "SWEPT_ENOMEM",
            -4: "SWEPT_EHIP", -5: "SWEPT_EUNSUPPORTED", -6: "SWEPT_ETIMEOUT"}

@@ -667,6 +667,50 @@ struct BatchArgs {
     int stage;
 };
 
+// Stage s of tile t of one ring of n points tiled at the even boundaries
+// Xp(0) = 0 < Xp(1) < ... < Xp(T) = n, extended periodically
+// (Xp(i + T) = Xp(i) + n).  re: the ring's right-edge buffer (tile t's
+// entries at offset Xp(t)); le_in / le_out: its left-edge buffers of the
+// previous and this stage parity (region i's entries at offset Xp(i)).
+template <class S, int P, class XF>
+__device__ __forceinline__ void tiled_region(typename S::T* u, int64_t n, int64_t L, int T,
+                                             const XF& Xp, int t, int s, typename S::Pt* re_ring,
+                                             const typename S::Pt* le_in_ring,
+                                             typename S::Pt* le_out_ring,
+                                             const typename S::Consts& c,
+                                             typename S::Pt* chain)
+{
+    using Pt = typename S::Pt;
+    const int64_t xs = Xp((int64_t)t + s), x1 = Xp((int64_t)t + 1);
+    const int64_t b = (xs - x1) / 2;
+    if (s > 0 && b >= L)
+        return;                  // this tile's regions are all above the target level
+    const int kp = (int)((x1 - Xp(t)) / 2);
+    const int i = (int)(((int64_t)t + s) % T);
+    const int ks = (int)((Xp((int64_t)i + 1) - Xp(i)) / 2);
+    const int64_t J = ((xs + x1) / 2) % n;
+    Pt* re = re_ring + Xp(t);
+    const Pt* le_in = le_in_ring + Xp(i);
+    Pt* le_out = le_out_ring + Xp(i);
+    if (s > 0 && kp == ks && kp % (64 * P) == 0 && b + 2 * (int64_t)kp - 1 < L) {
+        // a full square diamond strictly below the target level: the
+        // continuous-band schedule, whose cycles start at phase b mod NPHASE
+        if constexpr (S::NPHASE == 1) {
+            cont_region<S, P, 0>(re, re, le_in, le_out, chain, kp, c);
+        } else {
+            static_assert(S::NPHASE == 4, "one or four sub-timesteps per step");
+            switch ((int)(b % 4)) {
+            case 0: cont_region<S, P, 0>(re, re, le_in, le_out, chain, kp, c); break;
+            case 1: cont_region<S, P, 1>(re, re, le_in, le_out, chain, kp, c); break;
+            case 2: cont_region<S, P, 2>(re, re, le_in, le_out, chain, kp, c); break;
+            default: cont_region<S, P, 3>(re, re, le_in, le_out, chain, kp, c); break;
+            }
+        }
+        return;
+    }
+    banded_region<S, P>(u, re, re, le_in, le_out, chain, n, L, b, J, kp, ks, s == 0, c);
+}
+
 template <class S, int P>
 __global__ __launch_bounds__(64) void swept_batch_kernel(BatchArgs<S> g)
 {
@@ -674,40 +718,40 @@ __global__ __launch_bounds__(64) void swept_batch_kernel(BatchArgs<S> g)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const BatchTask task = g.tasks[blockIdx.x];
     const BatchInst<S> I = g.inst[task.inst];
-    const int s = g.stage;
-    const int t = task.tile;
     const int64_t* X = g.X + I.x_off;
     const int T = I.tiles;
-    auto Xp = [&](int64_t i) { return X[i % T] + (i / T) * I.n; };
-    const int64_t xs = Xp((int64_t)t + s), x1 = Xp((int64_t)t + 1);
-    const int64_t b = (xs - x1) / 2;
-    if (s > 0 && b >= I.L)
-        return;                  // this tile's regions are all above the target level
-    const int kp = (int)((X[t + 1] - X[t]) / 2);
-    const int i = (int)(((int64_t)t + s) % T);
-    const int ks = (int)((X[i + 1] - X[i]) / 2);
-    const int64_t J = ((xs + x1) / 2) % I.n;
-    Pt* re = g.re + I.e_off + X[t];
-    const Pt* le_in = g.le[(s + 1) & 1] + I.e_off + X[i];
-    Pt* le_out = g.le[s & 1] + I.e_off + X[i];
-    Pt* chain = reinterpret_cast<Pt*>(smem_raw);
-    if (s > 0 && kp == ks && kp % (64 * P) == 0 && b + 2 * (int64_t)kp - 1 < I.L) {
-        // a full square diamond strictly below the target level: the
-        // continuous-band schedule, whose cycles start at phase b mod NPHASE
-        if constexpr (S::NPHASE == 1) {
-            cont_region<S, P, 0>(re, re, le_in, le_out, chain, kp, I.c);
-        } else {
-            static_assert(S::NPHASE == 4, "one or four sub-timesteps per step");
-            switch ((int)(b % 4)) {
-            case 0: cont_region<S, P, 0>(re, re, le_in, le_out, chain, kp, I.c); break;
-            case 1: cont_region<S, P, 1>(re, re, le_in, le_out, chain, kp, I.c); break;
-            case 2: cont_region<S, P, 2>(re, re, le_in, le_out, chain, kp, I.c); break;
-            default: cont_region<S, P, 3>(re, re, le_in, le_out, chain, kp, I.c); break;
-            }
-        }
-        return;
-    }
-    banded_region<S, P>(I.u, re, re, le_in, le_out, chain, I.n, I.L, b, J, kp, ks, s == 0, I.c);
+    const int64_t n = I.n;
+    auto Xp = [&](int64_t i) { return X[i % T] + (i / T) * n; };
+    tiled_region<S, P>(I.u, n, I.L, T, Xp, task.tile, g.stage, g.re + I.e_off,
+                       g.le[(g.stage + 1) & 1] + I.e_off, g.le[g.stage & 1] + I.e_off, I.c,
+                       reinterpret_cast<Pt*>(smem_raw));
+}
+
+// One field on the same tiling, its boundaries computed instead of read from a
+// table: T - 1 tiles of 2k points and a last one of the remainder,
+// X_t = 2kt for t < T and X_T = n.  Workgroup t runs tile t.
+template <class S>
+struct RaggedArgs {
+    using Pt = typename S::Pt;
+    typename S::T* u;        // the field (n points; the two-fold cover for an odd field)
+    Pt* re;                  // right edges, n points
+    Pt* le[2];               // left edges by stage parity, n points each
+    int64_t n, L;
+    int k, tiles, stage;
+    typename S::Consts c;
+};
+
+template <class S, int P>
+__global__ __launch_bounds__(64) void swept_ragged_kernel(RaggedArgs<S> g)
+{
+    using Pt = typename S::Pt;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int T = g.tiles;
+    const int64_t n = g.n, w = 2 * (int64_t)g.k;
+    auto Xp = [&](int64_t i) { return (i % T) * w + (i / T) * n; };
+    tiled_region<S, P>(g.u, n, g.L, T, Xp, (int)blockIdx.x, g.stage, g.re,
+                       g.le[(g.stage + 1) & 1], g.le[g.stage & 1], g.c,
+                       reinterpret_cast<Pt*>(smem_raw));
 }
 
 template <class S>

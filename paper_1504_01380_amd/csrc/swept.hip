@@ -195,11 +195,15 @@ struct Plan {
     int64_t W = 0, k = 0, tiles = 0, stages = 0;
     int P = 1;
     int mode = SWEPT_MODE_NAIVE;
+    int64_t ring = 0;   // SWEPT_MODE_STAGE_RAGGED: the tiled ring (nx, or 2nx for odd nx)
 };
 
 constexpr size_t kMaxLds = 64 * 1024;
 // the lane-frame kernel holds a region and its V edges in one wavefront
 constexpr int64_t kLaneMaxK = 32;
+// the unequal tiling is used automatically from this depth up (shallower
+// regions would hardly beat one launch per step)
+constexpr int64_t kRaggedMinK = 4;
 
 // Measured on MI355X (20,000-step heat at N = 2^24, binary64 and binary32;
 // KS at N = 2^20; heat at N = 4096): W = 1024 is fastest for every stencil on
@@ -269,7 +273,8 @@ bool lane_fits(int id, int64_t k)
 // Tilings chosen by swept_autotune, per stencil and size class floor(log2 nx).
 struct Tuned {
     int64_t W;
-    int P;   // pairs per lane; 0: the lane-frame kernel
+    int P;                 // pairs per lane; 0: the lane-frame kernel
+    bool ragged = false;   // the unequal tiling of depth W/2 (SWEPT_MODE_STAGE_RAGGED)
 };
 std::map<std::pair<int, int>, Tuned> g_tuned;
 // Batch depth per stencil id chosen by swept_autotune_batch (0 = default).
@@ -282,6 +287,40 @@ std::pair<int, int> tune_key(int id, int64_t nx)
     while ((int64_t(1) << (b + 1)) <= nx)
         ++b;
     return {id, b};
+}
+
+// The unequal tiling of swept_advance (SWEPT_MODE_STAGE_RAGGED), that of
+// one batch instance: a ring of 2h points (h = nx/2 for even nx; odd nx runs
+// on its two-fold cover, h = nx) in T = ceil(h/k) tiles, T-1 of 2k points and
+// the last of the remainder.  Regions between two full tiles are k x k
+// squares (on the continuous-band schedule below the target level when k is
+// a multiple of the band 64P), the others rectangles on the banded one.
+int ragged_plan(int64_t nx, int64_t L, int32_t id, int64_t want_k, int want_P, Plan* p)
+{
+    *p = Plan{};
+    const int64_t ring = nx % 2 == 0 ? nx : 2 * nx;
+    const int64_t h = ring / 2;
+    int64_t k = std::max<int64_t>(1, std::min(want_k > 0 ? want_k : target_tile(id) / 2, h));
+    while (k > 1 && stage_lds_bytes(id, 2 * k) > kMaxLds)
+        --k;
+    int P = want_P > 0 ? want_P : (g_ctx.ppl > 0 ? g_ctx.ppl : auto_ppl(id, k));
+    if (P > pmax(id))
+        return fail(SWEPT_EUNSUPPORTED, "this stencil takes at most %d pairs per lane", pmax(id));
+    if (k >= 2 * 64 * P && want_k <= 0)
+        k -= k % (64 * P);   // full squares a multiple of the band
+    const int64_t T = (h + k - 1) / k;
+    const int64_t rem = h - (T - 1) * k;
+    p->W = 2 * k;
+    p->k = k;
+    p->tiles = T;
+    p->P = P;
+    p->ring = ring;
+    // stage s >= 1 of tile t starts at level (X_{t+s} - X_{t+1})/2, the sum of
+    // s-1 consecutive half-widths, which hold the short tile at most
+    // ceil((s-1)/T) times; a tile's regions end once that level reaches L
+    p->stages = L == 0 ? 0 : 2 + (L + k - rem) * T / h;
+    p->mode = SWEPT_MODE_STAGE_RAGGED;
+    return SWEPT_OK;
 }
 
 // Tiles of W = 2k points (paper, Section 3: each node owns an even number of
@@ -303,6 +342,8 @@ int make_plan(int64_t nx, int64_t nsteps, int32_t id, Plan* p)
             p->mode = SWEPT_MODE_NAIVE;   // the naive schedule was fastest
             return SWEPT_OK;
         }
+        if (it != g_tuned.end() && it->second.ragged)
+            return ragged_plan(nx, L, id, it->second.W / 2, it->second.P, p);
         if (it != g_tuned.end() && tile_fits(id, nx, it->second.W) &&
             (it->second.P > 0 || lane_fits(id, it->second.W / 2))) {
             W = it->second.W;
@@ -310,6 +351,8 @@ int make_plan(int64_t nx, int64_t nsteps, int32_t id, Plan* p)
             lane = it->second.P == 0;
         }
     }
+    if (g_ctx.mode == SWEPT_MODE_STAGE_RAGGED)
+        return ragged_plan(nx, L, id, g_ctx.tile_w / 2, 0, p);
     if (W > 0) {
         // tuned for this stencil and size class
     } else if (g_ctx.tile_w > 0) {
@@ -330,6 +373,11 @@ int make_plan(int64_t nx, int64_t nsteps, int32_t id, Plan* p)
                 W = w;
                 break;
             }
+        // One tiling rule for every nx: when no even width within a factor
+        // of two of the target divides nx (odd nx, or an awkward even one),
+        // tile the ring unequally at the target depth instead.
+        if (!lane && g_ctx.mode == SWEPT_MODE_AUTO && 2 * W < cap && cap / 2 >= kRaggedMinK)
+            return ragged_plan(nx, L, id, cap / 2, 0, p);
     }
     if (W == 0) {
         if (g_ctx.mode == SWEPT_MODE_STAGE || g_ctx.mode == SWEPT_MODE_STAGE_BANDED || lane)
@@ -470,6 +518,82 @@ int run_swept(void* u, int64_t nx, int64_t L, const typename S::Consts& c, const
             HIP_TRY(hipEventRecord(g_ctx.events[(size_t)s + 1], g_ctx.stream));
         }
     }
+    HIP_TRY(hipGetLastError());
+    if (g_ctx.profiling)
+        g_ctx.recorded = p.stages;
+    return SWEPT_OK;
+}
+
+unsigned grid_for(int64_t n, int block);
+
+template <class S, int P>
+void launch_ragged(const RaggedArgs<S>& a, size_t lds, hipStream_t st, int tiles)
+{
+    hipLaunchKernelGGL((swept_ragged_kernel<S, P>), dim3(tiles), dim3(64), lds, st, a);
+}
+
+// The unequal tiling of one field (ragged_plan): the stages of its T tiles,
+// one launch each, on the field itself or, for odd nx, on its two-fold cover
+// in the scratch (the scheme commutes with the translation by nx, so the
+// cover stays nx-periodic and its first nx points are the field's result).
+template <class S>
+int run_ragged(void* u, int64_t nx, int64_t L, const typename S::Consts& c, const Plan& p)
+{
+    using Pt = typename S::Pt;
+    using T = typename S::T;
+    const int64_t ring = p.ring;
+    const bool cover = ring != nx;
+    const size_t cov_b = cover ? ((size_t)ring * sizeof(T) + 255) / 256 * 256 : 0;
+    const size_t edge = (size_t)ring * sizeof(Pt);
+    int rc = ensure_scratch(cov_b + 3 * edge);
+    if (rc)
+        return rc;
+    unsigned char* base = static_cast<unsigned char*>(scratch_base());
+    T* field = cover ? reinterpret_cast<T*>(base) : static_cast<T*>(u);
+    Pt* re = reinterpret_cast<Pt*>(base + cov_b);
+    if (cover)
+        hipLaunchKernelGGL((batch_cover_kernel<S>), dim3(grid_for(ring, 256)), dim3(256), 0,
+                           g_ctx.stream, static_cast<const T*>(u), field, nx, 2);
+    RaggedArgs<S> a{};
+    a.u = field;
+    a.re = re;
+    a.le[0] = re + ring;
+    a.le[1] = re + 2 * ring;
+    a.n = ring;
+    a.L = L;
+    a.k = (int)p.k;
+    a.tiles = (int)p.tiles;
+    a.c = c;
+    const size_t lds = stage_lds<S>(2 * p.k, true);
+    if (g_ctx.profiling) {
+        rc = reserve_events(p.stages);
+        if (rc)
+            return rc;
+        HIP_TRY(hipEventRecord(g_ctx.events[0], g_ctx.stream));
+    }
+    constexpr int PMAX = pmax_of<S>();
+    for (int64_t st = 0; st < p.stages; ++st) {
+        a.stage = (int)st;
+        switch (p.P) {
+        case 1: launch_ragged<S, 1>(a, lds, g_ctx.stream, (int)p.tiles); break;
+        case 2: launch_ragged<S, 2>(a, lds, g_ctx.stream, (int)p.tiles); break;
+        case 4:
+            if constexpr (PMAX >= 4)
+                launch_ragged<S, 4>(a, lds, g_ctx.stream, (int)p.tiles);
+            else
+                return fail(SWEPT_EUNSUPPORTED, "this stencil takes at most %d pairs per lane",
+                            PMAX);
+            break;
+        default: return fail(SWEPT_EUNSUPPORTED, "the unequal tiling takes 1, 2 or 4 pairs per lane");
+        }
+        if (g_ctx.profiling) {
+            g_ctx.kinds[(size_t)st] = 3;
+            HIP_TRY(hipEventRecord(g_ctx.events[(size_t)st + 1], g_ctx.stream));
+        }
+    }
+    if (cover)
+        hipLaunchKernelGGL((batch_cover_kernel<S>), dim3(grid_for(nx, 256)), dim3(256), 0,
+                           g_ctx.stream, static_cast<const T*>(field), static_cast<T*>(u), nx, 1);
     HIP_TRY(hipGetLastError());
     if (g_ctx.profiling)
         g_ctx.recorded = p.stages;
@@ -1109,6 +1233,19 @@ int advance_dispatch(void* u, int64_t nx, int64_t nsteps, int32_t id, const doub
     if (p.mode == SWEPT_MODE_NAIVE)
         return naive_dispatch(u, nx, nsteps, id, params);
     const int64_t L = nsteps * substeps_of(id);
+    if (p.mode == SWEPT_MODE_STAGE_RAGGED) {
+        switch (id) {
+        case SWEPT_HEAT_F64: return run_ragged<HeatF64>(u, nx, L, heat64_consts(params), p);
+        case SWEPT_HEAT_F32: return run_ragged<HeatF32>(u, nx, L, heat32_consts(params), p);
+        case SWEPT_EULER_F64: return run_ragged<EulerF64>(u, nx, L, euler_consts(params), p);
+        case SWEPT_HEAT_F64_FMA:
+            return run_ragged<HeatFmaF64>(u, nx, L, heat64_consts(params), p);
+        case SWEPT_HEAT_F32_FMA:
+            return run_ragged<HeatFmaF32>(u, nx, L, heat32_consts(params), p);
+        case SWEPT_KS_F64_FMA: return run_ragged<KSFmaF64>(u, nx, L, ks_consts(params), p);
+        default: return run_ragged<KSF64>(u, nx, L, ks_consts(params), p);
+        }
+    }
     switch (id) {
     case SWEPT_HEAT_F64: return run_swept<HeatF64>(u, nx, L, heat64_consts(params), p);
     case SWEPT_HEAT_F32: return run_swept<HeatF32>(u, nx, L, heat32_consts(params), p);
@@ -1300,11 +1437,12 @@ size_t field_bytes(int id)
 // returns its time and its number of stages.
 // P = 0: the lane-frame kernel
 int timed_swept(void* f, int64_t nx, int64_t nsteps, int id, const double* params, int64_t W,
-                int P, int reps, double* sec, int64_t* stages)
+                int P, int reps, double* sec, int64_t* stages, bool ragged = false)
 {
     g_ctx.tile_w = (int)W;
     g_ctx.ppl = P;
-    g_ctx.mode = P == 0 ? SWEPT_MODE_STAGE_LANE : SWEPT_MODE_STAGE;
+    g_ctx.mode = ragged ? SWEPT_MODE_STAGE_RAGGED
+                        : (P == 0 ? SWEPT_MODE_STAGE_LANE : SWEPT_MODE_STAGE);
     Plan p;
     int rc = make_plan(nx, nsteps, id, &p);
     if (rc)
@@ -1460,6 +1598,29 @@ int autotune(int64_t nx, int64_t nsteps, int id, const double* params, double* r
             }
         }
     }
+    {   // the unequal tiling, which the untuned plan takes where no good even
+        // width divides nx: timed on the whole grid over sixteen of its stages
+        g_tuned.erase(tune_key(id, nx));
+        g_ctx.tile_w = 0;
+        g_ctx.ppl = 0;
+        g_ctx.mode = SWEPT_MODE_AUTO;
+        Plan rg;
+        const bool have = make_plan(nx, nsteps, id, &rg) == SWEPT_OK &&
+                          rg.mode == SWEPT_MODE_STAGE_RAGGED;
+        g_err.clear();
+        if (have) {
+            const int64_t Lp = std::min(nsteps * S, std::max<int64_t>(16 * rg.k, 64));
+            const int64_t np = std::max<int64_t>(1, (Lp + S - 1) / S);
+            rc = timed_swept(f.p, nx, np, id, params, rg.W, rg.P, 3, &t, nullptr, true);
+            if (rc)
+                return rc;
+            const double rate = (double)nx * (double)np / t;
+            if (rate > best_rate) {
+                best_rate = rate;
+                best = Tuned{rg.W, rg.P, true};
+            }
+        }
+    }
     g_tuned[tune_key(id, nx)] = best;
     if (report) {
         const double r[8] = {tau, s1, sfull, nstar, w0, (double)std::max<int64_t>(best.W, 0),
@@ -1585,7 +1746,8 @@ int swept_set_tuning(int32_t tile_w, int32_t pairs_per_lane, int32_t mode)
         pairs_per_lane != 8)
         return fail(SWEPT_EINVAL, "pairs per lane %d not in {0,1,2,4,8}", pairs_per_lane);
     if (mode != SWEPT_MODE_AUTO && mode != SWEPT_MODE_STAGE && mode != SWEPT_MODE_NAIVE &&
-        mode != SWEPT_MODE_STAGE_BANDED && mode != SWEPT_MODE_STAGE_LANE)
+        mode != SWEPT_MODE_STAGE_BANDED && mode != SWEPT_MODE_STAGE_LANE &&
+        mode != SWEPT_MODE_STAGE_RAGGED)
         return fail(SWEPT_EINVAL, "unknown mode %d", mode);
     g_ctx.tile_w = tile_w;
     g_ctx.ppl = pairs_per_lane;

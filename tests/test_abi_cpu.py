@@ -54,7 +54,8 @@ def test_tuning_validation(swept):
     assert lib.swept_set_tuning(3, 0, 0) == -1      # odd tile
     assert lib.swept_set_tuning(0, 3, 0) == -1      # bad pairs per lane
     assert lib.swept_set_tuning(0, 0, 9) == -1      # bad mode
-    assert lib.swept_set_tuning(0, 0, 5) == -1
+    assert lib.swept_set_tuning(0, 0, 6) == -1
+    assert lib.swept_set_tuning(0, 0, 5) == 0       # unequal tiles
     assert lib.swept_set_tuning(0, 0, 4) == 0       # the lane-frame kernel
     assert lib.swept_set_tuning(0, 0, 0) == 0
     assert lib.swept_set_tuning(128, 2, 1) == 0
@@ -63,7 +64,7 @@ def test_tuning_validation(swept):
 
 def test_plan_geometry(swept):
     """The planner (host logic, no device needed): tiles of W = 2k points that
-    divide the grid, ceil(L/k)+1 stages, naive fallback for odd grids."""
+    divide the grid, ceil(L/k)+1 stages; unequal tiles for odd grids."""
     lib = swept.lib()
     lib.swept_set_tuning(0, 0, 0)
     p = swept.plan(1 << 24, 20000, "heat")
@@ -74,7 +75,9 @@ def test_plan_geometry(swept):
     assert (1 << 24) % p["tile_w"] == 0 and p["tiles"] * p["tile_w"] == 4096
     p = swept.plan(1 << 20, 50000, "ks")
     assert p["stages"] == 1 + (4 * 50000 + p["depth_k"] - 1) // p["depth_k"]
-    assert swept.plan(1001, 5, "heat")["mode"] == swept.MODE_NAIVE   # odd: no even tile
+    # odd: unequal tiles of the two-fold cover; tiny odd grids: naive
+    assert swept.plan(1001, 5, "heat")["mode"] == swept.MODE_STAGE_RAGGED
+    assert swept.plan(127, 5, "heat")["mode"] == swept.MODE_NAIVE
     lib.swept_set_tuning(0, 0, swept.MODE_STAGE)
     out = (ctypes.c_int64 * 6)()
     assert lib.swept_plan(1001, 5, 0, out) == -5                    # SWEPT_EUNSUPPORTED
@@ -138,3 +141,24 @@ def test_mean_square_window_bounds_are_checked(swept):
             swept.window_mean_square_value(u, 10, "ks", [0.005, 0.5], bad)
         with pytest.raises(ValueError):
             swept.WindowMeanSquare.apply(u, 10, "ks", [0.005, 0.5], bad)
+
+
+def test_plan_has_no_cliff_for_awkward_grids(swept):
+    """Grids whose even divisors are all far below the target tile (8198 =
+    2 x 4099, 8186, 6126, 2^24 + 2) and odd grids get tiles near the target
+    depth (the unequal tiling), never 2-point tiles with a stage per step."""
+    swept.lib().swept_set_tuning(0, 0, 0)
+    for n in (8198, 8186, 6126, (1 << 24) + 2, 1001, (1 << 20) + 1):
+        for st in ("heat", "ks", "euler"):
+            p = swept.plan(n, 10000, st)
+            target = min(1024, n // 16) // 2
+            assert p["mode"] == swept.MODE_STAGE_RAGGED, (n, st, p)
+            assert p["depth_k"] >= min(target, 128) // 2, (n, st, p)
+            L = 10000 * (4 if st != "heat" else 1)
+            h = n // 2 if n % 2 == 0 else n          # half the tiled ring
+            assert p["stages"] <= (L + p["depth_k"]) * p["tiles"] // h + 2, (n, st, p)
+    # a forced unequal tiling of a divisible grid: T - 1 tiles of 600 points
+    swept.lib().swept_set_tuning(600, 0, swept.MODE_STAGE_RAGGED)
+    p = swept.plan(4096, 100, "heat")
+    assert (p["tile_w"], p["tiles"], p["mode"]) == (600, 7, swept.MODE_STAGE_RAGGED)
+    swept.lib().swept_set_tuning(0, 0, 0)

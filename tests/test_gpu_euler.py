@@ -68,7 +68,7 @@ def test_euler_auto_plan_and_odd_grid(sw, oracle_mod):
     import torch
     p = sw.plan(1 << 20, 100, "euler", torch.float64)
     assert p["mode"] == sw.MODE_STAGE and p["tile_w"] * 72 <= 64 * 1024
-    q0 = workloads.euler_mirrored_sod(1001)            # odd: the naive schedule
+    q0 = workloads.euler_mirrored_sod(1001)            # odd: unequal tiles of the cover
     assert same_bits(run(sw, sw.advance, q0, 60), want(oracle_mod, q0, 60))
 
 

@@ -140,9 +140,9 @@ def test_zero_steps_is_noop(sw):
     assert same_bits(run(sw, sw.naive_advance, u0, 0, "heat", HEAT_P), u0)
 
 
-def test_odd_grid_falls_back_to_same_bits(sw, oracle_mod):
+def test_odd_grid_runs_on_its_cover(sw, oracle_mod):
     u0 = workloads.white_noise(1001, seed=3)
-    assert sw.plan(1001, 50, "heat")["mode"] == sw.MODE_NAIVE
+    assert sw.plan(1001, 50, "heat")["mode"] == sw.MODE_STAGE_RAGGED
     assert same_bits(run(sw, sw.advance, u0, 50, "heat", HEAT_P), oracle_mod.heat(u0, 50, 0.25))
 
 

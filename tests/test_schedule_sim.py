@@ -247,3 +247,53 @@ def test_continuous_face_sharing(k, P, lanes, b):
     for m in range(k):   # last pair (k-1) at step m
         assert chain[2 * m] == (m - (k - 1) - 1, b + m + k)
         assert chain[2 * m + 1] == (m - (k - 1), b + m + k)
+
+
+@pytest.mark.parametrize("n,nsteps,stencil", [
+    (130, 30, "heat"),    # even, no even divisor near the target: unequal tiles
+    (131, 23, "heat"),    # odd: unequal tiles of the two-fold cover
+    (258, 41, "heat"),
+    (8198, 3, "heat"),    # the grid whose equal tiling was 2 points wide
+    (129, 9, "ks"),
+    (194, 7, "ks"),
+])
+def test_single_field_unequal_plan(oracle_mod, n, nsteps, stencil):
+    """The unequal tiling the library plans for a single field without a good
+    even divisor (swept_plan, host logic): T-1 tiles of half-width k and the
+    remainder, of the ring or its two-fold cover; its emulated schedule
+    computes every (point, level) once and gives the oracle's bits."""
+    import paper_1504_01380_amd as swept
+    swept.lib().swept_set_tuning(0, 0, 0)
+    p = swept.plan(n, nsteps, stencil)
+    assert p["mode"] == swept.MODE_STAGE_RAGGED
+    ring = n if n % 2 == 0 else 2 * n
+    k, T = p["depth_k"], p["tiles"]
+    ks_list = _split(ring // 2, k)
+    assert len(ks_list) == T and p["tile_w"] == 2 * k
+    if stencil == "heat":
+        u0 = workloads.white_noise(n, seed=n)
+        st, L, want = swept_sim.heat_step(0.3), nsteps, oracle_mod.heat(u0, nsteps, 0.3)
+    else:
+        u0 = workloads.smoothed_noise(n, seed=n)
+        st, L = swept_sim.ks_step(0.005, 0.5), 4 * nsteps
+        want = oracle_mod.ks(u0, nsteps, 0.005, 0.5)
+    field = list(u0) if ring == n else list(u0) + list(u0)
+    # KS phases need the band (lanes x pairs) a multiple of 4, as 64P is on the GPU
+    got, visits = swept_sim.simulate_tiles(field, nsteps, ks_list, 1, st,
+                                           lanes=2 if stencil == "heat" else 4, track=True,
+                                           cont=True)
+    ok, why = swept_sim.levels_complete(visits, ring, L, 0)
+    assert ok, why
+    assert same_bits(np.array(got[:n]), want)
+    # the plan launches every stage in which some tile still has a region
+    # below the target level: stage s of tile t starts at (X_{t+s} - X_{t+1})/2
+    X = [0]
+    for kt in ks_list:
+        X.append(X[-1] + 2 * kt)
+
+    def Xp(i):
+        return X[i % T] + (i // T) * ring
+
+    last = max(s for s in range(1, 4 * L + 4)
+               if any((Xp(t + s) - Xp(t + 1)) // 2 < L for t in range(T)))
+    assert last + 1 <= p["stages"] <= last + 3
