@@ -358,7 +358,6 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
                                           typename S::Pt* chain, int lane, int j, int rs,
                                           int next_slot, int wslot, bool wlast,
                                           typename S::Pt* re_store,
-                                          const typename S::Pt* re_load,
                                           const typename S::Consts& c, face_t<S> (&Fn)[P],
                                           void* fch, int fslot)
 {
@@ -384,10 +383,6 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
                     A[q] = An[q];
                     B[q] = Bn[q];
                     F[q] = Fn[q];
-                    if (re_load) {
-                        Bn[q] = re_load[0];
-                        An[q] = re_load[1];
-                    }
                 }
             }
             const Pt cBq = (q == 0) ? inB : B[q - 1];
@@ -422,10 +417,6 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
                     re_store[1] = A[q];
                     A[q] = An[q];
                     B[q] = Bn[q];
-                    if (re_load) {
-                        Bn[q] = re_load[0];
-                        An[q] = re_load[1];
-                    }
                 }
             }
             const Pt rA = (q == 0) ? inA : A[q - 1];
@@ -478,22 +469,20 @@ __device__ __forceinline__ void cont_head_group(int j0, int k, int nb, int cyc,
         const int j = j0 + I;
         const int rs = j / P;
         const int next_slot = (j + 1 == k) ? 0 : j + 1;
-        // last slot: step m = sigma - (NB-1) mod k of its band
-        const int wslot = (j + k - (NB - 1)) % k;
+        // last slot: step m = sigma - (NB-1) mod k of its band (j < NB here,
+        // so j + k - (NB-1) lies in [k - NB + 1, k])
+        const int wraw = j + k - (NB - 1);
+        const int wslot = wraw == k ? 0 : wraw;
         // it is active from step NB-1 of the fill to step NB-2 of the drain
         const bool wlast = MASK == 1 ? (j == NB - 1) : (MASK == 2 ? (j < NB - 1) : true);
         typename S::Pt* re_store = nullptr;
-        const typename S::Pt* re_load = nullptr;
-        if constexpr (TRANS) {
+        if constexpr (TRANS)
             re_store = re_out + 2 * ((cyc - 1) * NB + j);
-            if (cyc + 1 < nb)
-                re_load = re + 2 * ((cyc + 1) * NB + j);
-        }
         // the chain entry the last slot wrote one step before (j < 64P here)
         const int fslot = j + k - NB;
         cont_step<S, P, PH, MASK, TRANS ? QS : -1>(A, B, An, Bn, cA, cB, chain, lane, j, rs,
-                                                   next_slot, wslot, wlast, re_store, re_load, c,
-                                                   Fn, fch, fslot);
+                                                   next_slot, wslot, wlast, re_store, c, Fn, fch,
+                                                   fslot);
         cont_head_group<S, P, PH0, MASK, TRANS, I + 1, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
                                                           chain, re, re_out, lane, c, Fn, fch);
     }
@@ -514,8 +503,8 @@ __device__ __forceinline__ void cont_body_group(int j0, int k, typename S::Pt (&
         const int j = j0 + I;
         const int next_slot = (j + 1 == k) ? 0 : j + 1;
         cont_step<S, P, (PH0 + I) % S::NPHASE, 0, -1>(A, B, An, Bn, cA, cB, chain, lane, j, 0,
-                                                      next_slot, j - (NB - 1), true, nullptr,
-                                                      nullptr, c, Fn, fch, j - NB);
+                                                      next_slot, j - (NB - 1), true, nullptr, c,
+                                                      Fn, fch, j - NB);
         cont_body_group<S, P, PH0, I + 1, U>(j0, k, A, B, An, Bn, cA, cB, chain, lane, c, Fn,
                                              fch);
     }
@@ -598,6 +587,17 @@ __device__ __forceinline__ void cont_region(const typename S::Pt* re, typename S
             for (int j0 = 0; j0 < NB; j0 += G)
                 cont_head_group<S, P, PH0, 0, true, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
                                                           chain, re, re_out, lane, cst, Fn, fch);
+            // every slot has entered band cyc: fetch band cyc+1's left-edge
+            // states for all of them at once (used k - 64P steps or more
+            // later, at the next cycle's head)
+            if (cyc + 1 < nb) {
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    const int e = lane * P + q;
+                    Bn[q] = re[2 * ((cyc + 1) * NB + e)];
+                    An[q] = re[2 * ((cyc + 1) * NB + e) + 1];
+                }
+            }
         }
         for (int j0 = NB; j0 < k; j0 += U)
             cont_body_group<S, P, PH0, 0, U>(j0, k, A, B, An, Bn, cA, cB, chain, lane, cst, Fn,
