@@ -86,6 +86,15 @@ template <class S>
 struct chain_prefetch<S, std::void_t<decltype(S::kChainPrefetch)>>
     : std::integral_constant<bool, S::kChainPrefetch> {};
 
+// A stencil may set kChainStore: the continuous kernel's last slot then
+// stores into the LDS chain only the components of its pair that the next
+// sub-timestep reads (S::chain_store<PH>), instead of the whole points.
+template <class S, class = void>
+struct has_chain_store : std::false_type {};
+template <class S>
+struct has_chain_store<S, std::void_t<decltype(S::kChainStore)>>
+    : std::integral_constant<bool, S::kChainStore> {};
+
 // A stencil may set kFaces: its flux sub-timesteps then come as face fluxes
 // (face_of, step_faces), and the continuous kernel computes each face once.
 template <class S, class = void>
@@ -437,8 +446,13 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
         }
     }
     if (wlast && lane == 63) {  // the last slot traces the band's left edge
-        chain[2 * wslot] = B[P - 1];
-        chain[2 * wslot + 1] = A[P - 1];
+        if constexpr (has_chain_store<S>::value) {
+            S::template chain_store<PH>(&chain[2 * wslot], &chain[2 * wslot + 1], B[P - 1],
+                                        A[P - 1]);
+        } else {
+            chain[2 * wslot] = B[P - 1];
+            chain[2 * wslot + 1] = A[P - 1];
+        }
     }
 }
 

@@ -154,6 +154,23 @@ struct KSF64 {
         }
     }
 
+    // A pair's state after sub-timestep PH is read only by sub-timestep PH+1
+    // (of the pair beside it): D2 of a (PH+1 even) reads u and a of the
+    // centre point B and a of A; F (PH+1 odd) reads u, a, b of B and a, b of
+    // A.  The continuous kernel's LDS chain keeps only those components.
+    static constexpr bool kChainStore = true;
+    template <int PH>
+    __device__ __forceinline__ static void chain_store(Pt* dB, Pt* dA, const Pt& B, const Pt& A)
+    {
+        dB->u = B.u;
+        dB->a = B.a;
+        dA->a = A.a;
+        if constexpr (PH == 0 || PH == 2) {
+            dB->b = B.b;
+            dA->b = A.b;
+        }
+    }
+
     // Discrete adjoint: the transposed Jacobian of each sub-timestep, in the
     // pull form (the cotangent of a point from the cotangents of the three
     // points of the level above that read it).  A cotangent carries

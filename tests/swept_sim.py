@@ -37,6 +37,22 @@ def ks_step(dt, dx):
     return f, 4, (lambda v: (v, v, 0.0)), (lambda p: p[0])
 
 
+NAN = float("nan")
+
+
+def _chain_store(ph, B, A, oldB, oldA):
+    """What the continuous kernel's last slot leaves in the LDS chain after
+    sub-timestep ph: whole points for one-value stencils; for KS points
+    (u, a, b) only what sub-timestep ph+1 reads (B's u and a, A's a, plus
+    both b when ph+1 is a flux step) -- here the other components become NaN,
+    so a read of one of them would show in the result."""
+    if not isinstance(B, tuple):
+        return B, A
+    if ph in (0, 2):
+        return (B[0], B[1], B[2]), (NAN, A[1], A[2])
+    return (B[0], B[1], NAN), (NAN, A[1], NAN)
+
+
 def _cont_stage(t, J, b, k, P, lanes, RE, chain, step, nph, n, visits):
     """One full diamond on the continuous-band schedule of
     swept_diamond_cont_kernel: slot e works on band (sigma-e) div k, step
@@ -66,9 +82,6 @@ def _cont_stage(t, J, b, k, P, lanes, RE, chain, step, nph, n, visits):
                         RE[t][2 * ((cyc - 1) * NB + j)] = B[e]
                         RE[t][2 * ((cyc - 1) * NB + j) + 1] = A[e]
                         A[e], B[e] = An[e], Bn[e]
-                        if cyc + 1 < nb:
-                            Bn[e] = RE[t][2 * ((cyc + 1) * NB + j)]
-                            An[e] = RE[t][2 * ((cyc + 1) * NB + j) + 1]
                     act = True
                     if mask == 1:
                         act = e <= j
@@ -90,8 +103,15 @@ def _cont_stage(t, J, b, k, P, lanes, RE, chain, step, nph, n, visits):
             wlast = (j == NB - 1) if mask == 1 else ((j < NB - 1) if mask == 2 else True)
             if wlast:
                 ws = (j + k - (NB - 1)) % k
-                chain[2 * ws], chain[2 * ws + 1] = B[NB - 1], A[NB - 1]
+                chain[2 * ws], chain[2 * ws + 1] = _chain_store(ph, B[NB - 1], A[NB - 1],
+                                                                chain[2 * ws], chain[2 * ws + 1])
             cA, cB = nA, nB
+            if trans and j == NB - 1 and cyc + 1 < nb:
+                # every slot has entered band cyc: band cyc+1's left-edge
+                # states, for all slots at once
+                for e in range(NB):
+                    Bn[e] = RE[t][2 * ((cyc + 1) * NB + e)]
+                    An[e] = RE[t][2 * ((cyc + 1) * NB + e) + 1]
     for e in range(NB):
         RE[t][2 * ((nb - 1) * NB + e)] = B[e]
         RE[t][2 * ((nb - 1) * NB + e) + 1] = A[e]
