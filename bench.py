@@ -284,22 +284,33 @@ def batch_workload(sw, torch, workloads, tune=True):
             a.copy_(b)
         torch.cuda.synchronize()
 
-    t0 = time.perf_counter()
-    sw.advance_batch(us, ns, kinds, pars)         # warm-up: plan, capture the graph
-    torch.cuda.synchronize()
-    rec["first_call_s"] = time.perf_counter() - t0
-    ts = []
-    for _ in range(3):
-        restore()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        sw.advance_batch(us, ns, kinds, pars)
-        e1.record()
-        e1.synchronize()
-        ts.append(e0.elapsed_time(e1) / 1e3)
-    t = sorted(ts)[1]
+    def timed(schedule):
+        sw.set_batch_schedule(schedule, 0)
+        t0 = time.perf_counter()
+        sw.advance_batch(us, ns, kinds, pars)     # warm-up: plan, capture the graph
+        torch.cuda.synchronize()
+        first = time.perf_counter() - t0
+        ts = []
+        for _ in range(3):
+            restore()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sw.advance_batch(us, ns, kinds, pars)
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        sw.sync()
+        return sorted(ts)[1], first
+
+    # one launch per stage first, then the default: one persistent launch
+    ts_, _ = timed(sw.BATCH_STAGED)
+    rec["staged"] = work / ts_
+    rec["staged_ms"] = ts_ * 1e3
+    t, rec["first_call_s"] = timed(sw.BATCH_PERSISTENT)
+    rec["schedule"] = "persistent (one launch, per-tile stage flags)"
     rec["swept"] = work / t
     rec["swept_ms"] = t * 1e3
+    rec["persistent_vs_staged"] = ts_ / t
     sw.naive_advance_batch(us[:64], [min(x, 4) for x in ns[:64]], kinds[:64], pars[:64])
     restore()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

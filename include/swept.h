@@ -64,7 +64,8 @@ typedef enum {
     SWEPT_ENOMEM = -3,        /* device allocation of scratch failed */
     SWEPT_EHIP = -4,          /* a HIP runtime call or kernel launch failed */
     SWEPT_EUNSUPPORTED = -5,  /* valid request this build cannot run (e.g. tiling impossible) */
-    SWEPT_ETIMEOUT = -6       /* reserved: a bounded device-side wait gave up */
+    SWEPT_ETIMEOUT = -6       /* a bounded device-side wait gave up (persistent batch,
+                                 reported by swept_sync) */
 } swept_status;
 
 /*
@@ -236,13 +237,59 @@ int swept_naive_substep_advance(void *u, int64_t nx, int64_t nsteps, int32_t ste
  * below the target level run on the continuous-band schedule); the regions
  * next to the short tile are rectangles of k_t pairs by k_{t+s} steps.  An
  * odd length runs on its two-fold cover
- * (the field repeated twice, which the scheme keeps repeated).  All tiles of
- * all instances advance one stage per kernel launch; the launches of a
- * batch are captured into one HIP graph, which is reused when the same
- * batch (same sizes, steps, parameters and pointers) is advanced again.
+ * (the field repeated twice, which the scheme keeps repeated).
+ *
+ * Schedule (swept_set_batch_schedule).  SWEPT_BATCH_PERSISTENT, the default:
+ * one persistent kernel launch per stencil runs every region of every stage
+ * of every instance.  Its workgroups (as many as the GPU holds at once)
+ * take regions from device counters, in stage-major order with the
+ * instances with the most stages first, and a region waits only for the two
+ * regions of the previous stage it reads (its own tile's and the next
+ * tile's) -- the paper's point-to-point communication stage, in which a
+ * node needs only the edge it kept and the edge its neighbour sends
+ * (Section 3) -- so instances and tiles run ahead of one another as far as
+ * their data allows.  A wait that exceeds the spin limit gives up: the
+ * launch ends early, the fields are left partly advanced, and the next
+ * swept_sync returns SWEPT_ETIMEOUT (SWEPT_EHIP if a queue was left
+ * unserved, which a check after the launch detects).  SWEPT_BATCH_STAGED:
+ * all tiles of all instances advance one stage per kernel launch (two
+ * launches per stage, heat and KS).
+ * Either way the launches of a batch are captured into one HIP graph, which
+ * is reused when the same batch (same sizes, steps, parameters and
+ * pointers) is advanced again.  Uses library scratch for the tables, the
+ * edges (three copies of each ring) and, on the persistent schedule, one
+ * flag per tile and one task number per region (below 2^31, else
+ * SWEPT_EUNSUPPORTED).
  */
 int swept_advance_batch(void *const *u, const int64_t *nx, const int64_t *nsteps,
                         const int32_t *stencil_id, const double *params, int64_t count);
+
+/* Schedules for swept_set_batch_schedule. */
+enum {
+    SWEPT_BATCH_PERSISTENT = 0,   /* one persistent launch for the whole batch (default) */
+    SWEPT_BATCH_STAGED = 1        /* one launch per stage and stencil */
+};
+
+/*
+ * Select the schedule of later swept_advance_batch calls (the results are the
+ * same bits either way) and tune the persistent one:
+ *  - spin_limit: microseconds after which a wait gives up (0: the default,
+ *    60 s; a wait normally lasts at most a few regions' run times);
+ *  - chunk: task numbers a workgroup takes per claim (0: the default, 2);
+ *    each run of them inside one stage shares one wait for its inputs;
+ *  - queues: independent schedules per stencil, the instances spread over
+ *    them by work, each with its own counter.  0, the default: one queue
+ *    per XCD, served only by the workgroups running on that XCD (so one L2
+ *    holds every exchange of an instance and the hand-over needs no L2
+ *    write-back), when a probe of the XCC_ID values tells the XCDs apart,
+ *    else 32 queues; a positive number: that many queues, workgroup w
+ *    serving queue w mod queues, the hand-over at agent scope.
+ * Needs no device; kept until swept_finalize.  SWEPT_EINVAL for an unknown
+ * schedule, a limit below 0 or above 2^40 us, a chunk outside [0, 32] or
+ * queues outside [0, 1024].
+ */
+int swept_set_batch_schedule(int32_t schedule, int64_t spin_limit, int32_t chunk,
+                             int32_t queues);
 
 /*
  * The naive schedule for a batch, the baseline of swept_advance_batch: one
@@ -381,7 +428,11 @@ int swept_window_objective(const void *u0, int64_t nx, int64_t nsteps, int32_t s
                            const double *params, int32_t nparams, int64_t window_first,
                            double window_weight, const void *cot_final, void *J_out);
 
-/* Wait for the current stream; report asynchronous kernel errors. */
+/*
+ * Wait for the current stream; report asynchronous kernel errors, and
+ * SWEPT_ETIMEOUT if a persistent batch launched since the last call gave up
+ * a wait (the flag is then cleared).
+ */
 int swept_sync(void);
 
 /* Message for the last failure on this thread ("" if none).  Never NULL. */

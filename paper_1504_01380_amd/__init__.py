@@ -26,6 +26,7 @@ HEAT_F64_FMA, HEAT_F32_FMA, KS_F64_FMA = 4, 5, 6
 NOALLOC_SCRATCH_BYTES = 128 << 20   # SWEPT_NOALLOC_SCRATCH_BYTES
 MODE_AUTO, MODE_STAGE, MODE_NAIVE, MODE_STAGE_BANDED, MODE_STAGE_LANE, MODE_STAGE_RAGGED = \
     0, 1, 2, 3, 4, 5
+BATCH_PERSISTENT, BATCH_STAGED = 0, 1
 
 _STATUS = {0: "SWEPT_OK", -1: "SWEPT_EINVAL", -2: "SWEPT_ENOTINIT", -3: "SWEPT_ENOMEM",
            -4: "SWEPT_EHIP", -5: "SWEPT_EUNSUPPORTED", -6: "SWEPT_ETIMEOUT"}
@@ -35,8 +36,8 @@ EXPORTS = ("swept_init", "swept_set_stream", "swept_set_tuning", "swept_plan",
            "swept_naive_substep_advance",
            "swept_set_profiling", "swept_stage_times", "swept_adjoint", "swept_naive_adjoint",
            "swept_advance_batch", "swept_window_objective",
-           "swept_naive_advance_batch", "swept_autotune", "swept_autotune_batch",
-           "swept_clear_tuning",
+           "swept_naive_advance_batch", "swept_set_batch_schedule", "swept_autotune",
+           "swept_autotune_batch", "swept_clear_tuning",
            "swept_sync", "swept_last_error", "swept_finalize")
 
 
@@ -67,6 +68,7 @@ def _load() -> ctypes.CDLL:
     L.swept_advance_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(i64),
                                       ctypes.POINTER(i32), dp, i64]
     L.swept_naive_advance_batch.argtypes = L.swept_advance_batch.argtypes
+    L.swept_set_batch_schedule.argtypes = [i32, i64, i32, i32]
     L.swept_autotune.argtypes = [i64, i64, i32, dp, i32, dp]
     L.swept_autotune_batch.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32),
                                        dp, i64, ctypes.POINTER(i64)]
@@ -161,6 +163,16 @@ def _params(params: Sequence[float]):
 
 def set_tuning(tile_w: int = 0, pairs_per_lane: int = 0, mode: int = MODE_AUTO) -> None:
     _check(_lib.swept_set_tuning(int(tile_w), int(pairs_per_lane), int(mode)), "swept_set_tuning")
+
+
+def set_batch_schedule(schedule: int = BATCH_PERSISTENT, spin_limit: int = 0,
+                       chunk: int = 0, queues: int = 0) -> None:
+    """BATCH_PERSISTENT (one launch per stencil for the whole batch) or
+    BATCH_STAGED (one launch per stage); for the persistent one, the wait
+    limit in microseconds, the task numbers per claim and the number of
+    queues (0: the library's defaults)."""
+    _check(_lib.swept_set_batch_schedule(int(schedule), int(spin_limit), int(chunk),
+                                         int(queues)), "swept_set_batch_schedule")
 
 
 def plan(nx: int, nsteps: int, stencil, dtype: torch.dtype | None = None) -> dict:

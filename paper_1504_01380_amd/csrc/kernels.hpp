@@ -155,7 +155,33 @@ __device__ __forceinline__ void band_update(typename S::Pt (&A)[P], typename S::
 // final state of every pair (re_out, the new right edge) and the last
 // pair's state at every step (le_out, the new left edge); points that reach
 // level L are written to u.  chain is 2*ks points of LDS.
-template <class S, int P>
+// An edge value another workgroup may have written in the same launch.
+// COH (the persistent batch on XCD-local queues): a device-scope load, which
+// skips this CU's L1 (it may hold the value from an earlier region) and is
+// served by the XCD's L2, where the writer's stores land -- so the reader
+// needs no cache invalidation.  Otherwise an ordinary load (a kernel
+// boundary or an agent-scope acquire orders it).
+template <class S, bool COH>
+__device__ __forceinline__ typename S::Pt ld_edge(const typename S::Pt* p)
+{
+    if constexpr (!COH) {
+        return *p;
+    } else {
+        using T = typename S::T;
+        using Pt = typename S::Pt;
+        static_assert(sizeof(Pt) % sizeof(T) == 0, "a point is a whole number of values");
+        constexpr int NW = (int)(sizeof(Pt) / sizeof(T));
+        Pt v;
+        T* dst = reinterpret_cast<T*>(&v);
+        const T* src = reinterpret_cast<const T*>(p);
+#pragma unroll
+        for (int i = 0; i < NW; ++i)
+            dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return v;
+    }
+}
+
+template <class S, int P, bool COH = false>
 __device__ __forceinline__ void banded_region(typename S::T* u, const typename S::Pt* re,
                                               typename S::Pt* re_out,
                                               const typename S::Pt* le_in,
@@ -170,7 +196,7 @@ __device__ __forceinline__ void banded_region(typename S::T* u, const typename S
     // right V edge of this region = left edge of the next tile's region of the previous stage
     if (!tri) {
         for (int i = lane; i < 2 * ks; i += 64)
-            chain[i] = le_in[i];
+            chain[i] = ld_edge<S, COH>(le_in + i);
     }
     __syncthreads();
 
@@ -196,8 +222,8 @@ __device__ __forceinline__ void banded_region(typename S::T* u, const typename S
                     A[q] = S::from_field(u[xa]);
                     B[q] = S::from_field(u[xa - 1]);
                 } else {      // left V edge at relative level d
-                    B[q] = re[2 * d];
-                    A[q] = re[2 * d + 1];
+                    B[q] = ld_edge<S, COH>(re + 2 * d);
+                    A[q] = ld_edge<S, COH>(re + 2 * d + 1);
                 }
             } else {
                 A[q] = S::from_field(T{});
@@ -530,7 +556,7 @@ __device__ __forceinline__ void cont_body_group(int j0, int k, typename S::Pt (&
 // buffer; le_in: the right V edge (pair -1 at step m); le_out: the new left
 // edge; chain: 2k points of LDS, followed for stencils with kFaces by the
 // face chain (k/2 faces).  PH0 = b mod NPHASE.
-template <class S, int P, int PH0>
+template <class S, int P, int PH0, bool COH = false>
 __device__ __forceinline__ void cont_region(const typename S::Pt* re, typename S::Pt* re_out,
                                             const typename S::Pt* le_in, typename S::Pt* le_out,
                                             typename S::Pt* chain, int k,
@@ -543,7 +569,7 @@ __device__ __forceinline__ void cont_region(const typename S::Pt* re, typename S
     const int lane = threadIdx.x;
     const int nb = k / NB;
     for (int i = lane; i < 2 * k; i += 64)
-        chain[i] = le_in[i];
+        chain[i] = ld_edge<S, COH>(le_in + i);
     __syncthreads();
     void* fch = nullptr;
     face_t<S> Fn[P];
@@ -564,11 +590,11 @@ __device__ __forceinline__ void cont_region(const typename S::Pt* re, typename S
 #pragma unroll
     for (int q = 0; q < P; ++q) {
         const int e = lane * P + q;
-        B[q] = re[2 * e];
-        A[q] = re[2 * e + 1];
+        B[q] = ld_edge<S, COH>(re + 2 * e);
+        A[q] = ld_edge<S, COH>(re + 2 * e + 1);
         if (nb > 1) {
-            Bn[q] = re[2 * (NB + e)];
-            An[q] = re[2 * (NB + e) + 1];
+            Bn[q] = ld_edge<S, COH>(re + 2 * (NB + e));
+            An[q] = ld_edge<S, COH>(re + 2 * (NB + e) + 1);
         } else {
             An[q] = A[q];
             Bn[q] = B[q];
@@ -608,8 +634,8 @@ __device__ __forceinline__ void cont_region(const typename S::Pt* re, typename S
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
                     const int e = lane * P + q;
-                    Bn[q] = re[2 * ((cyc + 1) * NB + e)];
-                    An[q] = re[2 * ((cyc + 1) * NB + e) + 1];
+                    Bn[q] = ld_edge<S, COH>(re + 2 * ((cyc + 1) * NB + e));
+                    An[q] = ld_edge<S, COH>(re + 2 * ((cyc + 1) * NB + e) + 1);
                 }
             }
         }
@@ -663,7 +689,7 @@ struct BatchInst {
     int64_t x_off;       // offset of X_0..X_T in the tile-boundary array
     int64_t e_off;       // offset of the instance's edges in the edge buffers (n points)
     int tiles;
-    int pad;
+    int tpos;            // persistent launch: index of tile 0 in the stencil's tile list
     typename S::Consts c;
 };
 
@@ -686,7 +712,7 @@ struct BatchArgs {
 // (Xp(i + T) = Xp(i) + n).  re: the ring's right-edge buffer (tile t's
 // entries at offset Xp(t)); le_in / le_out: its left-edge buffers of the
 // previous and this stage parity (region i's entries at offset Xp(i)).
-template <class S, int P, class XF>
+template <class S, int P, bool COH = false, class XF>
 __device__ __forceinline__ void tiled_region(typename S::T* u, int64_t n, int64_t L, int T,
                                              const XF& Xp, int t, int s, typename S::Pt* re_ring,
                                              const typename S::Pt* le_in_ring,
@@ -710,19 +736,19 @@ __device__ __forceinline__ void tiled_region(typename S::T* u, int64_t n, int64_
         // a full square diamond strictly below the target level: the
         // continuous-band schedule, whose cycles start at phase b mod NPHASE
         if constexpr (S::NPHASE == 1) {
-            cont_region<S, P, 0>(re, re, le_in, le_out, chain, kp, c);
+            cont_region<S, P, 0, COH>(re, re, le_in, le_out, chain, kp, c);
         } else {
             static_assert(S::NPHASE == 4, "one or four sub-timesteps per step");
             switch ((int)(b % 4)) {
-            case 0: cont_region<S, P, 0>(re, re, le_in, le_out, chain, kp, c); break;
-            case 1: cont_region<S, P, 1>(re, re, le_in, le_out, chain, kp, c); break;
-            case 2: cont_region<S, P, 2>(re, re, le_in, le_out, chain, kp, c); break;
-            default: cont_region<S, P, 3>(re, re, le_in, le_out, chain, kp, c); break;
+            case 0: cont_region<S, P, 0, COH>(re, re, le_in, le_out, chain, kp, c); break;
+            case 1: cont_region<S, P, 1, COH>(re, re, le_in, le_out, chain, kp, c); break;
+            case 2: cont_region<S, P, 2, COH>(re, re, le_in, le_out, chain, kp, c); break;
+            default: cont_region<S, P, 3, COH>(re, re, le_in, le_out, chain, kp, c); break;
             }
         }
         return;
     }
-    banded_region<S, P>(u, re, re, le_in, le_out, chain, n, L, b, J, kp, ks, s == 0, c);
+    banded_region<S, P, COH>(u, re, re, le_in, le_out, chain, n, L, b, J, kp, ks, s == 0, c);
 }
 
 template <class S, int P>
@@ -739,6 +765,216 @@ __global__ __launch_bounds__(64) void swept_batch_kernel(BatchArgs<S> g)
     tiled_region<S, P>(I.u, n, I.L, T, Xp, task.tile, g.stage, g.re + I.e_off,
                        g.le[(g.stage + 1) & 1] + I.e_off, g.le[g.stage & 1] + I.e_off, I.c,
                        reinterpret_cast<Pt*>(smem_raw));
+}
+
+// ----------------------------------------------------- persistent batch
+// One launch runs every stage of every instance of one stencil in a batch.
+// Tiles synchronise pairwise, as the paper's nodes do (Section 3: a node's
+// next stage needs only the edge it kept and the one its neighbour sent),
+// instead of all at once at a kernel boundary.
+// Its tasks (one region each) are numbered stage-major: all regions of stage
+// 0, then all of stage 1, and so on; inside a stage in order of decreasing
+// stage count of their instance (the longest instances start first).  A
+// workgroup takes the next few numbers from a counter and, for each run of
+// them inside one stage, waits until stage s-1 of every task's own tile and
+// next tile have been published, runs the regions and publishes their tiles
+// at stage s.  Every task that a claimed task waits for has a smaller
+// number and belongs to an earlier stage, so a workgroup that is already
+// running claimed it earlier and reaches it without waiting on anything
+// later: by induction over the numbers, the waits end.  They are bounded
+// all the same: after spin_ticks of waiting, or as soon as another
+// workgroup has given up, a workgroup sets `fault` and leaves (the host
+// reports a timeout).
+//
+// Those two waits give every ordering the stage-by-stage launches give.
+// Region (t, s) reads and rewrites tile t's right edge, which (t, s-1)
+// wrote; it reads the left edge at X_{t+s} of stage parity s-1, which
+// (t+1, s-1) wrote, and writes the one of parity s at the same place, which
+// only (t+1, s-1) reads.  Only stage 0 reads the field, and a region writes
+// its final level into tiles whose stage 0 it depends on.
+// The instances are split into `queues` independent schedules (balanced by
+// work), each with its own tile list, stage offsets and counter.  Two ways
+// to map workgroups to queues:
+//  - XCD-local (XL): queue j is served only by the workgroups running on
+//    XCD j (read from the hardware's XCC_ID register), so every region of an
+//    instance runs under one L2.  A region's edges reach the other
+//    workgroups of its queue once its stores have completed (the L1 is
+//    write-through), and they read edges with device-scope loads, which skip
+//    their own L1 (ld_edge): neither side touches the cache as a whole,
+//    where an agent-scope release writes back, and an acquire invalidates,
+//    the XCD's entire L2 at microseconds a time;
+//  - otherwise workgroup w serves queue w mod queues, and the release and
+//    acquire are at agent scope.
+template <class S>
+struct PersistArgs {
+    using Pt = typename S::Pt;
+    const BatchInst<S>* inst;
+    const BatchTask* tasks;      // per queue, the tiles; instance by instance, most stages first
+    const int64_t* toff;         // toff[j]: queue j's first entry in tasks
+    const int64_t* first;        // first[j*(smax+1) + s]: number of queue j's first task of
+                                 // stage s (within the queue); first[j*(smax+1) + smax] = its total
+    const int64_t* X;            // tile boundaries, as for swept_batch_kernel
+    Pt* re;
+    Pt* le[2];
+    int* done;                   // stages published, per tile (index tpos + t)
+    unsigned* counter;           // queue j's next task number at counter[j * kCounterStride]
+    int* fault;                  // set when a workgroup gives up waiting
+    int smax;
+    int queues;
+    uint64_t spin_ticks;         // 100 MHz ticks after which a wait gives up
+    int chunk;                   // task numbers taken per claim (1..32)
+};
+
+// The XCD this wave runs on (XCC_ID register, low four bits).
+__device__ __forceinline__ unsigned xcc_id()
+{
+    unsigned x;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+    return x & 0xfu;
+}
+
+__global__ __launch_bounds__(64) void xcc_probe_kernel(int* __restrict__ out)
+{
+    if (threadIdx.x == 0)
+        out[blockIdx.x] = (int)xcc_id();
+}
+constexpr int kCounterStride = 64;   // 256 bytes between the queues' counters
+
+// Wait until every lane's *p >= want (lanes with p == nullptr have nothing
+// to wait for); false if the wait gave up.  The bound is wall-clock time on
+// the 100 MHz real-time counter.
+__device__ __forceinline__ bool persist_wait(const int* p, int want, int* fault,
+                                             uint64_t limit_ticks)
+{
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    for (;;) {
+        const bool ok =
+            p == nullptr || __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want;
+        if (__all(ok))
+            return true;
+        if (__hip_atomic_load(fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+            __builtin_amdgcn_s_memrealtime() - t0 > limit_ticks) {
+            __hip_atomic_store(fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+template <class S, int P, bool XL>
+__device__ __forceinline__ void batch_persistent(const PersistArgs<S>& g)
+{
+    using Pt = typename S::Pt;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int lane = threadIdx.x;
+    const int j = XL ? (int)xcc_id() : (int)(blockIdx.x % (unsigned)g.queues);
+    if (j >= g.queues) {     // an XCD the host's probe did not see: report, run nothing
+        __hip_atomic_store(g.fault, 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    const BatchTask* tasks = g.tasks + g.toff[j];
+    const int64_t* first = g.first + (int64_t)j * (g.smax + 1);
+    unsigned* counter = g.counter + (int64_t)j * kCounterStride;
+    const int64_t total = first[g.smax];
+    int s = 0;    // this workgroup's stage; its task numbers only grow
+    for (;;) {
+        // claim `chunk` (<= 32) consecutive numbers; each run of them inside
+        // one stage waits for all its inputs (lane 2i: task i's own tile,
+        // lane 2i+1: its next tile) with one acquire, then runs them and
+        // publishes each (xcd_local) or the whole run (one agent release)
+        unsigned q0 = 0;
+        if (lane == 0)
+            q0 = atomicAdd(counter, (unsigned)g.chunk);
+        q0 = __builtin_amdgcn_readfirstlane(q0);
+        if ((int64_t)q0 >= total)
+            return;
+        const int64_t qe = (int64_t)q0 + g.chunk < total ? (int64_t)q0 + g.chunk : total;
+        for (int64_t q = q0; q < qe;) {
+            while (first[s + 1] <= q)
+                ++s;
+            const int64_t qs = qe < first[s + 1] ? qe : first[s + 1];
+            // the flag of lane 2i + side: task q+i's own tile (side 0) or next tile
+            int* flag = nullptr;
+            if (lane < 2 * (qs - q)) {
+                const BatchTask task = tasks[q + (lane >> 1) - first[s]];
+                const int tpos = g.inst[task.inst].tpos, T = g.inst[task.inst].tiles;
+                const int t = (lane & 1) ? (task.tile + 1 == T ? 0 : task.tile + 1) : task.tile;
+                flag = g.done + tpos + t;
+            }
+            if (s > 0) {
+                if (!persist_wait(flag, s, g.fault, g.spin_ticks))
+                    return;
+                if constexpr (XL)    // the edges are read with device-scope loads;
+                    asm volatile("" ::: "memory");   // keep them after the wait
+                else
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            for (int64_t x = q; x < qs; ++x) {
+                const BatchTask task = tasks[x - first[s]];
+                const BatchInst<S> I = g.inst[task.inst];
+                const int T = I.tiles;
+                const int64_t* X = g.X + I.x_off;
+                const int64_t n = I.n;
+                auto Xp = [&](int64_t i) { return X[i % T] + (i / T) * n; };
+                tiled_region<S, P, XL>(I.u, n, I.L, T, Xp, task.tile, s, g.re + I.e_off,
+                                       g.le[(s + 1) & 1] + I.e_off, g.le[s & 1] + I.e_off, I.c,
+                                       reinterpret_cast<Pt*>(smem_raw));
+                if constexpr (XL) {
+                    // publish at once: the release is only this wave's
+                    // stores reaching the shared L2
+                    __syncthreads();
+                    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                    if (lane == 2 * (x - q))
+                        __hip_atomic_store(flag, s + 1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            if constexpr (!XL) {
+                // one agent-scope release (an L2 write-back) for the whole run
+                __syncthreads();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                if (flag != nullptr && (lane & 1) == 0)
+                    __hip_atomic_store(flag, s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            q = qs;
+        }
+    }
+}
+
+// The task loop keeps a few more values live than one region does; the
+// bounds hold each stencil to the registers of the per-stage kernel's
+// occupancy (heat 8 waves per SIMD, KS 4).
+template <class S, int P, bool XL>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(S::kPersistWaves)))
+void swept_batch_persistent_kernel(PersistArgs<S> g)
+{
+    batch_persistent<S, P, XL>(g);
+}
+
+// After a persistent launch: every queue must have handed out all its task
+// numbers (a queue that no workgroup served would leave its instances
+// unfinished); fault = 2 otherwise.
+__global__ __launch_bounds__(64) void persist_check_kernel(const unsigned* __restrict__ counter,
+                                                           const int64_t* __restrict__ first,
+                                                           int smax, int queues,
+                                                           int* __restrict__ fault)
+{
+    for (int j = threadIdx.x; j < queues; j += blockDim.x)
+        if ((int64_t)counter[(int64_t)j * kCounterStride] < first[(int64_t)j * (smax + 1) + smax])
+            __hip_atomic_store(fault, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Zero the stage flags and the queues' counters before a persistent launch.
+__global__ __launch_bounds__(256) void persist_clear_kernel(int* __restrict__ done, int64_t n,
+                                                            unsigned* __restrict__ counter,
+                                                            int queues)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = i0; i < n; i += stride)
+        done[i] = 0;
+    for (int64_t j = i0; j < queues; j += stride)
+        counter[j * kCounterStride] = 0;
 }
 
 // One field on the same tiling, its boundaries computed instead of read from a

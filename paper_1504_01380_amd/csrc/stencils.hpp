@@ -56,6 +56,7 @@ struct Heat {
         T r;
     };
     static constexpr int NPHASE = 1;
+    static constexpr int kPersistWaves = 8;   // waves per SIMD of the persistent batch kernel
 
     __device__ __forceinline__ static Pt from_field(T v) { return Pt{v}; }
     __device__ __forceinline__ static T to_field(const Pt& p) { return p.u; }
@@ -126,6 +127,7 @@ struct KSF64 {
         double dt, h, c1, c2;
     };
     static constexpr int NPHASE = 4;
+    static constexpr int kPersistWaves = 4;   // waves per SIMD of the persistent batch kernel
 
     __device__ __forceinline__ static Pt from_field(double v) { return Pt{v, v, 0.0}; }
     __device__ __forceinline__ static double to_field(const Pt& p) { return p.u; }

@@ -43,6 +43,8 @@ struct Context {
     std::vector<hipEvent_t> events;   // events[i] before stage i, events[i+1] after it
     std::vector<int32_t> kinds;       // kernel used by each recorded stage
     int64_t recorded = 0;             // stages recorded by the last swept run
+    int* fault = nullptr;             // persistent batch: set by a wait that gave up
+    bool fault_unread = false;        // a persistent batch ran since swept_sync last looked
 };
 
 Context g_ctx;
@@ -280,6 +282,16 @@ std::map<std::pair<int, int>, Tuned> g_tuned;
 // Batch depth per stencil id chosen by swept_autotune_batch (0 = default).
 int64_t g_batch_want[3] = {0, 0, 0};
 constexpr int64_t kBatchWantDefault = 256;
+// swept_set_batch_schedule
+int g_batch_sched = SWEPT_BATCH_PERSISTENT;
+int64_t g_spin_limit = 0;               // microseconds; 0: kSpinDefault
+constexpr int64_t kSpinDefault = 60 * 1000 * 1000;
+// task numbers a workgroup of the persistent batch takes per claim
+constexpr int kChunkDefault = 2;
+int g_chunk = 0;                        // 0: kChunkDefault
+// independent queues of the persistent batch per stencil
+constexpr int kQueuesDefault = 32;
+int g_queues = 0;                       // 0: kQueuesDefault
 
 std::pair<int, int> tune_key(int id, int64_t nx)
 {
@@ -789,6 +801,172 @@ int launch_batch_stage(const BatchInst<S>* inst, const BatchTask* tasks, const i
     return SWEPT_OK;
 }
 
+// One stencil's persistent launch in a batch (swept_batch_persistent_kernel):
+// its instances split into Q queues by a greedy longest-first assignment of
+// their work (tiles x stages x k^2) to the least loaded queue; each queue's
+// tile list holds its instances in order of decreasing stage count, so
+// stage g's tasks are a prefix of it, numbered first[g] .. first[g+1]-1.
+struct PersistPlan {
+    std::vector<BatchTask> tasks;   // the queues' tile lists, one after another
+    std::vector<int64_t> toff;      // Q + 1 offsets into tasks
+    std::vector<int64_t> first;     // Q x (smax + 1)
+    int64_t max_total = 0;
+};
+
+PersistPlan persist_plan(const std::vector<BatchPlanInst>& P, bool ks, int64_t smax, int Q,
+                         std::vector<int>& tpos)
+{
+    PersistPlan pp;
+    std::vector<int64_t> ids;
+    auto work = [&](int64_t j) {
+        const BatchPlanInst& p = P[(size_t)j];
+        return (double)p.tiles * (double)p.stages * (double)p.kmax * (double)p.kmax;
+    };
+    for (int64_t j = 0; j < (int64_t)P.size(); ++j)
+        if ((P[(size_t)j].stencil == SWEPT_KS_F64) == ks && P[(size_t)j].L > 0)
+            ids.push_back(j);
+    std::stable_sort(ids.begin(), ids.end(), [&](int64_t x, int64_t y) { return work(x) > work(y); });
+    std::vector<std::vector<int64_t>> qi((size_t)Q);
+    std::vector<double> load((size_t)Q, 0.0);
+    for (int64_t j : ids) {
+        const size_t q = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+        qi[q].push_back(j);
+        load[q] += work(j);
+    }
+    pp.toff.push_back(0);
+    pp.first.assign((size_t)Q * (size_t)(smax + 1), 0);
+    for (int q = 0; q < Q; ++q) {
+        auto& v = qi[(size_t)q];
+        std::stable_sort(v.begin(), v.end(), [&](int64_t x, int64_t y) {
+            return P[(size_t)x].stages > P[(size_t)y].stages;
+        });
+        const int64_t base = (int64_t)pp.tasks.size();
+        for (int64_t j : v) {
+            tpos[(size_t)j] = (int)pp.tasks.size();
+            for (int t = 0; t < P[(size_t)j].tiles; ++t)
+                pp.tasks.push_back(BatchTask{(int)j, t});
+        }
+        pp.toff.push_back((int64_t)pp.tasks.size());
+        int64_t* f = pp.first.data() + (size_t)q * (size_t)(smax + 1);
+        size_t ptr = 0;
+        int64_t tiles_in = 0;    // tiles of the instances with more than g stages
+        for (int64_t g = 0; g < smax; ++g) {
+            while (ptr < v.size() && P[(size_t)v[ptr]].stages > g)
+                tiles_in += P[(size_t)v[ptr++]].tiles;
+            f[g + 1] = f[g] + tiles_in;
+        }
+        pp.max_total = std::max(pp.max_total, f[smax]);
+        (void)base;
+    }
+    return pp;
+}
+
+// The XCDs of the current device as the persistent batch sees them: m if
+// the XCC_ID values of 4096 one-wave workgroups are exactly 0..m-1 (the
+// hardware spreads workgroups over all XCDs), else 0 (agent-scope queues).
+std::map<int, int> g_xcds;
+
+int probe_xcds(int* m)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    auto it = g_xcds.find(dev);
+    if (it != g_xcds.end()) {
+        *m = it->second;
+        return SWEPT_OK;
+    }
+    constexpr int kBlocks = 4096;
+    int* d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(int) * kBlocks));
+    std::vector<int> h(kBlocks, -1);
+    hipLaunchKernelGGL(xcc_probe_kernel, dim3(kBlocks), dim3(64), 0, g_ctx.stream, d);
+    hipError_t e = hipMemcpyAsync(h.data(), d, sizeof(int) * kBlocks, hipMemcpyDeviceToHost,
+                                  g_ctx.stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(g_ctx.stream);
+    (void)hipFree(d);
+    if (e != hipSuccess)
+        return hip_fail(e, "XCD probe");
+    int hi = -1;
+    bool ok = true;
+    std::vector<int> seen(16, 0);
+    for (int x : h) {
+        ok = ok && x >= 0 && x < 16;
+        if (x >= 0 && x < 16) {
+            seen[(size_t)x] = 1;
+            hi = std::max(hi, x);
+        }
+    }
+    for (int x = 0; x <= hi; ++x)
+        ok = ok && seen[(size_t)x];
+    *m = ok ? hi + 1 : 0;
+    g_xcds[dev] = *m;
+    return SWEPT_OK;
+}
+
+template <class S>
+struct PersistLaunch {
+    PersistArgs<S> a{};
+    size_t lds = 0;
+    unsigned grid = 0;
+    int64_t tiles = 0;
+    bool xl = false;
+
+    int setup(const PersistPlan& pp, const BatchInst<S>* inst, const BatchTask* tasks,
+              const int64_t* toff, const int64_t* first, const int64_t* X,
+              typename S::Pt* edges, int64_t ering, int* done, unsigned* counter, int64_t smax,
+              int Q, bool xcd_local, int kmax, int64_t spin_limit)
+    {
+        tiles = (int64_t)pp.tasks.size();
+        if (pp.max_total <= 0)
+            return SWEPT_OK;
+        lds = (size_t)2 * kmax * sizeof(typename S::Pt);
+        int per_cu = 0, dev = 0;
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDevice(&dev));
+        HIP_TRY(hipGetDeviceProperties(&prop, dev));
+        xl = xcd_local;
+        const void* fn = xl ? reinterpret_cast<const void*>(&swept_batch_persistent_kernel<S, 2, true>)
+                            : reinterpret_cast<const void*>(&swept_batch_persistent_kernel<S, 2, false>);
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, lds));
+        // workgroup w serves queue w mod Q: at least one per queue
+        const int64_t resident = (int64_t)std::max(1, per_cu) * prop.multiProcessorCount;
+        grid = (unsigned)std::max<int64_t>(Q, resident / Q * Q);
+        a.inst = inst;
+        a.tasks = tasks;
+        a.toff = toff;
+        a.first = first;
+        a.X = X;
+        a.re = edges;
+        a.le[0] = edges + ering;
+        a.le[1] = edges + 2 * ering;
+        a.done = done;
+        a.counter = counter;
+        a.fault = g_ctx.fault;
+        a.smax = (int)smax;
+        a.queues = Q;
+        a.spin_ticks = (uint64_t)spin_limit * 100;   // the real-time counter runs at 100 MHz
+        a.chunk = g_chunk > 0 ? g_chunk : kChunkDefault;
+        return SWEPT_OK;
+    }
+
+    void launch(hipStream_t st) const
+    {
+        if (grid == 0)
+            return;
+        hipLaunchKernelGGL(persist_clear_kernel, dim3(grid_for(std::max<int64_t>(1, tiles), 256)),
+                           dim3(256), 0, st, a.done, tiles, a.counter, a.queues);
+        if (xl)
+            hipLaunchKernelGGL((swept_batch_persistent_kernel<S, 2, true>), dim3(grid), dim3(64),
+                               lds, st, a);
+        else
+            hipLaunchKernelGGL((swept_batch_persistent_kernel<S, 2, false>), dim3(grid), dim3(64),
+                               lds, st, a);
+        hipLaunchKernelGGL(persist_check_kernel, dim3(1), dim3(64), 0, st, a.counter, a.first,
+                           a.smax, a.queues, a.fault);
+    }
+};
+
 int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const int32_t* ids,
               const double* params, int64_t count)
 {
@@ -843,6 +1021,7 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
     std::vector<BatchTask> th, tk;
     std::vector<int64_t> sh, sk;  // stage count of the instance of each task
     int kmax_h = 1, kmax_k = 1;
+    std::vector<int> tpos((size_t)count, 0);
     for (int64_t j : order) {
         const BatchPlanInst& p = P[(size_t)j];
         if (p.L == 0)
@@ -859,6 +1038,27 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
     int64_t smax = 0;
     for (const auto& p : P)
         smax = std::max(smax, p.stages);
+    // persistent launches: each stencil's instances in Q queues, one per XCD
+    // unless a number of queues was set (or the XCDs could not be told apart)
+    const bool persist = g_batch_sched == SWEPT_BATCH_PERSISTENT;
+    int nxcd = 0;
+    if (persist && g_queues == 0) {
+        int rc0 = probe_xcds(&nxcd);
+        if (rc0)
+            return rc0;
+    }
+    const bool xcd_local = nxcd > 0;
+    const int Q = xcd_local ? nxcd : (g_queues > 0 ? g_queues : kQueuesDefault);
+    PersistPlan pph, ppk;
+    if (persist) {
+        pph = persist_plan(P, false, smax, Q, tpos);
+        ppk = persist_plan(P, true, smax, Q, tpos);
+        if (std::max(pph.max_total, ppk.max_total) >= (int64_t(1) << 31))
+            return fail(SWEPT_EUNSUPPORTED,
+                        "swept_advance_batch: %lld regions in one queue exceed the persistent "
+                        "launch's 2^31 task numbers (use SWEPT_BATCH_STAGED)",
+                        (long long)std::max(pph.max_total, ppk.max_total));
+    }
 
     // ---- device memory: [inst heat][inst ks][X][tasks h][tasks k][edges h][edges k][fields]
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
@@ -870,9 +1070,20 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
     const size_t b_eh = al(3 * (size_t)e_heat * sizeof(PtH));
     const size_t b_ek = al(3 * (size_t)e_ks * sizeof(PtK));
     const size_t b_f = al((size_t)f_tot * sizeof(double));
-    int rc = ensure_scratch(b_ih + b_ik + b_x + b_th + b_tk + b_eh + b_ek + b_f);
+    // persistent: [tasks h][tasks k][toff h, k][first h, k][done h, k][counters h, k]
+    const size_t b_pt = al(sizeof(BatchTask) * (pph.tasks.size() + ppk.tasks.size() + 1));
+    const size_t b_toff = al(sizeof(int64_t) * 2 * (size_t)(Q + 1));
+    const size_t b_first = al(sizeof(int64_t) * (pph.first.size() + ppk.first.size()));
+    const size_t b_done = al(sizeof(int) * (pph.tasks.size() + ppk.tasks.size() + 1));
+    const size_t b_cnt = al(sizeof(unsigned) * 2 * (size_t)Q * kCounterStride);
+    const size_t b_main = b_ih + b_ik + b_x + b_th + b_tk + b_eh + b_ek + b_f;
+    int rc = ensure_scratch(b_main + (persist ? b_pt + b_toff + b_first + b_done + b_cnt : 0));
     if (rc)
         return rc;
+    if (persist && !g_ctx.fault) {
+        HIP_TRY(hipMalloc(&g_ctx.fault, sizeof(int)));
+        HIP_TRY(hipMemset(g_ctx.fault, 0, sizeof(int)));
+    }
     unsigned char* base = static_cast<unsigned char*>(g_ctx.scratch);
     auto* d_ih = reinterpret_cast<BatchInst<HeatF64>*>(base);
     auto* d_ik = reinterpret_cast<BatchInst<KSF64>*>(base + b_ih);
@@ -882,6 +1093,11 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
     auto* d_eh = reinterpret_cast<PtH*>(base + b_ih + b_ik + b_x + b_th + b_tk);
     auto* d_ek = reinterpret_cast<PtK*>(base + b_ih + b_ik + b_x + b_th + b_tk + b_eh);
     auto* d_f = reinterpret_cast<double*>(base + b_ih + b_ik + b_x + b_th + b_tk + b_eh + b_ek);
+    auto* d_pt = reinterpret_cast<BatchTask*>(base + b_main);
+    auto* d_toff = reinterpret_cast<int64_t*>(base + b_main + b_pt);
+    auto* d_first = reinterpret_cast<int64_t*>(base + b_main + b_pt + b_toff);
+    auto* d_done = reinterpret_cast<int*>(base + b_main + b_pt + b_toff + b_first);
+    auto* d_cnt = reinterpret_cast<unsigned*>(base + b_main + b_pt + b_toff + b_first + b_done);
 
     std::vector<BatchInst<HeatF64>> ih((size_t)count);
     std::vector<BatchInst<KSF64>> ik((size_t)count);
@@ -889,11 +1105,11 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
         const BatchPlanInst& p = P[(size_t)j];
         double* field = p.f_off >= 0 ? d_f + p.f_off : static_cast<double*>(u[j]);
         if (p.stencil == SWEPT_KS_F64)
-            ik[(size_t)j] = BatchInst<KSF64>{field, p.n_ring, p.L, p.x_off, p.e_off, p.tiles, 0,
-                                            ks_consts(params + 2 * j)};
+            ik[(size_t)j] = BatchInst<KSF64>{field, p.n_ring, p.L, p.x_off, p.e_off, p.tiles,
+                                            tpos[(size_t)j], ks_consts(params + 2 * j)};
         else
-            ih[(size_t)j] = BatchInst<HeatF64>{field, p.n_ring, p.L, p.x_off, p.e_off, p.tiles, 0,
-                                              heat64_consts(params + 2 * j)};
+            ih[(size_t)j] = BatchInst<HeatF64>{field, p.n_ring, p.L, p.x_off, p.e_off, p.tiles,
+                                              tpos[(size_t)j], heat64_consts(params + 2 * j)};
     }
     HIP_TRY(hipStreamSynchronize(g_ctx.stream));
     HIP_TRY(hipMemcpy(d_ih, ih.data(), sizeof(BatchInst<HeatF64>) * (size_t)count, hipMemcpyHostToDevice));
@@ -903,6 +1119,20 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
         HIP_TRY(hipMemcpy(d_th, th.data(), sizeof(BatchTask) * th.size(), hipMemcpyHostToDevice));
     if (!tk.empty())
         HIP_TRY(hipMemcpy(d_tk, tk.data(), sizeof(BatchTask) * tk.size(), hipMemcpyHostToDevice));
+    if (persist) {
+        std::vector<BatchTask> pt(pph.tasks);
+        pt.insert(pt.end(), ppk.tasks.begin(), ppk.tasks.end());
+        std::vector<int64_t> toff(pph.toff), first(pph.first);
+        toff.insert(toff.end(), ppk.toff.begin(), ppk.toff.end());
+        first.insert(first.end(), ppk.first.begin(), ppk.first.end());
+        if (!pt.empty())
+            HIP_TRY(hipMemcpy(d_pt, pt.data(), sizeof(BatchTask) * pt.size(),
+                              hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(d_toff, toff.data(), sizeof(int64_t) * toff.size(),
+                          hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(d_first, first.data(), sizeof(int64_t) * first.size(),
+                          hipMemcpyHostToDevice));
+    }
 
     // ---- the launch sequence (captured once into a graph per batch)
     std::vector<int64_t> key;
@@ -919,13 +1149,33 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
     }
     key.push_back((int64_t)(intptr_t)g_ctx.scratch);
     key.push_back(g_ctx.tile_w);
+    key.push_back(g_batch_sched);
+    key.push_back(g_spin_limit);
+    key.push_back(g_chunk);
+    key.push_back(g_queues);
     for (int64_t w : g_batch_want)
         key.push_back(w);
     if (g_batch.exec && key == g_batch.key) {
         HIP_TRY(hipGraphLaunch(g_batch.exec, g_ctx.stream));
+        g_ctx.fault_unread |= persist;
         return SWEPT_OK;
     }
     batch_release();
+    // persistent launches: as many workgroups as can be resident at once
+    PersistLaunch<HeatF64> plh;
+    PersistLaunch<KSF64> plk;
+    if (persist) {
+        const int64_t lim = g_spin_limit > 0 ? g_spin_limit : kSpinDefault;
+        int rc2 = plh.setup(pph, d_ih, d_pt, d_toff, d_first, d_x, d_eh, e_heat, d_done, d_cnt,
+                            smax, Q, xcd_local, kmax_h, lim);
+        if (!rc2)
+            rc2 = plk.setup(ppk, d_ik, d_pt + pph.tasks.size(), d_toff + (Q + 1),
+                            d_first + pph.first.size(), d_x, d_ek, e_ks,
+                            d_done + pph.tasks.size(), d_cnt + (size_t)Q * kCounterStride, smax,
+                            Q, xcd_local, kmax_k, lim);
+        if (rc2)
+            return rc2;
+    }
     hipStream_t cs;
     HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
@@ -940,14 +1190,19 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
                                dim3(256), 0, cs, static_cast<const double*>(u[j]), d_f + p.f_off,
                                p.n_user, 2);
     }
-    size_t ph = 0, pk = 0;
-    for (int64_t g = 0; g < smax; ++g) {
-        while (ph < sh.size() && sh[ph] > g) ++ph;
-        while (pk < sk.size() && sk[pk] > g) ++pk;
-        launch_batch_stage<HeatF64>(d_ih, d_th, d_x, d_eh, d_eh + e_heat, d_eh + 2 * e_heat,
-                                    (int)g, (int64_t)ph, kmax_h, cs);
-        launch_batch_stage<KSF64>(d_ik, d_tk, d_x, d_ek, d_ek + e_ks, d_ek + 2 * e_ks, (int)g,
-                                  (int64_t)pk, kmax_k, cs);
+    if (persist) {
+        plh.launch(cs);
+        plk.launch(cs);
+    } else {
+        size_t ph = 0, pk = 0;
+        for (int64_t g = 0; g < smax; ++g) {
+            while (ph < sh.size() && sh[ph] > g) ++ph;
+            while (pk < sk.size() && sk[pk] > g) ++pk;
+            launch_batch_stage<HeatF64>(d_ih, d_th, d_x, d_eh, d_eh + e_heat, d_eh + 2 * e_heat,
+                                        (int)g, (int64_t)ph, kmax_h, cs);
+            launch_batch_stage<KSF64>(d_ik, d_tk, d_x, d_ek, d_ek + e_ks, d_ek + 2 * e_ks, (int)g,
+                                      (int64_t)pk, kmax_k, cs);
+        }
     }
     for (int64_t j = 0; j < count; ++j) {      // odd rings: copy one period back
         const BatchPlanInst& p = P[(size_t)j];
@@ -971,6 +1226,7 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
     g_batch.graph = graph;
     g_batch.exec = exec;
     HIP_TRY(hipGraphLaunch(exec, g_ctx.stream));
+    g_ctx.fault_unread |= persist;
     return SWEPT_OK;
 }
 
@@ -2049,6 +2305,47 @@ int swept_sync(void)
         return fail(SWEPT_ENOTINIT, "swept_init has not been called");
     HIP_TRY(hipStreamSynchronize(g_ctx.stream));
     HIP_TRY(hipGetLastError());
+    if (g_ctx.fault_unread && g_ctx.fault) {
+        int f = 0;
+        HIP_TRY(hipMemcpy(&f, g_ctx.fault, sizeof f, hipMemcpyDeviceToHost));
+        g_ctx.fault_unread = false;
+        if (f) {
+            HIP_TRY(hipMemset(g_ctx.fault, 0, sizeof f));
+            if (f == 1)
+                return fail(SWEPT_ETIMEOUT,
+                            "swept_advance_batch: a persistent launch gave up waiting for a "
+                            "region (spin limit %lld us); its fields are not valid",
+                            (long long)(g_spin_limit > 0 ? g_spin_limit : kSpinDefault));
+            return fail(SWEPT_EHIP,
+                        "swept_advance_batch: a persistent launch left a queue unserved (%s); "
+                        "its fields are not valid",
+                        f == 3 ? "a workgroup ran on an XCD the probe did not see"
+                               : "no workgroup took its last tasks");
+        }
+    }
+    return SWEPT_OK;
+}
+
+int swept_set_batch_schedule(int32_t schedule, int64_t spin_limit, int32_t chunk,
+                             int32_t queues)
+{
+    if (schedule != SWEPT_BATCH_PERSISTENT && schedule != SWEPT_BATCH_STAGED)
+        return fail(SWEPT_EINVAL, "swept_set_batch_schedule: unknown schedule %d", schedule);
+    if (spin_limit < 0)
+        return fail(SWEPT_EINVAL, "swept_set_batch_schedule: spin_limit %lld < 0",
+                    (long long)spin_limit);
+    if (chunk < 0 || chunk > 32)
+        return fail(SWEPT_EINVAL, "swept_set_batch_schedule: chunk %d outside [0, 32]", chunk);
+    if (spin_limit > (int64_t(1) << 40))
+        return fail(SWEPT_EINVAL, "swept_set_batch_schedule: spin_limit %lld us is too long",
+                    (long long)spin_limit);
+    if (queues < 0 || queues > 1024)
+        return fail(SWEPT_EINVAL, "swept_set_batch_schedule: queues %d outside [0, 1024]",
+                    queues);
+    g_batch_sched = schedule;
+    g_spin_limit = spin_limit;
+    g_chunk = chunk;
+    g_queues = queues;
     return SWEPT_OK;
 }
 
@@ -2062,9 +2359,15 @@ void swept_finalize(void)
         (void)hipFree(g_ctx.scratch);
     if (g_ctx.obj)
         (void)hipFree(g_ctx.obj);
+    if (g_ctx.fault)
+        (void)hipFree(g_ctx.fault);
     release_events();
     batch_release();
     swept_clear_tuning();
+    g_batch_sched = SWEPT_BATCH_PERSISTENT;
+    g_spin_limit = 0;
+    g_chunk = 0;
+    g_queues = 0;
     g_ctx = Context{};
 }
 

@@ -11,6 +11,7 @@ in (the scheme's local code), so the same emulation serves every stencil.
 from __future__ import annotations
 
 import math
+import random
 
 
 def heat_step(r):
@@ -333,6 +334,29 @@ def levels_complete(visits, n, L, k):
     return True, None
 
 
+class _Recorded(list):
+    """A list that logs (name, index, "r" or "w") for every element read or
+    written, into log[0] (a list, or None while not recording)."""
+
+    def __init__(self, data, name, log):
+        super().__init__(data)
+        self.name, self.log = name, log
+
+    def _note(self, i, kind):
+        if self.log[0] is None:
+            return
+        idx = range(*i.indices(len(self))) if isinstance(i, slice) else [i % len(self)]
+        self.log[0].extend((self.name, j, kind) for j in idx)
+
+    def __getitem__(self, i):
+        self._note(i, "r")
+        return super().__getitem__(i)
+
+    def __setitem__(self, i, v):
+        self._note(i, "w")
+        super().__setitem__(i, v)
+
+
 class _Offset:
     """A window of a flat list starting at `off` (a tile's slice of the edge
     buffer)."""
@@ -347,7 +371,9 @@ class _Offset:
         self.data[self.off + i] = v
 
 
-def simulate_tiles(u0, nsteps, ks_list, P, stencil, lanes=64, track=False, cont=False):
+def simulate_tiles(u0, nsteps, ks_list, P, stencil, lanes=64, track=False, cont=False,
+                   order="stage", seed=0, inplace=False, waits=("own", "next"),
+                   footprints=None, stages=None):
     """The swept schedule on tiles of unequal even widths 2*k_t (sum = N).
     Workgroup t keeps k_t pairs; at stage s its region is the rectangle of
     k_t pairs by k_{t+s} steps centred at J = (X_{t+s} + X_{t+1}) / 2 with
@@ -356,7 +382,21 @@ def simulate_tiles(u0, nsteps, ks_list, P, stencil, lanes=64, track=False, cont=
     Right edges live at offset X_t, left edges at offset X_{(t+s) mod T}.
     With cont, a square k x k region strictly below level L whose k is a
     multiple of lanes*P runs on the continuous-band schedule (as in
-    swept_batch_kernel), its cycles starting at phase b mod nph."""
+    swept_batch_kernel), its cycles starting at phase b mod nph.
+
+    order="stage" runs the regions stage by stage (the per-stage launches).
+    order="random" runs them in a random order (seeded) in which region
+    (t, s) only waits for what the persistent batch kernel waits for:
+    `waits` names "own" (stage s-1 of tile t) and "next" (stage s-1 of tile
+    t+1); a region whose wait is not met is never run early, and one that
+    is met may run at once.  Every tile runs `stages` regions (default: up
+    to the first stage whose regions all lie above the target level; the
+    batch host passes its bound 2 + (L + k - rem) T / h).  inplace=True
+    reads stage 0 from, and writes the final level into, one array, as the
+    kernels do.  With a dict
+    `footprints`, every region's reads and writes of the field and the edge
+    buffers are stored there under (t, s) as a set of (buffer, index,
+    "r"/"w")."""
     step, nph, from_field, to_field = stencil
     n = len(u0)
     T = len(ks_list)
@@ -370,19 +410,29 @@ def simulate_tiles(u0, nsteps, ks_list, P, stencil, lanes=64, track=False, cont=
         return X[r] + q * n
 
     L = nsteps * nph
-    u = list(u0)
-    out = list(u0)
+    log = [None]
+    u = _Recorded(u0, "u", log)
+    out = u if inplace else _Recorded(u0, "out", log)
     visits = {} if track else None
     if L == 0:
-        return u, visits
-    RE = [None] * n
-    LE = [[None] * n, [None] * n]
+        return list(u), visits
+    RE = _Recorded([None] * n, "re", log)
+    LE = [_Recorded([None] * n, "le0", log), _Recorded([None] * n, "le1", log)]
     band = lanes * P
-    s = 0
-    while True:
-        active = False
+
+    def region(t, s):
+        if footprints is None:
+            return region_body(t, s)
+        log[0] = []
+        ran = region_body(t, s)
+        footprints[(t, s)] = set(log[0])
+        log[0] = None
+        return ran
+
+    def region_body(t, s):
+        """Run region (t, s); False if it lies above the target level."""
         le_in, le_out = LE[(s + 1) % 2], LE[s % 2]
-        for t in range(T):
+        if True:
             kp, ks = ks_list[t], ks_list[(t + s) % T]
             J2 = Xp(t + s) + Xp(t + 1)
             assert J2 % 2 == 0
@@ -390,8 +440,7 @@ def simulate_tiles(u0, nsteps, ks_list, P, stencil, lanes=64, track=False, cont=
             b = (Xp(t + s) - Xp(t + 1)) // 2
             tri = s == 0
             if not tri and b >= L:
-                continue
-            active = True
+                return False
             re_off = X[t]
             le_off_out = X[(t + s) % T]
             le_off_in = X[(t + s) % T]   # written by workgroup t+1 at stage s-1
@@ -401,7 +450,7 @@ def simulate_tiles(u0, nsteps, ks_list, P, stencil, lanes=64, track=False, cont=
                 _cont_stage(0, J, b, kp, P, lanes, [_Offset(RE, re_off)], chain, step, nph, n,
                             visits)
                 le_out[le_off_out:le_off_out + 2 * ks] = chain
-                continue
+                return True
             for base in range(0, kp, band):
                 nvalid = min(band, kp - base)
                 tau_first = (ks - base) if tri else 0
@@ -463,7 +512,59 @@ def simulate_tiles(u0, nsteps, ks_list, P, stencil, lanes=64, track=False, cont=
                     d = base + e
                     RE[re_off + 2 * d], RE[re_off + 2 * d + 1] = B[e], A[e]
             le_out[le_off_out:le_off_out + 2 * ks] = chain
-        if not active:
+            return True
+
+    if order == "stage":
+        s = 0
+        while any([region(t, s) for t in range(T)]):
+            s += 1
+        return list(out), visits
+    assert order == "random"
+    if stages is None:     # every tile runs to the first stage at which all are above L
+        stages = 1
+        while any((Xp(t + stages) - Xp(t + 1)) // 2 < L for t in range(T)):
+            stages += 1
+    rng = random.Random(seed)
+    done = [0] * T                      # stages run, per tile
+    ready = lambda t: done[t] < stages and (  # noqa: E731
+        done[t] == 0 or "next" not in waits or done[(t + 1) % T] >= done[t])
+    while True:
+        cand = [t for t in range(T) if ready(t)]
+        if not cand:
             break
-        s += 1
-    return out, visits
+        t = rng.choice(cand)
+        region(t, done[t])
+        done[t] += 1
+    assert all(d == stages for d in done)
+    return list(out), visits
+
+
+def unordered_conflicts(footprints, T, waits=("own", "next")):
+    """Pairs of regions that the persistent kernel's two waits leave
+    unordered (neither reaches the other through (t, s-1) -> (t, s) and
+    (t+1, s-1) -> (t, s)) although one writes an element the other reads or
+    writes.  Empty when the waits order every conflicting access."""
+    stages = 1 + max(s for (_, s) in footprints)
+    # below[(t, s)]: every region that (t, s) waits for, directly or not
+    below = {}
+    for s in range(stages):
+        for t in range(T):
+            b = set()
+            if s > 0:
+                pre = ([(t, s - 1)] if "own" in waits else []) + \
+                    ([((t + 1) % T, s - 1)] if "next" in waits else [])
+                for p in pre:
+                    b.add(p)
+                    b |= below[p]
+            below[(t, s)] = b
+    writes = {r: {(a, i) for (a, i, k) in f if k == "w"} for r, f in footprints.items()}
+    touches = {r: {(a, i) for (a, i, _) in f} for r, f in footprints.items()}
+    bad = []
+    regions = sorted(footprints)
+    for x in regions:
+        for y in regions:
+            if x >= y or x in below[y] or y in below[x]:
+                continue
+            if writes[x] & touches[y] or writes[y] & touches[x]:
+                bad.append((x, y))
+    return bad

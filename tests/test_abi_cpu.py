@@ -162,3 +162,20 @@ def test_plan_has_no_cliff_for_awkward_grids(swept):
     p = swept.plan(4096, 100, "heat")
     assert (p["tile_w"], p["tiles"], p["mode"]) == (600, 7, swept.MODE_STAGE_RAGGED)
     swept.lib().swept_set_tuning(0, 0, 0)
+
+
+def test_batch_schedule_validation(swept):
+    """swept_set_batch_schedule needs no device and rejects unknown
+    schedules and negative spin limits."""
+    lib = swept.lib()
+    assert lib.swept_set_batch_schedule(2, 0, 0, 0) == -1
+    assert lib.swept_set_batch_schedule(-1, 0, 0, 0) == -1
+    assert lib.swept_set_batch_schedule(0, -5, 0, 0) == -1
+    assert "spin_limit" in swept.last_error()
+    assert lib.swept_set_batch_schedule(0, 0, -1, 0) == -1
+    assert lib.swept_set_batch_schedule(0, 0, 33, 0) == -1
+    assert "chunk" in swept.last_error()
+    assert lib.swept_set_batch_schedule(0, 0, 0, 1025) == -1
+    assert "queues" in swept.last_error()
+    assert lib.swept_set_batch_schedule(swept.BATCH_STAGED, 100, 4, 8) == 0
+    assert lib.swept_set_batch_schedule(swept.BATCH_PERSISTENT, 0, 0, 0) == 0

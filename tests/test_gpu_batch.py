@@ -1,6 +1,8 @@
 """Batched swept runs: every instance of a batch equals its own oracle run
 bit for bit (odd and even lengths, heat and KS, different step counts, tiles
-of unequal width), also when the captured graph is launched again."""
+of unequal width), also when the captured graph is launched again, on both
+schedules (one persistent launch, and one launch per stage); a persistent
+wait that gives up is reported, and the next batch is whole again."""
 import numpy as np
 import pytest
 
@@ -20,6 +22,14 @@ def sw():
     swept.set_tuning(0, 0, swept.MODE_AUTO)
     yield swept
     swept.set_tuning(0, 0, swept.MODE_AUTO)
+    swept.set_batch_schedule(swept.BATCH_PERSISTENT, 0)
+
+
+@pytest.fixture(autouse=True)
+def _default_schedule(sw):
+    sw.set_batch_schedule(sw.BATCH_PERSISTENT, 0)
+    yield
+    sw.set_batch_schedule(sw.BATCH_PERSISTENT, 0)
 
 
 def oracle_run(oracle_mod, stencil, u0, nsteps):
@@ -28,10 +38,12 @@ def oracle_run(oracle_mod, stencil, u0, nsteps):
     return oracle_mod.ks(u0, nsteps, *KS_P)
 
 
+@pytest.mark.parametrize("schedule", [0, 1])
 @pytest.mark.parametrize("tile", [0, 64, 16])
-def test_mixed_batch_bitwise(sw, oracle_mod, tile):
+def test_mixed_batch_bitwise(sw, oracle_mod, tile, schedule):
     import torch
     sw.set_tuning(tile, 0, sw.MODE_AUTO)
+    sw.set_batch_schedule(schedule, 0)
     g = workloads.rng(2024 + tile)
     sizes = [256, 257, 300, 1001, 2048, 3, 4, 999, 4096, 777, 513, 64]
     insts = []
@@ -131,3 +143,56 @@ def test_full_ensemble(sw, oracle_mod):
                 else oracle_mod.ks(i.u0, i.nsteps, *KS_P, threads=threads))
         print(key, i.n, i.nsteps, flush=True)
         assert same_bits(us[q].cpu().numpy(), want)
+
+
+def _ensemble_sample(count, seed, smin, smax):
+    insts = workloads.batch(count=count, seed=seed, smin=smin, smax=smax)
+    return (insts, [i.nsteps for i in insts], [i.stencil for i in insts],
+            [[0.25] if i.stencil == "heat" else KS_P for i in insts])
+
+
+@pytest.mark.parametrize("chunk,queues", [(1, 0), (3, 0), (0, 0), (32, 0), (1, 1), (3, 7),
+                                          (32, 64), (2, 1024)])
+def test_persistent_equals_staged(sw, chunk, queues):
+    """The two schedules run the same regions: the same bits on a sample of
+    the ensemble (sizes log-uniform in [256, 65536], odd ones included), for
+    claims of one task, of a few (runs that often cross a stage), the
+    default and many; on one queue per XCD (the default), and on one queue,
+    a few and more queues than instances with agent-scope hand-over."""
+    import torch
+    insts, ns, kinds, pars = _ensemble_sample(256, 11, 200, 2000)
+    got = {}
+    for sched in (sw.BATCH_STAGED, sw.BATCH_PERSISTENT):
+        sw.set_batch_schedule(sched, 0, chunk, queues)
+        us = [torch.from_numpy(i.u0).cuda() for i in insts]
+        print("schedule", sched, flush=True)
+        sw.advance_batch(us, ns, kinds, pars)
+        torch.cuda.synchronize()
+        sw.sync()
+        got[sched] = us
+    for q, (a, b) in enumerate(zip(got[0], got[1])):
+        assert torch.equal(a.view(torch.int64), b.view(torch.int64)), q
+
+
+def test_persistent_wait_that_gives_up_is_reported(sw, oracle_mod):
+    """A spin limit of one microsecond, set from the host: the regions of
+    later stages give up waiting, every workgroup leaves, and swept_sync
+    reports SWEPT_ETIMEOUT once; with the default limit the same batch is
+    whole."""
+    import torch
+    g = workloads.rng(5)
+    u0 = g.uniform(-1, 1, size=8192)
+    u = torch.from_numpy(u0.copy()).cuda()
+    sw.set_batch_schedule(sw.BATCH_PERSISTENT, 1)
+    sw.advance_batch([u], [3000], ["heat"], [[0.25]])
+    torch.cuda.synchronize()
+    with pytest.raises(sw.SweptError) as err:
+        sw.sync()
+    assert err.value.code == -6 and "gave up" in str(err.value)
+    sw.sync()                                  # reported once
+    sw.set_batch_schedule(sw.BATCH_PERSISTENT, 0)
+    u.copy_(torch.from_numpy(u0))
+    sw.advance_batch([u], [3000], ["heat"], [[0.25]])
+    torch.cuda.synchronize()
+    sw.sync()
+    assert same_bits(u.cpu().numpy(), oracle_mod.heat(u0, 3000, 0.25))

@@ -297,3 +297,99 @@ def test_single_field_unequal_plan(oracle_mod, n, nsteps, stencil):
     last = max(s for s in range(1, 4 * L + 4)
                if any((Xp(t + s) - Xp(t + 1)) // 2 < L for t in range(T)))
     assert last + 1 <= p["stages"] <= last + 3
+
+
+def _lanes(stencil):
+    """Emulated lanes per band: the KS band must hold a multiple of four pairs
+    (its cycles start at a fixed phase of the four sub-timesteps)."""
+    return 4 if stencil == "ks" else 2
+
+
+def _case(oracle_mod, stencil, n, nsteps):
+    if stencil == "heat":
+        u0 = workloads.white_noise(n, seed=n)
+        return u0, swept_sim.heat_step(0.25), nsteps, oracle_mod.heat(u0, nsteps, 0.25)
+    u0 = workloads.smoothed_noise(n, seed=n)
+    return (u0, swept_sim.ks_step(0.005, 0.5), 4 * nsteps,
+            oracle_mod.ks(u0, nsteps, 0.005, 0.5))
+
+
+PERSIST_CASES = [
+    ([3, 7, 2, 5, 6], 40, "heat", False), (_split(50, 8), 61, "heat", False),
+    ([6], 30, "heat", False), ([4, 4], 19, "heat", False), ([1, 1, 2], 9, "heat", False),
+    ([4, 5, 4], 7, "ks", False), (_split(21, 4), 6, "ks", False),
+    ([8, 8, 8], 11, "heat", True), ([8, 8, 8, 2], 9, "ks", True),
+]
+
+
+@pytest.mark.parametrize("ks_list,nsteps,stencil,cont", PERSIST_CASES)
+def test_persistent_waits_order_every_conflict(oracle_mod, ks_list, nsteps, stencil, cont):
+    """The persistent batch kernel lets region (t, s) run as soon as stage s-1
+    of tiles t and t+1 is published.  Every pair of regions those two waits
+    leave unordered must touch disjoint data: no element of the field or of
+    the edge buffers that one writes is read or written by the other, so
+    any interleaving of concurrent regions gives the stage-by-stage bits."""
+    n = 2 * sum(ks_list)
+    u0, st, _, want = _case(oracle_mod, stencil, n, nsteps)
+    fp = {}
+    got, _ = swept_sim.simulate_tiles(list(u0), nsteps, ks_list, 1, st, lanes=_lanes(stencil),
+                                      cont=cont, inplace=True, footprints=fp)
+    assert same_bits(np.array(got), want)
+    assert swept_sim.unordered_conflicts(fp, len(ks_list)) == []
+
+
+@pytest.mark.parametrize("ks_list,nsteps,stencil,cont", PERSIST_CASES)
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_persistent_orders_bitwise(oracle_mod, ks_list, nsteps, stencil, cont, seed):
+    """Regions run in random orders that respect only the two waits, on one
+    in-place field: every (point, level) exactly once, the oracle's bits."""
+    n = 2 * sum(ks_list)
+    u0, st, L, want = _case(oracle_mod, stencil, n, nsteps)
+    got, visits = swept_sim.simulate_tiles(list(u0), nsteps, ks_list, 1, st,
+                                           lanes=_lanes(stencil), track=True, cont=cont,
+                                           order="random", seed=seed, inplace=True)
+    ok, why = swept_sim.levels_complete(visits, n, L, 0)
+    assert ok, why
+    assert same_bits(np.array(got), want)
+
+
+@pytest.mark.parametrize("n,k,nsteps,stencil", [(100, 8, 61, "heat"), (42, 4, 6, "ks"),
+                                                (34, 17, 20, "heat")])
+def test_persistent_host_stage_bound(oracle_mod, n, k, nsteps, stencil):
+    """The batch host's stage count 2 + (L + k - rem) T / h, run by every tile
+    of the plan's split in a random order, completes the instance."""
+    ks_list = _split(n // 2, k)
+    u0, st, L, want = _case(oracle_mod, stencil, n, nsteps)
+    T, h, rem = len(ks_list), n // 2, ks_list[-1]
+    kt = ks_list[0] if T > 1 else h
+    stages = 2 + (L + kt - rem) * T // h
+    got, visits = swept_sim.simulate_tiles(list(u0), nsteps, ks_list, 1, st,
+                                           lanes=_lanes(stencil), track=True, order="random",
+                                           seed=n, inplace=True, stages=stages)
+    ok, why = swept_sim.levels_complete(visits, n, L, 0)
+    assert ok, why
+    assert same_bits(np.array(got), want)
+
+
+def test_persistent_without_the_next_wait_is_caught(oracle_mod):
+    """Planted in the emulation: with only the own-tile wait, regions that
+    read a neighbour's edge are left unordered against the region that
+    writes it -- the footprint check names them, and a random order gives
+    wrong bits or runs a region before its input exists."""
+    ks_list, nsteps = [4, 4, 4], 20
+    n = 2 * sum(ks_list)
+    u0, st, _, want = _case(oracle_mod, "heat", n, nsteps)
+    fp = {}
+    swept_sim.simulate_tiles(list(u0), nsteps, ks_list, 1, st, lanes=2, inplace=True,
+                             footprints=fp)
+    assert swept_sim.unordered_conflicts(fp, len(ks_list), waits=("own",))
+    wrong = 0
+    for seed in range(5):
+        try:
+            got, _ = swept_sim.simulate_tiles(list(u0), nsteps, ks_list, 1, st, lanes=2,
+                                              order="random", seed=seed, inplace=True,
+                                              waits=("own",))
+            wrong += not same_bits(np.array(got), want)
+        except TypeError:      # an edge read before any region wrote it (None)
+            wrong += 1
+    assert wrong > 0
