@@ -1004,6 +1004,31 @@ __global__ __launch_bounds__(64) void swept_ragged_kernel(RaggedArgs<S> g)
                        reinterpret_cast<Pt*>(smem_raw));
 }
 
+// The two-fold covers of a batch's odd rings in one launch: entry i copies
+// dst[j] = src[j mod n] for j < copies * n, with kCoverBlocks workgroups per
+// entry.
+struct CoverEntry {
+    const double* src;
+    double* dst;
+    int64_t n;
+    int64_t copies;
+};
+constexpr int kCoverBlocks = 8;
+
+__global__ __launch_bounds__(256) void batch_cover_all_kernel(const CoverEntry* __restrict__ tab,
+                                                             int count)
+{
+    const int i = (int)(blockIdx.x / kCoverBlocks);
+    if (i >= count)
+        return;
+    const CoverEntry e = tab[i];
+    const int64_t total = e.copies * e.n;
+    const int64_t stride = (int64_t)kCoverBlocks * blockDim.x;
+    for (int64_t j = (int64_t)(blockIdx.x % kCoverBlocks) * blockDim.x + threadIdx.x; j < total;
+         j += stride)
+        e.dst[j] = e.src[j % e.n];
+}
+
 template <class S>
 __global__ __launch_bounds__(256) void batch_cover_kernel(const typename S::T* __restrict__ src,
                                                          typename S::T* __restrict__ dst,

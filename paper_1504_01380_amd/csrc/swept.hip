@@ -1076,7 +1076,11 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
     const size_t b_first = al(sizeof(int64_t) * (pph.first.size() + ppk.first.size()));
     const size_t b_done = al(sizeof(int) * (pph.tasks.size() + ppk.tasks.size() + 1));
     const size_t b_cnt = al(sizeof(unsigned) * 2 * (size_t)Q * kCounterStride);
-    const size_t b_main = b_ih + b_ik + b_x + b_th + b_tk + b_eh + b_ek + b_f;
+    int ncover = 0;
+    for (const auto& p : P)
+        ncover += p.f_off >= 0;
+    const size_t b_cov = al(sizeof(CoverEntry) * 2 * (size_t)std::max(1, ncover));
+    const size_t b_main = b_ih + b_ik + b_x + b_th + b_tk + b_eh + b_ek + b_f + b_cov;
     int rc = ensure_scratch(b_main + (persist ? b_pt + b_toff + b_first + b_done + b_cnt : 0));
     if (rc)
         return rc;
@@ -1093,6 +1097,7 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
     auto* d_eh = reinterpret_cast<PtH*>(base + b_ih + b_ik + b_x + b_th + b_tk);
     auto* d_ek = reinterpret_cast<PtK*>(base + b_ih + b_ik + b_x + b_th + b_tk + b_eh);
     auto* d_f = reinterpret_cast<double*>(base + b_ih + b_ik + b_x + b_th + b_tk + b_eh + b_ek);
+    auto* d_cov = reinterpret_cast<CoverEntry*>(base + b_main - b_cov);   // in, then out
     auto* d_pt = reinterpret_cast<BatchTask*>(base + b_main);
     auto* d_toff = reinterpret_cast<int64_t*>(base + b_main + b_pt);
     auto* d_first = reinterpret_cast<int64_t*>(base + b_main + b_pt + b_toff);
@@ -1119,6 +1124,21 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
         HIP_TRY(hipMemcpy(d_th, th.data(), sizeof(BatchTask) * th.size(), hipMemcpyHostToDevice));
     if (!tk.empty())
         HIP_TRY(hipMemcpy(d_tk, tk.data(), sizeof(BatchTask) * tk.size(), hipMemcpyHostToDevice));
+    if (ncover > 0) {
+        std::vector<CoverEntry> cov(2 * (size_t)ncover);
+        size_t c = 0;
+        for (int64_t j = 0; j < count; ++j) {
+            const BatchPlanInst& p = P[(size_t)j];
+            if (p.f_off < 0)
+                continue;
+            cov[c] = CoverEntry{static_cast<const double*>(u[j]), d_f + p.f_off, p.n_user, 2};
+            cov[(size_t)ncover + c] =
+                CoverEntry{d_f + p.f_off, static_cast<double*>(u[j]), p.n_user, 1};
+            ++c;
+        }
+        HIP_TRY(hipMemcpy(d_cov, cov.data(), sizeof(CoverEntry) * cov.size(),
+                          hipMemcpyHostToDevice));
+    }
     if (persist) {
         std::vector<BatchTask> pt(pph.tasks);
         pt.insert(pt.end(), ppk.tasks.begin(), ppk.tasks.end());
@@ -1176,23 +1196,52 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
         if (rc2)
             return rc2;
     }
-    hipStream_t cs;
+    // the two persistent launches run side by side on a forked branch of the
+    // graph (each waits only on its own regions, so either may start first)
+    const bool fork = persist && plh.grid > 0 && plk.grid > 0;
+    hipStream_t cs, cs2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    auto release_capture_objects = [&]() {
+        (void)hipStreamDestroy(cs);
+        if (cs2)
+            (void)hipStreamDestroy(cs2);
+        if (ev_fork)
+            (void)hipEventDestroy(ev_fork);
+        if (ev_join)
+            (void)hipEventDestroy(ev_join);
+    };
+    if (fork) {
+        hipError_t e0 = hipStreamCreateWithFlags(&cs2, hipStreamNonBlocking);
+        if (e0 == hipSuccess)
+            e0 = hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming);
+        if (e0 == hipSuccess)
+            e0 = hipEventCreateWithFlags(&ev_join, hipEventDisableTiming);
+        if (e0 != hipSuccess) {
+            release_capture_objects();
+            return hip_fail(e0, "batch graph streams");
+        }
+    }
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
-        (void)hipStreamDestroy(cs);
+        release_capture_objects();
         return hip_fail(e, "hipStreamBeginCapture");
     }
-    for (int64_t j = 0; j < count; ++j) {      // odd rings: build the two-fold cover
-        const BatchPlanInst& p = P[(size_t)j];
-        if (p.f_off >= 0)
-            hipLaunchKernelGGL((batch_cover_kernel<HeatF64>), dim3(grid_for(p.n_ring, 256)),
-                               dim3(256), 0, cs, static_cast<const double*>(u[j]), d_f + p.f_off,
-                               p.n_user, 2);
-    }
+    if (ncover > 0)          // odd rings: build the two-fold covers
+        hipLaunchKernelGGL(batch_cover_all_kernel, dim3((unsigned)(ncover * kCoverBlocks)),
+                           dim3(256), 0, cs, d_cov, ncover);
     if (persist) {
+        if (fork) {
+            (void)hipEventRecord(ev_fork, cs);
+            (void)hipStreamWaitEvent(cs2, ev_fork, 0);
+            plk.launch(cs2);
+            (void)hipEventRecord(ev_join, cs2);
+        }
         plh.launch(cs);
-        plk.launch(cs);
+        if (fork)
+            (void)hipStreamWaitEvent(cs, ev_join, 0);
+        else
+            plk.launch(cs);
     } else {
         size_t ph = 0, pk = 0;
         for (int64_t g = 0; g < smax; ++g) {
@@ -1204,16 +1253,12 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
                                       (int64_t)pk, kmax_k, cs);
         }
     }
-    for (int64_t j = 0; j < count; ++j) {      // odd rings: copy one period back
-        const BatchPlanInst& p = P[(size_t)j];
-        if (p.f_off >= 0)
-            hipLaunchKernelGGL((batch_cover_kernel<HeatF64>), dim3(grid_for(p.n_user, 256)),
-                               dim3(256), 0, cs, d_f + p.f_off, static_cast<double*>(u[j]),
-                               p.n_user, 1);
-    }
+    if (ncover > 0)          // odd rings: copy one period back
+        hipLaunchKernelGGL(batch_cover_all_kernel, dim3((unsigned)(ncover * kCoverBlocks)),
+                           dim3(256), 0, cs, d_cov + ncover, ncover);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cs, &graph);
-    (void)hipStreamDestroy(cs);
+    release_capture_objects();
     if (e != hipSuccess)
         return hip_fail(e, "hipStreamEndCapture");
     hipGraphExec_t exec = nullptr;
