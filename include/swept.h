@@ -337,10 +337,12 @@ int swept_autotune(int64_t nx, int64_t nsteps, int32_t stencil_id, const double 
                    int32_t nparams, double *report);
 
 /*
- * Autotuner for swept_advance_batch: for each binary64 stencil present, times
- * the batch's own shapes (zero fields, each instance's steps cut to at most
- * 3072 sub-timesteps) at depths k = 128, 256, 384, 512 and keeps the fastest
- * for later batches.  depth_out (host, 3 entries indexed by stencil id)
+ * Autotuner for swept_advance_batch: times the batch's own shapes (zero
+ * fields; every step count scaled by one factor so that the longest instance
+ * runs 6144 sub-timesteps, the others in proportion) under the current
+ * schedule, best of two runs each, choosing the depth k in {128, 256, 384,
+ * 512} for KS and then for heat (each with the other's depth set, since the
+ * two stencils' launches overlap), and keeps the choice for later batches.  depth_out (host, 3 entries indexed by stencil id)
  * receives the chosen depth, 0 for a stencil not in the batch.  Allocates
  * and frees its own probe fields; synchronizes the stream.
  */
