@@ -277,13 +277,16 @@ enum {
  *    60 s; a wait normally lasts at most a few regions' run times);
  *  - chunk: task numbers a workgroup takes per claim (0: the default, 2);
  *    each run of them inside one stage shares one wait for its inputs;
- *  - queues: independent schedules per stencil, the instances spread over
+ *  - queues: independent schedules per stencil, whole instances spread over
  *    them by work, each with its own counter.  0, the default: one queue
  *    per XCD, served only by the workgroups running on that XCD (so one L2
  *    holds every exchange of an instance and the hand-over needs no L2
  *    write-back), when a probe of the XCC_ID values tells the XCDs apart,
- *    else 32 queues; a positive number: that many queues, workgroup w
- *    serving queue w mod queues, the hand-over at agent scope.
+ *    else 32 queues; and a batch whose instances cannot be spread evenly
+ *    (a queue with more than 1.25 times the mean work: a few large
+ *    instances, which would leave XCDs idle) runs one launch per stage
+ *    instead.  A positive number: that many queues, always persistent,
+ *    workgroup w serving queue w mod queues, the hand-over at agent scope.
  * Needs no device; kept until swept_finalize.  SWEPT_EINVAL for an unknown
  * schedule, a limit below 0 or above 2^40 us, a chunk outside [0, 32] or
  * queues outside [0, 1024].

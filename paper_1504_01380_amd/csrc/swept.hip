@@ -292,6 +292,9 @@ int g_chunk = 0;                        // 0: kChunkDefault
 // independent queues of the persistent batch per stencil
 constexpr int kQueuesDefault = 32;
 int g_queues = 0;                       // 0: kQueuesDefault
+// the persistent batch runs only when its most loaded queue carries at most
+// this multiple of the mean work (else one launch per stage)
+constexpr double kQueueImbalance = 1.25;
 
 std::pair<int, int> tune_key(int id, int64_t nx)
 {
@@ -811,6 +814,7 @@ struct PersistPlan {
     std::vector<int64_t> toff;      // Q + 1 offsets into tasks
     std::vector<int64_t> first;     // Q x (smax + 1)
     int64_t max_total = 0;
+    double load_max = 0.0, load_mean = 0.0;   // work per queue
 };
 
 PersistPlan persist_plan(const std::vector<BatchPlanInst>& P, bool ks, int64_t smax, int Q,
@@ -832,6 +836,10 @@ PersistPlan persist_plan(const std::vector<BatchPlanInst>& P, bool ks, int64_t s
         const size_t q = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
         qi[q].push_back(j);
         load[q] += work(j);
+    }
+    for (double l : load) {
+        pp.load_max = std::max(pp.load_max, l);
+        pp.load_mean += l / Q;
     }
     pp.toff.push_back(0);
     pp.first.assign((size_t)Q * (size_t)(smax + 1), 0);
@@ -1039,8 +1047,11 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
     for (const auto& p : P)
         smax = std::max(smax, p.stages);
     // persistent launches: each stencil's instances in Q queues, one per XCD
-    // unless a number of queues was set (or the XCDs could not be told apart)
-    const bool persist = g_batch_sched == SWEPT_BATCH_PERSISTENT;
+    // unless a number of queues was set (or the XCDs could not be told apart).
+    // A queue holds whole instances, so a batch whose instances cannot be
+    // spread evenly (a few large ones) would leave XCDs idle: such a batch
+    // takes one launch per stage instead.
+    bool persist = g_batch_sched == SWEPT_BATCH_PERSISTENT;
     int nxcd = 0;
     if (persist && g_queues == 0) {
         int rc0 = probe_xcds(&nxcd);
@@ -1053,6 +1064,16 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
     if (persist) {
         pph = persist_plan(P, false, smax, Q, tpos);
         ppk = persist_plan(P, true, smax, Q, tpos);
+        auto uneven = [](const PersistPlan& pp) {
+            return pp.load_max > kQueueImbalance * pp.load_mean;
+        };
+        if (g_queues == 0 && (uneven(pph) || uneven(ppk))) {
+            persist = false;
+            pph = PersistPlan{};
+            ppk = PersistPlan{};
+        }
+    }
+    if (persist) {
         if (std::max(pph.max_total, ppk.max_total) >= (int64_t(1) << 31))
             return fail(SWEPT_EUNSUPPORTED,
                         "swept_advance_batch: %lld regions in one queue exceed the persistent "

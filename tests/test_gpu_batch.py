@@ -174,25 +174,52 @@ def test_persistent_equals_staged(sw, chunk, queues):
         assert torch.equal(a.view(torch.int64), b.view(torch.int64)), q
 
 
-def test_persistent_wait_that_gives_up_is_reported(sw, oracle_mod):
+@pytest.mark.parametrize("count,queues", [(64, 0), (1, 1)])
+def test_persistent_wait_that_gives_up_is_reported(sw, oracle_mod, count, queues):
     """A spin limit of one microsecond, set from the host: the regions of
     later stages give up waiting, every workgroup leaves, and swept_sync
     reports SWEPT_ETIMEOUT once; with the default limit the same batch is
-    whole."""
+    whole.  On one queue per XCD (64 instances, which spread evenly) and on
+    one agent-scope queue (one instance)."""
     import torch
     g = workloads.rng(5)
-    u0 = g.uniform(-1, 1, size=8192)
-    u = torch.from_numpy(u0.copy()).cuda()
-    sw.set_batch_schedule(sw.BATCH_PERSISTENT, 1)
-    sw.advance_batch([u], [3000], ["heat"], [[0.25]])
+    u0s = [g.uniform(-1, 1, size=8192 + 2 * q) for q in range(count)]
+    us = [torch.from_numpy(u0.copy()).cuda() for u0 in u0s]
+    args = ([3000] * count, ["heat"] * count, [[0.25]] * count)
+    sw.set_batch_schedule(sw.BATCH_PERSISTENT, 1, 0, queues)
+    sw.advance_batch(us, *args)
     torch.cuda.synchronize()
     with pytest.raises(sw.SweptError) as err:
         sw.sync()
     assert err.value.code == -6 and "gave up" in str(err.value)
     sw.sync()                                  # reported once
-    sw.set_batch_schedule(sw.BATCH_PERSISTENT, 0)
-    u.copy_(torch.from_numpy(u0))
-    sw.advance_batch([u], [3000], ["heat"], [[0.25]])
+    sw.set_batch_schedule(sw.BATCH_PERSISTENT, 0, 0, queues)
+    for u, u0 in zip(us, u0s):
+        u.copy_(torch.from_numpy(u0))
+    sw.advance_batch(us, *args)
     torch.cuda.synchronize()
     sw.sync()
-    assert same_bits(u.cpu().numpy(), oracle_mod.heat(u0, 3000, 0.25))
+    for q in (0, count - 1):
+        assert same_bits(us[q].cpu().numpy(), oracle_mod.heat(u0s[q], 3000, 0.25))
+
+
+def test_few_large_instances(sw):
+    """A batch of a few large instances (which one queue per XCD cannot spread
+    evenly, so it runs one launch per stage) equals the instances' own
+    swept_advance runs."""
+    import torch
+    g = workloads.rng(8)
+    insts = [("heat", 1 << 20, 700), ("ks", 1 << 18, 150), ("heat", 3 * 65536 + 2, 301)]
+    us, solo = [], []
+    for st, n, ns in insts:
+        u0 = g.uniform(-1, 1, size=n) if st == "heat" else workloads.smoothed_noise(n, seed=n)
+        us.append(torch.from_numpy(u0).cuda())
+        v = torch.from_numpy(u0).cuda()
+        sw.advance(v, ns, st, [0.25] if st == "heat" else KS_P)
+        solo.append(v)
+    sw.advance_batch(us, [ns for _, _, ns in insts], [st for st, _, _ in insts],
+                     [[0.25] if st == "heat" else KS_P for st, _, _ in insts])
+    torch.cuda.synchronize()
+    sw.sync()
+    for q, (a, b) in enumerate(zip(us, solo)):
+        assert torch.equal(a.view(torch.int64), b.view(torch.int64)), q
