@@ -8,8 +8,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "swept.hip")
 DEPS = [os.path.join(PKG, "csrc", f) for f in ("stencils.hpp", "kernels.hpp")] + \
-    [os.path.join(ROOT, "include", "swept.h")]
+    [os.path.join(ROOT, "include", h) for h in ("swept.h", "swept_debug.h")]
 LIB = os.path.join(PKG, "libswept.so")
+LIB_COUNT = os.path.join(PKG, "libswept_count.so")
 ARCH = os.environ.get("SWEPT_OFFLOAD_ARCH", "gfx950")
 
 # -ffp-contract=off: no fused multiply-add, so every schedule gives the
@@ -22,15 +23,24 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile csrc/swept.hip into libswept.so next to this file."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["hipcc", *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"),
+def _compile(out: str, extra, verbose: bool) -> str:
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = ["hipcc", *HIPCC_FLAGS, *extra, "-I", os.path.join(ROOT, "include"),
            "-I", os.path.join(PKG, "csrc"), SRC, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False, counting: bool = True) -> str:
+    """Compile csrc/swept.hip into libswept.so next to this file and, with
+    counting, the test build libswept_count.so (SWEPT_COUNT_UPDATES: the
+    stage kernels count their point updates)."""
+    _compile(LIB, [], verbose)
+    if counting:
+        _compile(LIB_COUNT, ["-DSWEPT_COUNT_UPDATES"], verbose)
     return LIB
 
 

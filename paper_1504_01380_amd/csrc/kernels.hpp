@@ -124,6 +124,23 @@ constexpr bool face_phase()
 // One wave step of a band: every active pair advances one level.  Pairs are
 // visited from the last to the first so that pair q still reads pair q-1's
 // state from the previous step.
+// Debug build (SWEPT_COUNT_UPDATES): the stage kernels count every point
+// update they compute, two per active pair and wave step, so that a test
+// can check that a run computes each (point, sub-timestep level) once and no
+// more -- the swept rule's "no redundant computation" (Section 3) -- on the
+// GPU itself.  A no-op in the normal build.
+#ifdef SWEPT_COUNT_UPDATES
+__device__ unsigned long long g_update_count;
+__device__ __forceinline__ void count_pairs(bool act)
+{
+    const unsigned long long m = __ballot(act);
+    if ((threadIdx.x & 63) == 0)
+        atomicAdd(&g_update_count, 2ull * (unsigned long long)__popcll(m));
+}
+#else
+__device__ __forceinline__ void count_pairs(bool) {}
+#endif
+
 template <class S, int P, int PH>
 __device__ __forceinline__ void band_update(typename S::Pt (&A)[P], typename S::Pt (&B)[P],
                                             const typename S::Pt& inA,
@@ -135,6 +152,7 @@ __device__ __forceinline__ void band_update(typename S::Pt (&A)[P], typename S::
     for (int q = P - 1; q >= 0; --q) {
         const int m = mlane - q;
         const bool act = (unsigned)m < (unsigned)k && elane + q < nvalid;
+        count_pairs(act);
         if (act) {
             const Pt rA = (q == 0) ? inA : A[q - 1];
             const Pt cB = (q == 0) ? inB : B[q - 1];
@@ -426,6 +444,7 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
                 act = lane * P + q <= j;
             if constexpr (MASK == 2)
                 act = lane * P + q > j;
+            count_pairs(act);
             if (act) {
                 const Face G = S::template face_of<PH>(A[q], cBq, c);
                 const Face H = (q == 0) ? H0 : F[q - 1];
@@ -461,6 +480,7 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
                 act = lane * P + q <= j;
             if constexpr (MASK == 2)
                 act = lane * P + q > j;
+            count_pairs(act);
             if (act) {
                 B[q] = S::template step<PH>(B[q], A[q], cBq, c);
                 A[q] = S::template step<PH>(A[q], cBq, rA, c);

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "swept.h"
+#include "swept_debug.h"
 #include "kernels.hpp"
 
 // Scratch of swept_advance_noalloc: a fixed array that every GPU the library
@@ -2436,6 +2437,27 @@ int swept_set_batch_schedule(int32_t schedule, int64_t spin_limit, int32_t chunk
 }
 
 const char* swept_last_error(void) { return g_err.c_str(); }
+
+#ifdef SWEPT_COUNT_UPDATES
+int swept_debug_update_count(uint64_t* count, int32_t reset)
+{
+    if (!g_ctx.ready)
+        return fail(SWEPT_ENOTINIT, "swept_init has not been called");
+    if (!count)
+        return fail(SWEPT_EINVAL, "swept_debug_update_count: count is null");
+    HIP_TRY(hipStreamSynchronize(g_ctx.stream));
+    unsigned long long c = 0;
+    HIP_TRY(hipMemcpyFromSymbol(&c, HIP_SYMBOL(g_update_count), sizeof c, 0,
+                                hipMemcpyDeviceToHost));
+    *count = (uint64_t)c;
+    if (reset) {
+        c = 0;
+        HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(g_update_count), &c, sizeof c, 0,
+                                  hipMemcpyHostToDevice));
+    }
+    return SWEPT_OK;
+}
+#endif
 
 void swept_finalize(void)
 {

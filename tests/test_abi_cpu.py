@@ -179,3 +179,20 @@ def test_batch_schedule_validation(swept):
     assert "queues" in swept.last_error()
     assert lib.swept_set_batch_schedule(swept.BATCH_STAGED, 100, 4, 8) == 0
     assert lib.swept_set_batch_schedule(swept.BATCH_PERSISTENT, 0, 0, 0) == 0
+
+
+def test_counting_build_exports(swept):
+    """The counting build (SWEPT_COUNT_UPDATES) exports every entry point of
+    swept.h and the one of swept_debug.h; the normal library does not export
+    the debug one."""
+    count_lib = os.path.join(os.path.dirname(swept.LIB_PATH), "libswept_count.so")
+    if not os.path.exists(count_lib):
+        pytest.skip("libswept_count.so not built")
+    lib = ctypes.CDLL(count_lib)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert hasattr(lib, "swept_debug_update_count")
+    assert not hasattr(ctypes.CDLL(swept.LIB_PATH), "swept_debug_update_count")
+    c = ctypes.c_uint64()
+    lib.swept_finalize()
+    assert lib.swept_debug_update_count(ctypes.byref(c), 0) == -2    # before swept_init
