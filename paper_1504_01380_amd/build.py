@@ -12,6 +12,10 @@ DEPS = [os.path.join(PKG, "csrc", f) for f in ("stencils.hpp", "kernels.hpp")] +
 LIB = os.path.join(PKG, "libswept.so")
 LIB_COUNT = os.path.join(PKG, "libswept_count.so")
 ARCH = os.environ.get("SWEPT_OFFLOAD_ARCH", "gfx950")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+# roctx ranges around the entry points (rocprofv3 --marker-trace)
+LINK = ["-L" + os.path.join(ROCM, "lib"), "-lrocprofiler-sdk-roctx",
+        "-Wl,-rpath," + os.path.join(ROCM, "lib")]
 
 # -ffp-contract=off: no fused multiply-add, so every schedule gives the
 # oracle's bits.  Packed FP32 instructions are disabled for all device code.
@@ -26,7 +30,7 @@ HIPCC_FLAGS = [
 def _compile(out: str, extra, verbose: bool) -> str:
     tmp = out + ".tmp%d" % os.getpid()
     cmd = ["hipcc", *HIPCC_FLAGS, *extra, "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(PKG, "csrc"), SRC, "-o", tmp]
+           "-I", os.path.join(PKG, "csrc"), SRC, "-o", tmp, *LINK]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

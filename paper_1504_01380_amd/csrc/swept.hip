@@ -15,6 +15,8 @@
 #include <utility>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "swept.h"
 #include "swept_debug.h"
 #include "kernels.hpp"
@@ -2044,6 +2046,15 @@ int autotune_batch(const int64_t* nx, const int64_t* nsteps, const int32_t* ids,
 
 }  // namespace
 
+// A roctx range around each entry point (visible to rocprofv3 --marker-trace;
+// a no-op when no profiler is attached).
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
+
 // ===================================================================== C ABI
 
 extern "C" {
@@ -2118,6 +2129,7 @@ int swept_plan(int64_t nx, int64_t nsteps, int32_t stencil_id, int64_t* out)
 int swept_advance(void* u, int64_t nx, int64_t nsteps, int32_t stencil_id, const double* params,
                   int32_t nparams)
 {
+    TraceRange trace_range("swept_advance");
     int rc = check_common(u, nx, nsteps, stencil_id, params, nparams);
     if (rc)
         return rc;
@@ -2154,6 +2166,7 @@ int swept_advance_noalloc(void* u, int64_t nx, int64_t nsteps, int32_t stencil_i
 int swept_naive_advance(void* u, int64_t nx, int64_t nsteps, int32_t stencil_id,
                         const double* params, int32_t nparams)
 {
+    TraceRange trace_range("swept_naive_advance");
     int rc = check_common(u, nx, nsteps, stencil_id, params, nparams);
     if (rc)
         return rc;
@@ -2165,6 +2178,7 @@ int swept_naive_advance(void* u, int64_t nx, int64_t nsteps, int32_t stencil_id,
 int swept_naive_substep_advance(void* u, int64_t nx, int64_t nsteps, int32_t stencil_id,
                                 const double* params, int32_t nparams)
 {
+    TraceRange trace_range("swept_naive_substep_advance");
     int rc = check_common(u, nx, nsteps, stencil_id, params, nparams);
     if (rc)
         return rc;
@@ -2181,6 +2195,7 @@ int swept_naive_substep_advance(void* u, int64_t nx, int64_t nsteps, int32_t ste
 int swept_advance_batch(void* const* u, const int64_t* nx, const int64_t* nsteps,
                         const int32_t* stencil_id, const double* params, int64_t count)
 {
+    TraceRange trace_range("swept_advance_batch");
     if (!g_ctx.ready)
         return fail(SWEPT_ENOTINIT, "swept_init has not been called");
     if (count < 0 || (count > 0 && (!u || !nx || !nsteps || !stencil_id || !params)))
@@ -2205,6 +2220,7 @@ int swept_advance_batch(void* const* u, const int64_t* nx, const int64_t* nsteps
 int swept_naive_advance_batch(void* const* u, const int64_t* nx, const int64_t* nsteps,
                               const int32_t* stencil_id, const double* params, int64_t count)
 {
+    TraceRange trace_range("swept_naive_advance_batch");
     if (!g_ctx.ready)
         return fail(SWEPT_ENOTINIT, "swept_init has not been called");
     if (count < 0 || (count > 0 && (!u || !nx || !nsteps || !stencil_id || !params)))
@@ -2227,6 +2243,7 @@ int swept_naive_advance_batch(void* const* u, const int64_t* nx, const int64_t* 
 int swept_autotune(int64_t nx, int64_t nsteps, int32_t stencil_id, const double* params,
                    int32_t nparams, double* report)
 {
+    TraceRange trace_range("swept_autotune");
     int rc = check_problem(nx, nsteps, stencil_id, params, nparams);
     if (rc)
         return rc;
@@ -2242,6 +2259,7 @@ int swept_autotune(int64_t nx, int64_t nsteps, int32_t stencil_id, const double*
 int swept_autotune_batch(const int64_t* nx, const int64_t* nsteps, const int32_t* stencil_id,
                          const double* params, int64_t count, int64_t* depth_out)
 {
+    TraceRange trace_range("swept_autotune_batch");
     if (!g_ctx.ready)
         return fail(SWEPT_ENOTINIT, "swept_init has not been called");
     if (count < 0 || !depth_out || (count > 0 && (!nx || !nsteps || !stencil_id || !params)))
@@ -2307,6 +2325,7 @@ int swept_adjoint(const void* u0, void* grad_u0, int64_t nx, int64_t nsteps, int
                   const double* params, int32_t nparams, int64_t window_first,
                   double window_weight, const void* cot_final)
 {
+    TraceRange trace_range("swept_adjoint");
     int rc = check_common(u0, nx, nsteps, stencil_id, params, nparams);
     if (rc)
         return rc;
@@ -2330,6 +2349,7 @@ int swept_window_objective(const void* u0, int64_t nx, int64_t nsteps, int32_t s
                            const double* params, int32_t nparams, int64_t window_first,
                            double window_weight, const void* cot_final, void* J_out)
 {
+    TraceRange trace_range("swept_window_objective");
     int rc = check_common(u0, nx, nsteps, stencil_id, params, nparams);
     if (rc)
         return rc;
@@ -2348,6 +2368,7 @@ int swept_naive_adjoint(const void* u0, void* grad_u0, int64_t nx, int64_t nstep
                         int32_t stencil_id, const double* params, int32_t nparams,
                         int64_t window_first, double window_weight, const void* cot_final)
 {
+    TraceRange trace_range("swept_naive_adjoint");
     int rc = check_common(u0, nx, nsteps, stencil_id, params, nparams);
     if (rc)
         return rc;
