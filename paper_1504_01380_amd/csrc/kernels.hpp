@@ -95,6 +95,16 @@ template <class S>
 struct has_chain_store<S, std::void_t<decltype(S::kChainStore)>>
     : std::integral_constant<bool, S::kChainStore> {};
 
+// A stencil may set kUnmaskedDrain: in the continuous kernel's drain every
+// slot then keeps computing after it has stored its final state (MASK 3 of
+// cont_step), which saves the per-pair masking where a step is long (KS);
+// otherwise a finished slot idles and all store at the end (MASK 2).
+template <class S, class = void>
+struct unmasked_drain : std::false_type {};
+template <class S>
+struct unmasked_drain<S, std::void_t<decltype(S::kUnmaskedDrain)>>
+    : std::integral_constant<bool, S::kUnmaskedDrain> {};
+
 // A stencil may set kFaces: its flux sub-timesteps then come as face fluxes
 // (face_of, step_faces), and the continuous kernel computes each face once.
 template <class S, class = void>
@@ -388,8 +398,12 @@ __global__ __launch_bounds__(64) void swept_stage_kernel(StageArgs<S> g)
 // k are multiples of 4, all slots are at the same sub-timestep modulo 4.
 
 // MASK: 0 = all slots active; 1 = pipeline fill (slot e active iff e <= j);
-// 2 = pipeline drain (slot e active iff e > j).  QS >= 0: slot (rs, QS)
-// changes band before it computes.
+// 2 = pipeline drain (slot e active iff e > j); 3 = the drain unmasked:
+// slot e has finished at step e, where it stores its final state, and from
+// then on computes values that no active slot reads (slot e+1 reads slot
+// e's state of the step before, its last one; a finished slot's values
+// reach only slots that have finished too).  QS >= 0: slot (rs, QS) stores
+// its state before it computes, and (MASK 0) changes band.
 //
 // Face sharing (stencils with kFaces, flux sub-timesteps).  Pair e's update
 // needs three faces: F[e] between its B and A, G between its A and pair
@@ -433,9 +447,11 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
                 if (lane == rs) {
                     re_store[0] = B[q];
                     re_store[1] = A[q];
-                    A[q] = An[q];
-                    B[q] = Bn[q];
-                    F[q] = Fn[q];
+                    if constexpr (MASK != 3) {
+                        A[q] = An[q];
+                        B[q] = Bn[q];
+                        F[q] = Fn[q];
+                    }
                 }
             }
             const Pt cBq = (q == 0) ? inB : B[q - 1];
@@ -444,7 +460,7 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
                 act = lane * P + q <= j;
             if constexpr (MASK == 2)
                 act = lane * P + q > j;
-            count_pairs(act);
+            count_pairs(MASK == 3 ? lane * P + q > j : act);
             if (act) {
                 const Face G = S::template face_of<PH>(A[q], cBq, c);
                 const Face H = (q == 0) ? H0 : F[q - 1];
@@ -466,11 +482,13 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
 #pragma unroll
         for (int q = P - 1; q >= 0; --q) {
             if (QS == q) {     // folded at compile time after unrolling
-                if (lane == rs) {  // this slot enters the next band
+                if (lane == rs) {  // this slot enters the next band (or, MASK 3, ends)
                     re_store[0] = B[q];
                     re_store[1] = A[q];
-                    A[q] = An[q];
-                    B[q] = Bn[q];
+                    if constexpr (MASK != 3) {
+                        A[q] = An[q];
+                        B[q] = Bn[q];
+                    }
                 }
             }
             const Pt rA = (q == 0) ? inA : A[q - 1];
@@ -480,7 +498,7 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
                 act = lane * P + q <= j;
             if constexpr (MASK == 2)
                 act = lane * P + q > j;
-            count_pairs(act);
+            count_pairs(MASK == 3 ? lane * P + q > j : act);
             if (act) {
                 B[q] = S::template step<PH>(B[q], A[q], cBq, c);
                 A[q] = S::template step<PH>(A[q], cBq, rA, c);
@@ -509,8 +527,8 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
 
 // Head of a cycle, steps j = j0 .. j0+G-1 (G = max(P, NPHASE) divides 64P):
 // step j = rs*P + QS is the one at which slot j changes band (cycles
-// 1..nb-1), or a step of the pipeline fill (cycle 0) or drain (after the
-// last band).
+// 1..nb-1) or, in the drain after the last band, ends; or a step of the
+// pipeline fill (cycle 0).
 template <class S, int P, int PH0, int MASK, bool TRANS, int I, int G>
 __device__ __forceinline__ void cont_head_group(int j0, int k, int nb, int cyc,
                                                 typename S::Pt (&A)[P], typename S::Pt (&B)[P],
@@ -534,7 +552,7 @@ __device__ __forceinline__ void cont_head_group(int j0, int k, int nb, int cyc,
         const int wraw = j + k - (NB - 1);
         const int wslot = wraw == k ? 0 : wraw;
         // it is active from step NB-1 of the fill to step NB-2 of the drain
-        const bool wlast = MASK == 1 ? (j == NB - 1) : (MASK == 2 ? (j < NB - 1) : true);
+        const bool wlast = MASK == 1 ? (j == NB - 1) : (MASK >= 2 ? (j < NB - 1) : true);
         typename S::Pt* re_store = nullptr;
         if constexpr (TRANS)
             re_store = re_out + 2 * ((cyc - 1) * NB + j);
@@ -629,10 +647,23 @@ __device__ __forceinline__ void cont_region(const typename S::Pt* re, typename S
                                                            chain, re, re_out, lane, cst, Fn,
                                                            fch);
         } else if (cyc == nb) {
-            for (int j0 = 0; j0 < NB; j0 += G)
-                cont_head_group<S, P, PH0, 2, false, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
-                                                           chain, re, re_out, lane, cst, Fn,
-                                                           fch);
+            if constexpr (unmasked_drain<S>::value) {  // each slot stores at its own step
+                for (int j0 = 0; j0 < NB; j0 += G)
+                    cont_head_group<S, P, PH0, 3, true, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA,
+                                                              cB, chain, re, re_out, lane, cst,
+                                                              Fn, fch);
+            } else {
+                for (int j0 = 0; j0 < NB; j0 += G)
+                    cont_head_group<S, P, PH0, 2, false, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA,
+                                                               cB, chain, re, re_out, lane, cst,
+                                                               Fn, fch);
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    const int e = lane * P + q;
+                    re_out[2 * ((nb - 1) * NB + e)] = B[q];
+                    re_out[2 * ((nb - 1) * NB + e) + 1] = A[q];
+                }
+            }
             break;
         } else {
             if constexpr (has_faces<S>::value) {
@@ -664,12 +695,6 @@ __device__ __forceinline__ void cont_region(const typename S::Pt* re, typename S
                                              fch);
     }
 
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-        const int e = lane * P + q;
-        re_out[2 * ((nb - 1) * NB + e)] = B[q];
-        re_out[2 * ((nb - 1) * NB + e) + 1] = A[q];
-    }
     __syncthreads();
     for (int i = lane; i < 2 * k; i += 64)
         le_out[i] = chain[i];
@@ -901,7 +926,7 @@ __device__ __forceinline__ void batch_persistent(const PersistArgs<S>& g)
         // claim `chunk` (<= 32) consecutive numbers; each run of them inside
         // one stage waits for all its inputs (lane 2i: task i's own tile,
         // lane 2i+1: its next tile) with one acquire, then runs them and
-        // publishes each (xcd_local) or the whole run (one agent release)
+        // publishes each (XL) or the whole run (one agent release)
         unsigned q0 = 0;
         if (lane == 0)
             q0 = atomicAdd(counter, (unsigned)g.chunk);
@@ -973,7 +998,7 @@ void swept_batch_persistent_kernel(PersistArgs<S> g)
 
 // After a persistent launch: every queue must have handed out all its task
 // numbers (a queue that no workgroup served would leave its instances
-// unfinished); fault = 2 otherwise.
+// unfinished); fault = 2 otherwise, unless a wait already gave up (1).
 __global__ __launch_bounds__(64) void persist_check_kernel(const unsigned* __restrict__ counter,
                                                            const int64_t* __restrict__ first,
                                                            int smax, int queues,
@@ -981,7 +1006,7 @@ __global__ __launch_bounds__(64) void persist_check_kernel(const unsigned* __res
 {
     for (int j = threadIdx.x; j < queues; j += blockDim.x)
         if ((int64_t)counter[(int64_t)j * kCounterStride] < first[(int64_t)j * (smax + 1) + smax])
-            __hip_atomic_store(fault, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            atomicCAS(fault, 0, 2);
 }
 
 // Zero the stage flags and the queues' counters before a persistent launch.

@@ -35,6 +35,7 @@ def ks_step(dt, dx):
             return (c[0], c[0] + h * rhs(l, c, r), c[2])
         un = c[0] + dt * rhs(l, c, r)
         return (un, un, c[2])
+    f.unmasked_drain = True   # as the KS continuous kernel (kUnmaskedDrain)
     return f, 4, (lambda v: (v, v, 0.0)), (lambda p: p[0])
 
 
@@ -54,10 +55,20 @@ def _chain_store(ph, B, A, oldB, oldA):
     return (B[0], B[1], NAN), (NAN, A[1], NAN)
 
 
+def _poison(p):
+    """A point of the same kind as p whose every component is NaN."""
+    return tuple(NAN for _ in p) if isinstance(p, tuple) else NAN
+
+
 def _cont_stage(t, J, b, k, P, lanes, RE, chain, step, nph, n, visits):
     """One full diamond on the continuous-band schedule of
     swept_diamond_cont_kernel: slot e works on band (sigma-e) div k, step
-    (sigma-e) mod k at wave step sigma and changes band at sigma = beta*k+e."""
+    (sigma-e) mod k at wave step sigma and changes band at sigma = beta*k+e.
+    In the drain (after the last band) the slots that have finished are
+    idle, or, for a stencil whose step function has unmasked_drain (KS, as
+    in the kernel), slot e stores its final state at step e and then keeps
+    computing; here its state becomes NaN there, so a read of it by a slot
+    that has not finished would show in the result."""
     NB = lanes * P
     nb = k // NB
     A = [RE[t][2 * e + 1] for e in range(NB)]
@@ -65,11 +76,12 @@ def _cont_stage(t, J, b, k, P, lanes, RE, chain, step, nph, n, visits):
     An = [RE[t][2 * (NB + e) + 1] if nb > 1 else None for e in range(NB)]
     Bn = [RE[t][2 * (NB + e)] if nb > 1 else None for e in range(NB)]
     cA, cB = chain[1], chain[0]
+    drain = 3 if getattr(step, "unmasked_drain", False) else 2
     for cyc in range(nb + 1):
         steps = range(NB) if cyc == nb else range(k)
         for j in steps:
             sigma = cyc * k + j
-            mask = 1 if (cyc == 0 and j < NB) else (2 if cyc == nb else 0)
+            mask = 1 if (cyc == 0 and j < NB) else (drain if cyc == nb else 0)
             trans = 0 < cyc < nb and j < NB
             inA = [cA] + [A[(r - 1) * P + P - 1] for r in range(1, lanes)]
             inB = [cB] + [B[(r - 1) * P + P - 1] for r in range(1, lanes)]
@@ -79,29 +91,27 @@ def _cont_stage(t, J, b, k, P, lanes, RE, chain, step, nph, n, visits):
             for r in range(lanes):
                 for q in range(P - 1, -1, -1):
                     e = r * P + q
-                    if trans and e == j:
+                    if (trans or mask == 3) and e == j:
                         RE[t][2 * ((cyc - 1) * NB + j)] = B[e]
                         RE[t][2 * ((cyc - 1) * NB + j) + 1] = A[e]
-                        A[e], B[e] = An[e], Bn[e]
-                    act = True
-                    if mask == 1:
-                        act = e <= j
-                    elif mask == 2:
-                        act = e > j
-                    if not act:
+                        if mask == 3:
+                            A[e] = B[e] = _poison(A[e])
+                        else:
+                            A[e], B[e] = An[e], Bn[e]
+                    if (mask == 1 and e > j) or (mask == 2 and e <= j):
                         continue
                     rA = inA[r] if q == 0 else A[e - 1]
                     cBv = inB[r] if q == 0 else B[e - 1]
                     B[e] = step(ph, B[e], A[e], cBv)
                     A[e] = step(ph, A[e], cBv, rA)
-                    if visits is not None:
+                    if visits is not None and not (mask == 3 and e <= j):
                         beta, m = divmod(sigma - e, k)
                         d = beta * NB + e
                         lvl = b + m + d + 1
                         xa = (J + m - d) % n
                         for x in (xa, (xa - 1) % n):
                             visits[(x, lvl)] = visits.get((x, lvl), 0) + 1
-            wlast = (j == NB - 1) if mask == 1 else ((j < NB - 1) if mask == 2 else True)
+            wlast = (j == NB - 1) if mask == 1 else ((j < NB - 1) if mask >= 2 else True)
             if wlast:
                 ws = (j + k - (NB - 1)) % k
                 chain[2 * ws], chain[2 * ws + 1] = _chain_store(ph, B[NB - 1], A[NB - 1],
@@ -113,9 +123,10 @@ def _cont_stage(t, J, b, k, P, lanes, RE, chain, step, nph, n, visits):
                 for e in range(NB):
                     Bn[e] = RE[t][2 * ((cyc + 1) * NB + e)]
                     An[e] = RE[t][2 * ((cyc + 1) * NB + e) + 1]
-    for e in range(NB):
-        RE[t][2 * ((nb - 1) * NB + e)] = B[e]
-        RE[t][2 * ((nb - 1) * NB + e) + 1] = A[e]
+    if drain == 2:
+        for e in range(NB):
+            RE[t][2 * ((nb - 1) * NB + e)] = B[e]
+            RE[t][2 * ((nb - 1) * NB + e) + 1] = A[e]
 
 
 def cont_faces_symbolic(k, P, b, lanes=64):
