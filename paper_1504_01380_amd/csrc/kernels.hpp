@@ -95,15 +95,17 @@ template <class S>
 struct has_chain_store<S, std::void_t<decltype(S::kChainStore)>>
     : std::integral_constant<bool, S::kChainStore> {};
 
-// A stencil may set kUnmaskedDrain: in the continuous kernel's drain every
-// slot then keeps computing after it has stored its final state (MASK 3 of
-// cont_step), which saves the per-pair masking where a step is long (KS);
-// otherwise a finished slot idles and all store at the end (MASK 2).
+// A stencil may set kUnmaskedEnds: the continuous kernel's pipeline fill
+// and drain then run unmasked (MASK 4 and 3 of cont_step): a slot computes
+// before it has taken its first state and after it has stored its final
+// one, which saves the per-pair masking where a step is long (KS).
+// Otherwise a slot idles until its start and after its end, and all slots
+// store at the end (MASK 1 and 2).
 template <class S, class = void>
-struct unmasked_drain : std::false_type {};
+struct unmasked_ends : std::false_type {};
 template <class S>
-struct unmasked_drain<S, std::void_t<decltype(S::kUnmaskedDrain)>>
-    : std::integral_constant<bool, S::kUnmaskedDrain> {};
+struct unmasked_ends<S, std::void_t<decltype(S::kUnmaskedEnds)>>
+    : std::integral_constant<bool, S::kUnmaskedEnds> {};
 
 // A stencil may set kFaces: its flux sub-timesteps then come as face fluxes
 // (face_of, step_faces), and the continuous kernel computes each face once.
@@ -402,8 +404,11 @@ __global__ __launch_bounds__(64) void swept_stage_kernel(StageArgs<S> g)
 // slot e has finished at step e, where it stores its final state, and from
 // then on computes values that no active slot reads (slot e+1 reads slot
 // e's state of the step before, its last one; a finished slot's values
-// reach only slots that have finished too).  QS >= 0: slot (rs, QS) stores
-// its state before it computes, and (MASK 0) changes band.
+// reach only slots that have finished too); 4 = the fill unmasked: slot e
+// takes its first state at step e and computes before that values that no
+// active slot reads (an active slot reads only lower slots, all active).
+// QS >= 0: slot (rs, QS) stores its state before it computes (MASK 0, 3)
+// and takes its next one (MASK 0, 4).
 //
 // Face sharing (stencils with kFaces, flux sub-timesteps).  Pair e's update
 // needs three faces: F[e] between its B and A, G between its A and pair
@@ -445,8 +450,10 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
         for (int q = P - 1; q >= 0; --q) {
             if (QS == q) {
                 if (lane == rs) {
-                    re_store[0] = B[q];
-                    re_store[1] = A[q];
+                    if constexpr (MASK != 4) {
+                        re_store[0] = B[q];
+                        re_store[1] = A[q];
+                    }
                     if constexpr (MASK != 3) {
                         A[q] = An[q];
                         B[q] = Bn[q];
@@ -460,7 +467,7 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
                 act = lane * P + q <= j;
             if constexpr (MASK == 2)
                 act = lane * P + q > j;
-            count_pairs(MASK == 3 ? lane * P + q > j : act);
+            count_pairs(MASK == 3 ? lane * P + q > j : (MASK == 4 ? lane * P + q <= j : act));
             if (act) {
                 const Face G = S::template face_of<PH>(A[q], cBq, c);
                 const Face H = (q == 0) ? H0 : F[q - 1];
@@ -482,9 +489,11 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
 #pragma unroll
         for (int q = P - 1; q >= 0; --q) {
             if (QS == q) {     // folded at compile time after unrolling
-                if (lane == rs) {  // this slot enters the next band (or, MASK 3, ends)
-                    re_store[0] = B[q];
-                    re_store[1] = A[q];
+                if (lane == rs) {  // this slot enters the next band (MASK 3: ends)
+                    if constexpr (MASK != 4) {
+                        re_store[0] = B[q];
+                        re_store[1] = A[q];
+                    }
                     if constexpr (MASK != 3) {
                         A[q] = An[q];
                         B[q] = Bn[q];
@@ -498,7 +507,7 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
                 act = lane * P + q <= j;
             if constexpr (MASK == 2)
                 act = lane * P + q > j;
-            count_pairs(MASK == 3 ? lane * P + q > j : act);
+            count_pairs(MASK == 3 ? lane * P + q > j : (MASK == 4 ? lane * P + q <= j : act));
             if (act) {
                 B[q] = S::template step<PH>(B[q], A[q], cBq, c);
                 A[q] = S::template step<PH>(A[q], cBq, rA, c);
@@ -527,8 +536,8 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
 
 // Head of a cycle, steps j = j0 .. j0+G-1 (G = max(P, NPHASE) divides 64P):
 // step j = rs*P + QS is the one at which slot j changes band (cycles
-// 1..nb-1) or, in the drain after the last band, ends; or a step of the
-// pipeline fill (cycle 0).
+// 1..nb-1), starts (the fill, cycle 0) or ends (the drain after the last
+// band).
 template <class S, int P, int PH0, int MASK, bool TRANS, int I, int G>
 __device__ __forceinline__ void cont_head_group(int j0, int k, int nb, int cyc,
                                                 typename S::Pt (&A)[P], typename S::Pt (&B)[P],
@@ -552,13 +561,15 @@ __device__ __forceinline__ void cont_head_group(int j0, int k, int nb, int cyc,
         const int wraw = j + k - (NB - 1);
         const int wslot = wraw == k ? 0 : wraw;
         // it is active from step NB-1 of the fill to step NB-2 of the drain
-        const bool wlast = MASK == 1 ? (j == NB - 1) : (MASK >= 2 ? (j < NB - 1) : true);
+        const bool wlast = (MASK == 1 || MASK == 4) ? (j == NB - 1)
+                                                    : (MASK >= 2 ? (j < NB - 1) : true);
         typename S::Pt* re_store = nullptr;
         if constexpr (TRANS)
             re_store = re_out + 2 * ((cyc - 1) * NB + j);
         // the chain entry the last slot wrote one step before (j < 64P here)
         const int fslot = j + k - NB;
-        cont_step<S, P, PH, MASK, TRANS ? QS : -1>(A, B, An, Bn, cA, cB, chain, lane, j, rs,
+        cont_step<S, P, PH, MASK, (TRANS || MASK == 4) ? QS : -1>(A, B, An, Bn, cA, cB, chain,
+                                                                 lane, j, rs,
                                                    next_slot, wslot, wlast, re_store, c, Fn, fch,
                                                    fslot);
         cont_head_group<S, P, PH0, MASK, TRANS, I + 1, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
@@ -630,7 +641,10 @@ __device__ __forceinline__ void cont_region(const typename S::Pt* re, typename S
         const int e = lane * P + q;
         B[q] = ld_edge<S, COH>(re + 2 * e);
         A[q] = ld_edge<S, COH>(re + 2 * e + 1);
-        if (nb > 1) {
+        if constexpr (unmasked_ends<S>::value) {  // taken at the slot's fill step
+            An[q] = A[q];
+            Bn[q] = B[q];
+        } else if (nb > 1) {
             Bn[q] = ld_edge<S, COH>(re + 2 * (NB + e));
             An[q] = ld_edge<S, COH>(re + 2 * (NB + e) + 1);
         } else {
@@ -642,12 +656,27 @@ __device__ __forceinline__ void cont_region(const typename S::Pt* re, typename S
 
     for (int cyc = 0;; ++cyc) {
         if (cyc == 0) {
-            for (int j0 = 0; j0 < NB; j0 += G)
-                cont_head_group<S, P, PH0, 1, false, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
-                                                           chain, re, re_out, lane, cst, Fn,
-                                                           fch);
+            if constexpr (unmasked_ends<S>::value) {
+                for (int j0 = 0; j0 < NB; j0 += G)
+                    cont_head_group<S, P, PH0, 4, false, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA,
+                                                               cB, chain, re, re_out, lane, cst,
+                                                               Fn, fch);
+                if (nb > 1) {   // every slot has started: band 1's left-edge states
+#pragma unroll
+                    for (int q = 0; q < P; ++q) {
+                        const int e = lane * P + q;
+                        Bn[q] = ld_edge<S, COH>(re + 2 * (NB + e));
+                        An[q] = ld_edge<S, COH>(re + 2 * (NB + e) + 1);
+                    }
+                }
+            } else {
+                for (int j0 = 0; j0 < NB; j0 += G)
+                    cont_head_group<S, P, PH0, 1, false, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA,
+                                                               cB, chain, re, re_out, lane, cst,
+                                                               Fn, fch);
+            }
         } else if (cyc == nb) {
-            if constexpr (unmasked_drain<S>::value) {  // each slot stores at its own step
+            if constexpr (unmasked_ends<S>::value) {  // each slot stores at its own step
                 for (int j0 = 0; j0 < NB; j0 += G)
                     cont_head_group<S, P, PH0, 3, true, 0, G>(j0, k, nb, cyc, A, B, An, Bn, cA,
                                                               cB, chain, re, re_out, lane, cst,

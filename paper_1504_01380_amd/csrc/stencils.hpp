@@ -128,9 +128,9 @@ struct KSF64 {
     };
     static constexpr int NPHASE = 4;
     static constexpr int kPersistWaves = 4;   // waves per SIMD of the persistent batch kernel
-    // the continuous kernel's drain runs unmasked: a KS wave step is long
-    // enough that masking the finished slots costs more than their updates
-    static constexpr bool kUnmaskedDrain = true;
+    // the continuous kernel's fill and drain run unmasked: a KS wave step is
+    // long enough that masking the idle slots costs more than their updates
+    static constexpr bool kUnmaskedEnds = true;
 
     __device__ __forceinline__ static Pt from_field(double v) { return Pt{v, v, 0.0}; }
     __device__ __forceinline__ static double to_field(const Pt& p) { return p.u; }

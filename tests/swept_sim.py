@@ -35,7 +35,7 @@ def ks_step(dt, dx):
             return (c[0], c[0] + h * rhs(l, c, r), c[2])
         un = c[0] + dt * rhs(l, c, r)
         return (un, un, c[2])
-    f.unmasked_drain = True   # as the KS continuous kernel (kUnmaskedDrain)
+    f.unmasked_ends = True   # as the KS continuous kernel (kUnmaskedEnds)
     return f, 4, (lambda v: (v, v, 0.0)), (lambda p: p[0])
 
 
@@ -64,24 +64,31 @@ def _cont_stage(t, J, b, k, P, lanes, RE, chain, step, nph, n, visits):
     """One full diamond on the continuous-band schedule of
     swept_diamond_cont_kernel: slot e works on band (sigma-e) div k, step
     (sigma-e) mod k at wave step sigma and changes band at sigma = beta*k+e.
-    In the drain (after the last band) the slots that have finished are
-    idle, or, for a stencil whose step function has unmasked_drain (KS, as
-    in the kernel), slot e stores its final state at step e and then keeps
-    computing; here its state becomes NaN there, so a read of it by a slot
-    that has not finished would show in the result."""
+    In the pipeline fill and drain the slots that have not started or have
+    finished are idle; for a stencil whose step function has unmasked_ends
+    (KS, as in the kernel) they keep computing: slot e takes its first state
+    at fill step e and stores its final one at drain step e.  Here a slot's
+    state is NaN before its start and after its end, so a read of it by an
+    active slot would show in the result."""
     NB = lanes * P
     nb = k // NB
+    unmasked = getattr(step, "unmasked_ends", False)
     A = [RE[t][2 * e + 1] for e in range(NB)]
     B = [RE[t][2 * e] for e in range(NB)]
-    An = [RE[t][2 * (NB + e) + 1] if nb > 1 else None for e in range(NB)]
-    Bn = [RE[t][2 * (NB + e)] if nb > 1 else None for e in range(NB)]
+    if unmasked:   # taken at each slot's fill step
+        An, Bn = A, B
+        A = [_poison(p) for p in An]
+        B = [_poison(p) for p in Bn]
+    else:
+        An = [RE[t][2 * (NB + e) + 1] if nb > 1 else None for e in range(NB)]
+        Bn = [RE[t][2 * (NB + e)] if nb > 1 else None for e in range(NB)]
     cA, cB = chain[1], chain[0]
-    drain = 3 if getattr(step, "unmasked_drain", False) else 2
+    fill, drain = (4, 3) if unmasked else (1, 2)
     for cyc in range(nb + 1):
         steps = range(NB) if cyc == nb else range(k)
         for j in steps:
             sigma = cyc * k + j
-            mask = 1 if (cyc == 0 and j < NB) else (drain if cyc == nb else 0)
+            mask = fill if (cyc == 0 and j < NB) else (drain if cyc == nb else 0)
             trans = 0 < cyc < nb and j < NB
             inA = [cA] + [A[(r - 1) * P + P - 1] for r in range(1, lanes)]
             inB = [cB] + [B[(r - 1) * P + P - 1] for r in range(1, lanes)]
@@ -91,9 +98,10 @@ def _cont_stage(t, J, b, k, P, lanes, RE, chain, step, nph, n, visits):
             for r in range(lanes):
                 for q in range(P - 1, -1, -1):
                     e = r * P + q
-                    if (trans or mask == 3) and e == j:
-                        RE[t][2 * ((cyc - 1) * NB + j)] = B[e]
-                        RE[t][2 * ((cyc - 1) * NB + j) + 1] = A[e]
+                    if (trans or mask in (3, 4)) and e == j:
+                        if mask != 4:
+                            RE[t][2 * ((cyc - 1) * NB + j)] = B[e]
+                            RE[t][2 * ((cyc - 1) * NB + j) + 1] = A[e]
                         if mask == 3:
                             A[e] = B[e] = _poison(A[e])
                         else:
@@ -104,20 +112,21 @@ def _cont_stage(t, J, b, k, P, lanes, RE, chain, step, nph, n, visits):
                     cBv = inB[r] if q == 0 else B[e - 1]
                     B[e] = step(ph, B[e], A[e], cBv)
                     A[e] = step(ph, A[e], cBv, rA)
-                    if visits is not None and not (mask == 3 and e <= j):
+                    if visits is not None and not ((mask == 3 and e <= j) or
+                                                   (mask == 4 and e > j)):
                         beta, m = divmod(sigma - e, k)
                         d = beta * NB + e
                         lvl = b + m + d + 1
                         xa = (J + m - d) % n
                         for x in (xa, (xa - 1) % n):
                             visits[(x, lvl)] = visits.get((x, lvl), 0) + 1
-            wlast = (j == NB - 1) if mask == 1 else ((j < NB - 1) if mask >= 2 else True)
+            wlast = (j == NB - 1) if mask in (1, 4) else ((j < NB - 1) if mask >= 2 else True)
             if wlast:
                 ws = (j + k - (NB - 1)) % k
                 chain[2 * ws], chain[2 * ws + 1] = _chain_store(ph, B[NB - 1], A[NB - 1],
                                                                 chain[2 * ws], chain[2 * ws + 1])
             cA, cB = nA, nB
-            if trans and j == NB - 1 and cyc + 1 < nb:
+            if (trans or mask == 4) and j == NB - 1 and cyc + 1 < nb:
                 # every slot has entered band cyc: band cyc+1's left-edge
                 # states, for all slots at once
                 for e in range(NB):
