@@ -31,6 +31,9 @@ VALU_LANE_OPS = CUS * SIMDS_PER_CU * LANES_PER_SIMD * CLOCK_HZ   # 39.3e12 FP64 
 VALU_LANE_OPS_F32 = 2 * VALU_LANE_OPS
 HBM_PEAK = 8.0e12
 HEAT_OPS_PER_UPDATE = 5           # add, mul, sub, mul, add (no fused multiply-add)
+# the same bits in four: add, fma(-2, u, s), mul, add (the fused-Laplacian form the
+# library takes for binary64 heat once its range check passes); an FMA issues once
+HEAT_FUSED_LAP_OPS = 4
 HEAT_FMA_OPS_PER_UPDATE = 3       # add, fma, fma (the contraction-on stencil)
 KS_FMA_OPS_PER_STEP = 22          # 3 + 8 + 3 + 8 instructions per point-step, fused
 # LDS: 128 bytes per clock per CU (the CDNA3 ISA figure; the CDNA4 LDS is
@@ -200,6 +203,12 @@ KS_OPS_PER_STEP = 30  # per point-step: 4 sub-timesteps (4 + 11 + 4 + 11 flops, 
 EULER_OPS_PER_STEP = 320
 
 
+def heat_ops(sw) -> int:
+    """VALU instructions per binary64 heat update of the last swept_advance
+    call: 4 in the fused-Laplacian form, 5 in the canonical one."""
+    return HEAT_FUSED_LAP_OPS if sw.last_heat_form() == sw.FORM_FUSED else HEAT_OPS_PER_UPDATE
+
+
 def other_workloads(sw, torch, workloads, tune=True):
     """The other single-field workloads: heat N=4096 (launch-latency bound
     when stepped naively), KS N=2^20 and Euler N=2^20 cells (four
@@ -239,6 +248,9 @@ def other_workloads(sw, torch, workloads, tune=True):
             t = sum(ts) / len(ts)
             rec[label] = n * nsteps / t
             rec[label + "_ms"] = t * 1e3
+            if label == "swept" and st == "heat":
+                ops = heat_ops(sw)
+                rec["ops_per_update"] = ops
         rec["speedup_vs_naive"] = rec["swept"] / rec["naive"]
         rec["swept_frac_alu"] = ops * rec["swept"] / VALU_LANE_OPS
         rec["naive_GBps"] = naive_bytes * rec["naive"] / 1e9
@@ -496,9 +508,10 @@ def tile_sweep(sw, torch, workloads, args):
             plan = sw.plan(n, nsteps, "heat", torch.float64)
             times, _ = timed_runs(sw, torch, sw.advance, u0, nsteps, [0.25], 2, 1)
             t = min(times)
+            ops = heat_ops(sw)
             print(json.dumps({"tile_w": W, "pairs_per_lane": P, "stages": plan["stages"],
-                              "ms": t * 1e3, "value": n * nsteps / t,
-                              "frac_alu": HEAT_OPS_PER_UPDATE * n * nsteps / t / VALU_LANE_OPS}),
+                              "ms": t * 1e3, "value": n * nsteps / t, "ops_per_update": ops,
+                              "frac_alu": ops * n * nsteps / t / VALU_LANE_OPS}),
                   flush=True)
     sw.set_tuning(0, 0, sw.MODE_AUTO)
 
@@ -601,7 +614,8 @@ def main():
     times, u_swept = timed_runs(sw, torch, sw.advance, u0, nsteps, [0.25], args.steps,
                                 args.warmup, after=record)
     sw.set_profiling(False)
-    progress("heat f64 swept runs done")
+    ops = heat_ops(sw)     # the form the timed runs took (both give the same bits)
+    progress("heat f64 swept runs done (%d VALU instructions per update)" % ops)
     t = sum(times) / len(times)
     updates = float(n) * nsteps
     value = updates / t
@@ -613,7 +627,7 @@ def main():
     kname = ("swept_diamond_cont_kernel<Heat<double>,%d>" if kinds == {1} else
              "swept_stage_kernel<Heat<double>,%d>") % plan["pairs_per_lane"]
     updates_per_launch = float(tiles) * 2 * k * k
-    flops_per_launch = HEAT_OPS_PER_UPDATE * updates_per_launch
+    flops_per_launch = ops * updates_per_launch
     avg_launch = (sum(diamond_ms) / len(diamond_ms) / 1e3) if diamond_ms else float("nan")
     achieved = flops_per_launch / avg_launch
     edge_bytes = float(tiles) * 4 * 2 * k * 8   # RE in/out + LE in/out, 2k values each
@@ -631,10 +645,13 @@ def main():
                 "traffic": measured_traffic(kname),
                 "kernel": kname, "launches_per_step": len(diamond_ms) // max(1, args.steps),
                 "stages_per_step": plan["stages"], "avg_launch_ms": avg_launch * 1e3,
-                "flops_per_launch": flops_per_launch, "ops_per_update": HEAT_OPS_PER_UPDATE,
+                "flops_per_launch": flops_per_launch, "ops_per_update": ops,
+                "heat_form": "fused Laplacian" if ops == HEAT_FUSED_LAP_OPS else "canonical",
+                "counting": "FP64 VALU instructions issued per update (a fused multiply-add "
+                            "issues once)",
                 "stage_sum_ms": sum(stage_ms) / max(1, len(stage_ms)),
                 "algorithmic_bytes_per_launch": edge_bytes,
-                "whole_run_frac": HEAT_OPS_PER_UPDATE * value / VALU_LANE_OPS}
+                "whole_run_frac": ops * value / VALU_LANE_OPS}
 
     out = {
         "metric": "point-updates/sec swept vs naive per-step (1 MI355X), % of VALU/HBM peak",
@@ -663,6 +680,18 @@ def main():
                         "hbm_frac": naive * HEAT_NAIVE_BYTES[8] / HBM_PEAK}
         out["speedup_vs_naive"] = value / naive
         progress("heat f64 naive done")
+        # the same swept runs evaluating the five operations as written
+        sw.set_heat_form(sw.FORM_CANONICAL)
+        ct, uc = timed_runs(sw, torch, sw.advance, u0, nsteps, [0.25], 2, 1)
+        sw.set_heat_form(sw.FORM_AUTO)
+        canon = updates / (sum(ct) / len(ct))
+        out["canonical_form"] = {
+            "swept": canon, "ms": sum(ct) / len(ct) * 1e3, "ops_per_update": HEAT_OPS_PER_UPDATE,
+            "swept_frac_alu": HEAT_OPS_PER_UPDATE * canon / VALU_LANE_OPS,
+            "speedup_vs_naive": canon / naive,
+            "bits_equal_default": bool(torch.equal(uc.view(torch.int64),
+                                                   u_swept.view(torch.int64)))}
+        progress("heat f64 canonical form done")
         u32 = u0.float()
         tune32 = None if args.no_tune else sw.autotune(n, nsteps, "heat", [0.25], torch.float32)
         plan32 = sw.plan(n, nsteps, "heat", torch.float32)

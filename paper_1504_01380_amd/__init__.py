@@ -27,11 +27,14 @@ NOALLOC_SCRATCH_BYTES = 128 << 20   # SWEPT_NOALLOC_SCRATCH_BYTES
 MODE_AUTO, MODE_STAGE, MODE_NAIVE, MODE_STAGE_BANDED, MODE_STAGE_LANE, MODE_STAGE_RAGGED = \
     0, 1, 2, 3, 4, 5
 BATCH_PERSISTENT, BATCH_STAGED = 0, 1
+# how swept_advance evaluates binary64 heat (both give the canonical bits)
+FORM_AUTO, FORM_CANONICAL, FORM_FUSED = 0, 1, 2
 
 _STATUS = {0: "SWEPT_OK", -1: "SWEPT_EINVAL", -2: "SWEPT_ENOTINIT", -3: "SWEPT_ENOMEM",
            -4: "SWEPT_EHIP", -5: "SWEPT_EUNSUPPORTED", -6: "SWEPT_ETIMEOUT"}
 
-EXPORTS = ("swept_init", "swept_set_stream", "swept_set_tuning", "swept_plan",
+EXPORTS = ("swept_init", "swept_set_stream", "swept_set_tuning", "swept_set_heat_form",
+           "swept_last_heat_form", "swept_plan",
            "swept_advance", "swept_advance_noalloc", "swept_naive_advance",
            "swept_naive_substep_advance",
            "swept_set_profiling", "swept_stage_times", "swept_adjoint", "swept_naive_adjoint",
@@ -58,6 +61,8 @@ def _load() -> ctypes.CDLL:
     L.swept_init.argtypes = [ctypes.c_int]
     L.swept_set_stream.argtypes = [vp]
     L.swept_set_tuning.argtypes = [i32, i32, i32]
+    L.swept_set_heat_form.argtypes = [i32]
+    L.swept_last_heat_form.argtypes = [ctypes.POINTER(i32)]
     L.swept_plan.argtypes = [i64, i64, i32, ctypes.POINTER(i64)]
     for f in (L.swept_advance, L.swept_advance_noalloc, L.swept_naive_advance,
               L.swept_naive_substep_advance):
@@ -163,6 +168,21 @@ def _params(params: Sequence[float]):
 
 def set_tuning(tile_w: int = 0, pairs_per_lane: int = 0, mode: int = MODE_AUTO) -> None:
     _check(_lib.swept_set_tuning(int(tile_w), int(pairs_per_lane), int(mode)), "swept_set_tuning")
+
+
+def set_heat_form(form: int = FORM_AUTO) -> None:
+    """FORM_AUTO (the fused Laplacian where the library's range check allows
+    it) or FORM_CANONICAL (the five operations as written) for binary64 heat
+    in advance(); both give the same bits."""
+    _check(_lib.swept_set_heat_form(int(form)), "swept_set_heat_form")
+
+
+def last_heat_form() -> int:
+    """FORM_FUSED or FORM_CANONICAL: how the last binary64 heat advance()
+    evaluated its updates (0 before any); synchronises the library's stream."""
+    out = ctypes.c_int32(0)
+    _check(_lib.swept_last_heat_form(ctypes.byref(out)), "swept_last_heat_form")
+    return int(out.value)
 
 
 def set_batch_schedule(schedule: int = BATCH_PERSISTENT, spin_limit: int = 0,

@@ -57,7 +57,55 @@ struct StageArgs {
     int tiles;               // n / W
     int tri;                 // 1 for stage 0
     typename S::Consts c;
+    unsigned long long guard;  // call id of the range check (0: the canonical form only)
 };
+
+// The stencil a kernel runs once the call's range check has passed: the
+// fused-Laplacian form of binary64 heat (HeatLap), which gives the canonical
+// bits from fewer operations; void where there is none.
+template <class S>
+struct fused_form {
+    using type = void;
+};
+template <>
+struct fused_form<HeatF64> {
+    using type = HeatLapF64;
+};
+template <class S>
+constexpr bool has_fused_form = !std::is_void_v<typename fused_form<S>::type>;
+// a stencil type as a value, for the kernels' generic lambdas
+template <class S>
+struct stencil_tag {
+    using type = S;
+};
+
+// The largest call id whose initial field failed the range check, per
+// device (calls are numbered from 1 by the host and only ever raise it).  A
+// stage kernel of call `guard` takes the fused form while the mark is below
+// its id: a call whose own check failed has raised the mark to at least its
+// id (in an earlier launch on the same stream), so it never does.
+__device__ unsigned long long g_form_mark;
+
+__device__ __forceinline__ bool fused_ok(unsigned long long guard)
+{
+    return guard != 0 && g_form_mark < guard;
+}
+
+// The range check of the fused heat form: any finite |u| above `bound`
+// (a sixteenth of the largest finite value) marks the call.
+template <class T>
+__global__ __launch_bounds__(256) void heat_range_kernel(const T* __restrict__ u, int64_t n,
+                                                         T bound, unsigned long long id)
+{
+    bool bad = false;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+        const T v = u[i];
+        bad = bad || (__builtin_isfinite(v) && __builtin_fabs(v) > bound);
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0)
+        atomicMax(&g_form_mark, id);
+}
 
 __device__ __forceinline__ int64_t wrapn(int64_t x, int64_t n)
 {
@@ -382,9 +430,20 @@ __global__ __launch_bounds__(64) void swept_stage_kernel(StageArgs<S> g)
     const int k = g.k;
     const int tn = (t + 1 == g.tiles) ? 0 : t + 1;
     const int64_t J = wrapn((int64_t)t * (2 * (int64_t)k) + g.J0, g.n);
-    banded_region<S, P>(g.u, g.re + (size_t)t * k * 2, g.re_out + (size_t)t * k * 2,
-                        g.le_in + (size_t)tn * k * 2, g.le_out + (size_t)t * k * 2,
-                        reinterpret_cast<Pt*>(smem_raw), g.n, g.L, g.b, J, k, k, g.tri != 0, g.c);
+    auto run = [&](auto sx) {
+        using SX = typename decltype(sx)::type;
+        banded_region<SX, P>(g.u, g.re + (size_t)t * k * 2, g.re_out + (size_t)t * k * 2,
+                             g.le_in + (size_t)tn * k * 2, g.le_out + (size_t)t * k * 2,
+                             reinterpret_cast<Pt*>(smem_raw), g.n, g.L, g.b, J, k, k,
+                             g.tri != 0, g.c);
+    };
+    if constexpr (has_fused_form<S>) {
+        if (fused_ok(g.guard)) {
+            run(stencil_tag<typename fused_form<S>::type>{});
+            return;
+        }
+    }
+    run(stencil_tag<S>{});
 }
 
 // ------------------------------------------------- continuous diamond stage
@@ -431,7 +490,7 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
                                           int next_slot, int wslot, bool wlast,
                                           typename S::Pt* re_store,
                                           const typename S::Consts& c, face_t<S> (&Fn)[P],
-                                          void* fch, int fslot)
+                                          void* fch, int fslot, bool wmirror, int k)
 {
     using Pt = typename S::Pt;
     if constexpr (face_phase<S, PH>()) {
@@ -522,9 +581,16 @@ __device__ __forceinline__ void cont_step(typename S::Pt (&A)[P], typename S::Pt
         if constexpr (has_chain_store<S>::value) {
             S::template chain_store<PH>(&chain[2 * wslot], &chain[2 * wslot + 1], B[P - 1],
                                         A[P - 1]);
+            if (chain_prefetch<S>::value && wmirror)
+                S::template chain_store<PH>(&chain[2 * k], &chain[2 * k + 1], B[P - 1],
+                                            A[P - 1]);
         } else {
             chain[2 * wslot] = B[P - 1];
             chain[2 * wslot + 1] = A[P - 1];
+            if (chain_prefetch<S>::value && wmirror) {
+                chain[2 * k] = B[P - 1];
+                chain[2 * k + 1] = A[P - 1];
+            }
         }
     }
 }
@@ -555,7 +621,7 @@ __device__ __forceinline__ void cont_head_group(int j0, int k, int nb, int cyc,
         constexpr int PH = (PH0 + I) % S::NPHASE;
         const int j = j0 + I;
         const int rs = j / P;
-        const int next_slot = (j + 1 == k) ? 0 : j + 1;
+        const int next_slot = j + 1;   // entry k mirrors entry 0 (read at j = k - 1)
         // last slot: step m = sigma - (NB-1) mod k of its band (j < NB here,
         // so j + k - (NB-1) lies in [k - NB + 1, k])
         const int wraw = j + k - (NB - 1);
@@ -571,7 +637,7 @@ __device__ __forceinline__ void cont_head_group(int j0, int k, int nb, int cyc,
         cont_step<S, P, PH, MASK, (TRANS || MASK == 4) ? QS : -1>(A, B, An, Bn, cA, cB, chain,
                                                                  lane, j, rs,
                                                    next_slot, wslot, wlast, re_store, c, Fn, fch,
-                                                   fslot);
+                                                   fslot, wraw == k, k);
         cont_head_group<S, P, PH0, MASK, TRANS, I + 1, G>(j0, k, nb, cyc, A, B, An, Bn, cA, cB,
                                                           chain, re, re_out, lane, c, Fn, fch);
     }
@@ -590,21 +656,30 @@ __device__ __forceinline__ void cont_body_group(int j0, int k, typename S::Pt (&
     if constexpr (I < U) {
         constexpr int NB = 64 * P;
         const int j = j0 + I;
-        const int next_slot = (j + 1 == k) ? 0 : j + 1;
         cont_step<S, P, (PH0 + I) % S::NPHASE, 0, -1>(A, B, An, Bn, cA, cB, chain, lane, j, 0,
-                                                      next_slot, j - (NB - 1), true, nullptr, c,
-                                                      Fn, fch, j - NB);
+                                                      j + 1, j - (NB - 1), true, nullptr, c,
+                                                      Fn, fch, j - NB, false, k);
         cont_body_group<S, P, PH0, I + 1, U>(j0, k, A, B, An, Bn, cA, cB, chain, lane, c, Fn,
                                              fch);
     }
+}
+
+// Points of cont_region's LDS chain at depth k (the face chain not included):
+// k entries of two, and for stencils that prefetch a copy of entry 0.
+template <class S>
+constexpr int64_t cont_chain_points(int64_t k)
+{
+    return 2 * k + (chain_prefetch<S>::value ? 2 : 0);
 }
 
 // One full diamond region (k x k pairs, every level below the target) on
 // the continuous-band schedule.  re: the left V edge (pair d at step -1),
 // read and then overwritten in place by re_out when they are the same
 // buffer; le_in: the right V edge (pair -1 at step m); le_out: the new left
-// edge; chain: 2k points of LDS, followed for stencils with kFaces by the
-// face chain (k/2 faces).  PH0 = b mod NPHASE.
+// edge; chain: k entries of two points in LDS (cont_chain_points), followed
+// for stencils that prefetch by a copy of entry 0 as entry k, so that slot 0
+// reads entry j + 1 at every step j without a wrap, and for stencils with
+// kFaces by the face chain (k/2 faces).  PH0 = b mod NPHASE.
 template <class S, int P, int PH0, bool COH = false>
 __device__ __forceinline__ void cont_region(const typename S::Pt* re, typename S::Pt* re_out,
                                             const typename S::Pt* le_in, typename S::Pt* le_out,
@@ -619,6 +694,8 @@ __device__ __forceinline__ void cont_region(const typename S::Pt* re, typename S
     const int nb = k / NB;
     for (int i = lane; i < 2 * k; i += 64)
         chain[i] = ld_edge<S, COH>(le_in + i);
+    if (chain_prefetch<S>::value && lane < 2)
+        chain[2 * k + lane] = ld_edge<S, COH>(le_in + lane);
     __syncthreads();
     void* fch = nullptr;
     face_t<S> Fn[P];
@@ -653,6 +730,14 @@ __device__ __forceinline__ void cont_region(const typename S::Pt* re, typename S
         }
     }
     Pt cA = chain[1], cB = chain[0];
+    {   // the chain's address in a VGPR (an opaque per-lane zero, in units of
+        // two points so the 16-byte alignment stays known): the per-step LDS
+        // accesses then take their offsets from it instead of a copy of a
+        // scalar address in every step
+        int vz;
+        asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
+        chain += 2 * vz;
+    }
 
     for (int cyc = 0;; ++cyc) {
         if (cyc == 0) {
@@ -737,9 +822,19 @@ __global__ __launch_bounds__(64) void swept_diamond_cont_kernel(StageArgs<S> g)
     const int t = blockIdx.x;
     const int k = g.k;
     const int tn = (t + 1 == g.tiles) ? 0 : t + 1;
-    cont_region<S, P, 0>(g.re + (size_t)t * k * 2, g.re_out + (size_t)t * k * 2,
-                         g.le_in + (size_t)tn * k * 2, g.le_out + (size_t)t * k * 2,
-                         reinterpret_cast<Pt*>(smem_raw), k, g.c);
+    auto run = [&](auto sx) {
+        using SX = typename decltype(sx)::type;
+        cont_region<SX, P, 0>(g.re + (size_t)t * k * 2, g.re_out + (size_t)t * k * 2,
+                              g.le_in + (size_t)tn * k * 2, g.le_out + (size_t)t * k * 2,
+                              reinterpret_cast<Pt*>(smem_raw), k, g.c);
+    };
+    if constexpr (has_fused_form<S>) {
+        if (fused_ok(g.guard)) {
+            run(stencil_tag<typename fused_form<S>::type>{});
+            return;
+        }
+    }
+    run(stencil_tag<S>{});
 }
 
 // ------------------------------------------------------------------ batch
@@ -1063,6 +1158,7 @@ struct RaggedArgs {
     int64_t n, L;
     int k, tiles, stage;
     typename S::Consts c;
+    unsigned long long guard;  // call id of the range check (0: the canonical form only)
 };
 
 template <class S, int P>
@@ -1073,9 +1169,19 @@ __global__ __launch_bounds__(64) void swept_ragged_kernel(RaggedArgs<S> g)
     const int T = g.tiles;
     const int64_t n = g.n, w = 2 * (int64_t)g.k;
     auto Xp = [&](int64_t i) { return (i % T) * w + (i / T) * n; };
-    tiled_region<S, P>(g.u, n, g.L, T, Xp, (int)blockIdx.x, g.stage, g.re,
-                       g.le[(g.stage + 1) & 1], g.le[g.stage & 1], g.c,
-                       reinterpret_cast<Pt*>(smem_raw));
+    auto run = [&](auto sx) {
+        using SX = typename decltype(sx)::type;
+        tiled_region<SX, P>(g.u, n, g.L, T, Xp, (int)blockIdx.x, g.stage, g.re,
+                            g.le[(g.stage + 1) & 1], g.le[g.stage & 1], g.c,
+                            reinterpret_cast<Pt*>(smem_raw));
+    };
+    if constexpr (has_fused_form<S>) {
+        if (fused_ok(g.guard)) {
+            run(stencil_tag<typename fused_form<S>::type>{});
+            return;
+        }
+    }
+    run(stencil_tag<S>{});
 }
 
 // The two-fold covers of a batch's odd rings in one launch: entry i copies
@@ -1581,8 +1687,9 @@ __device__ __forceinline__ typename S::Pt lane_row(const typename S::Pt& v,
     }
 }
 
-template <class S, bool FIELD>
-__global__ __launch_bounds__(64) void swept_lane_kernel(StageArgs<S> g)
+// SX: the stencil whose sub-timesteps the rows compute (S or its fused form)
+template <class S, class SX, bool FIELD>
+__device__ __forceinline__ void lane_stage(const StageArgs<S>& g)
 {
     using Pt = typename S::Pt;
     constexpr int NPH = S::NPHASE;
@@ -1627,16 +1734,16 @@ __global__ __launch_bounds__(64) void swept_lane_kernel(StageArgs<S> g)
     }
     levels_up<NPH>(g.b - 1, j0 + 1, min(k - 1, jtop), [&](int j, auto ph) {
         constexpr int PH = decltype(ph)::value;
-        v = pick(iA == j, eA, pick(iB == j, eB, lane_row<S, PH>(v, g.c)));
+        v = pick(iA == j, eA, pick(iB == j, eB, lane_row<SX, PH>(v, g.c)));
     });
     auto up_level = [&](int j, auto ph, auto outer) {
         constexpr int PH = decltype(ph)::value;
         if constexpr (decltype(outer)::value) {   // k = 32: the outermost columns' neighbours
             const Pt l = dpp_record_keep<kWaveShr1>(v, oL);
             const Pt r = dpp_record_keep<kWaveShl1>(v, oR);
-            v = S::template step<PH>(l, v, r, g.c);
+            v = SX::template step<PH>(l, v, r, g.c);
         } else {
-            v = lane_row<S, PH>(v, g.c);
+            v = lane_row<SX, PH>(v, g.c);
         }
         const bool own = (unsigned)(dx - (j - 2 * k)) <= (unsigned)(4 * k - 1 - 2 * j);
         const unsigned at = (unsigned)(ly.template base_h<true>(j) + dx - low) * PB;
@@ -1662,6 +1769,18 @@ __global__ __launch_bounds__(64) void swept_lane_kernel(StageArgs<S> g)
         le_out[2 * i] = U(j, j - 2 * k);
         le_out[2 * i + 1] = U(j, j - 2 * k + 1);
     }
+}
+
+template <class S, bool FIELD>
+__global__ __launch_bounds__(64) void swept_lane_kernel(StageArgs<S> g)
+{
+    if constexpr (FIELD && has_fused_form<S>) {
+        if (fused_ok(g.guard)) {
+            lane_stage<S, typename fused_form<S>::type, FIELD>(g);
+            return;
+        }
+    }
+    lane_stage<S, S, FIELD>(g);
 }
 
 // Zero time steps: the gradient is the seed at level 0.

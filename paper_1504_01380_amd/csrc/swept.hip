@@ -6,10 +6,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <string>
 #include <utility>
@@ -48,6 +50,9 @@ struct Context {
     int64_t recorded = 0;             // stages recorded by the last swept run
     int* fault = nullptr;             // persistent batch: set by a wait that gave up
     bool fault_unread = false;        // a persistent batch ran since swept_sync last looked
+    int heat_form = SWEPT_FORM_AUTO;  // swept_set_heat_form
+    int last_form = 0;                // last binary64 heat call: SWEPT_FORM_* (0: none yet)
+    unsigned long long last_guard = 0;  // its range check's call id (0: none)
 };
 
 Context g_ctx;
@@ -238,20 +243,22 @@ int auto_ppl(int id, int64_t k)
     return std::min(pmax(id) == 2 ? 1 : 4, k >= 512 ? 4 : (k >= 128 ? 2 : 1));
 }
 
-// LDS of the stage kernels: the 2k-point edge chain and, on the continuous
-// kernel of a stencil that shares face fluxes (Euler), the face chain (k/2
-// faces).  LDS sets how many workgroups share a CU: Euler at W = 256 takes
-// 19,968 bytes, eight per CU.
+// LDS of the stage kernels: the 2k-point edge chain (with one more entry on
+// the continuous kernel of a stencil that prefetches it, see
+// cont_chain_points) and, on the continuous kernel of a stencil that shares
+// face fluxes (Euler), the face chain (k/2 faces).  LDS sets how many
+// workgroups share a CU: Euler at W = 256 takes 19,968 bytes, eight per CU.
 size_t stage_lds_bytes(int id, int64_t W)
 {
-    const size_t face = base_id(id) == SWEPT_EULER_F64 ? sizeof(EulerF64::Face) : 0;
-    return (size_t)W * pt_bytes(id) + (size_t)(W / 4) * face;
+    const bool euler = base_id(id) == SWEPT_EULER_F64;
+    const size_t face = euler ? sizeof(EulerF64::Face) : 0;
+    return (size_t)(W + (euler ? 0 : 2)) * pt_bytes(id) + (size_t)(W / 4) * face;
 }
 
 template <class S>
 size_t stage_lds(int64_t W, bool cont)
 {
-    size_t bytes = (size_t)W * sizeof(typename S::Pt);
+    size_t bytes = (size_t)(cont ? cont_chain_points<S>(W / 2) : W) * sizeof(typename S::Pt);
     if constexpr (has_faces<S>::value)
         if (cont)
             bytes += (size_t)(W / 4) * sizeof(typename S::Face);
@@ -466,6 +473,41 @@ size_t lane_lds(int64_t k)
     return (size_t)(k * k + 3 * k + 3) * sizeof(typename S::Pt);
 }
 
+unsigned grid_for(int64_t n, int block);
+
+// Call ids of the range check; the device marks only ever rise to them.
+std::atomic<unsigned long long> g_call_id{0};
+// Longest run (in levels) the fused form's bound covers with room to spare
+// (the argument at HeatLap needs about 3e15).
+constexpr int64_t kFusedMaxLevels = 1000000000000000LL;
+
+// The fused heat form's preconditions: the host checks r and the run length
+// and, if they hold, enqueues the check of the initial field (heat_range_kernel),
+// whose result the stage kernels read on the device.  Returns the call id
+// for the stage kernels (0: the canonical form).  Stencils without a fused
+// form return 0 and leave the record of the last heat call alone.
+template <class S>
+unsigned long long range_check(const void* u, int64_t n, const typename S::Consts& c, int64_t L)
+{
+    if constexpr (!has_fused_form<S>) {
+        return 0;
+    } else {
+        using T = typename S::T;
+        g_ctx.last_guard = 0;
+        g_ctx.last_form = SWEPT_FORM_CANONICAL;
+        if (g_ctx.heat_form == SWEPT_FORM_CANONICAL || !(c.r >= 0 && c.r <= 0.5) ||
+            L > kFusedMaxLevels)
+            return 0;
+        const unsigned long long id = ++g_call_id;
+        hipLaunchKernelGGL(heat_range_kernel<T>, dim3(grid_for(n, 256)), dim3(256), 0,
+                           g_ctx.stream, static_cast<const T*>(u), n,
+                           std::numeric_limits<T>::max() / 16, id);
+        g_ctx.last_guard = id;
+        g_ctx.last_form = SWEPT_FORM_FUSED;   // until the mark says otherwise
+        return id;
+    }
+}
+
 template <class S>
 int run_swept(void* u, int64_t nx, int64_t L, const typename S::Consts& c, const Plan& p)
 {
@@ -487,6 +529,7 @@ int run_swept(void* u, int64_t nx, int64_t L, const typename S::Consts& c, const
     a.k = (int)p.k;
     a.tiles = (int)p.tiles;
     a.c = c;
+    a.guard = range_check<S>(u, nx, c, L);
     if (g_ctx.profiling) {
         rc = reserve_events(p.stages);
         if (rc)
@@ -573,6 +616,7 @@ int run_ragged(void* u, int64_t nx, int64_t L, const typename S::Consts& c, cons
         hipLaunchKernelGGL((batch_cover_kernel<S>), dim3(grid_for(ring, 256)), dim3(256), 0,
                            g_ctx.stream, static_cast<const T*>(u), field, nx, 2);
     RaggedArgs<S> a{};
+    a.guard = range_check<S>(u, nx, c, L);
     a.u = field;
     a.re = re;
     a.le[0] = re + ring;
@@ -802,7 +846,7 @@ int launch_batch_stage(const BatchInst<S>* inst, const BatchTask* tasks, const i
     a.le[0] = le0;
     a.le[1] = le1;
     a.stage = stage;
-    const size_t lds = (size_t)2 * kmax * sizeof(typename S::Pt);
+    const size_t lds = (size_t)cont_chain_points<S>(kmax) * sizeof(typename S::Pt);
     hipLaunchKernelGGL((swept_batch_kernel<S, 2>), dim3((unsigned)ntasks), dim3(64), lds, st, a);
     return SWEPT_OK;
 }
@@ -931,7 +975,7 @@ struct PersistLaunch {
         tiles = (int64_t)pp.tasks.size();
         if (pp.max_total <= 0)
             return SWEPT_OK;
-        lds = (size_t)2 * kmax * sizeof(typename S::Pt);
+        lds = (size_t)cont_chain_points<S>(kmax) * sizeof(typename S::Pt);
         int per_cu = 0, dev = 0;
         hipDeviceProp_t prop;
         HIP_TRY(hipGetDevice(&dev));
@@ -1555,8 +1599,13 @@ int advance_dispatch(void* u, int64_t nx, int64_t nsteps, int32_t id, const doub
     int rc = make_plan(nx, nsteps, id, &p);
     if (rc)
         return rc;
-    if (p.mode == SWEPT_MODE_NAIVE)
+    if (p.mode == SWEPT_MODE_NAIVE) {
+        if (id == SWEPT_HEAT_F64) {
+            g_ctx.last_guard = 0;
+            g_ctx.last_form = SWEPT_FORM_CANONICAL;
+        }
         return naive_dispatch(u, nx, nsteps, id, params);
+    }
     const int64_t L = nsteps * substeps_of(id);
     if (p.mode == SWEPT_MODE_STAGE_RAGGED) {
         switch (id) {
@@ -2106,6 +2155,33 @@ int swept_set_tuning(int32_t tile_w, int32_t pairs_per_lane, int32_t mode)
     g_ctx.tile_w = tile_w;
     g_ctx.ppl = pairs_per_lane;
     g_ctx.mode = mode;
+    return SWEPT_OK;
+}
+
+int swept_set_heat_form(int32_t form)
+{
+    if (form != SWEPT_FORM_AUTO && form != SWEPT_FORM_CANONICAL)
+        return fail(SWEPT_EINVAL, "heat form %d is neither SWEPT_FORM_AUTO nor "
+                                  "SWEPT_FORM_CANONICAL", form);
+    g_ctx.heat_form = form;
+    return SWEPT_OK;
+}
+
+int swept_last_heat_form(int32_t* form)
+{
+    if (!form)
+        return fail(SWEPT_EINVAL, "form is null");
+    if (!g_ctx.ready)
+        return fail(SWEPT_ENOTINIT, "swept_init has not been called");
+    *form = g_ctx.last_form;
+    if (g_ctx.last_form == SWEPT_FORM_FUSED) {
+        unsigned long long mark = 0;
+        HIP_TRY(hipStreamSynchronize(g_ctx.stream));
+        HIP_TRY(hipMemcpyFromSymbol(&mark, HIP_SYMBOL(g_form_mark), sizeof(mark), 0,
+                                    hipMemcpyDeviceToHost));
+        if (mark >= g_ctx.last_guard)
+            *form = SWEPT_FORM_CANONICAL;
+    }
     return SWEPT_OK;
 }
 

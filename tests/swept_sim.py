@@ -69,9 +69,12 @@ def _cont_stage(t, J, b, k, P, lanes, RE, chain, step, nph, n, visits):
     (KS, as in the kernel) they keep computing: slot e takes its first state
     at fill step e and stores its final one at drain step e.  Here a slot's
     state is NaN before its start and after its end, so a read of it by an
-    active slot would show in the result."""
+    active slot would show in the result.  As in the kernel, the chain holds
+    a copy of entry 0 as entry k, which the last slot updates with entry 0,
+    and slot 0 prefetches entry j + 1 at every step j (no wrap at j = k - 1)."""
     NB = lanes * P
     nb = k // NB
+    chain.extend([chain[0], chain[1]])
     unmasked = getattr(step, "unmasked_ends", False)
     A = [RE[t][2 * e + 1] for e in range(NB)]
     B = [RE[t][2 * e] for e in range(NB)]
@@ -92,7 +95,7 @@ def _cont_stage(t, J, b, k, P, lanes, RE, chain, step, nph, n, visits):
             trans = 0 < cyc < nb and j < NB
             inA = [cA] + [A[(r - 1) * P + P - 1] for r in range(1, lanes)]
             inB = [cB] + [B[(r - 1) * P + P - 1] for r in range(1, lanes)]
-            ns = 0 if j + 1 == k else j + 1
+            ns = j + 1
             nA, nB = chain[2 * ns + 1], chain[2 * ns]
             ph = (b + sigma) % nph
             for r in range(lanes):
@@ -125,6 +128,10 @@ def _cont_stage(t, J, b, k, P, lanes, RE, chain, step, nph, n, visits):
                 ws = (j + k - (NB - 1)) % k
                 chain[2 * ws], chain[2 * ws + 1] = _chain_store(ph, B[NB - 1], A[NB - 1],
                                                                 chain[2 * ws], chain[2 * ws + 1])
+                if ws == 0:
+                    chain[2 * k], chain[2 * k + 1] = _chain_store(ph, B[NB - 1], A[NB - 1],
+                                                                  chain[2 * k],
+                                                                  chain[2 * k + 1])
             cA, cB = nA, nB
             if (trans or mask == 4) and j == NB - 1 and cyc + 1 < nb:
                 # every slot has entered band cyc: band cyc+1's left-edge
@@ -136,6 +143,7 @@ def _cont_stage(t, J, b, k, P, lanes, RE, chain, step, nph, n, visits):
         for e in range(NB):
             RE[t][2 * ((nb - 1) * NB + e)] = B[e]
             RE[t][2 * ((nb - 1) * NB + e) + 1] = A[e]
+    del chain[2 * k:]                     # the copy of entry 0 is not part of the edge
 
 
 def cont_faces_symbolic(k, P, b, lanes=64):

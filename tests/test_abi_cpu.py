@@ -47,6 +47,17 @@ def test_calls_before_init_fail_cleanly(swept):
     assert "swept_init" in swept.last_error()
     assert lib.swept_sync() == -2
     assert lib.swept_set_stream(None) == -2
+    form = ctypes.c_int32(7)
+    assert lib.swept_last_heat_form(ctypes.byref(form)) == -2
+
+
+def test_heat_form_validation(swept):
+    lib = swept.lib()
+    assert lib.swept_set_heat_form(2) == -1     # FUSED is reported, not requested
+    assert lib.swept_set_heat_form(-1) == -1
+    assert lib.swept_last_heat_form(None) == -1
+    assert lib.swept_set_heat_form(swept.FORM_CANONICAL) == 0
+    assert lib.swept_set_heat_form(swept.FORM_AUTO) == 0
 
 
 def test_tuning_validation(swept):
