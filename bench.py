@@ -66,8 +66,8 @@ def parse():
                          "benchmark line)")
     ap.add_argument("--profile-mix", action="store_true",
                     help="short run for rocprofv3 instruction counters: one swept run each of "
-                         "heat (2^24, 2,000 steps, W=1024 P=4), KS (2^20, 1,000 steps, W=512 "
-                         "P=2) and Euler (2^20 cells, 300 steps, W=256 P=1)")
+                         "heat (2^24, 2,000 steps, W=1024 P=4), KS (2^20, 1,000 steps, W=1024 "
+                         "P=4) and Euler (2^20 cells, 300 steps, W=256 P=1)")
     return ap.parse_args()
 
 
@@ -483,7 +483,7 @@ def profile_mix(sw, torch, workloads):
     we, wk = workloads.WORKLOADS["euler"], workloads.WORKLOADS["ks"]
     for name, st, nsteps, par, W, P in (
             ("heat_large", "heat", 2000, [0.25], 1024, 4),
-            ("ks", "ks", 1000, [wk["dt"], wk["dx"]], 512, 2),
+            ("ks", "ks", 1000, [wk["dt"], wk["dx"]], 1024, 4),
             ("euler", "euler", 300, [we["cfl"] / we["n"], 1.0 / we["n"], we["gamma"]], 256, 1)):
         sw.set_tuning(W, P, sw.MODE_AUTO)
         u = torch.from_numpy(workloads.initial(name)).cuda()
