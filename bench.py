@@ -204,8 +204,8 @@ EULER_OPS_PER_STEP = 320
 
 
 def heat_ops(sw) -> int:
-    """VALU instructions per binary64 heat update of the last swept_advance
-    call: 4 in the fused-Laplacian form, 5 in the canonical one."""
+    """VALU instructions per heat update of the last swept_advance call: 4
+    in the fused-Laplacian form, 5 in the canonical one."""
     return HEAT_FUSED_LAP_OPS if sw.last_heat_form() == sw.FORM_FUSED else HEAT_OPS_PER_UPDATE
 
 
@@ -696,11 +696,13 @@ def main():
         tune32 = None if args.no_tune else sw.autotune(n, nsteps, "heat", [0.25], torch.float32)
         plan32 = sw.plan(n, nsteps, "heat", torch.float32)
         st, _ = timed_runs(sw, torch, sw.advance, u32, nsteps, [0.25], 2, 1)
+        ops32 = heat_ops(sw)
         nt32, _ = timed_runs(sw, torch, sw.naive_advance, u32, nsteps, [0.25], 1, 1)
         s32 = updates / (sum(st) / len(st))
         n32 = updates / nt32[0]
         out["f32"] = {"swept": s32, "naive": n32, "speedup_vs_naive": s32 / n32,
-                      "swept_frac_alu": HEAT_OPS_PER_UPDATE * s32 / VALU_LANE_OPS_F32,
+                      "ops_per_update": ops32,
+                      "swept_frac_alu": ops32 * s32 / VALU_LANE_OPS_F32,
                       "naive_hbm_frac": n32 * HEAT_NAIVE_BYTES[4] / HBM_PEAK,
                       "tile_w": plan32["tile_w"], "pairs_per_lane": plan32["pairs_per_lane"],
                       "tuning": tune32}

@@ -162,22 +162,24 @@ int swept_set_stream(void *hip_stream);
 int swept_set_tuning(int32_t tile_w, int32_t pairs_per_lane, int32_t mode);
 
 /*
- * How swept_advance and swept_advance_noalloc evaluate SWEPT_HEAT_F64 (the
- * heat sub-timestep of the paper's Section 4).  Both forms give the
- * canonical bits defined above.
+ * How swept_advance and swept_advance_noalloc evaluate SWEPT_HEAT_F64 and
+ * SWEPT_HEAT_F32 (the heat sub-timestep of the paper's Section 4).  Both
+ * forms give the canonical bits defined above.
  *  - SWEPT_FORM_AUTO (the default): the stage kernels compute
  *    (u[i-1] + u[i+1]) - 2*u[i] as one fused multiply-add,
- *    fma(-2, u[i], u[i-1] + u[i+1]).  2*u[i] is exact whenever it is
- *    finite, so the subtraction rounds the same exact difference once, as
- *    the fused multiply-add does: four operations per point instead of five.
- *    The kernels take this form when 0 <= r <= 1/2, the run is shorter than
- *    1e15 steps, and a check of the initial field on the device (one extra
- *    read of u, enqueued with the stages) finds no finite |u| above
- *    DBL_MAX/16.  For such r each update is a convex combination of its
- *    three inputs, so no point comes near DBL_MAX/2, the only place where
- *    the two forms differ (2*u overflows, the fused form does not); a
- *    non-finite value only produces non-finite values, alike in both forms.
- *    Otherwise the kernels evaluate the five operations as written.
+ *    fma(-2, u[i], u[i-1] + u[i+1]), in the field's precision.  2*u[i] is
+ *    exact whenever it is finite, so the subtraction rounds the same exact
+ *    difference once, as the fused multiply-add does: four operations per
+ *    point instead of five.  The kernels take this form when 0 <= r <= 1/2
+ *    (r as rounded to the field's type), the run is at most 1e15 steps
+ *    (binary64) or 1e6 steps (binary32), and a check of the initial field on
+ *    the device (one extra read of u, enqueued with the stages) finds no
+ *    finite |u| above a sixteenth of the type's largest finite value (MAX).
+ *    For such r each update is a convex combination of its three inputs, so
+ *    no point comes near MAX/2, the only place where the two forms differ
+ *    (2*u overflows, the fused form does not); a non-finite value only
+ *    produces non-finite values, alike in both forms.  Otherwise the
+ *    kernels evaluate the five operations as written.
  *  - SWEPT_FORM_CANONICAL: always the five operations as written.
  * The setting persists until changed.  Other stencil ids, swept_naive_advance,
  * the batch and the adjoints always evaluate their schemes as written.
@@ -191,9 +193,10 @@ int swept_set_heat_form(int32_t form);
 
 /*
  * The form the last swept_advance or swept_advance_noalloc call with
- * SWEPT_HEAT_F64 evaluated (SWEPT_FORM_FUSED or SWEPT_FORM_CANONICAL; the
- * naive schedule counts as canonical), or 0 before any such call.  It
- * synchronises the library's stream to read the device-side check.
+ * SWEPT_HEAT_F64 or SWEPT_HEAT_F32 evaluated (SWEPT_FORM_FUSED or
+ * SWEPT_FORM_CANONICAL; the naive schedule counts as canonical), or 0 before
+ * any such call.  It synchronises the library's stream to read the
+ * device-side check.
  */
 int swept_last_heat_form(int32_t *form);
 

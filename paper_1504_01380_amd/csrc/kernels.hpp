@@ -61,8 +61,8 @@ struct StageArgs {
 };
 
 // The stencil a kernel runs once the call's range check has passed: the
-// fused-Laplacian form of binary64 heat (HeatLap), which gives the canonical
-// bits from fewer operations; void where there is none.
+// fused-Laplacian form of heat (HeatLap), which gives the canonical bits from
+// fewer operations; void where there is none.
 template <class S>
 struct fused_form {
     using type = void;
@@ -70,6 +70,10 @@ struct fused_form {
 template <>
 struct fused_form<HeatF64> {
     using type = HeatLapF64;
+};
+template <>
+struct fused_form<HeatF32> {
+    using type = HeatLapF32;
 };
 template <class S>
 constexpr bool has_fused_form = !std::is_void_v<typename fused_form<S>::type>;

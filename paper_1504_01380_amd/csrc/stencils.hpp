@@ -263,14 +263,13 @@ using HeatFmaF32 = HeatFma<float>;
 // is what fma(-2, u, s) computes.  The two differ only where |u| exceeds
 // half the largest finite value (2u overflows, the fused form does not).
 // The kernels take this form only after the library has checked, for the
-// call at hand, that 0 <= r <= 1/2 and every finite |u0| is at most a
-// sixteenth of the largest finite value: for such r the update is a convex
-// combination of the three inputs, so no point ever comes near that bound
-// (each level can exceed the previous level's largest magnitude by a few
-// roundings at most; with the 16x margin, that takes more than 1e15 steps),
-// and a non-finite input yields non-finite outputs in both forms alike.
-// Binary64 only: in binary32 the fused form ran slower than the five
-// operations (62 ms against 38 ms on the 2^24-point heat workload).
+// call at hand, that 0 <= r <= 1/2, the run is not too long, and every
+// finite |u0| is at most a sixteenth of the largest finite value: for such
+// r the update is a convex combination of the three inputs, so each level
+// exceeds the previous level's largest magnitude by at most 7 units of
+// roundoff relative, and growing 8x takes more than 2e15 steps in binary64
+// and 4e6 in binary32 (the library allows 1e15 and 1e6).  A non-finite input
+// yields non-finite outputs in both forms alike.
 template <class TT>
 struct HeatLap : Heat<TT> {
     using Base = Heat<TT>;
@@ -280,12 +279,13 @@ struct HeatLap : Heat<TT> {
     __device__ __forceinline__ static Pt step(const Pt& l, const Pt& c, const Pt& r,
                                               const Consts& k)
     {
-        const TT lap = __builtin_fma(TT(-2), c.u, l.u + r.u);
+        const TT lap = fmad(TT(-2), c.u, l.u + r.u);
         return Pt{c.u + k.r * lap};
     }
 };
 
 using HeatLapF64 = HeatLap<double>;
+using HeatLapF32 = HeatLap<float>;
 
 // KS: D2(a) = fma(-2, a, a[i-1] + a[i+1]) * c2,
 //     F(a,b) = -(fma(a, D1(a), b) + D2(b)),  v = fma(h, F, u),  u' = fma(dt, F, u)

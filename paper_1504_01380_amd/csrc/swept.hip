@@ -51,7 +51,7 @@ struct Context {
     int* fault = nullptr;             // persistent batch: set by a wait that gave up
     bool fault_unread = false;        // a persistent batch ran since swept_sync last looked
     int heat_form = SWEPT_FORM_AUTO;  // swept_set_heat_form
-    int last_form = 0;                // last binary64 heat call: SWEPT_FORM_* (0: none yet)
+    int last_form = 0;                // last heat call: SWEPT_FORM_* (0: none yet)
     unsigned long long last_guard = 0;  // its range check's call id (0: none)
 };
 
@@ -478,8 +478,9 @@ unsigned grid_for(int64_t n, int block);
 // Call ids of the range check; the device marks only ever rise to them.
 std::atomic<unsigned long long> g_call_id{0};
 // Longest run (in levels) the fused form's bound covers with room to spare
-// (the argument at HeatLap needs about 3e15).
-constexpr int64_t kFusedMaxLevels = 1000000000000000LL;
+// (the argument at HeatLap: about 2e15 in binary64, 4e6 in binary32).
+template <class T>
+constexpr int64_t kFusedMaxLevels = sizeof(T) == 8 ? 1000000000000000LL : 1000000LL;
 
 // The fused heat form's preconditions: the host checks r and the run length
 // and, if they hold, enqueues the check of the initial field (heat_range_kernel),
@@ -496,7 +497,7 @@ unsigned long long range_check(const void* u, int64_t n, const typename S::Const
         g_ctx.last_guard = 0;
         g_ctx.last_form = SWEPT_FORM_CANONICAL;
         if (g_ctx.heat_form == SWEPT_FORM_CANONICAL || !(c.r >= 0 && c.r <= 0.5) ||
-            L > kFusedMaxLevels)
+            L > kFusedMaxLevels<T>)
             return 0;
         const unsigned long long id = ++g_call_id;
         hipLaunchKernelGGL(heat_range_kernel<T>, dim3(grid_for(n, 256)), dim3(256), 0,
@@ -1600,7 +1601,7 @@ int advance_dispatch(void* u, int64_t nx, int64_t nsteps, int32_t id, const doub
     if (rc)
         return rc;
     if (p.mode == SWEPT_MODE_NAIVE) {
-        if (id == SWEPT_HEAT_F64) {
+        if (id == SWEPT_HEAT_F64 || id == SWEPT_HEAT_F32) {
             g_ctx.last_guard = 0;
             g_ctx.last_form = SWEPT_FORM_CANONICAL;
         }

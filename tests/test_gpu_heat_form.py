@@ -1,9 +1,11 @@
-"""The fused-Laplacian evaluation of binary64 heat in swept_advance.
+"""The fused-Laplacian evaluation of heat (binary64 and binary32) in
+swept_advance.
 
 (u[i-1] + u[i+1]) - 2u equals fma(-2, u, u[i-1] + u[i+1]) bit for bit while
 2u is finite; the library takes the fused form only after its range check
-(0 <= r <= 1/2, every finite |u0| <= DBL_MAX/16), which keeps every point far
-from DBL_MAX/2 (paper, Section 4: the heat sub-timestep).  Both forms must
+(0 <= r <= 1/2, every finite |u0| <= MAX/16 for the type's largest finite
+value MAX), which keeps every point far from MAX/2 (paper, Section 4: the
+heat sub-timestep).  Both forms must
 give the oracle's bits; the checks here also make sure the fused form is the
 one taken where it is allowed, that data or parameters outside the allowed
 range take the five operations as written, and that one call's failed check
@@ -18,6 +20,7 @@ pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
 DMAX = np.finfo(np.float64).max
+FMAX = np.finfo(np.float32).max
 
 
 @pytest.fixture(scope="module")
@@ -66,9 +69,10 @@ PLANS = [("cont_W1024_P4", 1 << 16, 1500, (1024, 4, 1)),
          ("auto", 5000, 300, (0, 0, 0))]
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("label,nx,nsteps,tuning", PLANS)
-def test_fused_form_is_taken_and_exact(sw, oracle_mod, label, nx, nsteps, tuning):
-    u0 = workloads.white_noise(nx, seed=nx + 3)
+def test_fused_form_is_taken_and_exact(sw, oracle_mod, label, nx, nsteps, tuning, dtype):
+    u0 = workloads.white_noise(nx, seed=nx + 3, dtype=dtype)
     want = oracle_mod.heat(u0, nsteps, 0.25)
     sw.set_tuning(*tuning)
     got = run(sw, u0, nsteps, 0.25)
@@ -80,30 +84,39 @@ def test_fused_form_is_taken_and_exact(sw, oracle_mod, label, nx, nsteps, tuning
     assert same_bits(got, want)
 
 
-@pytest.mark.parametrize("r", [0.0, 0.1, 0.3, 0.5])
-def test_fused_form_over_the_allowed_r(sw, oracle_mod, r):
-    u0 = workloads.white_noise(1 << 14, seed=77)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("r", [0.0, 0.1, 0.3, 0.5, 0.5000000000000001])
+def test_fused_form_over_the_allowed_r(sw, oracle_mod, r, dtype):
+    """0 <= r <= 1/2 as the field's type rounds it (the double just above
+    1/2 rounds to 1/2 in binary32)."""
+    if dtype == np.float64 and r > 0.5:
+        pytest.skip("outside the allowed range in binary64")
+    u0 = workloads.white_noise(1 << 14, seed=77, dtype=dtype)
     sw.set_tuning(256, 2, 1)
     got = run(sw, u0, 900, r)
     assert sw.last_heat_form() == sw.FORM_FUSED
     assert same_bits(got, oracle_mod.heat(u0, 900, r))
 
 
-@pytest.mark.parametrize("r", [-0.05, 0.5000000000000001, 0.6, 1.0])
-def test_r_outside_the_range_takes_the_canonical_form(sw, oracle_mod, r):
-    u0 = workloads.white_noise(1 << 14, seed=78)
+@pytest.mark.parametrize("dtype,r", [(np.float64, -0.05), (np.float64, 0.5000000000000001),
+                                     (np.float64, 0.6), (np.float64, 1.0),
+                                     (np.float32, -0.05), (np.float32, 0.50000006),
+                                     (np.float32, 0.6)])
+def test_r_outside_the_range_takes_the_canonical_form(sw, oracle_mod, dtype, r):
+    u0 = workloads.white_noise(1 << 14, seed=78, dtype=dtype)
     sw.set_tuning(256, 2, 1)
     got = run(sw, u0, 120, r)
     assert sw.last_heat_form() == sw.FORM_CANONICAL
     assert same_bits_up_to_nan(got, oracle_mod.heat(u0, 120, r))
 
 
-def test_values_near_the_overflow_take_the_canonical_form(sw, oracle_mod):
-    """Values of 0.4..0.6 DBL_MAX: 2u overflows for half of them, so the
+@pytest.mark.parametrize("dtype,big", [(np.float64, DMAX), (np.float32, FMAX)])
+def test_values_near_the_overflow_take_the_canonical_form(sw, oracle_mod, dtype, big):
+    """Values of 0.4..0.6 MAX: 2u overflows for half of them, so the
     oracle's run fills with infinities and NaNs, which the fused form would
     not produce.  The range check must send the call to the canonical form."""
     rng = np.random.default_rng(5)
-    u0 = DMAX * (0.5 + 0.1 * rng.uniform(-1.0, 1.0, 1 << 14))
+    u0 = (big * (0.5 + 0.1 * rng.uniform(-1.0, 1.0, 1 << 14))).astype(dtype)
     want = oracle_mod.heat(u0, 40, 0.25)
     assert not np.all(np.isfinite(want))        # the case separates the two forms
     sw.set_tuning(256, 2, 1)
@@ -112,11 +125,13 @@ def test_values_near_the_overflow_take_the_canonical_form(sw, oracle_mod):
     assert same_bits_up_to_nan(got, want)
 
 
-def test_the_bound_is_a_sixteenth_of_the_largest_value(sw, oracle_mod):
-    u0 = workloads.white_noise(1 << 14, seed=79)
+@pytest.mark.parametrize("dtype,big", [(np.float64, DMAX), (np.float32, FMAX)])
+def test_the_bound_is_a_sixteenth_of_the_largest_value(sw, oracle_mod, dtype, big):
+    u0 = workloads.white_noise(1 << 14, seed=79, dtype=dtype)
     sw.set_tuning(256, 2, 1)
-    for scale, form in ((DMAX / 16, sw.FORM_FUSED),
-                        (np.nextafter(DMAX / 16, np.inf), sw.FORM_CANONICAL)):
+    lim = dtype(big / 16)
+    for scale, form in ((lim, sw.FORM_FUSED),
+                        (np.nextafter(lim, dtype(np.inf)), sw.FORM_CANONICAL)):
         v = u0.copy()
         v[123] = scale
         got = run(sw, v, 200, 0.25)

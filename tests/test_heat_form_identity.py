@@ -20,9 +20,12 @@ import numpy as np
 import pytest
 
 import workloads
+from tests.test_oracle_fma_pins import round32
 
 DMAX = np.finfo(np.float64).max
+FMAX = np.finfo(np.float32).max
 EPS = 2.0 ** -53                    # unit roundoff of binary64
+EPS32 = 2.0 ** -24                  # unit roundoff of binary32
 
 
 def fma_exact(a: float, b: float, c: float) -> float:
@@ -55,6 +58,22 @@ def test_canonical_laplacian_equals_the_fused_one(lo, hi):
             assert (s2 - 2.0 * u) == fma_exact(-2.0, u, s2)
 
 
+@pytest.mark.parametrize("lo,hi", [(-149, -120), (-30, 10), (-3, 3), (100, 125)])
+def test_canonical_laplacian_equals_the_fused_one_binary32(lo, hi):
+    """The same identity in binary32: s - fl32(2u) == fl32(s - 2u exactly)
+    for |u| <= FLT_MAX/2, subnormals included."""
+    rng = np.random.default_rng(lo + 3000)
+    us = np.array(random_doubles(rng, 3000, lo, hi)).astype(np.float32)
+    ss = np.array(random_doubles(rng, 3000, lo, hi)).astype(np.float32)
+    two = np.float32(2.0)
+    for u, s in zip(us, ss):
+        for s2 in (s, two * u, np.nextafter(two * u, np.float32(np.inf)), s + two * u):
+            if not np.isfinite(s2) or abs(u) > FMAX / 2 or abs(s2) > FMAX / 2:
+                continue
+            exact = Fraction(float(s2)) - 2 * Fraction(float(u))
+            assert float(np.float32(s2 - two * u)) == round32(exact)
+
+
 def test_the_forms_differ_only_past_half_the_largest_value():
     u, s = 0.6 * DMAX, DMAX
     assert math.isinf(s - 2.0 * u)              # 2u overflows
@@ -80,6 +99,22 @@ def test_the_largest_magnitude_stays_bounded(oracle_mod, r):
         u = oracle_mod.heat(u, 200, r)
         assert np.all(np.isfinite(u))
         assert np.max(np.abs(u)) <= bound
+
+
+@pytest.mark.parametrize("r", [0.5, 0.25, 0.1])
+def test_the_largest_magnitude_stays_bounded_binary32(oracle_mod, r):
+    """The binary32 run at the check's bound FLT_MAX/16: max|u| stays within
+    max|u0| * (1 + 7 eps32)^n."""
+    n, steps = 512, 2000
+    rng = np.random.default_rng(12)
+    u0 = ((FMAX / 16) * rng.choice([-1.0, 1.0], n) * rng.uniform(0.999, 1.0, n)).astype(np.float32)
+    u0[::7] = np.float32(FMAX / 16)
+    bound = float(np.max(np.abs(u0))) * (1.0 + 7.0 * EPS32) ** steps
+    u = u0
+    for _ in range(steps // 200):
+        u = oracle_mod.heat(u, 200, r)
+        assert u.dtype == np.float32 and np.all(np.isfinite(u))
+        assert float(np.max(np.abs(u))) <= bound
 
 
 def test_white_noise_workload_is_far_inside_the_bound():
