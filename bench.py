@@ -231,7 +231,7 @@ def other_workloads(sw, torch, workloads, tune=True):
         plan = sw.plan(n, nsteps, st)
         rec = {"n": n, "time_steps": nsteps, "tile_w": plan["tile_w"],
                "pairs_per_lane": plan["pairs_per_lane"], "stages": plan["stages"],
-               "tuning": tuned}
+               "mode": plan["mode"], "tuning": tuned}
         for label, fn, reps in (("swept", sw.advance, 3), ("naive", sw.naive_advance, 1)):
             u = u0.clone()
             fn(u, nsteps, st, par)           # warm-up
