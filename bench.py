@@ -323,6 +323,7 @@ def batch_workload(sw, torch, workloads, tune=True):
     rec["swept"] = work / t
     rec["swept_ms"] = t * 1e3
     rec["persistent_vs_staged"] = ts_ / t
+    rec["heat_form"] = "fused-Laplacian" if sw.last_heat_form() == sw.FORM_FUSED else "canonical"
     sw.naive_advance_batch(us[:64], [min(x, 4) for x in ns[:64]], kinds[:64], pars[:64])
     restore()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

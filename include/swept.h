@@ -162,9 +162,9 @@ int swept_set_stream(void *hip_stream);
 int swept_set_tuning(int32_t tile_w, int32_t pairs_per_lane, int32_t mode);
 
 /*
- * How swept_advance and swept_advance_noalloc evaluate SWEPT_HEAT_F64 and
- * SWEPT_HEAT_F32 (the heat sub-timestep of the paper's Section 4).  Both
- * forms give the canonical bits defined above.
+ * How swept_advance, swept_advance_noalloc and swept_advance_batch evaluate
+ * SWEPT_HEAT_F64 and SWEPT_HEAT_F32 (the heat sub-timestep of the paper's
+ * Section 4).  Both forms give the canonical bits defined above.
  *  - SWEPT_FORM_AUTO (the default): the stage kernels compute
  *    (u[i-1] + u[i+1]) - 2*u[i] as one fused multiply-add,
  *    fma(-2, u[i], u[i-1] + u[i+1]), in the field's precision.  2*u[i] is
@@ -179,10 +179,13 @@ int swept_set_tuning(int32_t tile_w, int32_t pairs_per_lane, int32_t mode);
  *    no point comes near MAX/2, the only place where the two forms differ
  *    (2*u overflows, the fused form does not); a non-finite value only
  *    produces non-finite values, alike in both forms.  Otherwise the
- *    kernels evaluate the five operations as written.
+ *    kernels evaluate the five operations as written.  A batch takes one
+ *    verdict for all its heat instances: every one must meet the
+ *    conditions (its r, its step count, its field), else all of them run
+ *    the five operations; each launch of a batch checks its fields again.
  *  - SWEPT_FORM_CANONICAL: always the five operations as written.
- * The setting persists until changed.  Other stencil ids, swept_naive_advance,
- * the batch and the adjoints always evaluate their schemes as written.
+ * The setting persists until changed.  Other stencil ids, swept_naive_advance
+ * and the adjoints always evaluate their schemes as written.
  */
 enum {
     SWEPT_FORM_AUTO = 0,
@@ -193,10 +196,10 @@ int swept_set_heat_form(int32_t form);
 
 /*
  * The form the last swept_advance or swept_advance_noalloc call with
- * SWEPT_HEAT_F64 or SWEPT_HEAT_F32 evaluated (SWEPT_FORM_FUSED or
- * SWEPT_FORM_CANONICAL; the naive schedule counts as canonical), or 0 before
- * any such call.  It synchronises the library's stream to read the
- * device-side check.
+ * SWEPT_HEAT_F64 or SWEPT_HEAT_F32, or the last swept_advance_batch call with
+ * a heat instance, evaluated (SWEPT_FORM_FUSED or SWEPT_FORM_CANONICAL; the
+ * naive schedule counts as canonical), or 0 before any such call.  It
+ * synchronises the library's stream to read the device-side check.
  */
 int swept_last_heat_form(int32_t *form);
 

@@ -173,13 +173,14 @@ def set_tuning(tile_w: int = 0, pairs_per_lane: int = 0, mode: int = MODE_AUTO) 
 def set_heat_form(form: int = FORM_AUTO) -> None:
     """FORM_AUTO (the fused Laplacian where the library's range check allows
     it) or FORM_CANONICAL (the five operations as written) for heat in
-    advance(); both give the same bits."""
+    advance() and advance_batch(); both give the same bits."""
     _check(_lib.swept_set_heat_form(int(form)), "swept_set_heat_form")
 
 
 def last_heat_form() -> int:
-    """FORM_FUSED or FORM_CANONICAL: how the last heat advance() evaluated
-    its updates (0 before any); synchronises the library's stream."""
+    """FORM_FUSED or FORM_CANONICAL: how the last heat advance(), or the
+    last advance_batch() with a heat instance, evaluated its updates (0
+    before any); synchronises the library's stream."""
     out = ctypes.c_int32(0)
     _check(_lib.swept_last_heat_form(ctypes.byref(out)), "swept_last_heat_form")
     return int(out.value)

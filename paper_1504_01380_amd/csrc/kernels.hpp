@@ -95,6 +95,18 @@ __device__ __forceinline__ bool fused_ok(unsigned long long guard)
     return guard != 0 && g_form_mark < guard;
 }
 
+// The same verdict for a batch, whose launch sequence is captured once and
+// launched again with the same arguments: nonzero once the range check of
+// the current launch found a heat instance out of range.  Each launch of the
+// sequence clears it (batch_form_clear_kernel) and checks its heat instances
+// (heat_range_batch_kernel) before their first region reads it.
+__device__ int g_batch_form_bad;
+
+__device__ __forceinline__ bool batch_fused_ok(int fusable)
+{
+    return fusable != 0 && g_batch_form_bad == 0;
+}
+
 // The range check of the fused heat form: any finite |u| above `bound`
 // (a sixteenth of the largest finite value) marks the call.
 template <class T>
@@ -878,7 +890,33 @@ struct BatchArgs {
     typename S::Pt* re;         // right edges, all instances
     typename S::Pt* le[2];      // left edges, by stage parity
     int stage;
+    int fusable;                // heat: the batch's range check decides the form (0: canonical)
 };
+
+__global__ __launch_bounds__(64) void batch_form_clear_kernel()
+{
+    if (threadIdx.x == 0)
+        g_batch_form_bad = 0;
+}
+
+// The fused heat form's range check over every instance of a batch's heat
+// table (block row x: instance x; entries of other stencils have n = 0):
+// any finite |u| above `bound` raises the batch's verdict.
+template <class S>
+__global__ __launch_bounds__(256) void heat_range_batch_kernel(const BatchInst<S>* __restrict__ inst,
+                                                               typename S::T bound)
+{
+    const typename S::T* u = inst[blockIdx.x].u;
+    const int64_t n = inst[blockIdx.x].n;
+    bool bad = false;
+    const int64_t stride = (int64_t)gridDim.y * 256;
+    for (int64_t i = (int64_t)blockIdx.y * 256 + threadIdx.x; i < n; i += stride) {
+        const typename S::T v = u[i];
+        bad = bad || (__builtin_isfinite(v) && __builtin_fabs(v) > bound);
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0)
+        __hip_atomic_store(&g_batch_form_bad, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Stage s of tile t of one ring of n points tiled at the even boundaries
 // Xp(0) = 0 < Xp(1) < ... < Xp(T) = n, extended periodically
@@ -935,9 +973,19 @@ __global__ __launch_bounds__(64) void swept_batch_kernel(BatchArgs<S> g)
     const int T = I.tiles;
     const int64_t n = I.n;
     auto Xp = [&](int64_t i) { return X[i % T] + (i / T) * n; };
-    tiled_region<S, P>(I.u, n, I.L, T, Xp, task.tile, g.stage, g.re + I.e_off,
-                       g.le[(g.stage + 1) & 1] + I.e_off, g.le[g.stage & 1] + I.e_off, I.c,
-                       reinterpret_cast<Pt*>(smem_raw));
+    auto run = [&](auto sx) {
+        using SX = typename decltype(sx)::type;
+        tiled_region<SX, P>(I.u, n, I.L, T, Xp, task.tile, g.stage, g.re + I.e_off,
+                            g.le[(g.stage + 1) & 1] + I.e_off, g.le[g.stage & 1] + I.e_off, I.c,
+                            reinterpret_cast<Pt*>(smem_raw));
+    };
+    if constexpr (has_fused_form<S>) {
+        if (batch_fused_ok(g.fusable)) {
+            run(stencil_tag<typename fused_form<S>::type>{});
+            return;
+        }
+    }
+    run(stencil_tag<S>{});
 }
 
 // ----------------------------------------------------- persistent batch
@@ -996,6 +1044,7 @@ struct PersistArgs {
     int queues;
     uint64_t spin_ticks;         // 100 MHz ticks after which a wait gives up
     int chunk;                   // task numbers taken per claim (1..32)
+    int fusable;                 // as for swept_batch_kernel
 };
 
 // The XCD this wave runs on (XCC_ID register, low four bits).
@@ -1034,7 +1083,8 @@ __device__ __forceinline__ bool persist_wait(const int* p, int want, int* fault,
     }
 }
 
-template <class S, int P, bool XL>
+// SX: the stencil whose sub-timesteps the regions compute (S or its fused form)
+template <class S, class SX, int P, bool XL>
 __device__ __forceinline__ void batch_persistent(const PersistArgs<S>& g)
 {
     using Pt = typename S::Pt;
@@ -1089,7 +1139,7 @@ __device__ __forceinline__ void batch_persistent(const PersistArgs<S>& g)
                 const int64_t* X = g.X + I.x_off;
                 const int64_t n = I.n;
                 auto Xp = [&](int64_t i) { return X[i % T] + (i / T) * n; };
-                tiled_region<S, P, XL>(I.u, n, I.L, T, Xp, task.tile, s, g.re + I.e_off,
+                tiled_region<SX, P, XL>(I.u, n, I.L, T, Xp, task.tile, s, g.re + I.e_off,
                                        g.le[(s + 1) & 1] + I.e_off, g.le[s & 1] + I.e_off, I.c,
                                        reinterpret_cast<Pt*>(smem_raw));
                 if constexpr (XL) {
@@ -1121,7 +1171,13 @@ template <class S, int P, bool XL>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(S::kPersistWaves)))
 void swept_batch_persistent_kernel(PersistArgs<S> g)
 {
-    batch_persistent<S, P, XL>(g);
+    if constexpr (has_fused_form<S>) {
+        if (batch_fused_ok(g.fusable)) {
+            batch_persistent<S, typename fused_form<S>::type, P, XL>(g);
+            return;
+        }
+    }
+    batch_persistent<S, S, P, XL>(g);
 }
 
 // After a persistent launch: every queue must have handed out all its task

@@ -53,6 +53,7 @@ struct Context {
     int heat_form = SWEPT_FORM_AUTO;  // swept_set_heat_form
     int last_form = 0;                // last heat call: SWEPT_FORM_* (0: none yet)
     unsigned long long last_guard = 0;  // its range check's call id (0: none)
+    bool last_batch = false;          // the last heat call was a batch (verdict g_batch_form_bad)
 };
 
 Context g_ctx;
@@ -495,6 +496,7 @@ unsigned long long range_check(const void* u, int64_t n, const typename S::Const
     } else {
         using T = typename S::T;
         g_ctx.last_guard = 0;
+        g_ctx.last_batch = false;
         g_ctx.last_form = SWEPT_FORM_CANONICAL;
         if (g_ctx.heat_form == SWEPT_FORM_CANONICAL || !(c.r >= 0 && c.r <= 0.5) ||
             L > kFusedMaxLevels<T>)
@@ -835,7 +837,7 @@ int64_t batch_depth(int id, int64_t nring, int64_t want)
 template <class S>
 int launch_batch_stage(const BatchInst<S>* inst, const BatchTask* tasks, const int64_t* X,
                        typename S::Pt* re, typename S::Pt* le0, typename S::Pt* le1, int stage,
-                       int64_t ntasks, int kmax, hipStream_t st)
+                       int64_t ntasks, int kmax, int fusable, hipStream_t st)
 {
     if (ntasks <= 0)
         return SWEPT_OK;
@@ -847,6 +849,7 @@ int launch_batch_stage(const BatchInst<S>* inst, const BatchTask* tasks, const i
     a.le[0] = le0;
     a.le[1] = le1;
     a.stage = stage;
+    a.fusable = fusable;
     const size_t lds = (size_t)cont_chain_points<S>(kmax) * sizeof(typename S::Pt);
     hipLaunchKernelGGL((swept_batch_kernel<S, 2>), dim3((unsigned)ntasks), dim3(64), lds, st, a);
     return SWEPT_OK;
@@ -1067,6 +1070,29 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
             f_tot += p.n_ring;
         }
     }
+    // the fused heat form: one verdict for all heat instances of the batch,
+    // on the same conditions as a single field's (r and run length here,
+    // the range of every heat field on the device, heat_range_batch_kernel)
+    bool any_heat = false, fusable = g_ctx.heat_form == SWEPT_FORM_AUTO;
+    int64_t nmax_heat = 0;
+    for (int64_t j = 0; j < count; ++j) {
+        const BatchPlanInst& p = P[(size_t)j];
+        if (p.stencil != SWEPT_HEAT_F64)
+            continue;
+        any_heat = true;
+        nmax_heat = std::max(nmax_heat, p.n_ring);
+        const double r = heat64_consts(params + 2 * j).r;
+        fusable = fusable && r >= 0 && r <= 0.5 && p.L <= kFusedMaxLevels<double>;
+    }
+    fusable = fusable && any_heat;
+    // record of the last heat call, once the batch has been enqueued
+    auto record_form = [&]() {
+        if (!any_heat)
+            return;
+        g_ctx.last_guard = 0;
+        g_ctx.last_batch = fusable;
+        g_ctx.last_form = fusable ? SWEPT_FORM_FUSED : SWEPT_FORM_CANONICAL;
+    };
     // tasks of each stencil, sorted by the instance's stage count (descending),
     // so that the tasks of stage g are a prefix of the list
     std::vector<int64_t> order((size_t)count);
@@ -1242,11 +1268,13 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
     key.push_back(g_spin_limit);
     key.push_back(g_chunk);
     key.push_back(g_queues);
+    key.push_back(g_ctx.heat_form);
     for (int64_t w : g_batch_want)
         key.push_back(w);
     if (g_batch.exec && key == g_batch.key) {
         HIP_TRY(hipGraphLaunch(g_batch.exec, g_ctx.stream));
         g_ctx.fault_unread |= persist;
+        record_form();
         return SWEPT_OK;
     }
     batch_release();
@@ -1264,6 +1292,7 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
                             Q, xcd_local, kmax_k, lim);
         if (rc2)
             return rc2;
+        plh.a.fusable = fusable;
     }
     // the two persistent launches run side by side on a forked branch of the
     // graph (each waits only on its own regions, so either may start first)
@@ -1299,6 +1328,16 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
     if (ncover > 0)          // odd rings: build the two-fold covers
         hipLaunchKernelGGL(batch_cover_all_kernel, dim3((unsigned)(ncover * kCoverBlocks)),
                            dim3(256), 0, cs, d_cov, ncover);
+    // the heat fields' range check, on the heat branch (after the covers,
+    // which it reads for odd rings)
+    auto check_heat = [&]() {
+        if (!fusable)
+            return;
+        const unsigned rows = (unsigned)std::min<int64_t>(64, std::max<int64_t>(1, nmax_heat / 8192));
+        hipLaunchKernelGGL(batch_form_clear_kernel, dim3(1), dim3(64), 0, cs);
+        hipLaunchKernelGGL(heat_range_batch_kernel<HeatF64>, dim3((unsigned)count, rows), dim3(256),
+                           0, cs, d_ih, std::numeric_limits<double>::max() / 16);
+    };
     if (persist) {
         if (fork) {
             (void)hipEventRecord(ev_fork, cs);
@@ -1306,20 +1345,22 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
             plk.launch(cs2);
             (void)hipEventRecord(ev_join, cs2);
         }
+        check_heat();
         plh.launch(cs);
         if (fork)
             (void)hipStreamWaitEvent(cs, ev_join, 0);
         else
             plk.launch(cs);
     } else {
+        check_heat();
         size_t ph = 0, pk = 0;
         for (int64_t g = 0; g < smax; ++g) {
             while (ph < sh.size() && sh[ph] > g) ++ph;
             while (pk < sk.size() && sk[pk] > g) ++pk;
             launch_batch_stage<HeatF64>(d_ih, d_th, d_x, d_eh, d_eh + e_heat, d_eh + 2 * e_heat,
-                                        (int)g, (int64_t)ph, kmax_h, cs);
+                                        (int)g, (int64_t)ph, kmax_h, fusable, cs);
             launch_batch_stage<KSF64>(d_ik, d_tk, d_x, d_ek, d_ek + e_ks, d_ek + 2 * e_ks, (int)g,
-                                      (int64_t)pk, kmax_k, cs);
+                                      (int64_t)pk, kmax_k, 0, cs);
         }
     }
     if (ncover > 0)          // odd rings: copy one period back
@@ -1341,6 +1382,7 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
     g_batch.exec = exec;
     HIP_TRY(hipGraphLaunch(exec, g_ctx.stream));
     g_ctx.fault_unread |= persist;
+    record_form();
     return SWEPT_OK;
 }
 
@@ -1603,6 +1645,7 @@ int advance_dispatch(void* u, int64_t nx, int64_t nsteps, int32_t id, const doub
     if (p.mode == SWEPT_MODE_NAIVE) {
         if (id == SWEPT_HEAT_F64 || id == SWEPT_HEAT_F32) {
             g_ctx.last_guard = 0;
+            g_ctx.last_batch = false;
             g_ctx.last_form = SWEPT_FORM_CANONICAL;
         }
         return naive_dispatch(u, nx, nsteps, id, params);
@@ -2176,12 +2219,20 @@ int swept_last_heat_form(int32_t* form)
         return fail(SWEPT_ENOTINIT, "swept_init has not been called");
     *form = g_ctx.last_form;
     if (g_ctx.last_form == SWEPT_FORM_FUSED) {
-        unsigned long long mark = 0;
         HIP_TRY(hipStreamSynchronize(g_ctx.stream));
-        HIP_TRY(hipMemcpyFromSymbol(&mark, HIP_SYMBOL(g_form_mark), sizeof(mark), 0,
-                                    hipMemcpyDeviceToHost));
-        if (mark >= g_ctx.last_guard)
-            *form = SWEPT_FORM_CANONICAL;
+        if (g_ctx.last_batch) {
+            int bad = 0;
+            HIP_TRY(hipMemcpyFromSymbol(&bad, HIP_SYMBOL(g_batch_form_bad), sizeof(bad), 0,
+                                        hipMemcpyDeviceToHost));
+            if (bad != 0)
+                *form = SWEPT_FORM_CANONICAL;
+        } else {
+            unsigned long long mark = 0;
+            HIP_TRY(hipMemcpyFromSymbol(&mark, HIP_SYMBOL(g_form_mark), sizeof(mark), 0,
+                                        hipMemcpyDeviceToHost));
+            if (mark >= g_ctx.last_guard)
+                *form = SWEPT_FORM_CANONICAL;
+        }
     }
     return SWEPT_OK;
 }

@@ -1,5 +1,5 @@
 """The fused-Laplacian evaluation of heat (binary64 and binary32) in
-swept_advance.
+swept_advance and swept_advance_batch.
 
 (u[i-1] + u[i+1]) - 2u equals fma(-2, u, u[i-1] + u[i+1]) bit for bit while
 2u is finite; the library takes the fused form only after its range check
@@ -9,7 +9,9 @@ heat sub-timestep).  Both forms must
 give the oracle's bits; the checks here also make sure the fused form is the
 one taken where it is allowed, that data or parameters outside the allowed
 range take the five operations as written, and that one call's failed check
-does not stick to later calls."""
+does not stick to later calls.  A batch takes one verdict for all its heat
+instances and checks its fields again at every launch of its captured
+graph."""
 import numpy as np
 import pytest
 
@@ -173,3 +175,109 @@ def test_naive_and_noalloc_report_their_forms(sw, oracle_mod):
     got = run(sw, u0, 300, 0.25)
     assert sw.last_heat_form() == sw.FORM_CANONICAL
     assert same_bits(got, want)
+
+
+# ------------------------------------------------------------------ batches
+KS_P = [workloads.KS_DT, workloads.KS_DX]
+BATCH_SIZES = [256, 257, 1001, 2048, 4096, 777, 6000, 100]
+
+
+def mixed_batch(seed, r=0.25):
+    """(stencil, nsteps, u0, params): heat and KS alternately, odd and even
+    lengths (the odd heat ring runs on its two-fold cover)."""
+    g = workloads.rng(seed)
+    insts = []
+    for q, n in enumerate(BATCH_SIZES):
+        st = "heat" if q % 2 == 0 else "ks"
+        ns = int(g.integers(1, 400 if st == "heat" else 100))
+        insts.append((st, ns, g.uniform(-1, 1, n), [r] if st == "heat" else KS_P))
+    return insts
+
+
+def batch_oracle(oracle_mod, insts):
+    return [oracle_mod.heat(u0, ns, p[0]) if st == "heat" else oracle_mod.ks(u0, ns, *p)
+            for st, ns, u0, p in insts]
+
+
+def run_batch(sw, insts, us=None):
+    """Advance the batch; with `us`, refill those tensors (same pointers, so
+    the captured graph is launched again)."""
+    import torch
+    if us is None:
+        us = [torch.from_numpy(u0.copy()).cuda() for _, _, u0, _ in insts]
+    else:
+        for (_, _, u0, _), u in zip(insts, us):
+            u.copy_(torch.from_numpy(u0))
+    sw.advance_batch(us, [ns for _, ns, _, _ in insts], [st for st, _, _, _ in insts],
+                     [p for _, _, _, p in insts])
+    torch.cuda.synchronize()
+    sw.sync()
+    return us
+
+
+def assert_batch(us, want):
+    for u, w in zip(us, want):
+        assert same_bits_up_to_nan(u.cpu().numpy(), w)
+
+
+@pytest.fixture
+def batch_schedule(sw):
+    yield
+    sw.set_batch_schedule(sw.BATCH_PERSISTENT, 0)
+
+
+@pytest.mark.parametrize("schedule", ["persistent", "staged"])
+def test_batch_takes_the_fused_form(sw, oracle_mod, batch_schedule, schedule):
+    sw.set_batch_schedule(sw.BATCH_PERSISTENT if schedule == "persistent" else sw.BATCH_STAGED, 0)
+    insts = mixed_batch(31)
+    want = batch_oracle(oracle_mod, insts)
+    assert_batch(run_batch(sw, insts), want)
+    assert sw.last_heat_form() == sw.FORM_FUSED
+    sw.set_heat_form(sw.FORM_CANONICAL)
+    assert_batch(run_batch(sw, insts), want)
+    assert sw.last_heat_form() == sw.FORM_CANONICAL
+
+
+@pytest.mark.parametrize("schedule", ["persistent", "staged"])
+def test_batch_checks_its_fields_at_every_launch(sw, oracle_mod, batch_schedule, schedule):
+    """The same batch (same pointers: the captured graph runs again) with a
+    heat field of values near MAX/2 in the second launch, whose oracle run
+    overflows where the fused form would not: that launch must take the five
+    operations, and the next good launch the fused form again."""
+    sw.set_batch_schedule(sw.BATCH_PERSISTENT if schedule == "persistent" else sw.BATCH_STAGED, 0)
+    good = mixed_batch(32)
+    bad = list(good)
+    rng = np.random.default_rng(6)
+    st, ns, u0, p = bad[2]
+    bad[2] = (st, ns, DMAX * (0.5 + 0.1 * rng.uniform(-1.0, 1.0, u0.size)), p)
+    want_bad = batch_oracle(oracle_mod, bad)
+    assert not np.all(np.isfinite(want_bad[2]))     # the case separates the two forms
+    want_good = batch_oracle(oracle_mod, good)
+    us = run_batch(sw, good)
+    assert sw.last_heat_form() == sw.FORM_FUSED
+    assert_batch(us, want_good)
+    for insts, want, form in ((bad, want_bad, sw.FORM_CANONICAL),
+                              (good, want_good, sw.FORM_FUSED),
+                              (bad, want_bad, sw.FORM_CANONICAL)):
+        run_batch(sw, insts, us)
+        assert sw.last_heat_form() == form
+        assert_batch(us, want)
+
+
+def test_batch_r_outside_the_range_takes_the_canonical_form(sw, oracle_mod):
+    insts = mixed_batch(33)
+    st, ns, u0, _ = insts[4]
+    insts[4] = (st, min(ns, 100), u0, [0.6])
+    assert_batch(run_batch(sw, insts), batch_oracle(oracle_mod, insts))
+    assert sw.last_heat_form() == sw.FORM_CANONICAL
+
+
+def test_a_batch_without_heat_leaves_the_record(sw, oracle_mod):
+    u0 = workloads.white_noise(1 << 14, seed=83)
+    sw.set_tuning(256, 2, 1)
+    run(sw, u0, 100, 0.25)
+    assert sw.last_heat_form() == sw.FORM_FUSED
+    sw.set_tuning(0, 0, sw.MODE_AUTO)
+    insts = [i for i in mixed_batch(34) if i[0] == "ks"]
+    assert_batch(run_batch(sw, insts), batch_oracle(oracle_mod, insts))
+    assert sw.last_heat_form() == sw.FORM_FUSED
