@@ -1328,16 +1328,14 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
     if (ncover > 0)          // odd rings: build the two-fold covers
         hipLaunchKernelGGL(batch_cover_all_kernel, dim3((unsigned)(ncover * kCoverBlocks)),
                            dim3(256), 0, cs, d_cov, ncover);
-    // the heat fields' range check, on the heat branch (after the covers,
-    // which it reads for odd rings)
-    auto check_heat = [&]() {
-        if (!fusable)
-            return;
+    // the heat fields' range check, after the covers (which it reads for odd
+    // rings) and before both stencils' regions, while it has the GPU to itself
+    if (fusable) {
         const unsigned rows = (unsigned)std::min<int64_t>(64, std::max<int64_t>(1, nmax_heat / 8192));
         hipLaunchKernelGGL(batch_form_clear_kernel, dim3(1), dim3(64), 0, cs);
         hipLaunchKernelGGL(heat_range_batch_kernel<HeatF64>, dim3((unsigned)count, rows), dim3(256),
                            0, cs, d_ih, std::numeric_limits<double>::max() / 16);
-    };
+    }
     if (persist) {
         if (fork) {
             (void)hipEventRecord(ev_fork, cs);
@@ -1345,14 +1343,12 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
             plk.launch(cs2);
             (void)hipEventRecord(ev_join, cs2);
         }
-        check_heat();
         plh.launch(cs);
         if (fork)
             (void)hipStreamWaitEvent(cs, ev_join, 0);
         else
             plk.launch(cs);
     } else {
-        check_heat();
         size_t ph = 0, pk = 0;
         for (int64_t g = 0; g < smax; ++g) {
             while (ph < sh.size() && sh[ph] > g) ++ph;
