@@ -559,7 +559,7 @@ def size_sweep(sw, torch, workloads):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only; this build has no multi-GPU path "
+        print("bench.py measures one GPU only; the library has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
     import numpy as np

@@ -63,7 +63,7 @@ typedef enum {
     SWEPT_ENOTINIT = -2,      /* swept_init was not called (or failed) */
     SWEPT_ENOMEM = -3,        /* device allocation of scratch failed */
     SWEPT_EHIP = -4,          /* a HIP runtime call or kernel launch failed */
-    SWEPT_EUNSUPPORTED = -5,  /* valid request this build cannot run (e.g. tiling impossible) */
+    SWEPT_EUNSUPPORTED = -5,  /* valid request the library cannot run (e.g. tiling impossible) */
     SWEPT_ETIMEOUT = -6       /* a bounded device-side wait gave up (persistent batch,
                                  reported by swept_sync) */
 } swept_status;
@@ -180,7 +180,7 @@ int swept_set_tuning(int32_t tile_w, int32_t pairs_per_lane, int32_t mode);
  *    (2*u overflows, the fused form does not); a non-finite value only
  *    produces non-finite values, alike in both forms.  Otherwise the
  *    kernels evaluate the five operations as written.  A batch takes one
- *    verdict for all its heat instances: every one must meet the
+ *    decision for all its heat instances: every one must meet the
  *    conditions (its r, its step count, its field), else all of them run
  *    the five operations; each launch of a batch checks its fields again.
  *  - SWEPT_FORM_CANONICAL: always the five operations as written.

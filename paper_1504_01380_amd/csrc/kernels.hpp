@@ -95,7 +95,7 @@ __device__ __forceinline__ bool fused_ok(unsigned long long guard)
     return guard != 0 && g_form_mark < guard;
 }
 
-// The same verdict for a batch, whose launch sequence is captured once and
+// The same decision for a batch, whose launch sequence is captured once and
 // launched again with the same arguments: nonzero once the range check of
 // the current launch found a heat instance out of range.  Each launch of the
 // sequence clears it (batch_form_clear_kernel) and checks its heat instances
@@ -901,7 +901,7 @@ __global__ __launch_bounds__(64) void batch_form_clear_kernel()
 
 // The fused heat form's range check over every instance of a batch's heat
 // table (block row x: instance x; entries of other stencils have n = 0):
-// any finite |u| above `bound` raises the batch's verdict.
+// any finite |u| above `bound` raises the batch's flag.
 template <class S>
 __global__ __launch_bounds__(256) void heat_range_batch_kernel(const BatchInst<S>* __restrict__ inst,
                                                                typename S::T bound)

@@ -53,7 +53,7 @@ struct Context {
     int heat_form = SWEPT_FORM_AUTO;  // swept_set_heat_form
     int last_form = 0;                // last heat call: SWEPT_FORM_* (0: none yet)
     unsigned long long last_guard = 0;  // its range check's call id (0: none)
-    bool last_batch = false;          // the last heat call was a batch (verdict g_batch_form_bad)
+    bool last_batch = false;          // the last heat call was a batch (its flag: g_batch_form_bad)
 };
 
 Context g_ctx;
@@ -1070,7 +1070,7 @@ int run_batch(void* const* u, const int64_t* nx, const int64_t* nsteps, const in
             f_tot += p.n_ring;
         }
     }
-    // the fused heat form: one verdict for all heat instances of the batch,
+    // the fused heat form: one decision for all heat instances of the batch,
     // on the same conditions as a single field's (r and run length here,
     // the range of every heat field on the device, heat_range_batch_kernel)
     bool any_heat = false, fusable = g_ctx.heat_form == SWEPT_FORM_AUTO;

@@ -1,6 +1,6 @@
 """Write tests/golden/full_digests.json: SHA-256 digests of the oracle's
 whole-field results on the full-size workloads, so that GPU tests can compare
-every point of a full run with the oracle without running it on the GPU machine.
+every point of a full run with the oracle without running the oracle there.
 
 Calls only oracle/ (and the seeded input generators of workloads.py).  Each
 run is the plain full-grid step-by-step definition; at 8 host threads the

@@ -9,7 +9,7 @@ heat sub-timestep).  Both forms must
 give the oracle's bits; the checks here also make sure the fused form is the
 one taken where it is allowed, that data or parameters outside the allowed
 range take the five operations as written, and that one call's failed check
-does not stick to later calls.  A batch takes one verdict for all its heat
+does not stick to later calls.  A batch takes one decision for all its heat
 instances and checks its fields again at every launch of its captured
 graph."""
 import numpy as np
