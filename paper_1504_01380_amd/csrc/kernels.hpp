@@ -1165,8 +1165,9 @@ __device__ __forceinline__ void batch_persistent(const PersistArgs<S>& g)
 }
 
 // The task loop keeps a few more values live than one region does; the
-// bounds hold each stencil to the registers of the per-stage kernel's
-// occupancy (heat 8 waves per SIMD, KS 4).
+// bounds hold each stencil to the occupancy its regions reach anyway: heat
+// 8 waves per SIMD (its LDS chain allows more), KS 3 (at depth 256 its LDS
+// chain of 24-byte points fits 13 workgroups per CU).
 template <class S, int P, bool XL>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(S::kPersistWaves)))
 void swept_batch_persistent_kernel(PersistArgs<S> g)

@@ -127,7 +127,7 @@ struct KSF64 {
         double dt, h, c1, c2;
     };
     static constexpr int NPHASE = 4;
-    static constexpr int kPersistWaves = 4;   // waves per SIMD of the persistent batch kernel
+    static constexpr int kPersistWaves = 3;   // waves per SIMD of the persistent batch kernel
     // the continuous kernel's fill and drain run unmasked: a KS wave step is
     // long enough that masking the idle slots costs more than their updates
     static constexpr bool kUnmaskedEnds = true;
