@@ -117,7 +117,10 @@ using HeatF32 = Heat<float>;
 // F(a,b) = -(((a*D1(a)) + b) + D2(b)).
 // A point carries (u, a, b): at a step boundary a = u; after sub0 b = w;
 // after sub1 a = v; after sub2 b = z; sub3 writes u' into u and a.  The
-// unused slot holds a stale value that no sub-timestep reads.
+// unused slot holds a stale value that no sub-timestep reads.  Since a = u
+// (the same bits) until sub1 writes v, sub0 and sub1 read u wherever the
+// scheme reads a: their neighbours' a need not be moved between lanes or
+// kept in the LDS chain.
 struct KSF64 {
     using T = double;
     struct Pt {
@@ -138,38 +141,46 @@ struct KSF64 {
     {
         return Pt{dpp_shr1(s.u, old.u), dpp_shr1(s.a, old.a), dpp_shr1(s.b, old.b)};
     }
-    __device__ __forceinline__ static double rhs(const Pt& l, const Pt& c, const Pt& r,
-                                                 const Consts& k)
+    // F(a, b) at a point from the a and b of it and its two neighbours
+    __device__ __forceinline__ static double rhs(double la, double ca, double ra, double lb,
+                                                 double cb, double rb, const Consts& k)
     {
-        const double d1a = (r.a - l.a) * k.c1;
-        const double d2b = ((l.b + r.b) - 2.0 * c.b) * k.c2;
-        return -(((c.a * d1a) + c.b) + d2b);
+        const double d1a = (ra - la) * k.c1;
+        const double d2b = ((lb + rb) - 2.0 * cb) * k.c2;
+        return -(((ca * d1a) + cb) + d2b);
     }
     template <int PH>
     __device__ __forceinline__ static Pt step(const Pt& l, const Pt& c, const Pt& r,
                                               const Consts& k)
     {
-        if constexpr (PH == 0 || PH == 2) {
+        if constexpr (PH == 0) {          // a = u here
+            return Pt{c.u, c.u, ((l.u + r.u) - 2.0 * c.u) * k.c2};
+        } else if constexpr (PH == 2) {
             return Pt{c.u, c.a, ((l.a + r.a) - 2.0 * c.a) * k.c2};
-        } else if constexpr (PH == 1) {
-            return Pt{c.u, c.u + k.h * rhs(l, c, r, k), c.b};
+        } else if constexpr (PH == 1) {   // a = u here
+            return Pt{c.u, c.u + k.h * rhs(l.u, c.u, r.u, l.b, c.b, r.b, k), c.b};
         } else {
-            const double un = c.u + k.dt * rhs(l, c, r, k);
+            const double un = c.u + k.dt * rhs(l.a, c.a, r.a, l.b, c.b, r.b, k);
             return Pt{un, un, c.b};
         }
     }
 
     // A pair's state after sub-timestep PH is read only by sub-timestep PH+1
-    // (of the pair beside it): D2 of a (PH+1 even) reads u and a of the
-    // centre point B and a of A; F (PH+1 odd) reads u, a, b of B and a, b of
-    // A.  The continuous kernel's LDS chain keeps only those components.
+    // (of the pair beside it), whose centre point is B: sub0 reads u of both
+    // points; sub1 u and b of both; sub2 u and a of B and a of A; sub3 u, a,
+    // b of B and a, b of A.  The continuous kernel's LDS chain keeps only
+    // those components.
     static constexpr bool kChainStore = true;
     template <int PH>
     __device__ __forceinline__ static void chain_store(Pt* dB, Pt* dA, const Pt& B, const Pt& A)
     {
         dB->u = B.u;
-        dB->a = B.a;
-        dA->a = A.a;
+        if constexpr (PH == 3 || PH == 0) {
+            dA->u = A.u;
+        } else {
+            dB->a = B.a;
+            dA->a = A.a;
+        }
         if constexpr (PH == 0 || PH == 2) {
             dB->b = B.b;
             dA->b = A.b;
@@ -290,23 +301,26 @@ using HeatLapF32 = HeatLap<float>;
 // KS: D2(a) = fma(-2, a, a[i-1] + a[i+1]) * c2,
 //     F(a,b) = -(fma(a, D1(a), b) + D2(b)),  v = fma(h, F, u),  u' = fma(dt, F, u)
 struct KSFmaF64 : KSF64 {
-    __device__ __forceinline__ static double rhs(const Pt& l, const Pt& c, const Pt& r,
-                                                 const Consts& k)
+    __device__ __forceinline__ static double rhs(double la, double ca, double ra, double lb,
+                                                 double cb, double rb, const Consts& k)
     {
-        const double d1a = (r.a - l.a) * k.c1;
-        const double d2b = fmad(-2.0, c.b, l.b + r.b) * k.c2;
-        return -(fmad(c.a, d1a, c.b) + d2b);
+        const double d1a = (ra - la) * k.c1;
+        const double d2b = fmad(-2.0, cb, lb + rb) * k.c2;
+        return -(fmad(ca, d1a, cb) + d2b);
     }
+    // as KSF64, sub0 and sub1 read u where the scheme reads a (equal there)
     template <int PH>
     __device__ __forceinline__ static Pt step(const Pt& l, const Pt& c, const Pt& r,
                                               const Consts& k)
     {
-        if constexpr (PH == 0 || PH == 2) {
+        if constexpr (PH == 0) {
+            return Pt{c.u, c.u, fmad(-2.0, c.u, l.u + r.u) * k.c2};
+        } else if constexpr (PH == 2) {
             return Pt{c.u, c.a, fmad(-2.0, c.a, l.a + r.a) * k.c2};
         } else if constexpr (PH == 1) {
-            return Pt{c.u, fmad(k.h, rhs(l, c, r, k), c.u), c.b};
+            return Pt{c.u, fmad(k.h, rhs(l.u, c.u, r.u, l.b, c.b, r.b, k), c.u), c.b};
         } else {
-            const double un = fmad(k.dt, rhs(l, c, r, k), c.u);
+            const double un = fmad(k.dt, rhs(l.a, c.a, r.a, l.b, c.b, r.b, k), c.u);
             return Pt{un, un, c.b};
         }
     }

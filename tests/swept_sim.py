@@ -23,17 +23,21 @@ def heat_step(r):
 def ks_step(dt, dx):
     h, c1, c2 = 0.5 * dt, 1.0 / (2.0 * dx), 1.0 / (dx * dx)
 
-    def rhs(l, c, r):
-        d1a = (r[1] - l[1]) * c1
+    def rhs(l, c, r, ia):
+        d1a = (r[ia] - l[ia]) * c1
         d2b = ((l[2] + r[2]) - 2.0 * c[2]) * c2
-        return -(((c[1] * d1a) + c[2]) + d2b)
+        return -(((c[ia] * d1a) + c[2]) + d2b)
 
+    # as the kernel: a = u until sub1 writes v, so sub0 and sub1 read u
+    # (index 0) where the scheme reads a (index 1)
     def f(ph, l, c, r):
-        if ph in (0, 2):
+        if ph == 0:
+            return (c[0], c[0], ((l[0] + r[0]) - 2.0 * c[0]) * c2)
+        if ph == 2:
             return (c[0], c[1], ((l[1] + r[1]) - 2.0 * c[1]) * c2)
         if ph == 1:
-            return (c[0], c[0] + h * rhs(l, c, r), c[2])
-        un = c[0] + dt * rhs(l, c, r)
+            return (c[0], c[0] + h * rhs(l, c, r, 0), c[2])
+        un = c[0] + dt * rhs(l, c, r, 1)
         return (un, un, c[2])
     f.unmasked_ends = True   # as the KS continuous kernel (kUnmaskedEnds)
     return f, 4, (lambda v: (v, v, 0.0)), (lambda p: p[0])
@@ -45,14 +49,19 @@ NAN = float("nan")
 def _chain_store(ph, B, A, oldB, oldA):
     """What the continuous kernel's last slot leaves in the LDS chain after
     sub-timestep ph: whole points for one-value stencils; for KS points
-    (u, a, b) only what sub-timestep ph+1 reads (B's u and a, A's a, plus
-    both b when ph+1 is a flux step) -- here the other components become NaN,
-    so a read of one of them would show in the result."""
+    (u, a, b) only what sub-timestep ph+1 reads (sub0: u of both; sub1: u
+    and b of both; sub2: B's u and a, A's a; sub3: B's u, a and b, A's a and
+    b) -- here the other components become NaN, so a read of one of them
+    would show in the result."""
     if not isinstance(B, tuple):
         return B, A
-    if ph in (0, 2):
-        return (B[0], B[1], B[2]), (NAN, A[1], A[2])
-    return (B[0], B[1], NAN), (NAN, A[1], NAN)
+    if ph == 3:
+        return (B[0], NAN, NAN), (A[0], NAN, NAN)
+    if ph == 0:
+        return (B[0], NAN, B[2]), (A[0], NAN, A[2])
+    if ph == 1:
+        return (B[0], B[1], NAN), (NAN, A[1], NAN)
+    return (B[0], B[1], B[2]), (NAN, A[1], A[2])
 
 
 def _poison(p):
